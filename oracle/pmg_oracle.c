@@ -1,0 +1,1073 @@
+/*
+ * pmg_oracle.c -- plain FP64 CPU oracle of the p-multigrid gamma-cycle with
+ * cyclic-reduction line smoothers (arXiv 2504.10710).
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark; never by the GPU library.  It shares no
+ * code with the GPU path.  See pmg_oracle.h for conventions.
+ *
+ * Parity pins (tests/test_oracle_*.py) tie every routine below to something
+ * the paper or mathematics fixes: closed-form GLL rules, exactness of the
+ * quadrature, polynomial exactness of D and J, symmetry and null space of
+ * A, the Kronecker form of the undeformed operator, energy integrals of
+ * polynomials, Thomas/dense LU for the line solver, the dense Schur
+ * complement for the coarse line matrix, dense solves of the whole system,
+ * linearity and symmetry of the cycle, level-visit counts of the cost
+ * proposition, and the iteration counts printed in Table 1.
+ */
+#include "pmg_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_MAXLEV 16
+
+/* ------------------------------------------------------------------ */
+/* 1-D GLL building blocks (Sec. 2.2)                                  */
+/* ------------------------------------------------------------------ */
+
+/* Legendre L_p(x) and L_p'(x) by the three-term recurrence
+ * (k+1) L_{k+1} = (2k+1) x L_k - k L_{k-1} and L'_{k+1} = L'_{k-1} + (2k+1) L_k. */
+void or_legendre(int p, double x, double* L, double* dL)
+{
+    double l0 = 1.0, l1 = x, d0 = 0.0, d1 = 1.0;
+    if (p == 0) { *L = 1.0; *dL = 0.0; return; }
+    for (int k = 1; k < p; ++k) {
+        double l2 = ((2.0 * k + 1.0) * x * l1 - k * l0) / (k + 1.0);
+        double d2 = d0 + (2.0 * k + 1.0) * l1;
+        l0 = l1; l1 = l2; d0 = d1; d1 = d2;
+    }
+    *L = l1; *dL = d1;
+}
+
+/* Def. GLL quadrature rule: xi_0 = -1, xi_p = 1, interior nodes are the roots
+ * of L_p', weights rho_n = 2 / (p (p+1) L_p(xi_n)^2).  Interior roots by
+ * Newton's method on L_p' (second derivative from Legendre's equation
+ * (1-x^2) L'' = 2x L' - p(p+1) L), started from the Chebyshev-Lobatto
+ * points. */
+int or_gll(int p, double* xi, double* rho)
+{
+    if (p < 1) return -1;
+    xi[0] = -1.0; xi[p] = 1.0;
+    for (int n = 1; n < p; ++n) {
+        double x = -cos(M_PI * n / p);
+        int ok = 0;
+        for (int it = 0; it < 100; ++it) {
+            double L, dL;
+            or_legendre(p, x, &L, &dL);
+            double d2L = (2.0 * x * dL - p * (p + 1.0) * L) / (1.0 - x * x);
+            double dx = dL / d2L;
+            x -= dx;
+            if (fabs(dx) < 1e-16) { ok = 1; break; }
+        }
+        if (!ok) {
+            /* one more polish pass decides */
+            double L, dL;
+            or_legendre(p, x, &L, &dL);
+            if (fabs(dL) > 1e-10 * p * p) return -1;
+        }
+        xi[n] = x;
+    }
+    for (int n = 0; n <= p; ++n) {
+        double L, dL;
+        or_legendre(p, xi[n], &L, &dL);
+        rho[n] = 2.0 / (p * (p + 1.0) * L * L);
+    }
+    return 0;
+}
+
+/* Def. GLL interpolation basis: pi_j(x) = prod_{k != j} (x - xi_k) / (xi_j - xi_k).
+ * Its derivative at a node, written out from the product rule:
+ *   i != j : pi_j'(xi_i) = prod_{k != i,j} (xi_i - xi_k) / prod_{k != j} (xi_j - xi_k)
+ *   i == j : pi_j'(xi_j) = sum_{k != j} 1 / (xi_j - xi_k). */
+void or_deriv(int p, const double* xi, double* D)
+{
+    int n1 = p + 1;
+    for (int i = 0; i < n1; ++i) {
+        for (int j = 0; j < n1; ++j) {
+            double v;
+            if (i == j) {
+                v = 0.0;
+                for (int k = 0; k < n1; ++k)
+                    if (k != j) v += 1.0 / (xi[j] - xi[k]);
+            } else {
+                double num = 1.0, den = 1.0;
+                for (int k = 0; k < n1; ++k) {
+                    if (k != j) den *= (xi[j] - xi[k]);
+                    if (k != j && k != i) num *= (xi[i] - xi[k]);
+                }
+                v = num / den;
+            }
+            D[i * n1 + j] = v;
+        }
+    }
+}
+
+/* J[i][j] = pi^c_j(xf_i), straight from the product form of the basis. */
+void or_interp(int pc, const double* xic, int nf, const double* xf, double* J)
+{
+    int nc = pc + 1;
+    for (int i = 0; i < nf; ++i)
+        for (int j = 0; j < nc; ++j) {
+            double v = 1.0;
+            for (int k = 0; k < nc; ++k)
+                if (k != j) v *= (xf[i] - xic[k]) / (xic[j] - xic[k]);
+            J[i * nc + j] = v;
+        }
+}
+
+/* ------------------------------------------------------------------ */
+/* Line solvers (Sec. 3.2)                                              */
+/* ------------------------------------------------------------------ */
+
+/* Coarse matrix M0 = D - C A^{-1} B of Prop. "line coarse space" for m = 1
+ * blocks, with the F points at odd 1-based (even 0-based) positions
+ * (Def. odd-even reordering).  The stencil is the one the proof computes
+ * entry by entry (rows of C A^{-1} B): for the coarse point c at 0-based
+ * fine position i = 2k+1,
+ *   l0_k = -l_i l_{i-1} / a_{i-1}
+ *   a0_k =  a_i - l_i u_{i-1} / a_{i-1} - u_i l_{i+1} / a_{i+1}
+ *   u0_k = -u_i u_{i+1} / a_{i+1}
+ * where neighbours outside the line are absent.  (The statement of the
+ * proposition prints L_{i-1} in the middle term; the proof's product has
+ * U_{i-1}, which is what is used.) */
+void or_cr_coarse(int n, const double* l, const double* a, const double* u,
+                  double* l0, double* a0, double* u0)
+{
+    int nc = n / 2;
+    for (int k = 0; k < nc; ++k) {
+        int i = 2 * k + 1;
+        double ac = a[i];
+        double lc = 0.0, uc = 0.0;
+        ac -= l[i] * u[i - 1] / a[i - 1];
+        if (k > 0) lc = -l[i] * l[i - 1] / a[i - 1];
+        if (i + 1 < n) {
+            ac -= u[i] * l[i + 1] / a[i + 1];
+            if (i + 2 < n) uc = -u[i] * u[i + 1] / a[i + 1];
+        }
+        l0[k] = lc; a0[k] = ac; u0[k] = uc;
+    }
+}
+
+/* Direct multigrid line solver: Alg. 1 with the operators of Thm.
+ * "Two-level direct solver", applied recursively (Cor. "Direct multigrid
+ * solver"):
+ *   x = S^{-1} g,       S^{-1} = diag(1/a_F) on F points, 0 on C points
+ *   res = g - M x
+ *   gc = R res,         R = P^T
+ *   ec = M0^{-1} gc     (recursion; one unknown is a division)
+ *   y = x + P ec,       P: F rows -(l_F, u_F)/a_F, C rows identity.
+ * Every operator is applied as written (R as the full transpose of P). */
+int or_cr_solve(int n, const double* l, const double* a, const double* u,
+                const double* g, double* y)
+{
+    if (n <= 0) return 0;
+    if (n == 1) {
+        if (a[0] == 0.0) return -1;
+        y[0] = g[0] / a[0];
+        return 0;
+    }
+    int nc = n / 2;
+    double* x = (double*)calloc((size_t)n, sizeof(double));
+    double* res = (double*)calloc((size_t)n, sizeof(double));
+    double* gc = (double*)calloc((size_t)nc, sizeof(double));
+    double* ec = (double*)calloc((size_t)nc, sizeof(double));
+    double* l0 = (double*)calloc((size_t)nc, sizeof(double));
+    double* a0 = (double*)calloc((size_t)nc, sizeof(double));
+    double* u0 = (double*)calloc((size_t)nc, sizeof(double));
+    int rc = 0;
+
+    /* x = S^{-1} g */
+    for (int i = 0; i < n; i += 2) {
+        if (a[i] == 0.0) { rc = -1; goto out; }
+        x[i] = g[i] / a[i];
+    }
+    /* res = g - M x */
+    for (int i = 0; i < n; ++i) {
+        double mx = a[i] * x[i];
+        if (i > 0) mx += l[i] * x[i - 1];
+        if (i + 1 < n) mx += u[i] * x[i + 1];
+        res[i] = g[i] - mx;
+    }
+    /* gc = P^T res: column k of P has 1 at C row 2k+1, -u_{2k}/a_{2k} at F
+     * row 2k, and -l_{2k+2}/a_{2k+2} at F row 2k+2 (if it exists). */
+    for (int k = 0; k < nc; ++k) {
+        int i = 2 * k + 1;
+        double s = res[i];
+        s += (-u[i - 1] / a[i - 1]) * res[i - 1];
+        if (i + 1 < n) s += (-l[i + 1] / a[i + 1]) * res[i + 1];
+        gc[k] = s;
+    }
+    or_cr_coarse(n, l, a, u, l0, a0, u0);
+    rc = or_cr_solve(nc, l0, a0, u0, gc, ec);
+    if (rc) goto out;
+    /* y = x + P ec */
+    for (int i = 0; i < n; ++i) {
+        double pe;
+        if (i % 2 == 1) {
+            pe = ec[(i - 1) / 2];
+        } else {
+            pe = 0.0;
+            if (i >= 1) pe += (-l[i] / a[i]) * ec[(i - 2) / 2];
+            if (i + 1 < n) pe += (-u[i] / a[i]) * ec[i / 2];
+        }
+        y[i] = x[i] + pe;
+    }
+out:
+    free(x); free(res); free(gc); free(ec); free(l0); free(a0); free(u0);
+    return rc;
+}
+
+/* Thomas algorithm (forward elimination, back substitution). */
+int or_thomas(int n, const double* l, const double* a, const double* u,
+              const double* g, double* y)
+{
+    if (n <= 0) return 0;
+    double* c = (double*)malloc(sizeof(double) * (size_t)n);
+    double* d = (double*)malloc(sizeof(double) * (size_t)n);
+    double den = a[0];
+    int rc = 0;
+    if (den == 0.0) { rc = -1; goto out; }
+    c[0] = (n > 1 ? u[0] : 0.0) / den;
+    d[0] = g[0] / den;
+    for (int i = 1; i < n; ++i) {
+        den = a[i] - l[i] * c[i - 1];
+        if (den == 0.0) { rc = -1; goto out; }
+        c[i] = (i + 1 < n ? u[i] : 0.0) / den;
+        d[i] = (g[i] - l[i] * d[i - 1]) / den;
+    }
+    y[n - 1] = d[n - 1];
+    for (int i = n - 2; i >= 0; --i) y[i] = d[i] - c[i] * y[i + 1];
+out:
+    free(c); free(d);
+    return rc;
+}
+
+/* Gaussian elimination with partial pivoting. */
+int or_dense_solve(int n, double* A, double* g)
+{
+    for (int k = 0; k < n; ++k) {
+        int piv = k;
+        for (int i = k + 1; i < n; ++i)
+            if (fabs(A[i * n + k]) > fabs(A[piv * n + k])) piv = i;
+        if (A[piv * n + k] == 0.0) return -1;
+        if (piv != k) {
+            for (int j = 0; j < n; ++j) {
+                double t = A[k * n + j]; A[k * n + j] = A[piv * n + j]; A[piv * n + j] = t;
+            }
+            double t = g[k]; g[k] = g[piv]; g[piv] = t;
+        }
+        for (int i = k + 1; i < n; ++i) {
+            double f = A[i * n + k] / A[k * n + k];
+            if (f == 0.0) continue;
+            for (int j = k; j < n; ++j) A[i * n + j] -= f * A[k * n + j];
+            g[i] -= f * g[k];
+        }
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int j = i + 1; j < n; ++j) s -= A[i * n + j] * g[j];
+        g[i] = s / A[i * n + i];
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Discretisation on one level (Sec. 2.2, eq. discreteBilinear)        */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int p, n1, N, nint;
+    double* xi;    /* GLL nodes of this level */
+    double* rho;   /* GLL weights */
+    double* D;     /* derivative matrix n1 x n1 */
+    double* G;     /* dim*dim arrays of N: weighted inverse metric */
+    double* mass;  /* N: quadrature weight times det J */
+    double mindet;
+    /* line tridiagonals, per axis: (p-1)^dim entries each */
+    double* lo[3];
+    double* di[3];
+    double* up[3];
+    double* X;     /* physical node coordinates, dim*N */
+    double* J;     /* prolongation from level-1: n1 x (p_{l-1}+1) (NULL at l = 0) */
+    double* A0inv; /* dense inverse of the interior matrix (level 0 only) */
+} or_level;
+
+struct or_hier {
+    int dim, nlev, gamma, m, smoother;
+    double alpha;
+    or_level lev[OR_MAXLEV];
+    long long visits[OR_MAXLEV];
+};
+
+static int ipow(int b, int e) { int r = 1; while (e-- > 0) r *= b; return r; }
+
+/* node multi-index <-> linear index */
+static void unrank(int dim, int n1, int q, int* c)
+{
+    for (int a = 0; a < dim; ++a) { c[a] = q % n1; q /= n1; }
+}
+static int rank_(int dim, int n1, const int* c)
+{
+    int q = 0;
+    for (int a = dim - 1; a >= 0; --a) q = q * n1 + c[a];
+    return q;
+}
+static int is_interior(int dim, int n1, int q)
+{
+    int c[3];
+    unrank(dim, n1, q, c);
+    for (int a = 0; a < dim; ++a)
+        if (c[a] == 0 || c[a] == n1 - 1) return 0;
+    return 1;
+}
+
+int or_nodes(const or_hier* h, int l) { return h->lev[l].N; }
+
+/* Geometry of a mapped element (eq. DiscreteSpace; the paper defers the
+ * formulas to Deville-Fischer-Mund).  Isoparametric: the Jacobian
+ * dx_c/dxi_a at node q is D applied along axis a to the nodal coordinates.
+ * With Jinv = (dx/dxi)^{-1}, the integrand grad v_i . grad v_j becomes
+ * sum_ab (dv_i/dxi_a) Ginv_ab (dv_j/dxi_b), Ginv_ab = sum_c Jinv[a][c] Jinv[b][c],
+ * and the quadrature weight is phi = rho x rho (x rho) det J.
+ * G_ab = phi * Ginv_ab, mass = phi (mass matrix of eq. discreteBilinear,
+ * diagonal by collocation). */
+static int level_geometry(int dim, or_level* L, const double* X)
+{
+    int n1 = L->n1, N = L->N;
+    L->mindet = INFINITY;
+    for (int q = 0; q < N; ++q) {
+        int c[3];
+        unrank(dim, n1, q, c);
+        double Jm[3][3];
+        for (int comp = 0; comp < dim; ++comp)
+            for (int a = 0; a < dim; ++a) {
+                double s = 0.0;
+                int cc[3] = {c[0], c[1], c[2]};
+                for (int k = 0; k < n1; ++k) {
+                    cc[a] = k;
+                    s += L->D[c[a] * n1 + k] * X[comp * N + rank_(dim, n1, cc)];
+                }
+                Jm[comp][a] = s;
+            }
+        double det, inv[3][3];
+        if (dim == 2) {
+            det = Jm[0][0] * Jm[1][1] - Jm[0][1] * Jm[1][0];
+            inv[0][0] = Jm[1][1] / det;  inv[0][1] = -Jm[0][1] / det;
+            inv[1][0] = -Jm[1][0] / det; inv[1][1] = Jm[0][0] / det;
+        } else {
+            det = Jm[0][0] * (Jm[1][1] * Jm[2][2] - Jm[1][2] * Jm[2][1])
+                - Jm[0][1] * (Jm[1][0] * Jm[2][2] - Jm[1][2] * Jm[2][0])
+                + Jm[0][2] * (Jm[1][0] * Jm[2][1] - Jm[1][1] * Jm[2][0]);
+            /* inverse = adjugate / det; inv[a][comp] = dxi_a / dx_comp */
+            inv[0][0] = (Jm[1][1] * Jm[2][2] - Jm[1][2] * Jm[2][1]) / det;
+            inv[0][1] = (Jm[0][2] * Jm[2][1] - Jm[0][1] * Jm[2][2]) / det;
+            inv[0][2] = (Jm[0][1] * Jm[1][2] - Jm[0][2] * Jm[1][1]) / det;
+            inv[1][0] = (Jm[1][2] * Jm[2][0] - Jm[1][0] * Jm[2][2]) / det;
+            inv[1][1] = (Jm[0][0] * Jm[2][2] - Jm[0][2] * Jm[2][0]) / det;
+            inv[1][2] = (Jm[0][2] * Jm[1][0] - Jm[0][0] * Jm[1][2]) / det;
+            inv[2][0] = (Jm[1][0] * Jm[2][1] - Jm[1][1] * Jm[2][0]) / det;
+            inv[2][1] = (Jm[0][1] * Jm[2][0] - Jm[0][0] * Jm[2][1]) / det;
+            inv[2][2] = (Jm[0][0] * Jm[1][1] - Jm[0][1] * Jm[1][0]) / det;
+        }
+        if (det < L->mindet) L->mindet = det;
+        double w = 1.0;
+        for (int a = 0; a < dim; ++a) w *= L->rho[c[a]];
+        double phi = w * det;
+        L->mass[q] = phi;
+        for (int a = 0; a < dim; ++a)
+            for (int b = 0; b < dim; ++b) {
+                double s = 0.0;
+                for (int comp = 0; comp < dim; ++comp) s += inv[a][comp] * inv[b][comp];
+                L->G[(a * dim + b) * N + q] = phi * s;
+            }
+    }
+    return L->mindet > 0.0 ? 0 : -1;
+}
+
+/* Entry A[row, col] of eq. discreteBilinear: the quadrature sum over nodes q
+ * of sum_ab G_ab(q) d_a v_row(q) d_b v_col(q), where for the tensor basis
+ * d_a v_n(q) = D[q_a][n_a] if q agrees with n on every axis but a, else 0.
+ * The loops visit only the nodes q where d_a v_row(q) can be nonzero. */
+static double level_entry(int dim, const or_level* L, int row, int col)
+{
+    int n1 = L->n1, N = L->N;
+    int rn[3], cn[3];
+    unrank(dim, n1, row, rn);
+    unrank(dim, n1, col, cn);
+    double s = 0.0;
+    for (int a = 0; a < dim; ++a) {
+        for (int k = 0; k < n1; ++k) {
+            int qc[3] = {rn[0], rn[1], rn[2]};
+            qc[a] = k;
+            double da = L->D[k * n1 + rn[a]];
+            if (da == 0.0) continue;
+            int q = rank_(dim, n1, qc);
+            for (int b = 0; b < dim; ++b) {
+                int match = 1;
+                for (int e = 0; e < dim; ++e)
+                    if (e != b && qc[e] != cn[e]) { match = 0; break; }
+                if (!match) continue;
+                s += L->G[(a * dim + b) * N + q] * da * L->D[qc[b] * n1 + cn[b]];
+            }
+        }
+    }
+    return s;
+}
+
+/* A x on every row: the same quadrature sum organised by quadrature node.
+ * For each q: reference gradient g_b(q) = sum_k D[q_b][k] x(q with axis b <- k),
+ * flux f_a(q) = sum_b G_ab(q) g_b(q); then
+ * (A x)(n) = sum_a sum_k D[k][n_a] f_a(n with axis a <- k). */
+static void level_apply_all(int dim, const or_level* L, const double* x, double* y)
+{
+    int n1 = L->n1, N = L->N;
+    int stride[3] = {1, n1, n1 * n1};
+    double* flux = (double*)malloc(sizeof(double) * (size_t)N * dim);
+    for (int q = 0; q < N; ++q) {
+        int c[3];
+        unrank(dim, n1, q, c);
+        double g[3];
+        for (int b = 0; b < dim; ++b) {
+            /* node q with axis b <- k is q + (k - c[b]) * stride[b] */
+            int q0 = q - c[b] * stride[b];
+            double s = 0.0;
+            for (int k = 0; k < n1; ++k) s += L->D[c[b] * n1 + k] * x[q0 + k * stride[b]];
+            g[b] = s;
+        }
+        for (int a = 0; a < dim; ++a) {
+            double s = 0.0;
+            for (int b = 0; b < dim; ++b) s += L->G[(a * dim + b) * N + q] * g[b];
+            flux[a * N + q] = s;
+        }
+    }
+    for (int n = 0; n < N; ++n) {
+        int c[3];
+        unrank(dim, n1, n, c);
+        double s = 0.0;
+        for (int a = 0; a < dim; ++a) {
+            int n0 = n - c[a] * stride[a];
+            for (int k = 0; k < n1; ++k)
+                s += L->D[k * n1 + c[a]] * flux[a * N + n0 + k * stride[a]];
+        }
+        y[n] = s;
+    }
+    free(flux);
+}
+
+static void level_apply(int dim, const or_level* L, const double* x, double* y)
+{
+    level_apply_all(dim, L, x, y);
+    for (int q = 0; q < L->N; ++q)
+        if (!is_interior(dim, L->n1, q)) y[q] = 0.0;
+}
+
+/* Entry of the bilinear finite-element stiffness matrix A~_p of Sec. 3.1
+ * (the FEM line preconditioners of Def. line preconditioners): piecewise
+ * bilinear basis on the quadrilaterals whose corners are neighbouring GLL
+ * nodes (physical positions), element integrals by the 2x2 Gauss rule on the
+ * bilinear map of each quadrilateral.  2-D only. */
+static double fem_entry2(const or_level* L, int row, int col)
+{
+    int n1 = L->n1, N = L->N;
+    int ri = row % n1, rj = row / n1, ci = col % n1, cj = col / n1;
+    if (abs(ri - ci) > 1 || abs(rj - cj) > 1) return 0.0;
+    const double gp[2] = {0.5 - 0.5 / sqrt(3.0), 0.5 + 0.5 / sqrt(3.0)};
+    double s = 0.0;
+    /* elements (k,l) = lower-left corner; both nodes must be corners */
+    for (int k = ri - 1; k <= ri; ++k)
+        for (int l = rj - 1; l <= rj; ++l) {
+            if (k < 0 || l < 0 || k >= n1 - 1 || l >= n1 - 1) continue;
+            if (ci < k || ci > k + 1 || cj < l || cj > l + 1) continue;
+            double cx[4], cy[4];
+            for (int c = 0; c < 4; ++c) {
+                int q = (k + (c & 1)) + n1 * (l + (c >> 1));
+                cx[c] = L->X[q];
+                cy[c] = L->X[N + q];
+            }
+            int a = (ri - k) + 2 * (rj - l), b = (ci - k) + 2 * (cj - l);
+            for (int g1 = 0; g1 < 2; ++g1)
+                for (int g2 = 0; g2 < 2; ++g2) {
+                    double xi = gp[g1], et = gp[g2];
+                    /* reference gradients of the four corner functions */
+                    double dxi[4] = {-(1 - et), (1 - et), -et, et};
+                    double det_[4] = {-(1 - xi), -xi, (1 - xi), xi};
+                    double J00 = 0, J01 = 0, J10 = 0, J11 = 0;
+                    for (int c = 0; c < 4; ++c) {
+                        J00 += dxi[c] * cx[c]; J01 += det_[c] * cx[c];
+                        J10 += dxi[c] * cy[c]; J11 += det_[c] * cy[c];
+                    }
+                    double det = J00 * J11 - J01 * J10;
+                    /* physical gradient = J^{-T} reference gradient */
+                    double ga_x = ( J11 * dxi[a] - J10 * det_[a]) / det;
+                    double ga_y = (-J01 * dxi[a] + J00 * det_[a]) / det;
+                    double gb_x = ( J11 * dxi[b] - J10 * det_[b]) / det;
+                    double gb_y = (-J01 * dxi[b] + J00 * det_[b]) / det;
+                    s += 0.25 * fabs(det) * (ga_x * gb_x + ga_y * gb_y);
+                }
+        }
+    return s;
+}
+
+/* Line systems (Def. line preconditioners with half-bandwidth 1, Def.
+ * Axelsson incomplete bandwidth preconditioner): for every interior line
+ * along axis dir, the tridiagonal part of R A P on the p-1 interior nodes of
+ * the line; couplings to boundary nodes are dropped (Dirichlet nodes). */
+static double fem_entry_any(int dim, const or_level* L, int row, int col)
+{
+    (void)dim;
+    return fem_entry2(L, row, col);
+}
+
+static void level_lines(int dim, or_level* L, int dir, int smoother)
+{
+    int p = L->p, n1 = L->n1, n = p - 1;
+    int nl = ipow(n, dim - 1);
+    for (int line = 0; line < nl; ++line) {
+        int c[3], t = line, o = 0;
+        for (int a = 0; a < dim; ++a) {
+            if (a == dir) continue;
+            c[a] = 1 + t % n; t /= n; (void)o;
+        }
+        for (int s = 0; s < n; ++s) {
+            c[dir] = s + 1;
+            int row = rank_(dim, n1, c);
+            double lo = 0.0, up = 0.0, di;
+            double (*ent)(int, const or_level*, int, int) =
+                smoother == 1 ? fem_entry_any : level_entry;
+            di = ent(dim, L, row, row);
+            if (s > 0) {
+                int cc[3] = {c[0], c[1], c[2]};
+                cc[dir] = s;
+                lo = ent(dim, L, row, rank_(dim, n1, cc));
+            }
+            if (s + 1 < n) {
+                int cc[3] = {c[0], c[1], c[2]};
+                cc[dir] = s + 2;
+                up = ent(dim, L, row, rank_(dim, n1, cc));
+            }
+            L->lo[dir][line * n + s] = lo;
+            L->di[dir][line * n + s] = di;
+            L->up[dir][line * n + s] = up;
+        }
+    }
+}
+
+/* node index of position s on line `line` along axis dir */
+static int line_node(int dim, const or_level* L, int dir, int line, int s)
+{
+    int n = L->p - 1, c[3], t = line;
+    for (int a = 0; a < dim; ++a) {
+        if (a == dir) continue;
+        c[a] = 1 + t % n; t /= n;
+    }
+    c[dir] = s + 1;
+    return rank_(dim, L->n1, c);
+}
+
+static int level_line_solve(int dim, const or_level* L, int dir, const double* r, double* z)
+{
+    int n = L->p - 1;
+    int nl = ipow(n, dim - 1);
+    double* g = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double* y = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    int rc = 0;
+    for (int q = 0; q < L->N; ++q) z[q] = 0.0;
+    for (int line = 0; line < nl && !rc; ++line) {
+        for (int s = 0; s < n; ++s) g[s] = r[line_node(dim, L, dir, line, s)];
+        rc = or_cr_solve(n, L->lo[dir] + line * n, L->di[dir] + line * n,
+                         L->up[dir] + line * n, g, y);
+        for (int s = 0; s < n; ++s) z[line_node(dim, L, dir, line, s)] = y[s];
+    }
+    free(g); free(y);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Hierarchy                                                            */
+/* ------------------------------------------------------------------ */
+
+static void level_free(or_level* L)
+{
+    free(L->xi); free(L->rho); free(L->D); free(L->G); free(L->mass);
+    for (int a = 0; a < 3; ++a) { free(L->lo[a]); free(L->di[a]); free(L->up[a]); }
+    free(L->J); free(L->A0inv); free(L->X);
+    memset(L, 0, sizeof(*L));
+}
+
+void or_hier_destroy(or_hier* h)
+{
+    if (!h) return;
+    for (int l = 0; l < h->nlev; ++l) level_free(&h->lev[l]);
+    free(h);
+}
+
+or_hier* or_hier_create(int dim, int nlev, const int* p, const double* const* coords,
+                        int gamma, int m, double alpha, int smoother)
+{
+    if ((dim != 2 && dim != 3) || nlev < 1 || nlev > OR_MAXLEV || gamma < 1 || m < 0
+        || smoother < 0 || smoother > 1 || (smoother == 1 && dim != 2))
+        return NULL;
+    for (int l = 0; l < nlev; ++l)
+        if (p[l] < 2 || (l > 0 && p[l] <= p[l - 1])) return NULL;
+    or_hier* h = (or_hier*)calloc(1, sizeof(or_hier));
+    h->dim = dim; h->nlev = nlev; h->gamma = gamma; h->m = m; h->alpha = alpha;
+    h->smoother = smoother;
+    for (int l = 0; l < nlev; ++l) {
+        or_level* L = &h->lev[l];
+        L->p = p[l]; L->n1 = p[l] + 1; L->N = ipow(L->n1, dim);
+        L->nint = ipow(p[l] - 1, dim);
+        L->xi = (double*)malloc(sizeof(double) * L->n1);
+        L->rho = (double*)malloc(sizeof(double) * L->n1);
+        L->D = (double*)malloc(sizeof(double) * L->n1 * L->n1);
+        L->G = (double*)malloc(sizeof(double) * (size_t)L->N * dim * dim);
+        L->mass = (double*)malloc(sizeof(double) * (size_t)L->N);
+        if (or_gll(L->p, L->xi, L->rho)) goto fail;
+        or_deriv(L->p, L->xi, L->D);
+        L->X = (double*)malloc(sizeof(double) * (size_t)L->N * dim);
+        memcpy(L->X, coords[l], sizeof(double) * (size_t)L->N * dim);
+        if (level_geometry(dim, L, coords[l])) goto fail;
+        for (int a = 0; a < dim; ++a) {
+            L->lo[a] = (double*)malloc(sizeof(double) * (size_t)L->nint);
+            L->di[a] = (double*)malloc(sizeof(double) * (size_t)L->nint);
+            L->up[a] = (double*)malloc(sizeof(double) * (size_t)L->nint);
+            level_lines(dim, L, a, smoother);
+        }
+        if (l > 0) {
+            or_level* C = &h->lev[l - 1];
+            L->J = (double*)malloc(sizeof(double) * L->n1 * C->n1);
+            or_interp(C->p, C->xi, L->n1, L->xi, L->J);
+        }
+    }
+    {
+        /* M_0^{-1} = A_0^{-1} (Alg. 2): dense inverse of the interior matrix
+         * of the coarsest level, column by column with dense LU. */
+        or_level* L = &h->lev[0];
+        int n = L->nint;
+        double* A = (double*)malloc(sizeof(double) * (size_t)n * n);
+        double* W = (double*)malloc(sizeof(double) * (size_t)n * n);
+        double* e = (double*)malloc(sizeof(double) * (size_t)n);
+        L->A0inv = (double*)malloc(sizeof(double) * (size_t)n * n);
+        or_dense_interior(h, 0, A);
+        int bad = 0;
+        for (int j = 0; j < n && !bad; ++j) {
+            memcpy(W, A, sizeof(double) * (size_t)n * n);
+            for (int i = 0; i < n; ++i) e[i] = (i == j);
+            if (or_dense_solve(n, W, e)) bad = 1;
+            for (int i = 0; i < n; ++i) L->A0inv[i * n + j] = e[i];
+        }
+        free(A); free(W); free(e);
+        if (bad) goto fail;
+    }
+    return h;
+fail:
+    or_hier_destroy(h);
+    return NULL;
+}
+
+double or_geom(const or_hier* h, int l, double* G, double* mass)
+{
+    const or_level* L = &h->lev[l];
+    int d2 = h->dim * h->dim;
+    if (G) memcpy(G, L->G, sizeof(double) * (size_t)L->N * d2);
+    if (mass) memcpy(mass, L->mass, sizeof(double) * (size_t)L->N);
+    return L->mindet;
+}
+
+void or_apply(const or_hier* h, int l, const double* x, double* y)
+{
+    level_apply(h->dim, &h->lev[l], x, y);
+}
+
+void or_apply_all(const or_hier* h, int l, const double* x, double* y)
+{
+    level_apply_all(h->dim, &h->lev[l], x, y);
+}
+
+double or_entry(const or_hier* h, int l, int row, int col)
+{
+    return level_entry(h->dim, &h->lev[l], row, col);
+}
+
+double or_fem_entry(const or_hier* h, int l, int row, int col)
+{
+    if (h->dim != 2) return NAN;
+    return fem_entry2(&h->lev[l], row, col);
+}
+
+int or_dense_interior(const or_hier* h, int l, double* A)
+{
+    const or_level* L = &h->lev[l];
+    int n = L->nint;
+    if (!A) return n;
+    int* nodes = (int*)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    int k = 0;
+    for (int q = 0; q < L->N; ++q)
+        if (is_interior(h->dim, L->n1, q)) nodes[k++] = q;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            A[i * n + j] = level_entry(h->dim, L, nodes[i], nodes[j]);
+    free(nodes);
+    return n;
+}
+
+/* Sec. 2.3: A w = M f - A v with v = Dirichlet data on the boundary, 0 inside. */
+void or_rhs(const or_hier* h, const double* f, const double* g, double* b)
+{
+    const or_level* L = &h->lev[h->nlev - 1];
+    int N = L->N;
+    double* v = (double*)calloc((size_t)N, sizeof(double));
+    double* Av = (double*)calloc((size_t)N, sizeof(double));
+    for (int q = 0; q < N; ++q) v[q] = is_interior(h->dim, L->n1, q) ? 0.0 : g[q];
+    level_apply_all(h->dim, L, v, Av);
+    for (int q = 0; q < N; ++q)
+        b[q] = is_interior(h->dim, L->n1, q) ? L->mass[q] * f[q] - Av[q] : 0.0;
+    free(v); free(Av);
+}
+
+/* Apply the 1-D matrix M (rows_out x cols_in, row-major, or its transpose)
+ * along axis a of a tensor with extents ext[] (ext[a] == cols_in). */
+static void axis_apply(int dim, const int* ext, int a, const double* M, int rows, int cols,
+                       int transpose, const double* in, double* out)
+{
+    int eo[3] = {ext[0], ext[1], dim > 2 ? ext[2] : 1};
+    int ei[3] = {ext[0], ext[1], dim > 2 ? ext[2] : 1};
+    int nout = transpose ? cols : rows;
+    int nin = transpose ? rows : cols;
+    eo[a] = nout; ei[a] = nin;
+    for (int k = 0; k < eo[2]; ++k)
+        for (int j = 0; j < eo[1]; ++j)
+            for (int i = 0; i < eo[0]; ++i) {
+                int o[3] = {i, j, k};
+                double s = 0.0;
+                for (int t = 0; t < nin; ++t) {
+                    int ii[3] = {i, j, k};
+                    ii[a] = t;
+                    double mv = transpose ? M[t * cols + o[a]] : M[o[a] * cols + t];
+                    s += mv * in[ii[0] + ei[0] * (ii[1] + ei[1] * ii[2])];
+                }
+                out[i + eo[0] * (j + eo[1] * k)] = s;
+            }
+}
+
+/* Sec. 3.3: P_l is the tensor product of the 1-D interpolation J (fine
+ * nodes x coarse basis), R_l = P_l^T.  Applied one axis at a time. */
+void or_restrict(const or_hier* h, int l, const double* rf, double* rc)
+{
+    const or_level* F = &h->lev[l];
+    const or_level* C = &h->lev[l - 1];
+    int dim = h->dim;
+    int ext[3] = {F->n1, F->n1, F->n1};
+    size_t big = (size_t)F->N;
+    double* t0 = (double*)malloc(sizeof(double) * big);
+    double* t1 = (double*)malloc(sizeof(double) * big);
+    memcpy(t0, rf, sizeof(double) * big);
+    for (int a = 0; a < dim; ++a) {
+        axis_apply(dim, ext, a, F->J, F->n1, C->n1, 1, t0, t1);
+        ext[a] = C->n1;
+        double* s = t0; t0 = t1; t1 = s;
+    }
+    for (int q = 0; q < C->N; ++q) rc[q] = is_interior(dim, C->n1, q) ? t0[q] : 0.0;
+    free(t0); free(t1);
+}
+
+void or_prolong_add(const or_hier* h, int l, const double* ec, double* xf)
+{
+    const or_level* F = &h->lev[l];
+    const or_level* C = &h->lev[l - 1];
+    int dim = h->dim;
+    int ext[3] = {C->n1, C->n1, C->n1};
+    size_t big = (size_t)F->N;
+    double* t0 = (double*)malloc(sizeof(double) * big);
+    double* t1 = (double*)malloc(sizeof(double) * big);
+    memcpy(t0, ec, sizeof(double) * (size_t)C->N);
+    for (int a = 0; a < dim; ++a) {
+        axis_apply(dim, ext, a, F->J, F->n1, C->n1, 0, t0, t1);
+        ext[a] = F->n1;
+        double* s = t0; t0 = t1; t1 = s;
+    }
+    for (int q = 0; q < F->N; ++q) xf[q] += t0[q];
+    free(t0); free(t1);
+}
+
+void or_line_coefs(const or_hier* h, int l, int dir, double* lo, double* di, double* up)
+{
+    const or_level* L = &h->lev[l];
+    size_t n = (size_t)L->nint;
+    if (lo) memcpy(lo, L->lo[dir], sizeof(double) * n);
+    if (di) memcpy(di, L->di[dir], sizeof(double) * n);
+    if (up) memcpy(up, L->up[dir], sizeof(double) * n);
+}
+
+int or_line_solve(const or_hier* h, int l, int dir, const double* r, double* z)
+{
+    return level_line_solve(h->dim, &h->lev[l], dir, r, z);
+}
+
+/* Alg. 2 smoothing step: x_i = x_{i-1} + alpha B_dir^{-1} (r - A x_{i-1}). */
+int or_smooth(const or_hier* h, int l, int dir, const double* r, double* x)
+{
+    const or_level* L = &h->lev[l];
+    int N = L->N;
+    double* res = (double*)malloc(sizeof(double) * (size_t)N);
+    double* z = (double*)malloc(sizeof(double) * (size_t)N);
+    level_apply(h->dim, L, x, res);
+    for (int q = 0; q < N; ++q) res[q] = r[q] - res[q];
+    for (int q = 0; q < N; ++q)
+        if (!is_interior(h->dim, L->n1, q)) res[q] = 0.0;
+    int rc = level_line_solve(h->dim, L, dir, res, z);
+    for (int q = 0; q < N; ++q) x[q] += h->alpha * z[q];
+    free(res); free(z);
+    return rc;
+}
+
+/* Alg. 2 (Def. multigrid gamma-cycle).  Readings:
+ *  - pre-smoothing: m steps along the first axis ("horizontal" lines), then m
+ *    along the second ("vertical"), then m along the third in 3-D;
+ *  - the loop over g = 1..gamma carries the iterate: each pass takes the
+ *    current iterate, adds the coarse correction P M_{l-1}^{-1} R (r - A z)
+ *    and post-smooths it (m steps per axis, axes in reverse order); with the
+ *    literal "x_{2m}" in every pass, passes 2..gamma would repeat pass 1;
+ *  - level 0 is solved exactly: M_0^{-1} = A_0^{-1}. */
+int or_cycle(const or_hier* h, int l, const double* r, double* y)
+{
+    or_hier* hm = (or_hier*)h;
+    hm->visits[l]++;
+    const or_level* L = &h->lev[l];
+    int N = L->N, dim = h->dim;
+    if (l == 0) {
+        int n = L->nint, k = 0;
+        double* rin = (double*)malloc(sizeof(double) * (size_t)n);
+        int* nodes = (int*)malloc(sizeof(int) * (size_t)n);
+        for (int q = 0; q < N; ++q)
+            if (is_interior(dim, L->n1, q)) { nodes[k] = q; rin[k] = r[q]; ++k; }
+        for (int q = 0; q < N; ++q) y[q] = 0.0;
+        for (int i = 0; i < n; ++i) {
+            double s = 0.0;
+            for (int j = 0; j < n; ++j) s += L->A0inv[i * n + j] * rin[j];
+            y[nodes[i]] = s;
+        }
+        free(rin); free(nodes);
+        return 0;
+    }
+    const or_level* C = &h->lev[l - 1];
+    int rc = 0;
+    double* z = (double*)calloc((size_t)N, sizeof(double));
+    double* res = (double*)malloc(sizeof(double) * (size_t)N);
+    double* rc_ = (double*)malloc(sizeof(double) * (size_t)C->N);
+    double* ec = (double*)malloc(sizeof(double) * (size_t)C->N);
+    for (int a = 0; a < dim && !rc; ++a)
+        for (int s = 0; s < h->m && !rc; ++s) rc = or_smooth(h, l, a, r, z);
+    for (int g = 0; g < h->gamma && !rc; ++g) {
+        level_apply(dim, L, z, res);
+        for (int q = 0; q < N; ++q) res[q] = r[q] - res[q];
+        for (int q = 0; q < N; ++q)
+            if (!is_interior(dim, L->n1, q)) res[q] = 0.0;
+        or_restrict(h, l, res, rc_);
+        rc = or_cycle(h, l - 1, rc_, ec);
+        if (rc) break;
+        or_prolong_add(h, l, ec, z);
+        for (int a = dim - 1; a >= 0 && !rc; --a)
+            for (int s = 0; s < h->m && !rc; ++s) rc = or_smooth(h, l, a, r, z);
+    }
+    memcpy(y, z, sizeof(double) * (size_t)N);
+    free(z); free(res); free(rc_); free(ec);
+    return rc;
+}
+
+void or_visits(const or_hier* h, long long* visits)
+{
+    for (int l = 0; l < h->nlev; ++l) visits[l] = h->visits[l];
+}
+void or_reset_visits(or_hier* h)
+{
+    memset(h->visits, 0, sizeof(h->visits));
+}
+
+/* ------------------------------------------------------------------ */
+/* Outer Krylov solvers on the finest level                            */
+/* ------------------------------------------------------------------ */
+
+static double dot(int N, const double* a, const double* b)
+{
+    double s = 0.0;
+    for (int i = 0; i < N; ++i) s += a[i] * b[i];
+    return s;
+}
+
+static double true_relres(const or_hier* h, const double* b, const double* x, double bn)
+{
+    int l = h->nlev - 1, N = h->lev[l].N;
+    double* r = (double*)malloc(sizeof(double) * (size_t)N);
+    or_apply(h, l, x, r);
+    for (int i = 0; i < N; ++i) r[i] = b[i] - r[i];
+    double rn = sqrt(dot(N, r, r));
+    free(r);
+    return rn / bn;
+}
+
+/* Right-preconditioned flexible GMRES with modified Gram-Schmidt and
+ * restarts (the paper's outer solver is GMRES; the flexible form is the
+ * same method for a fixed linear preconditioner and stays valid when the
+ * preconditioner varies).  Convergence is declared on the true residual. */
+int or_fgmres(const or_hier* h, const double* b, double* x, double rtol, int maxit,
+              int restart, double* hist, int* iters)
+{
+    int l = h->nlev - 1, N = h->lev[l].N;
+    int k = restart;
+    double* V = (double*)calloc((size_t)N * (k + 1), sizeof(double));
+    double* Z = (double*)calloc((size_t)N * k, sizeof(double));
+    double* H = (double*)calloc((size_t)(k + 1) * k, sizeof(double));
+    double* cs = (double*)calloc((size_t)k, sizeof(double));
+    double* sn = (double*)calloc((size_t)k, sizeof(double));
+    double* gv = (double*)calloc((size_t)(k + 1), sizeof(double));
+    double* yv = (double*)calloc((size_t)k, sizeof(double));
+    double* w = (double*)calloc((size_t)N, sizeof(double));
+    int it = 0, status = 1;
+    for (int i = 0; i < N; ++i) x[i] = 0.0;
+    double bn = sqrt(dot(N, b, b));
+    if (hist) hist[0] = 1.0;
+    if (bn == 0.0) { status = 0; goto out; }
+    while (it < maxit) {
+        /* r = b - A x */
+        or_apply(h, l, x, w);
+        for (int i = 0; i < N; ++i) V[i] = b[i] - w[i];
+        double beta = sqrt(dot(N, V, V));
+        if (beta / bn <= rtol) { status = 0; break; }
+        for (int i = 0; i < N; ++i) V[i] /= beta;
+        for (int i = 0; i <= k; ++i) gv[i] = 0.0;
+        gv[0] = beta;
+        int j, used = 0, breakdown = 0;
+        for (j = 0; j < k && it < maxit; ++j) {
+            double* vj = V + (size_t)j * N;
+            double* zj = Z + (size_t)j * N;
+            if (or_cycle(h, l, vj, zj)) { status = -1; goto out; }
+            or_apply(h, l, zj, w);
+            for (int i = 0; i <= j; ++i) {
+                double hij = dot(N, w, V + (size_t)i * N);
+                H[i * k + j] = hij;
+                for (int q = 0; q < N; ++q) w[q] -= hij * V[(size_t)i * N + q];
+            }
+            double hn = sqrt(dot(N, w, w));
+            H[(j + 1) * k + j] = hn;
+            if (hn != 0.0)
+                for (int q = 0; q < N; ++q) V[(size_t)(j + 1) * N + q] = w[q] / hn;
+            else
+                breakdown = 1;
+            for (int i = 0; i < j; ++i) {
+                double t = cs[i] * H[i * k + j] + sn[i] * H[(i + 1) * k + j];
+                H[(i + 1) * k + j] = -sn[i] * H[i * k + j] + cs[i] * H[(i + 1) * k + j];
+                H[i * k + j] = t;
+            }
+            double a = H[j * k + j], bb = H[(j + 1) * k + j];
+            double rr = sqrt(a * a + bb * bb);
+            if (rr == 0.0) { status = -1; goto out; }
+            cs[j] = a / rr; sn[j] = bb / rr;
+            H[j * k + j] = rr; H[(j + 1) * k + j] = 0.0;
+            gv[j + 1] = -sn[j] * gv[j];
+            gv[j] = cs[j] * gv[j];
+            ++it;
+            used = j + 1;
+            if (hist) hist[it] = fabs(gv[j + 1]) / bn;
+            if (fabs(gv[j + 1]) / bn <= rtol || breakdown) break;
+        }
+        /* x += Z y, H y = g (upper triangular) */
+        for (int i = used - 1; i >= 0; --i) {
+            double s = gv[i];
+            for (int q = i + 1; q < used; ++q) s -= H[i * k + q] * yv[q];
+            yv[i] = s / H[i * k + i];
+        }
+        for (int i = 0; i < used; ++i)
+            for (int q = 0; q < N; ++q) x[q] += yv[i] * Z[(size_t)i * N + q];
+        if (true_relres(h, b, x, bn) <= rtol) { status = 0; break; }
+        if (breakdown) { status = -1; break; }
+    }
+out:
+    if (iters) *iters = it;
+    free(V); free(Z); free(H); free(cs); free(sn); free(gv); free(yv); free(w);
+    return status;
+}
+
+/* Preconditioned conjugate gradients (valid when M^{-1} is symmetric positive
+ * definite, e.g. gamma = 1 with positive-definite line systems). */
+int or_pcg(const or_hier* h, const double* b, double* x, double rtol, int maxit,
+           double* hist, int* iters)
+{
+    int l = h->nlev - 1, N = h->lev[l].N;
+    double* r = (double*)malloc(sizeof(double) * (size_t)N);
+    double* z = (double*)malloc(sizeof(double) * (size_t)N);
+    double* p = (double*)malloc(sizeof(double) * (size_t)N);
+    double* q = (double*)malloc(sizeof(double) * (size_t)N);
+    int it = 0, status = 1;
+    for (int i = 0; i < N; ++i) { x[i] = 0.0; r[i] = b[i]; }
+    double bn = sqrt(dot(N, b, b));
+    if (hist) hist[0] = 1.0;
+    if (bn == 0.0) { status = 0; goto out; }
+    if (or_cycle(h, l, r, z)) { status = -1; goto out; }
+    memcpy(p, z, sizeof(double) * (size_t)N);
+    double rz = dot(N, r, z);
+    while (it < maxit) {
+        or_apply(h, l, p, q);
+        double pq = dot(N, p, q);
+        if (pq <= 0.0) { status = -1; break; }
+        double al = rz / pq;
+        for (int i = 0; i < N; ++i) { x[i] += al * p[i]; r[i] -= al * q[i]; }
+        ++it;
+        double rn = sqrt(dot(N, r, r)) / bn;
+        if (hist) hist[it] = rn;
+        if (rn <= rtol) {
+            if (true_relres(h, b, x, bn) <= rtol) { status = 0; break; }
+        }
+        if (or_cycle(h, l, r, z)) { status = -1; break; }
+        double rz2 = dot(N, r, z);
+        double be = rz2 / rz;
+        rz = rz2;
+        for (int i = 0; i < N; ++i) p[i] = z[i] + be * p[i];
+    }
+out:
+    if (iters) *iters = it;
+    free(r); free(z); free(p); free(q);
+    return status;
+}
+
+/* Flexible CG with one-term orthogonalisation (the search direction is made
+ * A-orthogonal to the previous one; valid for a nonsymmetric or varying
+ * preconditioner). */
+int or_fcg(const or_hier* h, const double* b, double* x, double rtol, int maxit,
+           double* hist, int* iters)
+{
+    int l = h->nlev - 1, N = h->lev[l].N;
+    double* r = (double*)malloc(sizeof(double) * (size_t)N);
+    double* z = (double*)malloc(sizeof(double) * (size_t)N);
+    double* p = (double*)malloc(sizeof(double) * (size_t)N);
+    double* q = (double*)malloc(sizeof(double) * (size_t)N);
+    int it = 0, status = 1;
+    for (int i = 0; i < N; ++i) { x[i] = 0.0; r[i] = b[i]; }
+    double bn = sqrt(dot(N, b, b));
+    if (hist) hist[0] = 1.0;
+    if (bn == 0.0) { status = 0; goto out; }
+    if (or_cycle(h, l, r, z)) { status = -1; goto out; }
+    memcpy(p, z, sizeof(double) * (size_t)N);
+    or_apply(h, l, p, q);
+    while (it < maxit) {
+        double pq = dot(N, p, q);
+        if (pq <= 0.0) { status = -1; break; }
+        double al = dot(N, p, r) / pq;
+        for (int i = 0; i < N; ++i) { x[i] += al * p[i]; r[i] -= al * q[i]; }
+        ++it;
+        double rn = sqrt(dot(N, r, r)) / bn;
+        if (hist) hist[it] = rn;
+        if (rn <= rtol) {
+            if (true_relres(h, b, x, bn) <= rtol) { status = 0; break; }
+        }
+        if (or_cycle(h, l, r, z)) { status = -1; break; }
+        double be = -dot(N, z, q) / pq;
+        for (int i = 0; i < N; ++i) p[i] = z[i] + be * p[i];
+        or_apply(h, l, p, q);
+    }
+out:
+    if (iters) *iters = it;
+    free(r); free(z); free(p); free(q);
+    return status;
+}
