@@ -1,0 +1,240 @@
+#!/usr/bin/env python3
+"""Throughput benchmark: batched GLL spectral Poisson solves to 1e-10 relative
+residual, preconditioned by the p-multigrid gamma-cycle, on one MI355X.
+
+Workload (default): 2-D deformed square, p = 128 (129 x 129 nodes),
+gamma-cycle p = 128 -> 64 -> ... -> 2, FP64, mapping
+x = s + a sin(pi s) sin(pi t), y = t + b sin(2 pi s) sin(pi t), a, b ~ U[0, 0.15],
+16-mode Fourier right-hand side, 8-mode Dirichlet data; synthetic, seeded.
+
+A step is one pass of the whole path over one batch of B problems already
+resident in HBM: setup (geometry, line tridiagonals and their
+cyclic-reduction factors on every level), Dirichlet lifting of the
+right-hand side, the preconditioned Krylov solve, and the final lift.
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64 (256 CUs x 2.4 GHz x 128 flop/clk)
+PEAK_FP32_TFLOPS = 157.3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--p", type=int, default=128)
+    ap.add_argument("--gamma", type=int, default=1)
+    ap.add_argument("--alpha", type=float, default=0.16)
+    ap.add_argument("--smoother", choices=["fem", "gll"], default="fem")
+    ap.add_argument("--prec", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--krylov", choices=["fgmres", "pcg", "fcg"], default="fgmres")
+    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--rtol", type=float, default=1e-10)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="budget of the oracle CPU baseline (0 disables it)")
+    return ap.parse_args()
+
+
+def flops_per_solve(dim, p, gamma, m, iters, krylov, restart):
+    """Algorithmic flop count of one solve (model stated in the design doc)."""
+    def level_costs(pl):
+        n1 = pl + 1
+        N = n1 ** dim
+        nint = (pl - 1) ** dim
+        apply_ = (4 * dim * n1 + (2 * dim * dim - dim) + 1) * N
+        cr = 11 * nint
+        n1c = pl // 2 + 1
+        if dim == 2:
+            transfer = 2 * n1 * n1c * (n1 + n1c)
+        else:
+            transfer = 2 * (n1**3 * n1c + n1**2 * n1c**2 + n1 * n1c**3)
+        return apply_, cr, transfer
+
+    levels = []
+    pl = p
+    while pl >= 2:
+        levels.append(pl)
+        pl //= 2
+    cycle = 0.0
+    for depth, pl in enumerate(levels):
+        visits = gamma ** depth
+        if pl == 2:
+            cycle += visits * 1
+            continue
+        a, c, t = level_costs(pl)
+        sweeps = dim * m * (1 + gamma)
+        cycle += visits * ((sweeps - 1 + gamma) * a + sweeps * c + 2 * gamma * t)
+    a_f, _, _ = level_costs(p)
+    N = (p + 1) ** dim
+    total = 0.0
+    if krylov == "fgmres":
+        j = 0
+        restarts = 1
+        for _ in range(iters):
+            total += cycle + a_f + 4 * (j + 1) * N + 3 * N
+            j += 1
+            if j == restart:
+                j = 0
+                restarts += 1
+        total += restarts * (a_f + 4 * N) + iters * 2 * N
+    else:
+        total += (iters + 1) * (cycle + a_f + 12 * N)
+    return total
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not "
+                          "part of this build (independent problems shard by request across "
+                          "GPUs with no collectives)", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2504_10710_amd import inputs, pmg
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    B, p = args.batch, args.p
+    dim = 2
+    smoother = pmg.PMG_SMOOTHER_FEM if args.smoother == "fem" else pmg.PMG_SMOOTHER_GLL
+    prec = pmg.PMG_F32 if args.prec == "f32" else pmg.PMG_F64
+    krylov = {"fgmres": pmg.PMG_FGMRES, "pcg": pmg.PMG_PCG, "fcg": pmg.PMG_FCG}[args.krylov]
+    desc = pmg.make_desc(dim=dim, p_fine=p, batch=B, gamma=args.gamma, m=1, alpha=args.alpha,
+                         smoother=smoother, inner_prec=prec, krylov=krylov,
+                         restart=args.restart, max_iter=500, rtol=args.rtol)
+
+    # ---- synthetic inputs (seeded), resident in HBM before timing
+    t0 = time.time()
+    probs = [inputs.config2(s) for s in range(B)]
+    ps = inputs.halving_degrees(p, 2)
+    coords = []
+    for q in ps:
+        xi = pmg.pmg_gll(q)[0]
+        coords.append(torch.from_numpy(np.stack([pr.coords(xi) for pr in probs])).to(dev))
+    xi = pmg.pmg_gll(p)[0]
+    Xf = [pr.coords(xi) for pr in probs]
+    f = torch.from_numpy(np.stack([pr.f(x) for pr, x in zip(probs, Xf)])).to(dev)
+    g = torch.from_numpy(np.stack([pr.g(x) for pr, x in zip(probs, Xf)])).to(dev)
+    ws = torch.empty(pmg.pmg_workspace_bytes(desc), dtype=torch.uint8, device=dev)
+    info = torch.empty(B * pmg.INFO_BYTES, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(f)
+    x = torch.empty_like(f)
+    u = torch.empty_like(f)
+    torch.cuda.synchronize()
+    print(f"[bench] inputs ready: B={B} p={p} ws={ws.numel() / 2**30:.2f} GiB "
+          f"({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
+
+    stream = torch.cuda.current_stream()
+    ev = []
+
+    def step(timed):
+        h = pmg.pmg_setup(desc, coords, ws, info)
+        pmg.pmg_rhs(h, f, g, b)
+        if timed:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+        pmg.pmg_solve(h, b, x, info)
+        if timed:
+            e1.record(stream)
+            ev.append((e0, e1))
+        pmg.pmg_lift(h, x, g, u)
+        pmg.pmg_destroy(h)
+
+    for i in range(args.warmup):
+        step(False)
+        torch.cuda.synchronize()
+        print(f"[bench] warmup step {i} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for i in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t1
+    nfo = pmg.info_to_numpy(info)
+    ok = int(np.sum(nfo["status"] == 0))
+    its = nfo["iterations"]
+    solve_ms = [a.elapsed_time(bb) for a, bb in ev]
+    solve_s = sum(solve_ms) / len(solve_ms) / 1e3
+    ms_per_step = elapsed / args.steps * 1e3
+    value = B * args.steps / elapsed
+    print(f"[bench] timed {args.steps} steps: {ms_per_step:.1f} ms/step, solve kernel "
+          f"{solve_s * 1e3:.1f} ms, ok {ok}/{B}, its min/med/max {its.min()}/"
+          f"{int(np.median(its))}/{its.max()}, max relres {nfo['relres'].max():.2e}",
+          file=sys.stderr, flush=True)
+
+    flops = sum(flops_per_solve(dim, p, args.gamma, 1, int(k), args.krylov, args.restart)
+                for k in its)
+    achieved = flops / solve_s / 1e12
+    peak = PEAK_FP32_TFLOPS if args.prec == "f32" else PEAK_FP64_TFLOPS
+    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 5), "traffic": None,
+                "kernel": f"k_solve<{'float' if args.prec == 'f32' else 'double'}, {p}, 2>",
+                "flops_per_launch": flops}
+
+    cpu = None
+    if args.cpu_seconds > 0:
+        cpu = cpu_baseline(args, probs, ps)
+
+    ndof = (p - 1) ** 2
+    line = {
+        "metric": "solves/s to 1e-10 rel. residual",
+        "value": round(value, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if args.prec == "f32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"2-D deformed square GLL Poisson, p={p}, gamma-cycle {p}->2",
+                   "batch": B, "gamma": args.gamma, "m": 1, "alpha": args.alpha,
+                   "smoother": args.smoother, "krylov": args.krylov, "rtol": args.rtol,
+                   "inner_precision": args.prec, "interior_dofs": ndof,
+                   "dof_per_s": round(value * ndof, 1),
+                   "iterations_median": int(np.median(its)), "converged": ok},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(args, probs, ps):
+    """The oracle (plain FP64 C, one thread) on a bounded sample of the same
+    workload: whole solves (setup + lifting + Krylov) of the first problems."""
+    from oracle import oracle as orc
+
+    smoother = 1 if args.smoother == "fem" else 0
+    solver = args.krylov
+    t0 = time.perf_counter()
+    n = 0
+    while n < 2 or (time.perf_counter() - t0 < args.cpu_seconds and n < len(probs)):
+        pr = probs[n]
+        oc = [pr.coords(orc.gll(q)[0]) for q in ps]
+        h = orc.Hier(2, ps, oc, gamma=args.gamma, m=1, alpha=args.alpha, smoother=smoother)
+        bo = h.rhs(pr.f(oc[-1]), pr.g(oc[-1]))
+        getattr(h, solver)(bo, rtol=args.rtol, maxit=500)
+        n += 1
+    dt = time.perf_counter() - t0
+    return {"value": round(n / dt, 4), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} whole solves of the same workload (problems 0..{n - 1}), "
+                      f"{dt:.1f} s on one host core"}
+
+
+if __name__ == "__main__":
+    main()

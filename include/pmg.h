@@ -1,0 +1,210 @@
+/*
+ * pmg.h -- C ABI of libpmg, an MI355X (gfx950) implementation of the
+ * p-multigrid gamma-cycle with cyclic-reduction line smoothers of
+ * Lucero Lorca, Rosenberg, Jankov, McCoid and Gander, "On an efficient line
+ * smoother for the p-multigrid gamma-cycle" (arXiv 2504.10710), used as the
+ * preconditioner of an outer Krylov solve of the GLL spectral Poisson
+ * problem on one mapped element.
+ *
+ * Conventions shared by every call
+ *   - Batches.  A handle describes B independent problems of one shape
+ *     (dimension, finest degree, hierarchy).  Every device array holds the B
+ *     problems back to back, problem b at offset b * (per-problem size).
+ *   - Nodes.  Level l has degree p_l = p_coarse * 2^l (p_coarse = 2), n1 =
+ *     p_l + 1 nodes per axis and N_l = n1^dim nodes; node (i0, i1[, i2]) has
+ *     index i0 + n1*i1 (+ n1^2*i2), first axis fastest (lexicographic order of
+ *     Sec. 3.1).  Vectors are full node arrays; residuals and corrections
+ *     carry zeros on boundary nodes (Dirichlet elimination, Sec. 2.3).
+ *   - Memory.  The caller owns all device memory and streams.  The library
+ *     never allocates device memory: pmg_workspace_bytes() reports the size
+ *     of the one workspace the caller passes to pmg_setup(); host-side
+ *     handles are the only thing the library allocates (freed by
+ *     pmg_destroy()).
+ *   - Streams.  Device work is enqueued asynchronously on the given stream
+ *     (NULL = default stream); no call synchronises unless documented.
+ *   - Errors.  Every call returns PMG_OK (0) or a negative PMG_E* code and
+ *     never throws.  pmg_last_error() returns a thread-local message for the
+ *     last failure.  Errors found by kernels (det J <= 0, zero pivots, no
+ *     convergence, NaN) are reported per problem in the pmg_info array.
+ *   - Precision.  prec = PMG_F64 operates on double arrays, PMG_F32 on float
+ *     arrays (the mixed-precision inner path); a handle built with
+ *     inner_prec = PMG_F64 supports PMG_F64 calls only.
+ */
+#ifndef PMG_H
+#define PMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* pmg_stream_t; /* hipStream_t */
+
+enum {
+    PMG_OK = 0,
+    PMG_EINVAL = -1,     /* bad argument or unsupported shape */
+    PMG_ENOMEM = -2,     /* workspace too small */
+    PMG_EDEVICE = -3,    /* HIP runtime error */
+    PMG_EGEOM = -4,      /* det J <= 0 somewhere (per-problem status) */
+    PMG_ENAN = -5,       /* NaN or Inf in a residual (per-problem status) */
+    PMG_EBREAKDOWN = -6, /* Krylov breakdown before convergence */
+    PMG_ENOTCONV = -7,   /* max_iter reached */
+    PMG_EPIVOT = -8      /* zero pivot in a line factorisation */
+};
+
+enum { PMG_F64 = 0, PMG_F32 = 1 };
+enum { PMG_SMOOTHER_GLL = 0, PMG_SMOOTHER_FEM = 1 };
+enum { PMG_FGMRES = 0, PMG_PCG = 1, PMG_FCG = 2 };
+
+#define PMG_MAX_LEVELS 9
+
+/* Problem and method description.
+ *   dim        2 or 3
+ *   p_fine     finest degree: a power of two, 4..256 (2-D) or 4..64 (3-D);
+ *              levels halve down to p = 2 (one interior node, solved exactly:
+ *              M_0^{-1} = A_0^{-1} in Alg. 2)
+ *   batch      B >= 1 problems
+ *   gamma, m, alpha   gamma-cycle parameters of Alg. 2 (gamma >= 1 coarse
+ *              corrections per visit, m smoothing steps per axis, relaxation
+ *              alpha > 0)
+ *   smoother   PMG_SMOOTHER_GLL: tridiagonal part of A_p along each line
+ *              (Def. line preconditioners with half-bandwidth 1);
+ *              PMG_SMOOTHER_FEM: tridiagonal line systems of the bilinear
+ *              finite-element matrix on the GLL node mesh (2-D only)
+ *   inner_prec PMG_F64, or PMG_F32 for an FP32 gamma-cycle inside FP64
+ *              Krylov (geometric factors and the outer solve stay FP64)
+ *   krylov     PMG_FGMRES (right-preconditioned, modified Gram-Schmidt,
+ *              restarted), PMG_PCG, PMG_FCG (flexible CG)
+ *   restart    FGMRES restart length (1..64)
+ *   max_iter   iteration cap of the outer solve
+ *   rtol       stop when ||b - A x||_2 <= rtol ||b||_2 (true residual) */
+typedef struct {
+    int dim;
+    int p_fine;
+    int batch;
+    int gamma;
+    int m;
+    double alpha;
+    int smoother;
+    int inner_prec;
+    int krylov;
+    int restart;
+    int max_iter;
+    double rtol;
+} pmg_desc;
+
+/* Per-problem result of the device solve (written by pmg_solve). */
+typedef struct {
+    int status;       /* PMG_OK or a negative PMG_E* code */
+    int iterations;   /* outer Krylov iterations */
+    double relres;    /* final true relative residual ||b - A x|| / ||b|| (FP64) */
+    double min_detj;  /* minimum Jacobian determinant over all levels (setup) */
+} pmg_info;
+
+typedef struct pmg_handle pmg_handle;
+
+/* Thread-local text of the last error. */
+const char* pmg_last_error(void);
+
+/* Number of levels of a description (p_fine = 2^L * 2 gives L + 1). */
+int pmg_num_levels(const pmg_desc* desc, int* n_levels);
+
+/* GLL nodes xi[0..p] and weights rho[0..p] of order p (Def. GLL quadrature
+ * rule), and D[i*(p+1)+j] = pi_j'(xi_i) (derivative of the Lagrange basis of
+ * Def. GLL interpolation basis).  Host arrays; D may be NULL.  FP64. */
+int pmg_gll(int p, double* xi, double* rho, double* D);
+
+/* J[i*(p_c+1)+j] = pi^c_j(xi^f_i): the 1-D prolongation from degree p_c to
+ * degree p_f (Sec. 3.3, interpolation between GLL bases).  Host array of
+ * (p_f+1)*(p_c+1) doubles. */
+int pmg_interp(int p_c, int p_f, double* J);
+
+/* Bytes of device workspace pmg_setup needs for this description. */
+int pmg_workspace_bytes(const pmg_desc* desc, size_t* bytes);
+
+/* Build the hierarchy on the device (geometry of eq. DiscreteSpace and eq.
+ * discreteBilinear for every level, line tridiagonals and their
+ * cyclic-reduction factors, Sec. 3.2).
+ *   d_coords[l]  level-l physical node positions: B x dim x N_l doubles
+ *                (all first coordinates of a problem, then all second, ...)
+ *                at the level's GLL nodes; read during the call's stream work
+ *   d_ws         caller-owned device workspace of ws_bytes >= the size from
+ *                pmg_workspace_bytes; must stay valid until pmg_destroy
+ *   d_info       B pmg_info records (device), min_detj and status filled
+ * On return *out holds a host handle.  Problems with det J <= 0 or a zero
+ * pivot get status PMG_EGEOM / PMG_EPIVOT in d_info. */
+int pmg_setup(const pmg_desc* desc, const double* const* d_coords, void* d_ws,
+              size_t ws_bytes, pmg_info* d_info, pmg_stream_t stream, pmg_handle** out);
+
+/* Dirichlet lifting of Sec. 2.3 on the finest level:
+ * d_b = M f - A v on interior nodes, 0 on boundary nodes, where v is d_g on
+ * boundary nodes and 0 inside.  d_f, d_g, d_b: B x N doubles. */
+int pmg_rhs(pmg_handle* h, const double* d_f, const double* d_g, double* d_b,
+            pmg_stream_t stream);
+
+/* d_u = d_w on interior nodes and d_g on boundary nodes (u = w + v, Sec. 2.3).
+ * May be called in place (d_u == d_w). */
+int pmg_lift(pmg_handle* h, const double* d_w, const double* d_g, double* d_u,
+             pmg_stream_t stream);
+
+/* d_y = A_l d_x on interior rows, 0 on boundary rows (matrix-free sum
+ * factorisation of eq. discreteBilinear).  B x N_l arrays of the given
+ * precision. */
+int pmg_apply(pmg_handle* h, int level, int prec, const void* d_x, void* d_y,
+              pmg_stream_t stream);
+
+/* d_rc = R_l d_rf (level l -> l-1, R_l = P_l^T, Sec. 3.3); coarse boundary
+ * entries set to 0.  level >= 1. */
+int pmg_restrict(pmg_handle* h, int level, int prec, const void* d_rf, void* d_rc,
+                 pmg_stream_t stream);
+
+/* d_xf += P_l d_ec (level l-1 -> l, tensor product of the 1-D
+ * interpolation).  level >= 1. */
+int pmg_prolong_add(pmg_handle* h, int level, int prec, const void* d_ec, void* d_xf,
+                    pmg_stream_t stream);
+
+/* d_z = B_{l,dir}^{-1} d_r: every interior line along axis dir solved by the
+ * cyclic reduction of Thm. "Two-level direct solver" / Cor. "Direct
+ * multigrid solver" (block Jacobi over lines, Def. line preconditioners);
+ * boundary entries of d_z are 0. */
+int pmg_line_solve(pmg_handle* h, int level, int dir, int prec, const void* d_r,
+                   void* d_z, pmg_stream_t stream);
+
+/* One smoothing step of Alg. 2: d_x += alpha B_{l,dir}^{-1} (d_r - A_l d_x). */
+int pmg_line_smooth(pmg_handle* h, int level, int dir, int prec, const void* d_r,
+                    void* d_x, pmg_stream_t stream);
+
+/* d_y = M_L^{-1} d_r, one gamma-cycle of Alg. 2 from the finest level
+ * (B x N arrays of the given precision). */
+int pmg_gamma_cycle(pmg_handle* h, int prec, const void* d_r, void* d_y,
+                    pmg_stream_t stream);
+
+/* Outer solve A w = b on the finest level (FP64, zero initial guess),
+ * preconditioned by the gamma-cycle; d_x receives w (zero boundary), d_info
+ * per-problem status, iterations and true relative residual.  The whole
+ * iteration runs on the device, one workgroup per problem. */
+int pmg_solve(pmg_handle* h, const double* d_b, double* d_x, pmg_info* d_info,
+              pmg_stream_t stream);
+
+/* Per-level line-system tridiagonals (lower, diagonal, upper) of axis dir,
+ * (p_l-1)^dim doubles each per problem, line after line as described for the
+ * oracle-independent layout: lines ordered by the remaining interior
+ * indices (first remaining axis fastest), p_l - 1 entries per line.  For
+ * inspection and tests; FP64. */
+int pmg_line_coefs(pmg_handle* h, int level, int dir, double* d_lo, double* d_di,
+                   double* d_up, pmg_stream_t stream);
+
+/* Geometric factors of level l: d_G B x ncomp x N_l doubles (ncomp = 3 in
+ * 2-D: G_00, G_11, G_01; 6 in 3-D: G_00, G_11, G_22, G_01, G_02, G_12) and
+ * d_mass B x N_l doubles (may be NULL). */
+int pmg_geom(pmg_handle* h, int level, double* d_G, double* d_mass, pmg_stream_t stream);
+
+/* Release the host handle (the workspace stays the caller's). */
+int pmg_destroy(pmg_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

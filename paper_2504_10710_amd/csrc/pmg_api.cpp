@@ -1,0 +1,680 @@
+// pmg_api.cpp -- the C ABI of libpmg (include/pmg.h): argument checks,
+// workspace layout, host-side 1-D GLL tables, kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pmg_internal.hpp"
+
+using namespace pmg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* where)
+{
+    return fail(PMG_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------- 1-D GLL tables
+
+// Legendre L_n(x) and L_{n-1}(x) by the three-term recurrence.
+void legendre2(int n, double x, double& Ln, double& Lnm1)
+{
+    double a = 1.0, b = x;
+    if (n == 0) { Ln = 1.0; Lnm1 = 0.0; return; }
+    for (int k = 2; k <= n; ++k) {
+        double c = ((2.0 * k - 1.0) * x * b - (k - 1.0) * a) / k;
+        a = b;
+        b = c;
+    }
+    Ln = b;
+    Lnm1 = a;
+}
+
+// GLL nodes by the Lobatto fixed-point Newton iteration
+//   x <- x - (x L_p(x) - L_{p-1}(x)) / ((p + 1) L_p(x)),
+// whose fixed points are the zeros of (1 - x^2) L_p'(x), started from the
+// Chebyshev-Gauss-Lobatto points; weights 2 / (p (p+1) L_p(x)^2).
+bool gll_nodes(int p, std::vector<double>& xi, std::vector<double>& rho)
+{
+    xi.assign(p + 1, 0.0);
+    rho.assign(p + 1, 0.0);
+    for (int j = 0; j <= p; ++j) {
+        double x = -std::cos(M_PI * j / p);
+        if (j == 0 || j == p) {
+            xi[j] = x < 0 ? -1.0 : 1.0;
+            continue;
+        }
+        bool ok = false;
+        for (int it = 0; it < 200; ++it) {
+            double Lp, Lm;
+            legendre2(p, x, Lp, Lm);
+            double dx = (x * Lp - Lm) / ((p + 1.0) * Lp);
+            x -= dx;
+            if (std::fabs(dx) <= 2e-16 * (1.0 + std::fabs(x))) { ok = true; break; }
+        }
+        if (!ok) return false;
+        xi[j] = x;
+    }
+    // exact symmetry of the node set
+    for (int j = 0; j < (p + 1) / 2; ++j) {
+        double v = 0.5 * (xi[p - j] - xi[j]);
+        xi[j] = -v;
+        xi[p - j] = v;
+    }
+    if (p % 2 == 0) xi[p / 2] = 0.0;
+    for (int j = 0; j <= p; ++j) {
+        double Lp, Lm;
+        legendre2(p, xi[j], Lp, Lm);
+        rho[j] = 2.0 / (p * (p + 1.0) * Lp * Lp);
+    }
+    return true;
+}
+
+// Closed-form GLL differentiation matrix: D_ij = L_p(xi_i) / (L_p(xi_j) (xi_i - xi_j))
+// for i != j, D_00 = -p(p+1)/4, D_pp = p(p+1)/4, D_ii = 0 otherwise.
+void gll_deriv(int p, const std::vector<double>& xi, std::vector<double>& D)
+{
+    int n1 = p + 1;
+    std::vector<double> L(n1);
+    for (int i = 0; i < n1; ++i) {
+        double a, b;
+        legendre2(p, xi[i], a, b);
+        L[i] = a;
+    }
+    D.assign(n1 * n1, 0.0);
+    for (int i = 0; i < n1; ++i)
+        for (int j = 0; j < n1; ++j) {
+            if (i != j) D[i * n1 + j] = L[i] / (L[j] * (xi[i] - xi[j]));
+        }
+    D[0] = -p * (p + 1.0) / 4.0;
+    D[(n1 - 1) * n1 + (n1 - 1)] = p * (p + 1.0) / 4.0;
+}
+
+// Barycentric Lagrange interpolation from the coarse GLL nodes xc to the
+// points xf: J[i][j] = (w_j / (xf_i - xc_j)) / sum_k (w_k / (xf_i - xc_k)),
+// w_j = 1 / prod_{k != j} (xc_j - xc_k); exact rows where xf_i is a node.
+void bary_interp(const std::vector<double>& xc, const std::vector<double>& xf,
+                 std::vector<double>& J)
+{
+    int nc = (int)xc.size(), nf = (int)xf.size();
+    std::vector<double> w(nc, 1.0);
+    for (int j = 0; j < nc; ++j)
+        for (int k = 0; k < nc; ++k)
+            if (k != j) w[j] /= (xc[j] - xc[k]);
+    J.assign(nf * nc, 0.0);
+    for (int i = 0; i < nf; ++i) {
+        int hit = -1;
+        for (int j = 0; j < nc; ++j)
+            if (xf[i] == xc[j]) hit = j;
+        if (hit >= 0) { J[i * nc + hit] = 1.0; continue; }
+        double den = 0.0;
+        for (int j = 0; j < nc; ++j) den += w[j] / (xf[i] - xc[j]);
+        for (int j = 0; j < nc; ++j) J[i * nc + j] = (w[j] / (xf[i] - xc[j])) / den;
+    }
+}
+
+// ---------------------------------------------------------------- layout
+
+struct Layout {
+    size_t off = 0;
+    size_t take(size_t bytes)
+    {
+        size_t o = (off + 255) & ~size_t(255);
+        off = o + bytes;
+        return o;
+    }
+};
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int check_desc(const pmg_desc* d)
+{
+    if (!d) return fail(PMG_EINVAL, "desc is NULL");
+    if (d->dim != 2 && d->dim != 3) return fail(PMG_EINVAL, "dim must be 2 or 3 (got %d)", d->dim);
+    int pmax = d->dim == 2 ? 256 : 64;
+    if (!is_pow2(d->p_fine) || d->p_fine < 4 || d->p_fine > pmax)
+        return fail(PMG_EINVAL, "p_fine must be a power of two in [4, %d] (got %d)", pmax, d->p_fine);
+    if (d->batch < 1) return fail(PMG_EINVAL, "batch must be >= 1");
+    if (d->gamma < 1 || d->gamma > 16) return fail(PMG_EINVAL, "gamma must be in [1, 16]");
+    if (d->m < 0 || d->m > 8) return fail(PMG_EINVAL, "m must be in [0, 8]");
+    if (!(d->alpha > 0.0) || !std::isfinite(d->alpha)) return fail(PMG_EINVAL, "alpha must be > 0");
+    if (d->smoother != PMG_SMOOTHER_GLL && d->smoother != PMG_SMOOTHER_FEM)
+        return fail(PMG_EINVAL, "unknown smoother %d", d->smoother);
+    if (d->smoother == PMG_SMOOTHER_FEM && d->dim != 2)
+        return fail(PMG_EINVAL, "the FEM line smoother is 2-D only");
+    if (d->inner_prec != PMG_F64 && d->inner_prec != PMG_F32)
+        return fail(PMG_EINVAL, "unknown inner precision %d", d->inner_prec);
+    if (d->krylov != PMG_FGMRES && d->krylov != PMG_PCG && d->krylov != PMG_FCG)
+        return fail(PMG_EINVAL, "unknown Krylov method %d", d->krylov);
+    if (d->restart < 1 || d->restart > 64) return fail(PMG_EINVAL, "restart must be in [1, 64]");
+    if (d->max_iter < 1) return fail(PMG_EINVAL, "max_iter must be >= 1");
+    if (!(d->rtol > 0.0)) return fail(PMG_EINVAL, "rtol must be > 0");
+    return PMG_OK;
+}
+
+struct LevelShape {
+    int p, n1, N, n, NL, NC, CRW;
+};
+
+LevelShape level_shape(int dim, int l)
+{
+    LevelShape s;
+    s.p = 2 << l;
+    s.n1 = s.p + 1;
+    s.N = dim == 2 ? s.n1 * s.n1 : s.n1 * s.n1 * s.n1;
+    s.n = s.p - 1;
+    s.NL = dim == 2 ? s.n : s.n * s.n;
+    s.NC = dim == 2 ? 3 : 6;
+    s.CRW = cr_words(s.n);
+    return s;
+}
+
+}  // namespace
+
+struct pmg_handle {
+    pmg_desc d;
+    int nlev;
+    bool f32;
+    size_t ws_bytes;
+    char* ws;
+    // offsets
+    size_t o_rho[MAX_LEVELS], o_D64[MAX_LEVELS], o_DT64[MAX_LEVELS], o_J64[MAX_LEVELS],
+        o_JT64[MAX_LEVELS];
+    size_t o_D32[MAX_LEVELS], o_DT32[MAX_LEVELS], o_J32[MAX_LEVELS], o_JT32[MAX_LEVELS];
+    size_t o_G64[MAX_LEVELS], o_G32[MAX_LEVELS], o_X64[MAX_LEVELS];
+    size_t o_cr64[MAX_LEVELS][3], o_cr32[MAX_LEVELS][3];
+    size_t o_X[MAX_LEVELS], o_R[MAX_LEVELS], o_Tm[MAX_LEVELS], o_TR[MAX_LEVELS];
+    size_t o_mass, o_W1, o_W2, o_TR64, o_V, o_Z, o_Hs, o_detmin, o_pivot, o_cinv64, o_cinv32;
+    long long w1, w2, nv, hs;
+    size_t total;
+    // host copies of the tables uploaded at setup (kept alive for async copies)
+    std::vector<double> h64;
+    std::vector<float> h32;
+    Hier<double> H64;
+    Hier<float> H32;
+};
+
+namespace {
+
+void plan(pmg_handle* h)
+{
+    const pmg_desc& d = h->d;
+    const int dim = d.dim, B = d.batch;
+    const size_t tsz = h->f32 ? sizeof(float) : sizeof(double);
+    Layout L;
+    long long w = 0;
+    for (int l = 0; l < h->nlev; ++l) {
+        LevelShape s = level_shape(dim, l);
+        h->o_rho[l] = L.take(sizeof(double) * s.n1);
+        h->o_D64[l] = L.take(sizeof(double) * s.n1 * s.n1);
+        h->o_DT64[l] = L.take(sizeof(double) * s.n1 * s.n1);
+        h->o_D32[l] = L.take(sizeof(float) * s.n1 * s.n1);
+        h->o_DT32[l] = L.take(sizeof(float) * s.n1 * s.n1);
+        if (l > 0) {
+            int n1c = s.p / 2 + 1;
+            h->o_J64[l] = L.take(sizeof(double) * s.n1 * n1c);
+            h->o_JT64[l] = L.take(sizeof(double) * s.n1 * n1c);
+            h->o_J32[l] = L.take(sizeof(float) * s.n1 * n1c);
+            h->o_JT32[l] = L.take(sizeof(float) * s.n1 * n1c);
+            long long ww = (long long)(dim == 2 ? s.n1 : s.n1 * s.n1) * n1c;
+            if (ww > w) w = ww;
+        } else {
+            h->o_J64[l] = h->o_JT64[l] = h->o_J32[l] = h->o_JT32[l] = 0;
+        }
+    }
+    for (int l = 0; l < h->nlev; ++l) {
+        LevelShape s = level_shape(dim, l);
+        h->o_G64[l] = L.take(sizeof(double) * (size_t)B * s.NC * s.N);
+        h->o_G32[l] = h->f32 ? L.take(sizeof(float) * (size_t)B * s.NC * s.N) : 0;
+        h->o_X64[l] = L.take(sizeof(double) * (size_t)B * dim * s.N);
+        for (int a = 0; a < 3; ++a) {
+            h->o_cr64[l][a] = a < dim ? L.take(sizeof(double) * (size_t)B * 3 * s.CRW * s.NL) : 0;
+            h->o_cr32[l][a] =
+                (a < dim && h->f32) ? L.take(sizeof(float) * (size_t)B * 3 * s.CRW * s.NL) : 0;
+        }
+        h->o_X[l] = L.take(tsz * (size_t)B * s.N);
+        h->o_R[l] = L.take(tsz * (size_t)B * s.N);
+        h->o_Tm[l] = L.take(tsz * (size_t)B * s.N);
+        h->o_TR[l] = L.take(tsz * (size_t)B * dim * s.N);
+    }
+    LevelShape f = level_shape(dim, h->nlev - 1);
+    h->w1 = h->w2 = w;
+    h->o_mass = L.take(sizeof(double) * (size_t)B * f.N);
+    h->o_W1 = L.take(tsz * (size_t)B * w);
+    h->o_W2 = dim == 3 ? L.take(tsz * (size_t)B * w) : 0;
+    h->o_TR64 = L.take(sizeof(double) * (size_t)B * dim * f.N);
+    const int kr = d.restart;
+    h->nv = kr + 1 > 5 ? kr + 1 : 5;
+    h->hs = (long long)(kr + 1) * kr + 4LL * kr + 1;
+    h->o_V = L.take(sizeof(double) * (size_t)B * h->nv * f.N);
+    h->o_Z = L.take(sizeof(double) * (size_t)B * kr * f.N);
+    h->o_Hs = L.take(sizeof(double) * (size_t)B * h->hs);
+    h->o_detmin = L.take(sizeof(double) * (size_t)B * h->nlev);
+    h->o_pivot = L.take(sizeof(int) * (size_t)B);
+    h->o_cinv64 = L.take(sizeof(double) * (size_t)B);
+    h->o_cinv32 = L.take(sizeof(float) * (size_t)B);
+    h->total = L.take(0) + 256;
+}
+
+template <class T>
+void fill_hier(pmg_handle* h, Hier<T>& H, bool is32)
+{
+    memset(&H, 0, sizeof(H));
+    char* ws = h->ws;
+    const int dim = h->d.dim;
+    for (int l = 0; l < h->nlev; ++l) {
+        LevelData<T>& L = H.lev[l];
+        L.G64 = (const double*)(ws + h->o_G64[l]);
+        L.G = is32 ? (const T*)(ws + h->o_G32[l]) : (const T*)(ws + h->o_G64[l]);
+        L.mass = (l == h->nlev - 1) ? (const double*)(ws + h->o_mass) : nullptr;
+        L.X64 = (const double*)(ws + h->o_X64[l]);
+        for (int a = 0; a < dim; ++a)
+            L.cr[a] = is32 ? (const T*)(ws + h->o_cr32[l][a]) : (const T*)(ws + h->o_cr64[l][a]);
+        L.X = (T*)(ws + h->o_X[l]);
+        L.R = (T*)(ws + h->o_R[l]);
+        L.Tm = (T*)(ws + h->o_Tm[l]);
+        L.TR = (T*)(ws + h->o_TR[l]);
+        L.D = (const T*)(ws + (is32 ? h->o_D32[l] : h->o_D64[l]));
+        L.DT = (const T*)(ws + (is32 ? h->o_DT32[l] : h->o_DT64[l]));
+        if (l > 0) {
+            L.J = (const T*)(ws + (is32 ? h->o_J32[l] : h->o_J64[l]));
+            L.JT = (const T*)(ws + (is32 ? h->o_JT32[l] : h->o_JT64[l]));
+        }
+        L.D64 = (const double*)(ws + h->o_D64[l]);
+        L.DT64 = (const double*)(ws + h->o_DT64[l]);
+    }
+    H.cinv = (const T*)(ws + (is32 ? h->o_cinv32 : h->o_cinv64));
+    H.W1 = (T*)(ws + h->o_W1);
+    H.W2 = dim == 3 ? (T*)(ws + h->o_W2) : nullptr;
+    H.w1 = h->w1;
+    H.w2 = h->w2;
+    H.nlev = h->nlev;
+    H.gamma = h->d.gamma;
+    H.m = h->d.m;
+    H.alpha = (T)h->d.alpha;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pmg_last_error(void) { return g_err.c_str(); }
+
+int pmg_num_levels(const pmg_desc* desc, int* n_levels)
+{
+    int rc = check_desc(desc);
+    if (rc) return rc;
+    if (!n_levels) return fail(PMG_EINVAL, "n_levels is NULL");
+    *n_levels = ilog2(desc->p_fine);
+    return PMG_OK;
+}
+
+int pmg_gll(int p, double* xi, double* rho, double* D)
+{
+    if (p < 1 || p > 1024) return fail(PMG_EINVAL, "p must be in [1, 1024]");
+    if (!xi || !rho) return fail(PMG_EINVAL, "xi and rho must not be NULL");
+    std::vector<double> x, r, Dm;
+    if (!gll_nodes(p, x, r)) return fail(PMG_EINVAL, "GLL Newton iteration failed for p = %d", p);
+    memcpy(xi, x.data(), sizeof(double) * (p + 1));
+    memcpy(rho, r.data(), sizeof(double) * (p + 1));
+    if (D) {
+        gll_deriv(p, x, Dm);
+        memcpy(D, Dm.data(), sizeof(double) * (p + 1) * (p + 1));
+    }
+    return PMG_OK;
+}
+
+int pmg_interp(int p_c, int p_f, double* J)
+{
+    if (p_c < 1 || p_f < 1 || p_c > 1024 || p_f > 1024) return fail(PMG_EINVAL, "bad degrees");
+    if (!J) return fail(PMG_EINVAL, "J is NULL");
+    std::vector<double> xc, rc, xf, rf, Jm;
+    if (!gll_nodes(p_c, xc, rc) || !gll_nodes(p_f, xf, rf))
+        return fail(PMG_EINVAL, "GLL Newton iteration failed");
+    bary_interp(xc, xf, Jm);
+    memcpy(J, Jm.data(), sizeof(double) * (p_f + 1) * (p_c + 1));
+    return PMG_OK;
+}
+
+int pmg_workspace_bytes(const pmg_desc* desc, size_t* bytes)
+{
+    int rc = check_desc(desc);
+    if (rc) return rc;
+    if (!bytes) return fail(PMG_EINVAL, "bytes is NULL");
+    pmg_handle tmp;
+    tmp.d = *desc;
+    tmp.nlev = ilog2(desc->p_fine);
+    tmp.f32 = desc->inner_prec == PMG_F32;
+    plan(&tmp);
+    *bytes = tmp.total;
+    return PMG_OK;
+}
+
+int pmg_setup(const pmg_desc* desc, const double* const* d_coords, void* d_ws, size_t ws_bytes,
+              pmg_info* d_info, pmg_stream_t stream, pmg_handle** out)
+{
+    int rc = check_desc(desc);
+    if (rc) return rc;
+    if (!d_coords || !d_ws || !d_info || !out) return fail(PMG_EINVAL, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    pmg_handle* h = new pmg_handle();
+    h->d = *desc;
+    h->nlev = ilog2(desc->p_fine);
+    h->f32 = desc->inner_prec == PMG_F32;
+    plan(h);
+    if (ws_bytes < h->total) {
+        size_t need = h->total;
+        delete h;
+        return fail(PMG_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+    }
+    for (int l = 0; l < h->nlev; ++l)
+        if (!d_coords[l]) {
+            delete h;
+            return fail(PMG_EINVAL, "coordinates of level %d are NULL", l);
+        }
+    h->ws = (char*)d_ws;
+    h->ws_bytes = ws_bytes;
+    const int dim = desc->dim;
+
+    // host tables -> one staging buffer per precision, uploaded in one copy each
+    h->h64.assign(h->o_G64[0] / sizeof(double) + 1, 0.0);
+    h->h32.assign(h->o_G64[0] / sizeof(float) + 1, 0.0f);
+    std::vector<std::vector<double>> xis(h->nlev);
+    for (int l = 0; l < h->nlev; ++l) {
+        LevelShape sh = level_shape(dim, l);
+        std::vector<double> rho, D;
+        if (!gll_nodes(sh.p, xis[l], rho)) {
+            delete h;
+            return fail(PMG_EINVAL, "GLL Newton iteration failed for p = %d", sh.p);
+        }
+        gll_deriv(sh.p, xis[l], D);
+        double* t64 = h->h64.data();
+        float* t32 = h->h32.data();
+        for (int i = 0; i < sh.n1; ++i) t64[h->o_rho[l] / 8 + i] = rho[i];
+        for (int i = 0; i < sh.n1; ++i)
+            for (int j = 0; j < sh.n1; ++j) {
+                double v = D[i * sh.n1 + j];
+                t64[h->o_D64[l] / 8 + i * sh.n1 + j] = v;
+                t64[h->o_DT64[l] / 8 + j * sh.n1 + i] = v;
+                t32[h->o_D32[l] / 4 + i * sh.n1 + j] = (float)v;
+                t32[h->o_DT32[l] / 4 + j * sh.n1 + i] = (float)v;
+            }
+        if (l > 0) {
+            std::vector<double> J;
+            bary_interp(xis[l - 1], xis[l], J);
+            int n1c = sh.p / 2 + 1;
+            for (int i = 0; i < sh.n1; ++i)
+                for (int j = 0; j < n1c; ++j) {
+                    double v = J[i * n1c + j];
+                    t64[h->o_J64[l] / 8 + i * n1c + j] = v;
+                    t64[h->o_JT64[l] / 8 + j * sh.n1 + i] = v;
+                    t32[h->o_J32[l] / 4 + i * n1c + j] = (float)v;
+                    t32[h->o_JT32[l] / 4 + j * sh.n1 + i] = (float)v;
+                }
+        }
+    }
+    // The FP64 and FP32 tables interleave in [0, o_G64[0]); upload the FP64
+    // table regions from h64 and the FP32 regions from h32.
+    hipError_t e;
+    auto up64 = [&](size_t off, size_t n) {
+        return hipMemcpyAsync(h->ws + off, h->h64.data() + off / 8, n * 8, hipMemcpyHostToDevice, s);
+    };
+    auto up32 = [&](size_t off, size_t n) {
+        return hipMemcpyAsync(h->ws + off, h->h32.data() + off / 4, n * 4, hipMemcpyHostToDevice, s);
+    };
+    for (int l = 0; l < h->nlev; ++l) {
+        LevelShape sh = level_shape(dim, l);
+        size_t nn = (size_t)sh.n1 * sh.n1;
+        if ((e = up64(h->o_rho[l], sh.n1)) != hipSuccess ||
+            (e = up64(h->o_D64[l], nn)) != hipSuccess || (e = up64(h->o_DT64[l], nn)) != hipSuccess ||
+            (e = up32(h->o_D32[l], nn)) != hipSuccess || (e = up32(h->o_DT32[l], nn)) != hipSuccess) {
+            delete h;
+            return hip_fail(e, "table upload");
+        }
+        if (l > 0) {
+            size_t nj = (size_t)sh.n1 * (sh.p / 2 + 1);
+            if ((e = up64(h->o_J64[l], nj)) != hipSuccess || (e = up64(h->o_JT64[l], nj)) != hipSuccess ||
+                (e = up32(h->o_J32[l], nj)) != hipSuccess || (e = up32(h->o_JT32[l], nj)) != hipSuccess) {
+                delete h;
+                return hip_fail(e, "table upload");
+            }
+        }
+    }
+    fill_hier<double>(h, h->H64, false);
+    fill_hier<float>(h, h->H32, true);
+    // FP64 views used by the FP64-only operations of an FP32 handle
+    h->H64.lev[h->nlev - 1].TR = (double*)(h->ws + h->o_TR64);
+
+    SetupArgs a;
+    memset(&a, 0, sizeof(a));
+    for (int l = 0; l < h->nlev; ++l) {
+        a.coords[l] = d_coords[l];
+        for (int k = 0; k < 3; ++k) {
+            a.cr64[l][k] = k < dim ? (double*)(h->ws + h->o_cr64[l][k]) : nullptr;
+            a.cr32[l][k] = (k < dim && h->f32) ? (float*)(h->ws + h->o_cr32[l][k]) : nullptr;
+        }
+        a.G64[l] = (double*)(h->ws + h->o_G64[l]);
+        a.G32[l] = h->f32 ? (float*)(h->ws + h->o_G32[l]) : nullptr;
+        a.X64[l] = (double*)(h->ws + h->o_X64[l]);
+        a.rho[l] = (const double*)(h->ws + h->o_rho[l]);
+        a.D64[l] = (const double*)(h->ws + h->o_D64[l]);
+        a.DT64[l] = (const double*)(h->ws + h->o_DT64[l]);
+    }
+    a.mass = (double*)(h->ws + h->o_mass);
+    a.detmin = (double*)(h->ws + h->o_detmin);
+    a.pivot = (int*)(h->ws + h->o_pivot);
+    a.cinv64 = (double*)(h->ws + h->o_cinv64);
+    a.cinv32 = (float*)(h->ws + h->o_cinv32);
+    a.smoother = desc->smoother;
+    e = launch_setup(dim, desc->p_fine, h->nlev, desc->batch, a, d_info, s);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "setup kernels");
+    }
+    *out = h;
+    return PMG_OK;
+}
+
+static int check_h(pmg_handle* h)
+{
+    if (!h) return fail(PMG_EINVAL, "handle is NULL");
+    return PMG_OK;
+}
+
+static int check_prec(pmg_handle* h, int prec, bool* f32)
+{
+    if (prec != PMG_F64 && prec != PMG_F32) return fail(PMG_EINVAL, "unknown precision %d", prec);
+    if ((prec == PMG_F32) != h->f32)
+        return fail(PMG_EINVAL, "precision %s does not match the handle's inner precision",
+                    prec == PMG_F32 ? "F32" : "F64");
+    *f32 = prec == PMG_F32;
+    return PMG_OK;
+}
+
+static const void* hier_of(pmg_handle* h, bool f32)
+{
+    return f32 ? (const void*)&h->H32 : (const void*)&h->H64;
+}
+
+int pmg_rhs(pmg_handle* h, const double* d_f, const double* d_g, double* d_b, pmg_stream_t stream)
+{
+    int rc = check_h(h);
+    if (rc) return rc;
+    if (!d_f || !d_g || !d_b) return fail(PMG_EINVAL, "NULL argument");
+    hipError_t e = launch_rhs(h->d.dim, h->d.p_fine, h->d.batch, h->H64, d_f, d_g, d_b,
+                              (double*)(h->ws + h->o_V), (hipStream_t)stream);
+    return e == hipSuccess ? PMG_OK : hip_fail(e, "pmg_rhs");
+}
+
+int pmg_lift(pmg_handle* h, const double* d_w, const double* d_g, double* d_u, pmg_stream_t stream)
+{
+    int rc = check_h(h);
+    if (rc) return rc;
+    if (!d_w || !d_g || !d_u) return fail(PMG_EINVAL, "NULL argument");
+    hipError_t e = launch_lift(h->d.dim, h->d.p_fine, h->d.batch, d_w, d_g, d_u, (hipStream_t)stream);
+    return e == hipSuccess ? PMG_OK : hip_fail(e, "pmg_lift");
+}
+
+static int check_level(pmg_handle* h, int level, int lo)
+{
+    if (level < lo || level >= h->nlev)
+        return fail(PMG_EINVAL, "level %d out of range [%d, %d]", level, lo, h->nlev - 1);
+    return PMG_OK;
+}
+
+int pmg_apply(pmg_handle* h, int level, int prec, const void* d_x, void* d_y, pmg_stream_t stream)
+{
+    bool f32;
+    int rc;
+    if ((rc = check_h(h)) || (rc = check_level(h, level, 0)) || (rc = check_prec(h, prec, &f32)))
+        return rc;
+    if (!d_x || !d_y) return fail(PMG_EINVAL, "NULL argument");
+    hipError_t e = launch_apply(h->d.dim, 2 << level, f32, h->d.batch, hier_of(h, f32), d_x, d_y,
+                                (hipStream_t)stream);
+    return e == hipSuccess ? PMG_OK : hip_fail(e, "pmg_apply");
+}
+
+int pmg_restrict(pmg_handle* h, int level, int prec, const void* d_rf, void* d_rc, pmg_stream_t stream)
+{
+    bool f32;
+    int rc;
+    if ((rc = check_h(h)) || (rc = check_level(h, level, 1)) || (rc = check_prec(h, prec, &f32)))
+        return rc;
+    if (!d_rf || !d_rc) return fail(PMG_EINVAL, "NULL argument");
+    hipError_t e = launch_restrict(h->d.dim, 2 << level, f32, h->d.batch, hier_of(h, f32), d_rf,
+                                   d_rc, (hipStream_t)stream);
+    return e == hipSuccess ? PMG_OK : hip_fail(e, "pmg_restrict");
+}
+
+int pmg_prolong_add(pmg_handle* h, int level, int prec, const void* d_ec, void* d_xf,
+                    pmg_stream_t stream)
+{
+    bool f32;
+    int rc;
+    if ((rc = check_h(h)) || (rc = check_level(h, level, 1)) || (rc = check_prec(h, prec, &f32)))
+        return rc;
+    if (!d_ec || !d_xf) return fail(PMG_EINVAL, "NULL argument");
+    hipError_t e = launch_prolong(h->d.dim, 2 << level, f32, h->d.batch, hier_of(h, f32), d_ec,
+                                  d_xf, (hipStream_t)stream);
+    return e == hipSuccess ? PMG_OK : hip_fail(e, "pmg_prolong_add");
+}
+
+int pmg_line_solve(pmg_handle* h, int level, int dir, int prec, const void* d_r, void* d_z,
+                   pmg_stream_t stream)
+{
+    bool f32;
+    int rc;
+    if ((rc = check_h(h)) || (rc = check_level(h, level, 0)) || (rc = check_prec(h, prec, &f32)))
+        return rc;
+    if (dir < 0 || dir >= h->d.dim) return fail(PMG_EINVAL, "dir %d out of range", dir);
+    if (!d_r || !d_z) return fail(PMG_EINVAL, "NULL argument");
+    hipError_t e = launch_line_solve(h->d.dim, 2 << level, f32, h->d.batch, hier_of(h, f32), dir,
+                                     d_r, d_z, (hipStream_t)stream);
+    return e == hipSuccess ? PMG_OK : hip_fail(e, "pmg_line_solve");
+}
+
+int pmg_line_smooth(pmg_handle* h, int level, int dir, int prec, const void* d_r, void* d_x,
+                    pmg_stream_t stream)
+{
+    bool f32;
+    int rc;
+    if ((rc = check_h(h)) || (rc = check_level(h, level, 0)) || (rc = check_prec(h, prec, &f32)))
+        return rc;
+    if (dir < 0 || dir >= h->d.dim) return fail(PMG_EINVAL, "dir %d out of range", dir);
+    if (!d_r || !d_x) return fail(PMG_EINVAL, "NULL argument");
+    hipError_t e = launch_line_smooth(h->d.dim, 2 << level, f32, h->d.batch, hier_of(h, f32), dir,
+                                      d_r, d_x, (hipStream_t)stream);
+    return e == hipSuccess ? PMG_OK : hip_fail(e, "pmg_line_smooth");
+}
+
+int pmg_gamma_cycle(pmg_handle* h, int prec, const void* d_r, void* d_y, pmg_stream_t stream)
+{
+    bool f32;
+    int rc;
+    if ((rc = check_h(h)) || (rc = check_prec(h, prec, &f32))) return rc;
+    if (!d_r || !d_y) return fail(PMG_EINVAL, "NULL argument");
+    hipError_t e = launch_cycle(h->d.dim, h->d.p_fine, f32, h->d.batch, hier_of(h, f32), d_r, d_y,
+                                (hipStream_t)stream);
+    return e == hipSuccess ? PMG_OK : hip_fail(e, "pmg_gamma_cycle");
+}
+
+int pmg_solve(pmg_handle* h, const double* d_b, double* d_x, pmg_info* d_info, pmg_stream_t stream)
+{
+    int rc = check_h(h);
+    if (rc) return rc;
+    if (!d_b || !d_x || !d_info) return fail(PMG_EINVAL, "NULL argument");
+    SolveArgs a;
+    a.b = d_b;
+    a.x = d_x;
+    a.V = (double*)(h->ws + h->o_V);
+    a.Z = (double*)(h->ws + h->o_Z);
+    a.Hs = (double*)(h->ws + h->o_Hs);
+    a.TR64 = (double*)(h->ws + h->o_TR64);
+    a.info = d_info;
+    a.nv = h->nv;
+    a.hs = h->hs;
+    a.restart = h->d.restart;
+    a.max_iter = h->d.max_iter;
+    a.krylov = h->d.krylov;
+    a.rtol = h->d.rtol;
+    hipError_t e = launch_solve(h->d.dim, h->d.p_fine, h->f32, h->d.batch, hier_of(h, h->f32), a,
+                                (hipStream_t)stream);
+    return e == hipSuccess ? PMG_OK : hip_fail(e, "pmg_solve");
+}
+
+int pmg_line_coefs(pmg_handle* h, int level, int dir, double* d_lo, double* d_di, double* d_up,
+                   pmg_stream_t stream)
+{
+    int rc;
+    if ((rc = check_h(h)) || (rc = check_level(h, level, 0))) return rc;
+    if (dir < 0 || dir >= h->d.dim) return fail(PMG_EINVAL, "dir %d out of range", dir);
+    if (!d_lo || !d_di || !d_up) return fail(PMG_EINVAL, "NULL argument");
+    hipError_t e = launch_line_coefs(h->d.dim, 2 << level, h->d.batch, h->H64, h->d.smoother, dir,
+                                     d_lo, d_di, d_up, (hipStream_t)stream);
+    return e == hipSuccess ? PMG_OK : hip_fail(e, "pmg_line_coefs");
+}
+
+int pmg_geom(pmg_handle* h, int level, double* d_G, double* d_mass, pmg_stream_t stream)
+{
+    int rc;
+    if ((rc = check_h(h)) || (rc = check_level(h, level, 0))) return rc;
+    if (!d_G) return fail(PMG_EINVAL, "d_G is NULL");
+    LevelShape sh = level_shape(h->d.dim, level);
+    hipStream_t s = (hipStream_t)stream;
+    size_t nG = sizeof(double) * (size_t)h->d.batch * sh.NC * sh.N;
+    hipError_t e = hipMemcpyAsync(d_G, h->ws + h->o_G64[level], nG, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && d_mass) {
+        if (level != h->nlev - 1) return fail(PMG_EINVAL, "mass is stored for the finest level only");
+        e = hipMemcpyAsync(d_mass, h->ws + h->o_mass, sizeof(double) * (size_t)h->d.batch * sh.N,
+                           hipMemcpyDeviceToDevice, s);
+    }
+    return e == hipSuccess ? PMG_OK : hip_fail(e, "pmg_geom");
+}
+
+int pmg_destroy(pmg_handle* h)
+{
+    delete h;
+    return PMG_OK;
+}
+
+}  // extern "C"

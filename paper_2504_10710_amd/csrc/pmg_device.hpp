@@ -1,0 +1,464 @@
+// pmg_device.hpp -- device-side building blocks of the gfx950 p-multigrid
+// gamma-cycle with cyclic-reduction line smoothers (arXiv 2504.10710).
+//
+// Execution model: one workgroup of NT threads owns one problem of a batch
+// and runs every operation of that problem cooperatively; workgroup barriers
+// separate dependent phases.  Problems never share a workgroup, so results
+// do not depend on what else is in the batch.  All level data lives in the
+// caller's workspace in HBM; the per-problem working set of the smaller
+// levels stays in L2.
+//
+// Layouts (per problem, all levels):
+//   vectors     N = (p+1)^dim nodes, first axis fastest
+//   G           ncomp arrays of N: 2-D (G00, G11, G01), 3-D (G00, G11, G22,
+//               G01, G02, G12): weighted inverse metric of the mapping
+//   line data   per axis: 3 words x CRW x NL, line index fastest, where NL
+//               = (p-1)^(dim-1) lines, CRW = sum over cyclic-reduction levels
+//               of the level's unknown count, word (slot, w) at
+//               (slot*3 + w)*NL + line
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace pmg {
+
+constexpr int NT = 256;          // threads per workgroup
+constexpr int MAX_LEVELS = 9;
+
+__host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+__host__ __device__ constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+
+// Number of unknowns summed over the cyclic-reduction levels of a line of n
+// unknowns (n = 2^q - 1: levels of 2^(q-k) - 1 unknowns, k = 0..q-1).
+__host__ __device__ constexpr int cr_words(int n) { return n <= 1 ? n : n + cr_words(n / 2); }
+
+template <int P, int DIM>
+struct Shape {
+    static constexpr int n1 = P + 1;
+    static constexpr int N = ipow(n1, DIM);
+    static constexpr int n = P - 1;
+    static constexpr int NL = ipow(n, DIM - 1);
+    static constexpr int NC = DIM == 2 ? 3 : 6;
+    static constexpr int CRW = cr_words(n);
+    static constexpr int LEV = ilog2(P) - 1;   // level index (p = 2 is level 0)
+};
+
+// index of G_ab in the packed component list
+__host__ __device__ constexpr int gidx(int dim, int a, int b)
+{
+    return a == b ? a : (dim == 2 ? 2 : (a + b == 1 ? 3 : (a + b == 2 ? 4 : 5)));
+}
+
+template <class T>
+struct LevelData {
+    const double* G64;   // [B][NC][N] FP64 geometric factors
+    const T* G;          // [B][NC][N] in T (aliases G64 for T = double)
+    const double* mass;  // [B][N] finest level only
+    const double* X64;   // [B][DIM][N] physical node coordinates
+    const T* cr[3];      // [B][3][CRW][NL] cyclic-reduction factors per axis
+    T* X;                // [B][N] level iterate
+    T* R;                // [B][N] level right-hand side
+    T* Tm;               // [B][N] residual / line-solve buffer
+    T* TR;               // [B][DIM][N] apply fluxes
+    const T* D;          // [n1][n1]  D[i][j] = pi_j'(xi_i)
+    const T* DT;         // [n1][n1]  transpose
+    const T* J;          // [n1][n1c] prolongation from the next coarser level
+    const T* JT;         // [n1c][n1]
+    const double* D64;
+    const double* DT64;
+};
+
+template <class T>
+struct Hier {
+    LevelData<T> lev[MAX_LEVELS];
+    const T* cinv;       // [B] 1 / A_0 of the one interior node of level 0
+    T* W1;               // [B][w1] transfer temporaries
+    T* W2;               // [B][w2]
+    long long w1, w2;    // per-problem sizes of W1, W2
+    int nlev, gamma, m;
+    T alpha;
+};
+
+// ------------------------------------------------------------------ utilities
+
+__device__ inline void wg_barrier() { __syncthreads(); }
+
+template <class T>
+__device__ inline void wg_copy(T* __restrict__ dst, const T* __restrict__ src, int n)
+{
+    for (int i = threadIdx.x; i < n; i += NT) dst[i] = src[i];
+}
+
+template <class T>
+__device__ inline void wg_zero(T* dst, int n)
+{
+    for (int i = threadIdx.x; i < n; i += NT) dst[i] = T(0);
+}
+
+// Deterministic workgroup sum: fixed per-thread order, fixed tree.
+__device__ inline double wg_sum(double v, double* red)
+{
+    red[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ inline double wg_min(double v, double* red)
+{
+    red[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+template <int P, int DIM>
+__device__ inline bool is_boundary(int q)
+{
+    constexpr int n1 = P + 1;
+    int c0 = q % n1, c1 = (q / n1) % n1;
+    bool bd = c0 == 0 || c0 == P || c1 == 0 || c1 == P;
+    if (DIM == 3) {
+        int c2 = q / (n1 * n1);
+        bd = bd || c2 == 0 || c2 == P;
+    }
+    return bd;
+}
+
+// ------------------------------------------------------------------ operator
+
+// Matrix-free A x of eq. discreteBilinear by sum factorisation: reference
+// gradients g_b = D along axis b, fluxes f_a = sum_b G_ab g_b at every node,
+// then (A x)(n) = sum_a sum_k D[k][n_a] f_a(n with axis a <- k) on interior
+// rows.  RESID: out = r - A x.  out has zero boundary rows.
+template <class T, int P, int DIM, bool RESID>
+__device__ void apply_level(const T* __restrict__ G, const T* __restrict__ D,
+                            const T* __restrict__ DT, T* __restrict__ TR,
+                            const T* __restrict__ x, const T* __restrict__ r, T* __restrict__ out)
+{
+    using S = Shape<P, DIM>;
+    constexpr int n1 = S::n1, N = S::N;
+    for (int q = threadIdx.x; q < N; q += NT) {
+        int c[3] = {q % n1, (q / n1) % n1, DIM == 3 ? q / (n1 * n1) : 0};
+        T g[DIM];
+        {
+            const T* xr = x + (q - c[0]);
+            T s = 0;
+#pragma unroll 8
+            for (int k = 0; k < n1; ++k) s += DT[k * n1 + c[0]] * xr[k];
+            g[0] = s;
+        }
+#pragma unroll
+        for (int a = 1; a < DIM; ++a) {
+            const int st = a == 1 ? n1 : n1 * n1;
+            const T* xr = x + (q - c[a] * st);
+            const T* Dr = D + c[a] * n1;
+            T s = 0;
+#pragma unroll 8
+            for (int k = 0; k < n1; ++k) s += Dr[k] * xr[k * st];
+            g[a] = s;
+        }
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            T f = 0;
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) f += G[gidx(DIM, a, b) * N + q] * g[b];
+            TR[a * N + q] = f;
+        }
+    }
+    wg_barrier();
+    for (int q = threadIdx.x; q < N; q += NT) {
+        if (is_boundary<P, DIM>(q)) {
+            out[q] = T(0);
+            continue;
+        }
+        int c[3] = {q % n1, (q / n1) % n1, DIM == 3 ? q / (n1 * n1) : 0};
+        T y = 0;
+        {
+            const T* fr = TR + (q - c[0]);
+#pragma unroll 8
+            for (int k = 0; k < n1; ++k) y += D[k * n1 + c[0]] * fr[k];
+        }
+#pragma unroll
+        for (int a = 1; a < DIM; ++a) {
+            const int st = a == 1 ? n1 : n1 * n1;
+            const T* fr = TR + a * N + (q - c[a] * st);
+#pragma unroll 8
+            for (int k = 0; k < n1; ++k) y += D[k * n1 + c[a]] * fr[k * st];
+        }
+        out[q] = RESID ? r[q] - y : y;
+    }
+    wg_barrier();
+}
+
+// ------------------------------------------------------------------ line solver
+
+// node index of position s (0-based, interior) on line `line` along axis dir
+template <int P, int DIM>
+__device__ inline void line_base(int dir, int line, int& base, int& st)
+{
+    constexpr int n1 = P + 1, n = P - 1;
+    if (DIM == 2) {
+        int o = line + 1;
+        base = dir == 0 ? o * n1 : o;
+        st = dir == 0 ? 1 : n1;
+    } else {
+        int o1 = line % n + 1, o2 = line / n + 1;
+        if (dir == 0) { base = o1 * n1 + o2 * n1 * n1; st = 1; }
+        else if (dir == 1) { base = o1 + o2 * n1 * n1; st = n1; }
+        else { base = o1 + o2 * n1; st = n1 * n1; }
+    }
+}
+
+// Cyclic reduction as a direct multigrid (Thm. "Two-level direct solver",
+// Cor. "Direct multigrid solver"), one thread per line, in place on g.
+// Level k of a line of n = 2^q - 1 unknowns holds the unknowns at 1-based
+// positions t * 2^k; F points are t odd, C points t even (Def. odd-even
+// reordering).  Factors per level slot: F (1/a, -l/a, -u/a) = (S^{-1}, rows
+// of P); C (l, a, u) of that level's matrix, whose Schur complement
+// D - C A^{-1} B is the next level.
+//   down: x_F = g_F / a_F;  g_C -= l_C x_{C-1} + u_C x_{C+1}   (R (g - M x))
+//   coarsest: x = g / a
+//   up:   y_F = x_F - (l_F e_{F-1} + u_F e_{F+1}) / a_F         (x + P e)
+// FUSED: instead of storing z, x += alpha z.
+template <class T, int P, int DIM, bool FUSED>
+__device__ void line_cr(const T* __restrict__ cr, int dir, T* __restrict__ g,
+                        T* __restrict__ x, T alpha)
+{
+    using S = Shape<P, DIM>;
+    constexpr int n = S::n, NL = S::NL;
+    constexpr int NK = ilog2(n + 1);   // number of CR levels
+    for (int line = threadIdx.x; line < NL; line += NT) {
+        int base, st;
+        line_base<P, DIM>(dir, line, base, st);
+        auto node = [&](int s) { return base + (s + 1) * st; };
+        auto W = [&](int slot, int w) -> T { return cr[(slot * 3 + w) * NL + line]; };
+        int off = 0;
+#pragma unroll
+        for (int k = 0; k < NK - 1; ++k) {
+            const int nk = (n + 1) / (1 << k) - 1;
+#pragma unroll 4
+            for (int t = 0; t < nk; t += 2) {
+                int s = ((t + 1) << k) - 1;
+                g[node(s)] *= W(off + t, 0);
+            }
+#pragma unroll 4
+            for (int t = 1; t < nk; t += 2) {
+                int s = ((t + 1) << k) - 1;
+                int sl = (t << k) - 1, sr = ((t + 2) << k) - 1;
+                g[node(s)] -= W(off + t, 0) * g[node(sl)] + W(off + t, 2) * g[node(sr)];
+            }
+            off += nk;
+        }
+        {
+            int s = (1 << (NK - 1)) - 1;
+            g[node(s)] *= W(off, 0);
+        }
+#pragma unroll
+        for (int k = NK - 2; k >= 0; --k) {
+            const int nk = (n + 1) / (1 << k) - 1;
+            off -= nk;
+            if (FUSED && k == 0) {
+#pragma unroll 4
+                for (int t = 0; t < nk; ++t) {
+                    int s = t;
+                    T v;
+                    if ((t & 1) == 0) {
+                        v = g[node(s)];
+                        if (t >= 1) v += W(off + t, 1) * g[node(s - 1)];
+                        if (t + 1 < nk) v += W(off + t, 2) * g[node(s + 1)];
+                    } else {
+                        v = g[node(s)];
+                    }
+                    x[node(s)] += alpha * v;
+                }
+            } else {
+#pragma unroll 4
+                for (int t = 0; t < nk; t += 2) {
+                    int s = ((t + 1) << k) - 1;
+                    T v = g[node(s)];
+                    if (t >= 1) v += W(off + t, 1) * g[node((t << k) - 1)];
+                    if (t + 1 < nk) v += W(off + t, 2) * g[node(((t + 2) << k) - 1)];
+                    g[node(s)] = v;
+                }
+            }
+        }
+        if (FUSED && NK == 1) x[node(0)] += alpha * g[node(0)];
+    }
+    wg_barrier();
+}
+
+// ------------------------------------------------------------------ transfers
+
+// One axis of the restriction R = (J x J [x J])^T: out(.., o_a, ..) =
+// sum_t J[t][o_a] in(.., t, ..), in has extent n1f along a, out n1c.
+template <class T>
+__device__ void restrict_axis(const T* __restrict__ in, T* __restrict__ out, int e0, int e1,
+                              int e2, int a, int n1f, int n1c, const T* __restrict__ J,
+                              bool zero_boundary)
+{
+    int eo[3] = {e0, e1, e2};
+    eo[a] = n1c;
+    int ei[3] = {e0, e1, e2};
+    ei[a] = n1f;
+    const int tot = eo[0] * eo[1] * eo[2];
+    const int sti = a == 0 ? 1 : (a == 1 ? ei[0] : ei[0] * ei[1]);
+    for (int q = threadIdx.x; q < tot; q += NT) {
+        int o0 = q % eo[0], o1 = (q / eo[0]) % eo[1], o2 = q / (eo[0] * eo[1]);
+        int oa = a == 0 ? o0 : (a == 1 ? o1 : o2);
+        if (zero_boundary) {
+            bool bd = o0 == 0 || o0 == eo[0] - 1 || o1 == 0 || o1 == eo[1] - 1 ||
+                      (eo[2] > 1 && (o2 == 0 || o2 == eo[2] - 1));
+            if (bd) { out[q] = T(0); continue; }
+        }
+        int ii[3] = {o0, o1, o2};
+        ii[a] = 0;
+        const T* src = in + ii[0] + ei[0] * (ii[1] + ei[1] * ii[2]);
+        T s = 0;
+        for (int t = 0; t < n1f; ++t) s += J[t * n1c + oa] * src[t * sti];
+        out[q] = s;
+    }
+    wg_barrier();
+}
+
+// One axis of the prolongation P = J x J [x J]: out(.., o_a, ..) =
+// sum_t J[o_a][t] in(.., t, ..), in has extent n1c along a, out n1f.
+template <class T, bool ADD>
+__device__ void prolong_axis(const T* __restrict__ in, T* __restrict__ out, int e0, int e1,
+                             int e2, int a, int n1f, int n1c, const T* __restrict__ J,
+                             const T* __restrict__ JT)
+{
+    int eo[3] = {e0, e1, e2};
+    eo[a] = n1f;
+    int ei[3] = {e0, e1, e2};
+    ei[a] = n1c;
+    const int tot = eo[0] * eo[1] * eo[2];
+    const int sti = a == 0 ? 1 : (a == 1 ? ei[0] : ei[0] * ei[1]);
+    for (int q = threadIdx.x; q < tot; q += NT) {
+        int o0 = q % eo[0], o1 = (q / eo[0]) % eo[1], o2 = q / (eo[0] * eo[1]);
+        int ii[3] = {o0, o1, o2};
+        ii[a] = 0;
+        const T* src = in + ii[0] + ei[0] * (ii[1] + ei[1] * ii[2]);
+        T s = 0;
+        if (a == 0) {
+            for (int t = 0; t < n1c; ++t) s += JT[t * n1f + o0] * src[t * sti];
+        } else {
+            int oa = a == 1 ? o1 : o2;
+            for (int t = 0; t < n1c; ++t) s += J[oa * n1c + t] * src[t * sti];
+        }
+        if (ADD) out[q] += s; else out[q] = s;
+    }
+    wg_barrier();
+}
+
+// rc = R_l rf with zero coarse boundary (Sec. 3.3, R = P^T)
+template <class T, int P, int DIM>
+__device__ void restrict_level(const T* rf, T* rc, const T* J, T* w1, T* w2)
+{
+    constexpr int n1f = P + 1, n1c = P / 2 + 1;
+    if (DIM == 2) {
+        restrict_axis<T>(rf, w1, n1f, n1f, 1, 0, n1f, n1c, J, false);
+        restrict_axis<T>(w1, rc, n1c, n1f, 1, 1, n1f, n1c, J, true);
+    } else {
+        restrict_axis<T>(rf, w1, n1f, n1f, n1f, 0, n1f, n1c, J, false);
+        restrict_axis<T>(w1, w2, n1c, n1f, n1f, 1, n1f, n1c, J, false);
+        restrict_axis<T>(w2, rc, n1c, n1c, n1f, 2, n1f, n1c, J, true);
+    }
+}
+
+// xf += P_l ec
+template <class T, int P, int DIM>
+__device__ void prolong_level(const T* ec, T* xf, const T* J, const T* JT, T* w1, T* w2)
+{
+    constexpr int n1f = P + 1, n1c = P / 2 + 1;
+    if (DIM == 2) {
+        prolong_axis<T, false>(ec, w1, n1c, n1c, 1, 0, n1f, n1c, J, JT);
+        prolong_axis<T, true>(w1, xf, n1f, n1c, 1, 1, n1f, n1c, J, JT);
+    } else {
+        prolong_axis<T, false>(ec, w1, n1c, n1c, n1c, 0, n1f, n1c, J, JT);
+        prolong_axis<T, false>(w1, w2, n1f, n1c, n1c, 1, n1f, n1c, J, JT);
+        prolong_axis<T, true>(w2, xf, n1f, n1f, n1c, 2, n1f, n1c, J, JT);
+    }
+}
+
+// ------------------------------------------------------------------ gamma-cycle
+
+template <class T, int P, int DIM>
+__device__ inline const LevelData<T>& lvl(const Hier<T>& H)
+{
+    return H.lev[Shape<P, DIM>::LEV];
+}
+
+// x += alpha B_dir^{-1} (r - A x)   (Alg. 2 smoothing step)
+template <class T, int P, int DIM>
+__device__ void smooth_step(const Hier<T>& H, int b, int dir, const T* r, T* x, bool x_is_zero)
+{
+    using S = Shape<P, DIM>;
+    const LevelData<T>& L = lvl<T, P, DIM>(H);
+    T* tmp = L.Tm + (long long)b * S::N;
+    if (x_is_zero) {
+        wg_copy(tmp, r, S::N);
+        wg_barrier();
+    } else {
+        apply_level<T, P, DIM, true>(L.G + (long long)b * S::NC * S::N, L.D, L.DT,
+                                     L.TR + (long long)b * DIM * S::N, x, r, tmp);
+    }
+    line_cr<T, P, DIM, true>(L.cr[dir] + (long long)b * 3 * S::CRW * S::NL, dir, tmp, x, H.alpha);
+}
+
+// x = M_l^{-1} r (Alg. 2).  Readings: pre-smoothing m steps per axis in axis
+// order, then gamma passes of {coarse correction of the current iterate,
+// m post-smoothing steps per axis in reverse axis order}; level 0 (p = 2,
+// one interior node) is solved exactly.
+template <class T, int P, int DIM>
+__device__ void gamma_cycle(const Hier<T>& H, int b, const T* r, T* x)
+{
+    using S = Shape<P, DIM>;
+    const LevelData<T>& L = lvl<T, P, DIM>(H);
+    if constexpr (P == 2) {
+        // one interior node: M_0^{-1} = A_0^{-1} is a division
+        constexpr int c = DIM == 2 ? 4 : 13;
+        const T ia = H.cinv[b];
+        for (int q = threadIdx.x; q < S::N; q += NT) x[q] = q == c ? r[c] * ia : T(0);
+        wg_barrier();
+    } else {
+        using C = Shape<P / 2, DIM>;
+        const LevelData<T>& Lc = lvl<T, P / 2, DIM>(H);
+        T* rc = Lc.R + (long long)b * C::N;
+        T* xc = Lc.X + (long long)b * C::N;
+        T* tmp = L.Tm + (long long)b * S::N;
+        T* w1 = H.W1 + (long long)b * H.w1;
+        T* w2 = H.W2 ? H.W2 + (long long)b * H.w2 : nullptr;
+        wg_zero(x, S::N);
+        wg_barrier();
+        bool zero = true;
+        for (int dir = 0; dir < DIM; ++dir)
+            for (int s = 0; s < H.m; ++s) {
+                smooth_step<T, P, DIM>(H, b, dir, r, x, zero);
+                zero = false;
+            }
+        for (int g = 0; g < H.gamma; ++g) {
+            apply_level<T, P, DIM, true>(L.G + (long long)b * S::NC * S::N, L.D, L.DT,
+                                         L.TR + (long long)b * DIM * S::N, x, r, tmp);
+            restrict_level<T, P, DIM>(tmp, rc, L.J, w1, w2);
+            gamma_cycle<T, P / 2, DIM>(H, b, rc, xc);
+            prolong_level<T, P, DIM>(xc, x, L.J, L.JT, w1, w2);
+            for (int dir = DIM - 1; dir >= 0; --dir)
+                for (int s = 0; s < H.m; ++s) smooth_step<T, P, DIM>(H, b, dir, r, x, false);
+        }
+    }
+}
+
+}  // namespace pmg

@@ -1,0 +1,398 @@
+// pmg_setup.hip -- setup kernels (geometry, line tridiagonals and their
+// cyclic-reduction factors), Dirichlet lifting, line-coefficient export.
+//
+// Every kernel of the library runs one problem of the batch per workgroup
+// (grid = B, block = NT threads) and calls the device building blocks of
+// pmg_device.hpp.  Setup kernels run in FP64.
+#include <cmath>
+
+#include "pmg_dispatch.hpp"
+
+namespace pmg {
+
+// ================================================================== setup
+
+// Geometry of the mapped element (eq. DiscreteSpace, eq. discreteBilinear):
+// isoparametric Jacobian dx_c/dxi_a = D applied along axis a to the nodal
+// coordinates, phi = rho x rho (x rho) * det J, G_ab = phi * sum_c
+// (dxi_a/dx_c)(dxi_b/dx_c), mass = phi.
+template <int P, int DIM>
+__global__ void __launch_bounds__(NT) k_geom(const double* __restrict__ coords,
+                                             const double* __restrict__ rho,
+                                             const double* __restrict__ D,
+                                             const double* __restrict__ DT,
+                                             double* __restrict__ G, float* __restrict__ G32,
+                                             double* __restrict__ mass, double* __restrict__ X64,
+                                             double* __restrict__ detmin)
+{
+    using S = Shape<P, DIM>;
+    constexpr int n1 = S::n1, N = S::N, NC = S::NC;
+    __shared__ double red[NT];
+    const long long b = blockIdx.x;
+    const double* X = coords + b * DIM * N;
+    double* Gb = G + b * NC * N;
+    double dmin = INFINITY;
+    for (int q = threadIdx.x; q < N; q += NT) {
+        int c[3] = {q % n1, (q / n1) % n1, DIM == 3 ? q / (n1 * n1) : 0};
+        double Jm[3][3];
+        for (int comp = 0; comp < DIM; ++comp) {
+            const double* Xc = X + comp * N;
+            for (int a = 0; a < DIM; ++a) {
+                const int st = a == 0 ? 1 : (a == 1 ? n1 : n1 * n1);
+                const double* xr = Xc + (q - c[a] * st);
+                double s = 0.0;
+                if (a == 0)
+                    for (int k = 0; k < n1; ++k) s += DT[k * n1 + c[0]] * xr[k];
+                else
+                    for (int k = 0; k < n1; ++k) s += D[c[a] * n1 + k] * xr[k * st];
+                Jm[comp][a] = s;
+            }
+        }
+        double det, inv[3][3];
+        if (DIM == 2) {
+            det = Jm[0][0] * Jm[1][1] - Jm[0][1] * Jm[1][0];
+            double id = 1.0 / det;
+            inv[0][0] = Jm[1][1] * id;
+            inv[0][1] = -Jm[0][1] * id;
+            inv[1][0] = -Jm[1][0] * id;
+            inv[1][1] = Jm[0][0] * id;
+        } else {
+            // cofactors: inv[a][comp] = cof[comp][a] / det
+            double c00 = Jm[1][1] * Jm[2][2] - Jm[1][2] * Jm[2][1];
+            double c01 = Jm[1][2] * Jm[2][0] - Jm[1][0] * Jm[2][2];
+            double c02 = Jm[1][0] * Jm[2][1] - Jm[1][1] * Jm[2][0];
+            det = Jm[0][0] * c00 + Jm[0][1] * c01 + Jm[0][2] * c02;
+            double id = 1.0 / det;
+            inv[0][0] = c00 * id;
+            inv[1][0] = c01 * id;
+            inv[2][0] = c02 * id;
+            inv[0][1] = (Jm[0][2] * Jm[2][1] - Jm[0][1] * Jm[2][2]) * id;
+            inv[1][1] = (Jm[0][0] * Jm[2][2] - Jm[0][2] * Jm[2][0]) * id;
+            inv[2][1] = (Jm[0][1] * Jm[2][0] - Jm[0][0] * Jm[2][1]) * id;
+            inv[0][2] = (Jm[0][1] * Jm[1][2] - Jm[0][2] * Jm[1][1]) * id;
+            inv[1][2] = (Jm[0][2] * Jm[1][0] - Jm[0][0] * Jm[1][2]) * id;
+            inv[2][2] = (Jm[0][0] * Jm[1][1] - Jm[0][1] * Jm[1][0]) * id;
+        }
+        dmin = fmin(dmin, det);
+        double w = rho[c[0]] * rho[c[1]] * (DIM == 3 ? rho[c[2]] : 1.0);
+        double phi = w * det;
+        for (int a = 0; a < DIM; ++a)
+            for (int bb = a; bb < DIM; ++bb) {
+                double s = 0.0;
+                for (int comp = 0; comp < DIM; ++comp) s += inv[a][comp] * inv[bb][comp];
+                int gi = gidx(DIM, a, bb);
+                Gb[gi * N + q] = phi * s;
+                if (G32) G32[b * NC * N + gi * N + q] = (float)(phi * s);
+            }
+        if (mass) mass[b * N + q] = phi;
+        for (int comp = 0; comp < DIM; ++comp) X64[b * DIM * N + comp * N + q] = X[comp * N + q];
+    }
+    double m = wg_min(dmin, red);
+    if (threadIdx.x == 0) detmin[b] = m;
+}
+
+// Entry of the bilinear finite-element stiffness on the quadrilaterals of
+// neighbouring GLL nodes (FEM line preconditioners, Sec. 3.1): sum over the
+// elements having both nodes as corners of the 2x2-Gauss integral of
+// grad(phi_a).grad(phi_b) on the element's bilinear map.
+template <int P>
+__device__ double fem_entry_2d(const double* __restrict__ X, int i, int j, int i2, int j2)
+{
+    constexpr int n1 = P + 1, N = n1 * n1;
+    const double h = 0.5 / sqrt(3.0);
+    const double gq[2] = {0.5 - h, 0.5 + h};
+    double s = 0.0;
+    for (int ex = (i > i2 ? i : i2) - 1; ex <= (i < i2 ? i : i2); ++ex)
+        for (int ey = (j > j2 ? j : j2) - 1; ey <= (j < j2 ? j : j2); ++ey) {
+            if (ex < 0 || ey < 0 || ex >= P || ey >= P) continue;
+            double cx[4], cy[4];
+            for (int v = 0; v < 4; ++v) {
+                int q = (ex + (v & 1)) + n1 * (ey + (v >> 1));
+                cx[v] = X[q];
+                cy[v] = X[N + q];
+            }
+            const int va = (i - ex) + 2 * (j - ey), vb = (i2 - ex) + 2 * (j2 - ey);
+            for (int gx = 0; gx < 2; ++gx)
+                for (int gy = 0; gy < 2; ++gy) {
+                    const double u = gq[gx], v = gq[gy];
+                    // d/du and d/dv of the corner functions (1-u)(1-v), u(1-v), (1-u)v, uv
+                    const double du[4] = {-(1 - v), 1 - v, -v, v};
+                    const double dv[4] = {-(1 - u), -u, 1 - u, u};
+                    double xu = 0, xv = 0, yu = 0, yv = 0;
+                    for (int c = 0; c < 4; ++c) {
+                        xu += du[c] * cx[c];
+                        xv += dv[c] * cx[c];
+                        yu += du[c] * cy[c];
+                        yv += dv[c] * cy[c];
+                    }
+                    const double det = xu * yv - xv * yu;
+                    const double ax = (yv * du[va] - yu * dv[va]) / det;
+                    const double ay = (-xv * du[va] + xu * dv[va]) / det;
+                    const double bx = (yv * du[vb] - yu * dv[vb]) / det;
+                    const double by = (-xv * du[vb] + xu * dv[vb]) / det;
+                    s += 0.25 * fabs(det) * (ax * bx + ay * by);
+                }
+        }
+    return s;
+}
+
+// Entry of A_p (eq. discreteBilinear) between node q (multi-index c) and its
+// neighbour along axis dir (offset dd = -1, 0 or +1 along that axis), read off
+// the tensor-product structure: the G_dd term along the line, plus the
+// cross terms weighted by the diagonal entries D[c_b][c_b] of the other axes
+// (which vanish at interior GLL nodes up to rounding).
+template <int P, int DIM>
+__device__ double gll_entry(const double* __restrict__ Gb, const double* __restrict__ D, int q,
+                            const int* c, int dir, int dd)
+{
+    constexpr int n1 = P + 1, N = Shape<P, DIM>::N;
+    auto st = [](int a) { return a == 0 ? 1 : (a == 1 ? n1 : n1 * n1); };
+    double s = 0.0;
+    if (dd == 0) {
+        for (int a = 0; a < DIM; ++a) {
+            const double* Ga = Gb + gidx(DIM, a, a) * N + (q - c[a] * st(a));
+            for (int k = 0; k < n1; ++k) {
+                double d = D[k * n1 + c[a]];
+                s += d * d * Ga[k * st(a)];
+            }
+        }
+        for (int a = 0; a < DIM; ++a)
+            for (int b = 0; b < DIM; ++b)
+                if (a != b) s += Gb[gidx(DIM, a, b) * N + q] * D[c[a] * n1 + c[a]] * D[c[b] * n1 + c[b]];
+    } else {
+        const int cd = c[dir], ce = c[dir] + dd;
+        const int q2 = q + dd * st(dir);
+        const double* Gd = Gb + gidx(DIM, dir, dir) * N + (q - cd * st(dir));
+        for (int k = 0; k < n1; ++k) s += D[k * n1 + cd] * D[k * n1 + ce] * Gd[k * st(dir)];
+        for (int b = 0; b < DIM; ++b) {
+            if (b == dir) continue;
+            const double dbb = D[c[b] * n1 + c[b]];
+            s += dbb * (Gb[gidx(DIM, dir, b) * N + q2] * D[ce * n1 + cd] +
+                        Gb[gidx(DIM, dir, b) * N + q] * D[cd * n1 + ce]);
+        }
+    }
+    return s;
+}
+
+template <int P, int DIM>
+__device__ void line_raw(const double* Gb, const double* Xb, const double* D, int smoother,
+                         int dir, int line, int s, double& l, double& a, double& u)
+{
+    constexpr int n1 = P + 1, n = P - 1;
+    int base, st;
+    line_base<P, DIM>(dir, line, base, st);
+    const int q = base + (s + 1) * st;
+    int c[3] = {q % n1, (q / n1) % n1, DIM == 3 ? q / (n1 * n1) : 0};
+    if (smoother == PMG_SMOOTHER_FEM && DIM == 2) {
+        const int di = dir == 0 ? 1 : 0, dj = dir == 0 ? 0 : 1;
+        a = fem_entry_2d<P>(Xb, c[0], c[1], c[0], c[1]);
+        l = s > 0 ? fem_entry_2d<P>(Xb, c[0], c[1], c[0] - di, c[1] - dj) : 0.0;
+        u = s < n - 1 ? fem_entry_2d<P>(Xb, c[0], c[1], c[0] + di, c[1] + dj) : 0.0;
+    } else {
+        a = gll_entry<P, DIM>(Gb, D, q, c, dir, 0);
+        l = s > 0 ? gll_entry<P, DIM>(Gb, D, q, c, dir, -1) : 0.0;
+        u = s < n - 1 ? gll_entry<P, DIM>(Gb, D, q, c, dir, +1) : 0.0;
+    }
+}
+
+// Line tridiagonals and their cyclic-reduction factors, one thread per line.
+// Level-k slots first receive the raw (l, a, u) of the level-k matrix; the
+// coarse matrix D - C A^{-1} B of Prop. "line coarse space" (stencil of its
+// proof) fills the level-(k+1) slots; then the F slots are turned into
+// (1/a, -l/a, -u/a).  All in FP64, cast to FP32 when requested.
+template <int P, int DIM>
+__global__ void __launch_bounds__(NT) k_lines(const double* __restrict__ G,
+                                              const double* __restrict__ X64,
+                                              const double* __restrict__ D, int smoother,
+                                              double* cr0, double* cr1, double* cr2, float* f0,
+                                              float* f1, float* f2, int* pivot,
+                                              double* cinv64, float* cinv32)
+{
+    using S = Shape<P, DIM>;
+    constexpr int n = S::n, NL = S::NL, CRW = S::CRW, N = S::N, NC = S::NC;
+    const long long b = blockIdx.x;
+    const double* Gb = G + b * NC * N;
+    const double* Xb = X64 + b * DIM * N;
+    int bad = 0;
+    for (int dir = 0; dir < DIM; ++dir) {
+        double* cr = (dir == 0 ? cr0 : (dir == 1 ? cr1 : cr2)) + b * 3 * CRW * NL;
+        float* cf = dir == 0 ? f0 : (dir == 1 ? f1 : f2);
+        for (int line = threadIdx.x; line < NL; line += NT) {
+            auto W = [&](int slot, int w) -> double& { return cr[(slot * 3 + w) * NL + line]; };
+            for (int s = 0; s < n; ++s) {
+                double l, a, u;
+                line_raw<P, DIM>(Gb, Xb, D, smoother, dir, line, s, l, a, u);
+                W(s, 0) = l;
+                W(s, 1) = a;
+                W(s, 2) = u;
+            }
+            int off = 0, nk = n;
+            while (nk > 1) {
+                const int nc = nk / 2;
+                for (int t = 1; t < nk; t += 2) {
+                    const double lc = W(off + t, 0), ac = W(off + t, 1), uc = W(off + t, 2);
+                    const double lL = W(off + t - 1, 0), aL = W(off + t - 1, 1), uL = W(off + t - 1, 2);
+                    const double lR = W(off + t + 1, 0), aR = W(off + t + 1, 1), uR = W(off + t + 1, 2);
+                    const int sc = off + nk + (t - 1) / 2;
+                    W(sc, 0) = -lc * lL / aL;
+                    W(sc, 1) = ac - lc * uL / aL - uc * lR / aR;
+                    W(sc, 2) = -uc * uR / aR;
+                }
+                for (int t = 0; t < nk; t += 2) {
+                    const double a = W(off + t, 1);
+                    if (a == 0.0 || !isfinite(a)) bad = 1;
+                    const double ia = 1.0 / a;
+                    const double l = W(off + t, 0), u = W(off + t, 2);
+                    W(off + t, 0) = ia;
+                    W(off + t, 1) = -l * ia;
+                    W(off + t, 2) = -u * ia;
+                }
+                off += nk;
+                nk = nc;
+            }
+            {
+                const double a = W(off, 1);
+                if (a == 0.0 || !isfinite(a)) bad = 1;
+                W(off, 0) = 1.0 / a;
+                W(off, 1) = 0.0;
+                W(off, 2) = 0.0;
+            }
+            if (cf) {
+                float* cfb = cf + b * 3 * CRW * NL;
+                for (int slot = 0; slot < CRW; ++slot)
+                    for (int w = 0; w < 3; ++w)
+                        cfb[(slot * 3 + w) * NL + line] = (float)W(slot, w);
+            }
+        }
+    }
+    if (P == 2 && threadIdx.x == 0) {
+        // level 0: the exact coarse solve uses A_0 itself (eq. discreteBilinear),
+        // whatever line systems the smoother uses
+        constexpr int c = DIM == 2 ? 4 : 13;
+        const int cc[3] = {1, 1, 1};
+        const double a0 = gll_entry<P, DIM>(Gb, D, c, cc, 0, 0);
+        if (a0 == 0.0 || !isfinite(a0)) bad = 1;
+        cinv64[b] = 1.0 / a0;
+        if (cinv32) cinv32[b] = (float)(1.0 / a0);
+    }
+    if (bad) atomicOr(pivot + b, 1);
+}
+
+__global__ void k_setup_finish(const double* __restrict__ detmin, const int* __restrict__ pivot,
+                               int nlev, int B, pmg_info* __restrict__ info)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    double m = INFINITY;
+    for (int l = 0; l < nlev; ++l) m = fmin(m, detmin[(long long)l * B + b]);
+    pmg_info r;
+    r.min_detj = m;
+    r.iterations = 0;
+    r.relres = NAN;
+    r.status = !(m > 0.0) ? PMG_EGEOM : (pivot[b] ? PMG_EPIVOT : PMG_OK);
+    info[b] = r;
+}
+
+// ================================================================== RHS
+
+// b = M f - A v on interior nodes, 0 on the boundary (Sec. 2.3)
+template <int P, int DIM>
+__global__ void __launch_bounds__(NT) k_rhs(Hier<double> H, const double* __restrict__ f,
+                                            const double* __restrict__ g, double* __restrict__ bo,
+                                            double* __restrict__ tmp)
+{
+    using S = Shape<P, DIM>;
+    constexpr int N = S::N;
+    const long long b = blockIdx.x;
+    const LevelData<double>& L = H.lev[S::LEV];
+    double* v = tmp + b * N;
+    for (int q = threadIdx.x; q < N; q += NT) v[q] = is_boundary<P, DIM>(q) ? g[b * N + q] : 0.0;
+    wg_barrier();
+    double* out = bo + b * N;
+    apply_level<double, P, DIM, false>(L.G64 + b * S::NC * N, L.D64, L.DT64,
+                                       L.TR + b * DIM * N, v, nullptr, out);
+    for (int q = threadIdx.x; q < N; q += NT)
+        out[q] = is_boundary<P, DIM>(q) ? 0.0 : L.mass[b * N + q] * f[b * N + q] - out[q];
+}
+
+template <int P, int DIM>
+__global__ void __launch_bounds__(NT) k_lift(const double* __restrict__ w,
+                                             const double* __restrict__ g, double* u)
+{
+    constexpr int N = Shape<P, DIM>::N;
+    const long long b = blockIdx.x;
+    for (int q = threadIdx.x; q < N; q += NT)
+        u[b * N + q] = is_boundary<P, DIM>(q) ? g[b * N + q] : w[b * N + q];
+}
+
+template <int P, int DIM>
+__global__ void __launch_bounds__(NT) k_line_coefs(Hier<double> H, int smoother, int dir,
+                                                   double* lo, double* di, double* up)
+{
+    using S = Shape<P, DIM>;
+    constexpr int n = S::n, NL = S::NL;
+    const long long b = blockIdx.x;
+    const LevelData<double>& L = H.lev[S::LEV];
+    const double* Gb = L.G64 + b * S::NC * S::N;
+    const double* Xb = L.X64 + b * DIM * S::N;
+    const long long o = b * (long long)NL * n;
+    for (int k = threadIdx.x; k < NL * n; k += NT) {
+        int line = k / n, s = k % n;
+        double l, a, u;
+        line_raw<P, DIM>(Gb, Xb, L.D64, smoother, dir, line, s, l, a, u);
+        lo[o + k] = l;
+        di[o + k] = a;
+        up[o + k] = u;
+    }
+}
+
+
+hipError_t launch_setup(int dim, int p_fine, int nlev, int B, const SetupArgs& a, pmg_info* info,
+                        hipStream_t s)
+{
+    hipError_t e = hipMemsetAsync(a.pivot, 0, sizeof(int) * B, s);
+    if (e != hipSuccess) return e;
+    for (int l = 0; l < nlev; ++l) {
+        const int p = 2 << l;
+        double* mass = (p == p_fine) ? a.mass : nullptr;
+        PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_geom<P_, D_>), dim3(B), dim3(NT), 0, s,
+                                                   a.coords[l], a.rho[l], a.D64[l], a.DT64[l],
+                                                   a.G64[l], a.G32[l], mass, a.X64[l],
+                                                   a.detmin + (long long)l * B));
+        if ((e = last()) != hipSuccess) return e;
+        PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_lines<P_, D_>), dim3(B), dim3(NT), 0, s,
+                                                   a.G64[l], a.X64[l], a.D64[l], a.smoother,
+                                                   a.cr64[l][0], a.cr64[l][1], a.cr64[l][2],
+                                                   a.cr32[l][0], a.cr32[l][1], a.cr32[l][2],
+                                                   a.pivot, a.cinv64, a.cinv32));
+        if ((e = last()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_setup_finish, dim3((B + 255) / 256), dim3(256), 0, s, a.detmin, a.pivot,
+                       nlev, B, info);
+    return last();
+}
+
+hipError_t launch_rhs(int dim, int p, int B, const Hier<double>& H64, const double* f,
+                      const double* g, double* b, double* tmp, hipStream_t s)
+{
+    PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_rhs<P_, D_>), dim3(B), dim3(NT), 0, s, H64, f,
+                                               g, b, tmp));
+    return last();
+}
+
+hipError_t launch_lift(int dim, int p, int B, const double* w, const double* g, double* u,
+                       hipStream_t s)
+{
+    PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_lift<P_, D_>), dim3(B), dim3(NT), 0, s, w, g, u));
+    return last();
+}
+
+hipError_t launch_line_coefs(int dim, int p, int B, const Hier<double>& H64, int smoother, int dir,
+                             double* lo, double* di, double* up, hipStream_t s)
+{
+    PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_line_coefs<P_, D_>), dim3(B), dim3(NT), 0, s,
+                                               H64, smoother, dir, lo, di, up));
+    return last();
+}
+
+}  // namespace pmg

@@ -1,0 +1,15 @@
+// pmg_solve_f64.hip -- instances of the solve kernel, FP64 inner cycle.
+#include "pmg_solve.hpp"
+
+namespace pmg {
+
+hipError_t launch_solve_f64(int dim, int p, bool f32, int B, const void* H, const SolveArgs& a,
+                        hipStream_t s)
+{
+    PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_solve<double, P_, D_>), dim3(B),
+                                                              dim3(NT), 0, s, *(const Hier<double>*)H,
+                                                              a));
+    return last();
+}
+
+}  // namespace pmg

@@ -1,0 +1,234 @@
+"""Thin ctypes binding of ``libpmg.so`` (C ABI in ``include/pmg.h``).
+
+Argument marshalling only: every computation happens in the library's HIP
+kernels.  Device arrays are torch tensors (PyTorch supplies device memory and
+streams); they are passed to the library as raw pointers together with the
+current HIP stream.  If ``libpmg.so`` is missing the binding raises; there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpmg.so")
+_lib = None
+
+PMG_OK, PMG_EINVAL, PMG_ENOMEM, PMG_EDEVICE = 0, -1, -2, -3
+PMG_EGEOM, PMG_ENAN, PMG_EBREAKDOWN, PMG_ENOTCONV, PMG_EPIVOT = -4, -5, -6, -7, -8
+PMG_F64, PMG_F32 = 0, 1
+PMG_SMOOTHER_GLL, PMG_SMOOTHER_FEM = 0, 1
+PMG_FGMRES, PMG_PCG, PMG_FCG = 0, 1, 2
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EGEOM", -5: "ENAN",
+                -6: "EBREAKDOWN", -7: "ENOTCONV", -8: "EPIVOT"}
+
+
+class pmg_desc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("p_fine", ctypes.c_int), ("batch", ctypes.c_int),
+                ("gamma", ctypes.c_int), ("m", ctypes.c_int), ("alpha", ctypes.c_double),
+                ("smoother", ctypes.c_int), ("inner_prec", ctypes.c_int),
+                ("krylov", ctypes.c_int), ("restart", ctypes.c_int),
+                ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double)]
+
+
+INFO_DTYPE = np.dtype([("status", np.int32), ("iterations", np.int32),
+                       ("relres", np.float64), ("min_detj", np.float64)])
+INFO_BYTES = INFO_DTYPE.itemsize  # 24, the layout of pmg_info
+
+
+class PmgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        dp = ctypes.POINTER(ctypes.c_double)
+        sig = {
+            "pmg_last_error": (ctypes.c_char_p, []),
+            "pmg_num_levels": (i, [ctypes.POINTER(pmg_desc), ctypes.POINTER(i)]),
+            "pmg_gll": (i, [i, dp, dp, dp]),
+            "pmg_interp": (i, [i, i, dp]),
+            "pmg_workspace_bytes": (i, [ctypes.POINTER(pmg_desc), ctypes.POINTER(ctypes.c_size_t)]),
+            "pmg_setup": (i, [ctypes.POINTER(pmg_desc), ctypes.POINTER(vp), vp, ctypes.c_size_t,
+                              vp, vp, ctypes.POINTER(vp)]),
+            "pmg_rhs": (i, [vp, vp, vp, vp, vp]),
+            "pmg_lift": (i, [vp, vp, vp, vp, vp]),
+            "pmg_apply": (i, [vp, i, i, vp, vp, vp]),
+            "pmg_restrict": (i, [vp, i, i, vp, vp, vp]),
+            "pmg_prolong_add": (i, [vp, i, i, vp, vp, vp]),
+            "pmg_line_solve": (i, [vp, i, i, i, vp, vp, vp]),
+            "pmg_line_smooth": (i, [vp, i, i, i, vp, vp, vp]),
+            "pmg_gamma_cycle": (i, [vp, i, vp, vp, vp]),
+            "pmg_solve": (i, [vp, vp, vp, vp, vp]),
+            "pmg_line_coefs": (i, [vp, i, i, vp, vp, vp, vp]),
+            "pmg_geom": (i, [vp, i, vp, vp, vp]),
+            "pmg_destroy": (i, [vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    """Names the binding expects the library to export."""
+    return ["pmg_last_error", "pmg_num_levels", "pmg_gll", "pmg_interp", "pmg_workspace_bytes",
+            "pmg_setup", "pmg_rhs", "pmg_lift", "pmg_apply", "pmg_restrict", "pmg_prolong_add",
+            "pmg_line_solve", "pmg_line_smooth", "pmg_gamma_cycle", "pmg_solve",
+            "pmg_line_coefs", "pmg_geom", "pmg_destroy"]
+
+
+def _check(rc):
+    if rc != PMG_OK:
+        raise PmgError(rc, lib().pmg_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(stream)
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ------------------------------------------------------------------ host calls
+
+def pmg_gll(p: int):
+    xi = np.zeros(p + 1)
+    rho = np.zeros(p + 1)
+    D = np.zeros((p + 1) * (p + 1))
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(lib().pmg_gll(p, xi.ctypes.data_as(dp), rho.ctypes.data_as(dp), D.ctypes.data_as(dp)))
+    return xi, rho, D.reshape(p + 1, p + 1)
+
+
+def pmg_interp(p_c: int, p_f: int):
+    J = np.zeros((p_f + 1) * (p_c + 1))
+    _check(lib().pmg_interp(p_c, p_f, J.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return J.reshape(p_f + 1, p_c + 1)
+
+
+def make_desc(dim=2, p_fine=16, batch=1, gamma=1, m=1, alpha=0.16, smoother=PMG_SMOOTHER_FEM,
+              inner_prec=PMG_F64, krylov=PMG_FGMRES, restart=30, max_iter=200, rtol=1e-10):
+    return pmg_desc(dim, p_fine, batch, gamma, m, alpha, smoother, inner_prec, krylov, restart,
+                    max_iter, rtol)
+
+
+def pmg_num_levels(desc: pmg_desc) -> int:
+    n = ctypes.c_int(0)
+    _check(lib().pmg_num_levels(ctypes.byref(desc), ctypes.byref(n)))
+    return n.value
+
+
+def pmg_workspace_bytes(desc: pmg_desc) -> int:
+    n = ctypes.c_size_t(0)
+    _check(lib().pmg_workspace_bytes(ctypes.byref(desc), ctypes.byref(n)))
+    return n.value
+
+
+# ------------------------------------------------------------------ device calls
+
+def pmg_setup(desc, coords, ws, info, stream=None):
+    """coords: list (coarsest first) of float64 device tensors (B, dim, N_l);
+    ws: uint8 device tensor of pmg_workspace_bytes(desc); info: uint8 device
+    tensor of B * INFO_BYTES.  Returns the handle (c_void_p)."""
+    n = len(coords)
+    arr = (ctypes.c_void_p * n)(*[c.data_ptr() for c in coords])
+    h = ctypes.c_void_p()
+    _check(lib().pmg_setup(ctypes.byref(desc), arr, _ptr(ws), ws.numel() * ws.element_size(),
+                           _ptr(info), _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def pmg_rhs(h, f, g, b, stream=None):
+    _check(lib().pmg_rhs(h, _ptr(f), _ptr(g), _ptr(b), _stream(stream)))
+
+
+def pmg_lift(h, w, g, u, stream=None):
+    _check(lib().pmg_lift(h, _ptr(w), _ptr(g), _ptr(u), _stream(stream)))
+
+
+def pmg_apply(h, level, prec, x, y, stream=None):
+    _check(lib().pmg_apply(h, level, prec, _ptr(x), _ptr(y), _stream(stream)))
+
+
+def pmg_restrict(h, level, prec, rf, rc, stream=None):
+    _check(lib().pmg_restrict(h, level, prec, _ptr(rf), _ptr(rc), _stream(stream)))
+
+
+def pmg_prolong_add(h, level, prec, ec, xf, stream=None):
+    _check(lib().pmg_prolong_add(h, level, prec, _ptr(ec), _ptr(xf), _stream(stream)))
+
+
+def pmg_line_solve(h, level, dir, prec, r, z, stream=None):
+    _check(lib().pmg_line_solve(h, level, dir, prec, _ptr(r), _ptr(z), _stream(stream)))
+
+
+def pmg_line_smooth(h, level, dir, prec, r, x, stream=None):
+    _check(lib().pmg_line_smooth(h, level, dir, prec, _ptr(r), _ptr(x), _stream(stream)))
+
+
+def pmg_gamma_cycle(h, prec, r, y, stream=None):
+    _check(lib().pmg_gamma_cycle(h, prec, _ptr(r), _ptr(y), _stream(stream)))
+
+
+def pmg_solve(h, b, x, info, stream=None):
+    _check(lib().pmg_solve(h, _ptr(b), _ptr(x), _ptr(info), _stream(stream)))
+
+
+def pmg_line_coefs(h, level, dir, lo, di, up, stream=None):
+    _check(lib().pmg_line_coefs(h, level, dir, _ptr(lo), _ptr(di), _ptr(up), _stream(stream)))
+
+
+def pmg_geom(h, level, G, mass=None, stream=None):
+    _check(lib().pmg_geom(h, level, _ptr(G), _ptr(mass), _stream(stream)))
+
+
+def pmg_destroy(h):
+    if h:
+        _check(lib().pmg_destroy(h))
+
+
+def info_to_numpy(info_tensor) -> np.ndarray:
+    """Copy a device pmg_info array to a numpy structured array."""
+    raw = info_tensor.detach().to("cpu").numpy().tobytes()
+    return np.frombuffer(raw, dtype=INFO_DTYPE).copy()
+
+
+class Solver:
+    """Convenience owner of one batch: workspace, info array and handle.
+
+    Device memory comes from torch; all work runs in the library."""
+
+    def __init__(self, desc: pmg_desc, coords, device="cuda"):
+        import torch
+        self.desc = desc
+        self.nlev = pmg_num_levels(desc)
+        self.ws = torch.empty(pmg_workspace_bytes(desc), dtype=torch.uint8, device=device)
+        self.info = torch.empty(desc.batch * INFO_BYTES, dtype=torch.uint8, device=device)
+        self.coords = [c.contiguous() for c in coords]
+        self.h = pmg_setup(desc, self.coords, self.ws, self.info)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            pmg_destroy(h)
+            self.h = None
+
+    def info_host(self):
+        return info_to_numpy(self.info)

@@ -1,0 +1,52 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol the header
+declares, and its host-side calls and argument checks behave (no GPU work)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2504_10710_amd import pmg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pmg.h")).read()
+    return sorted(set(re.findall(r"^(?:int|const char\*)\s+(pmg_\w+)\s*\(", src, re.M)))
+
+
+def test_library_exports_header_symbols():
+    L = pmg.lib()
+    names = _declared()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(pmg.exported_symbols()) == names
+
+
+def test_host_gll_matches_closed_forms():
+    xi, rho, D = pmg.pmg_gll(4)
+    np.testing.assert_allclose(xi, [-1, -np.sqrt(3 / 7), 0, np.sqrt(3 / 7), 1], atol=1e-15)
+    np.testing.assert_allclose(rho, [1 / 10, 49 / 90, 32 / 45, 49 / 90, 1 / 10], rtol=1e-14)
+    np.testing.assert_allclose(D @ xi**3, 3 * xi**2, atol=1e-12)
+    J = pmg.pmg_interp(4, 8)
+    xf = pmg.pmg_gll(8)[0]
+    np.testing.assert_allclose(J @ xi**4, xf**4, atol=1e-13)
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(dim=4), "dim"), (dict(p_fine=12), "p_fine"), (dict(dim=3, p_fine=128), "p_fine"),
+    (dict(gamma=0), "gamma"), (dict(alpha=-1.0), "alpha"), (dict(dim=3, smoother=1), "FEM"),
+    (dict(restart=0), "restart"), (dict(batch=0), "batch"), (dict(krylov=7), "Krylov")])
+def test_invalid_descriptions(kw, msg):
+    with pytest.raises(pmg.PmgError) as e:
+        pmg.pmg_workspace_bytes(pmg.make_desc(**kw))
+    assert e.value.code == pmg.PMG_EINVAL and msg in str(e.value)
+
+
+def test_workspace_scales_with_batch():
+    a = pmg.pmg_workspace_bytes(pmg.make_desc(p_fine=128, batch=1))
+    b = pmg.pmg_workspace_bytes(pmg.make_desc(p_fine=128, batch=8))
+    assert 7 * a < b < 9 * a
+    assert pmg.pmg_num_levels(pmg.make_desc(p_fine=128)) == 7
