@@ -97,7 +97,8 @@ typedef struct {
 
 /* Per-problem result of the device solve (written by pmg_solve). */
 typedef struct {
-    int status;       /* PMG_OK or a negative PMG_E* code */
+    int status;       /* PMG_OK or a negative PMG_E* code; 1 while a pooled solve
+                         is still running */
     int iterations;   /* outer Krylov iterations */
     double relres;    /* final true relative residual ||b - A x|| / ||b|| (FP64) */
     double min_detj;  /* minimum Jacobian determinant over all levels (setup) */
@@ -203,6 +204,89 @@ int pmg_geom(pmg_handle* h, int level, double* d_G, double* d_mass, pmg_stream_t
 
 /* Release the host handle (the workspace stays the caller's). */
 int pmg_destroy(pmg_handle* h);
+
+/* ------------------------------------------------------------------------
+ * Serving: solve pools and a continuous-batching server.
+ *
+ * A pool holds desc->batch solve slots of one shape.  Requests are admitted
+ * into free slots one batch at a time (their setup and right-hand side are
+ * built for those slots only); pmg_pool_step then advances every running
+ * slot by iters_per_step outer iterations in one launch (captured once into a
+ * HIP graph and replayed).  Each slot's Krylov and multigrid state stays in
+ * the workspace between steps, and a pooled solve performs exactly the
+ * arithmetic of pmg_solve on the same problem, so its result does not depend
+ * on how it was batched or split into steps.  Only FGMRES and the CG
+ * variants of pmg_solve are available (the same code).
+ * ------------------------------------------------------------------------ */
+typedef struct pmg_pool pmg_pool;
+
+/* Workspace bytes of a pool of desc->batch slots (includes per-slot input
+ * staging, right-hand side, solution and info). */
+int pmg_pool_workspace_bytes(const pmg_desc* desc, size_t* bytes);
+
+/* Create a pool in the caller's workspace; every slot starts idle.  The pool
+ * keeps using `stream` for its graph; iters_per_step >= 1. */
+int pmg_pool_create(const pmg_desc* desc, int iters_per_step, void* d_ws, size_t ws_bytes,
+                    pmg_stream_t stream, pmg_pool** out);
+
+/* Admit n requests into the idle slots slots[0..n-1] (host array).  Request i
+ * provides d_coords[i*n_levels + l] (level-l coordinates, dim x N_l doubles,
+ * layout of pmg_setup), d_f[i] and d_g[i] (finest-level N doubles: source
+ * and Dirichlet data).  The inputs are copied into the slot before the call's
+ * stream work completes; the caller may reuse them afterwards. */
+int pmg_pool_admit(pmg_pool* pool, int n, const int* slots, const double* const* d_coords,
+                   const double* const* d_f, const double* const* d_g, pmg_stream_t stream);
+
+/* Advance every running slot by up to iters_per_step outer iterations. */
+int pmg_pool_step(pmg_pool* pool, pmg_stream_t stream);
+
+/* Synchronise the stream and copy every slot's state to the host:
+ * slot_status[s] = 1 running, 2 idle, 0 converged, < 0 failed (PMG_E*);
+ * info (may be NULL) receives the per-slot pmg_info. */
+int pmg_pool_poll(pmg_pool* pool, int* slot_status, pmg_info* info, pmg_stream_t stream);
+
+/* Write the finished solution of `slot` (Dirichlet data on the boundary,
+ * u = w + v of Sec. 2.3) to d_u (N doubles) and make the slot idle. */
+int pmg_pool_take(pmg_pool* pool, int slot, double* d_u, pmg_stream_t stream);
+
+int pmg_pool_destroy(pmg_pool* pool);
+
+/* A server owns one pool per shape class and admits queued requests in
+ * arrival order whenever a slot of their class is free and the summed
+ * footprint (per-slot workspace bytes) of the admitted, unfinished requests
+ * stays within budget_bytes.  Each pmg_server_step admits, launches one step
+ * of every non-empty pool (each pool on its own stream, so the classes'
+ * kernels overlap on the device), waits, and retires finished requests. */
+#define PMG_SERVER_MAX_CLASSES 8
+typedef struct {
+    int n_classes;
+    pmg_desc classes[PMG_SERVER_MAX_CLASSES]; /* .batch = slots of the class */
+    int iters_per_step;
+    size_t budget_bytes;
+} pmg_server_desc;
+
+typedef struct {
+    int queued, running, finished;
+    size_t bytes_in_use;
+    long long steps;
+} pmg_server_stats;
+
+typedef struct pmg_server pmg_server;
+
+int pmg_server_workspace_bytes(const pmg_server_desc* desc, size_t* bytes);
+int pmg_server_create(const pmg_server_desc* desc, void* d_ws, size_t ws_bytes,
+                      pmg_server** out);
+/* Queue a request of class cls.  d_coords holds n_levels pointers (level
+ * order, coarsest first); the device inputs must stay valid until the request
+ * is admitted (its step).  The solution is written to d_u (N doubles). */
+int pmg_server_submit(pmg_server* srv, int cls, const double* const* d_coords,
+                      const double* d_f, const double* d_g, double* d_u, long long* ticket);
+/* One scheduling step; *n_done (may be NULL) receives the requests retired. */
+int pmg_server_step(pmg_server* srv, int* n_done);
+/* 1 if the request has finished (info filled, d_u written), 0 if pending. */
+int pmg_server_poll(pmg_server* srv, long long ticket, pmg_info* info);
+int pmg_server_stats_get(pmg_server* srv, pmg_server_stats* stats);
+int pmg_server_destroy(pmg_server* srv);
 
 #ifdef __cplusplus
 }

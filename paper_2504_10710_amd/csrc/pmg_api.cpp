@@ -205,6 +205,11 @@ struct pmg_handle {
     size_t o_cr64[MAX_LEVELS][3], o_cr32[MAX_LEVELS][3];
     size_t o_X[MAX_LEVELS], o_R[MAX_LEVELS], o_Tm[MAX_LEVELS], o_TR[MAX_LEVELS];
     size_t o_mass, o_W1, o_W2, o_TR64, o_V, o_Z, o_Hs, o_detmin, o_pivot, o_cinv64, o_cinv32;
+    size_t o_sstatus, o_state;
+    // serving pools only: per-slot input staging, right-hand side, solution,
+    // info, and the slot list of an admission
+    bool pool = false;
+    size_t o_in_coords[MAX_LEVELS], o_in_f, o_in_g, o_b, o_x, o_info, o_slots;
     long long w1, w2, nv, hs;
     size_t total;
     // host copies of the tables uploaded at setup (kept alive for async copies)
@@ -273,6 +278,20 @@ void plan(pmg_handle* h)
     h->o_pivot = L.take(sizeof(int) * (size_t)B);
     h->o_cinv64 = L.take(sizeof(double) * (size_t)B);
     h->o_cinv32 = L.take(sizeof(float) * (size_t)B);
+    h->o_sstatus = L.take(sizeof(int) * (size_t)B);
+    h->o_state = L.take(sizeof(SolveState) * (size_t)B);
+    if (h->pool) {
+        for (int l = 0; l < h->nlev; ++l) {
+            LevelShape s = level_shape(dim, l);
+            h->o_in_coords[l] = L.take(sizeof(double) * (size_t)B * dim * s.N);
+        }
+        h->o_in_f = L.take(sizeof(double) * (size_t)B * f.N);
+        h->o_in_g = L.take(sizeof(double) * (size_t)B * f.N);
+        h->o_b = L.take(sizeof(double) * (size_t)B * f.N);
+        h->o_x = L.take(sizeof(double) * (size_t)B * f.N);
+        h->o_info = L.take(sizeof(pmg_info) * (size_t)B);
+        h->o_slots = L.take(sizeof(int) * (size_t)B);
+    }
     h->total = L.take(0) + 256;
 }
 
@@ -370,28 +389,23 @@ int pmg_workspace_bytes(const pmg_desc* desc, size_t* bytes)
     return PMG_OK;
 }
 
-int pmg_setup(const pmg_desc* desc, const double* const* d_coords, void* d_ws, size_t ws_bytes,
-              pmg_info* d_info, pmg_stream_t stream, pmg_handle** out)
+static int init_handle(const pmg_desc* desc, void* d_ws, size_t ws_bytes, bool pool,
+                       hipStream_t s, pmg_handle** out)
 {
     int rc = check_desc(desc);
     if (rc) return rc;
-    if (!d_coords || !d_ws || !d_info || !out) return fail(PMG_EINVAL, "NULL argument");
-    hipStream_t s = (hipStream_t)stream;
+    if (!d_ws || !out) return fail(PMG_EINVAL, "NULL argument");
     pmg_handle* h = new pmg_handle();
     h->d = *desc;
     h->nlev = ilog2(desc->p_fine);
     h->f32 = desc->inner_prec == PMG_F32;
+    h->pool = pool;
     plan(h);
     if (ws_bytes < h->total) {
         size_t need = h->total;
         delete h;
         return fail(PMG_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, need);
     }
-    for (int l = 0; l < h->nlev; ++l)
-        if (!d_coords[l]) {
-            delete h;
-            return fail(PMG_EINVAL, "coordinates of level %d are NULL", l);
-        }
     h->ws = (char*)d_ws;
     h->ws_bytes = ws_bytes;
     const int dim = desc->dim;
@@ -464,11 +478,15 @@ int pmg_setup(const pmg_desc* desc, const double* const* d_coords, void* d_ws, s
     fill_hier<float>(h, h->H32, true);
     // FP64 views used by the FP64-only operations of an FP32 handle
     h->H64.lev[h->nlev - 1].TR = (double*)(h->ws + h->o_TR64);
+    *out = h;
+    return PMG_OK;
+}
 
-    SetupArgs a;
+static void setup_args(pmg_handle* h, SetupArgs& a)
+{
+    const int dim = h->d.dim;
     memset(&a, 0, sizeof(a));
     for (int l = 0; l < h->nlev; ++l) {
-        a.coords[l] = d_coords[l];
         for (int k = 0; k < 3; ++k) {
             a.cr64[l][k] = k < dim ? (double*)(h->ws + h->o_cr64[l][k]) : nullptr;
             a.cr32[l][k] = (k < dim && h->f32) ? (float*)(h->ws + h->o_cr32[l][k]) : nullptr;
@@ -483,10 +501,29 @@ int pmg_setup(const pmg_desc* desc, const double* const* d_coords, void* d_ws, s
     a.mass = (double*)(h->ws + h->o_mass);
     a.detmin = (double*)(h->ws + h->o_detmin);
     a.pivot = (int*)(h->ws + h->o_pivot);
+    a.sstatus = (int*)(h->ws + h->o_sstatus);
     a.cinv64 = (double*)(h->ws + h->o_cinv64);
     a.cinv32 = (float*)(h->ws + h->o_cinv32);
-    a.smoother = desc->smoother;
-    e = launch_setup(dim, desc->p_fine, h->nlev, desc->batch, a, d_info, s);
+    a.smoother = h->d.smoother;
+}
+
+int pmg_setup(const pmg_desc* desc, const double* const* d_coords, void* d_ws, size_t ws_bytes,
+              pmg_info* d_info, pmg_stream_t stream, pmg_handle** out)
+{
+    if (!d_coords || !d_info || !out) return fail(PMG_EINVAL, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    pmg_handle* h = nullptr;
+    int rc = init_handle(desc, d_ws, ws_bytes, false, s, &h);
+    if (rc) return rc;
+    for (int l = 0; l < h->nlev; ++l)
+        if (!d_coords[l]) {
+            delete h;
+            return fail(PMG_EINVAL, "coordinates of level %d are NULL", l);
+        }
+    SetupArgs a;
+    setup_args(h, a);
+    for (int l = 0; l < h->nlev; ++l) a.coords[l] = d_coords[l];
+    hipError_t e = launch_setup(h->d.dim, h->d.p_fine, h->nlev, h->d.batch, a, d_info, s);
     if (e != hipSuccess) {
         delete h;
         return hip_fail(e, "setup kernels");
@@ -637,6 +674,11 @@ int pmg_solve(pmg_handle* h, const double* d_b, double* d_x, pmg_info* d_info, p
     a.max_iter = h->d.max_iter;
     a.krylov = h->d.krylov;
     a.rtol = h->d.rtol;
+    a.st = (SolveState*)(h->ws + h->o_state);
+    a.sstatus = (const int*)(h->ws + h->o_sstatus);
+    a.slots = nullptr;
+    a.budget = h->d.max_iter;
+    a.fresh = 1;
     hipError_t e = launch_solve(h->d.dim, h->d.p_fine, h->f32, h->d.batch, hier_of(h, h->f32), a,
                                 (hipStream_t)stream);
     return e == hipSuccess ? PMG_OK : hip_fail(e, "pmg_solve");
@@ -674,6 +716,428 @@ int pmg_geom(pmg_handle* h, int level, double* d_G, double* d_mass, pmg_stream_t
 int pmg_destroy(pmg_handle* h)
 {
     delete h;
+    return PMG_OK;
+}
+
+
+// ------------------------------------------------------------------ pools
+
+struct pmg_pool {
+    pmg_handle* h = nullptr;
+    int iters = 1;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t graph_stream = nullptr;
+    std::vector<std::vector<int>> pending;   // slot lists whose async upload may be in flight
+};
+
+static SolveArgs pool_solve_args(pmg_pool* P)
+{
+    pmg_handle* h = P->h;
+    SolveArgs a;
+    a.b = (const double*)(h->ws + h->o_b);
+    a.x = (double*)(h->ws + h->o_x);
+    a.V = (double*)(h->ws + h->o_V);
+    a.Z = (double*)(h->ws + h->o_Z);
+    a.Hs = (double*)(h->ws + h->o_Hs);
+    a.TR64 = (double*)(h->ws + h->o_TR64);
+    a.info = (pmg_info*)(h->ws + h->o_info);
+    a.nv = h->nv;
+    a.hs = h->hs;
+    a.restart = h->d.restart;
+    a.max_iter = h->d.max_iter;
+    a.krylov = h->d.krylov;
+    a.rtol = h->d.rtol;
+    a.st = (SolveState*)(h->ws + h->o_state);
+    a.sstatus = (const int*)(h->ws + h->o_sstatus);
+    a.slots = nullptr;
+    a.budget = P->iters;
+    a.fresh = 0;
+    return a;
+}
+
+int pmg_pool_workspace_bytes(const pmg_desc* desc, size_t* bytes)
+{
+    int rc = check_desc(desc);
+    if (rc) return rc;
+    if (!bytes) return fail(PMG_EINVAL, "bytes is NULL");
+    pmg_handle tmp;
+    tmp.d = *desc;
+    tmp.nlev = ilog2(desc->p_fine);
+    tmp.f32 = desc->inner_prec == PMG_F32;
+    tmp.pool = true;
+    plan(&tmp);
+    *bytes = tmp.total;
+    return PMG_OK;
+}
+
+int pmg_pool_create(const pmg_desc* desc, int iters_per_step, void* d_ws, size_t ws_bytes,
+                    pmg_stream_t stream, pmg_pool** out)
+{
+    if (!out) return fail(PMG_EINVAL, "out is NULL");
+    if (iters_per_step < 1) return fail(PMG_EINVAL, "iters_per_step must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    pmg_handle* h = nullptr;
+    int rc = init_handle(desc, d_ws, ws_bytes, true, s, &h);
+    if (rc) return rc;
+    hipError_t e = launch_pool_idle((SolveState*)(h->ws + h->o_state), desc->batch, s);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "pool init");
+    }
+    pmg_pool* P = new pmg_pool();
+    P->h = h;
+    P->iters = iters_per_step;
+    *out = P;
+    return PMG_OK;
+}
+
+int pmg_pool_admit(pmg_pool* P, int n, const int* slots, const double* const* d_coords,
+                   const double* const* d_f, const double* const* d_g, pmg_stream_t stream)
+{
+    if (!P) return fail(PMG_EINVAL, "pool is NULL");
+    pmg_handle* h = P->h;
+    const int B = h->d.batch, dim = h->d.dim;
+    if (n == 0) return PMG_OK;
+    if (n < 0 || n > B || !slots || !d_coords || !d_f || !d_g)
+        return fail(PMG_EINVAL, "bad admission arguments");
+    hipStream_t s = (hipStream_t)stream;
+    const int N = level_shape(dim, h->nlev - 1).N;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+        const int b = slots[i];
+        if (b < 0 || b >= B) return fail(PMG_EINVAL, "slot %d out of range", b);
+        for (int l = 0; l < h->nlev && e == hipSuccess; ++l) {
+            const size_t bytes = sizeof(double) * dim * level_shape(dim, l).N;
+            if (!d_coords[(size_t)i * h->nlev + l]) return fail(PMG_EINVAL, "NULL coordinates");
+            e = hipMemcpyAsync(h->ws + h->o_in_coords[l] + bytes * b, d_coords[(size_t)i * h->nlev + l],
+                               bytes, hipMemcpyDeviceToDevice, s);
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h->ws + h->o_in_f + sizeof(double) * N * b, d_f[i], sizeof(double) * N,
+                               hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h->ws + h->o_in_g + sizeof(double) * N * b, d_g[i], sizeof(double) * N,
+                               hipMemcpyDeviceToDevice, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "admission copies");
+    P->pending.emplace_back(slots, slots + n);
+    const int* hs = P->pending.back().data();
+    int* dslots = (int*)(h->ws + h->o_slots);
+    // each admission gets its own span of the device slot list
+    static_assert(sizeof(int) == 4, "int");
+    e = hipMemcpyAsync(dslots, hs, sizeof(int) * n, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "slot list upload");
+    SetupArgs a;
+    setup_args(h, a);
+    for (int l = 0; l < h->nlev; ++l) a.coords[l] = (const double*)(h->ws + h->o_in_coords[l]);
+    a.slots = dslots;
+    a.nslots = n;
+    pmg_info* info = (pmg_info*)(h->ws + h->o_info);
+    e = launch_setup(dim, h->d.p_fine, h->nlev, B, a, info, s);
+    if (e == hipSuccess)
+        e = launch_rhs(dim, h->d.p_fine, B, h->H64, (const double*)(h->ws + h->o_in_f),
+                       (const double*)(h->ws + h->o_in_g), (double*)(h->ws + h->o_b),
+                       (double*)(h->ws + h->o_V), s, dslots, n);
+    if (e == hipSuccess)
+        e = launch_pool_start(dslots, n, (const int*)(h->ws + h->o_sstatus),
+                              (SolveState*)(h->ws + h->o_state), info, s);
+    // the slot list is read by the kernels above before any later upload
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    P->pending.clear();
+    return e == hipSuccess ? PMG_OK : hip_fail(e, "admission kernels");
+}
+
+int pmg_pool_step(pmg_pool* P, pmg_stream_t stream)
+{
+    if (!P) return fail(PMG_EINVAL, "pool is NULL");
+    pmg_handle* h = P->h;
+    hipStream_t s = (hipStream_t)stream;
+    SolveArgs a = pool_solve_args(P);
+    const void* H = hier_of(h, h->f32);
+    hipError_t e;
+    if (s && !P->exec) {
+        // capture the step once; replays reuse it
+        e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t el = launch_solve(h->d.dim, h->d.p_fine, h->f32, h->d.batch, H, a, s);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(s, &g);
+            if (el == hipSuccess && e == hipSuccess && g) {
+                e = hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0);
+                if (e == hipSuccess) {
+                    P->graph = g;
+                    P->graph_stream = s;
+                } else {
+                    hipGraphDestroy(g);
+                    P->exec = nullptr;
+                }
+            } else if (g) {
+                hipGraphDestroy(g);
+            }
+        }
+        (void)hipGetLastError();
+    }
+    if (P->exec)
+        e = hipGraphLaunch(P->exec, s);
+    else
+        e = launch_solve(h->d.dim, h->d.p_fine, h->f32, h->d.batch, H, a, s);
+    return e == hipSuccess ? PMG_OK : hip_fail(e, "pool step");
+}
+
+int pmg_pool_poll(pmg_pool* P, int* slot_status, pmg_info* info, pmg_stream_t stream)
+{
+    if (!P || !slot_status) return fail(PMG_EINVAL, "NULL argument");
+    pmg_handle* h = P->h;
+    const int B = h->d.batch;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<SolveState> st(B);
+    hipError_t e = hipMemcpyAsync(st.data(), h->ws + h->o_state, sizeof(SolveState) * B,
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && info)
+        e = hipMemcpyAsync(info, h->ws + h->o_info, sizeof(pmg_info) * B, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "pool poll");
+    for (int b = 0; b < B; ++b) slot_status[b] = st[b].status;
+    return PMG_OK;
+}
+
+int pmg_pool_take(pmg_pool* P, int slot, double* d_u, pmg_stream_t stream)
+{
+    if (!P || !d_u) return fail(PMG_EINVAL, "NULL argument");
+    pmg_handle* h = P->h;
+    if (slot < 0 || slot >= h->d.batch) return fail(PMG_EINVAL, "slot out of range");
+    hipError_t e = launch_pool_take(h->d.dim, h->d.p_fine, slot, (const double*)(h->ws + h->o_x),
+                                    (const double*)(h->ws + h->o_in_g), d_u,
+                                    (SolveState*)(h->ws + h->o_state), (hipStream_t)stream);
+    return e == hipSuccess ? PMG_OK : hip_fail(e, "pool take");
+}
+
+int pmg_pool_destroy(pmg_pool* P)
+{
+    if (!P) return PMG_OK;
+    if (P->exec) hipGraphExecDestroy(P->exec);
+    if (P->graph) hipGraphDestroy(P->graph);
+    delete P->h;
+    delete P;
+    return PMG_OK;
+}
+
+// ------------------------------------------------------------------ server
+
+struct pmg_server {
+    pmg_server_desc d;
+    struct Req {
+        long long ticket;
+        int cls;
+        std::vector<const double*> coords;
+        const double* f;
+        const double* g;
+        double* u;
+        int slot = -1;
+        bool done = false;
+        pmg_info info;
+    };
+    struct Class {
+        pmg_pool* pool = nullptr;
+        hipStream_t stream = nullptr;
+        size_t footprint = 0;        // bytes per slot
+        std::vector<long long> slot_req;   // ticket per slot, -1 free
+        int running = 0;
+        int nlev = 0;
+    };
+    Class cls[PMG_SERVER_MAX_CLASSES];
+    std::vector<Req> reqs;           // indexed by ticket
+    std::vector<long long> queue;    // arrival order
+    size_t in_use = 0;
+    long long steps = 0;
+    int finished = 0;
+};
+
+static int check_server_desc(const pmg_server_desc* d)
+{
+    if (!d) return fail(PMG_EINVAL, "desc is NULL");
+    if (d->n_classes < 1 || d->n_classes > PMG_SERVER_MAX_CLASSES)
+        return fail(PMG_EINVAL, "n_classes must be in [1, %d]", PMG_SERVER_MAX_CLASSES);
+    if (d->iters_per_step < 1) return fail(PMG_EINVAL, "iters_per_step must be >= 1");
+    for (int c = 0; c < d->n_classes; ++c) {
+        int rc = check_desc(&d->classes[c]);
+        if (rc) return rc;
+    }
+    return PMG_OK;
+}
+
+int pmg_server_workspace_bytes(const pmg_server_desc* d, size_t* bytes)
+{
+    int rc = check_server_desc(d);
+    if (rc) return rc;
+    if (!bytes) return fail(PMG_EINVAL, "bytes is NULL");
+    size_t tot = 0;
+    for (int c = 0; c < d->n_classes; ++c) {
+        size_t b = 0;
+        if ((rc = pmg_pool_workspace_bytes(&d->classes[c], &b))) return rc;
+        tot += (b + 4095) & ~size_t(4095);
+    }
+    *bytes = tot;
+    return PMG_OK;
+}
+
+int pmg_server_create(const pmg_server_desc* d, void* d_ws, size_t ws_bytes, pmg_server** out)
+{
+    int rc = check_server_desc(d);
+    if (rc) return rc;
+    if (!d_ws || !out) return fail(PMG_EINVAL, "NULL argument");
+    size_t need = 0;
+    pmg_server_workspace_bytes(d, &need);
+    if (ws_bytes < need) return fail(PMG_ENOMEM, "server workspace too small: %zu < %zu", ws_bytes, need);
+    pmg_server* S = new pmg_server();
+    S->d = *d;
+    char* base = (char*)d_ws;
+    for (int c = 0; c < d->n_classes; ++c) {
+        size_t b = 0;
+        pmg_pool_workspace_bytes(&d->classes[c], &b);
+        pmg_server::Class& C = S->cls[c];
+        hipError_t e = hipStreamCreateWithFlags(&C.stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            pmg_server_destroy(S);
+            return hip_fail(e, "server stream");
+        }
+        if ((rc = pmg_pool_create(&d->classes[c], d->iters_per_step, base, b, (pmg_stream_t)C.stream,
+                                  &C.pool))) {
+            pmg_server_destroy(S);
+            return rc;
+        }
+        base += (b + 4095) & ~size_t(4095);
+        C.footprint = b / d->classes[c].batch;
+        C.slot_req.assign(d->classes[c].batch, -1);
+        C.nlev = ilog2(d->classes[c].p_fine);
+    }
+    *out = S;
+    return PMG_OK;
+}
+
+int pmg_server_submit(pmg_server* S, int c, const double* const* d_coords, const double* d_f,
+                      const double* d_g, double* d_u, long long* ticket)
+{
+    if (!S || !d_coords || !d_f || !d_g || !d_u || !ticket) return fail(PMG_EINVAL, "NULL argument");
+    if (c < 0 || c >= S->d.n_classes) return fail(PMG_EINVAL, "class %d out of range", c);
+    pmg_server::Req r;
+    r.ticket = (long long)S->reqs.size();
+    r.cls = c;
+    r.coords.assign(d_coords, d_coords + S->cls[c].nlev);
+    r.f = d_f;
+    r.g = d_g;
+    r.u = d_u;
+    memset(&r.info, 0, sizeof(r.info));
+    S->reqs.push_back(r);
+    S->queue.push_back(r.ticket);
+    *ticket = r.ticket;
+    return PMG_OK;
+}
+
+int pmg_server_step(pmg_server* S, int* n_done)
+{
+    if (!S) return fail(PMG_EINVAL, "server is NULL");
+    int rc;
+    const int nc = S->d.n_classes;
+    // 1. admissions in arrival order, within slots and the byte budget
+    std::vector<std::vector<int>> slots(nc);
+    std::vector<std::vector<const double*>> coords(nc), fs(nc), gs(nc);
+    std::vector<long long> keep;
+    for (long long t : S->queue) {
+        pmg_server::Req& r = S->reqs[t];
+        pmg_server::Class& C = S->cls[r.cls];
+        int free_slot = -1;
+        if (S->in_use + C.footprint <= S->d.budget_bytes) {
+            for (int b = 0; b < (int)C.slot_req.size(); ++b)
+                if (C.slot_req[b] < 0) { free_slot = b; break; }
+        }
+        if (free_slot < 0) { keep.push_back(t); continue; }
+        C.slot_req[free_slot] = t;
+        r.slot = free_slot;
+        S->in_use += C.footprint;
+        C.running++;
+        slots[r.cls].push_back(free_slot);
+        coords[r.cls].insert(coords[r.cls].end(), r.coords.begin(), r.coords.end());
+        fs[r.cls].push_back(r.f);
+        gs[r.cls].push_back(r.g);
+    }
+    S->queue.swap(keep);
+    for (int c = 0; c < nc; ++c)
+        if (!slots[c].empty() &&
+            (rc = pmg_pool_admit(S->cls[c].pool, (int)slots[c].size(), slots[c].data(),
+                                 coords[c].data(), fs[c].data(), gs[c].data(),
+                                 (pmg_stream_t)S->cls[c].stream)))
+            return rc;
+    // 2. one step of every class with running slots (classes overlap on the device)
+    for (int c = 0; c < nc; ++c)
+        if (S->cls[c].running > 0 &&
+            (rc = pmg_pool_step(S->cls[c].pool, (pmg_stream_t)S->cls[c].stream)))
+            return rc;
+    S->steps++;
+    // 3. retire finished requests
+    int done = 0;
+    for (int c = 0; c < nc; ++c) {
+        pmg_server::Class& C = S->cls[c];
+        if (C.running == 0) continue;
+        const int B = (int)C.slot_req.size();
+        std::vector<int> st(B);
+        std::vector<pmg_info> inf(B);
+        if ((rc = pmg_pool_poll(C.pool, st.data(), inf.data(), (pmg_stream_t)C.stream))) return rc;
+        bool took = false;
+        for (int b = 0; b < B; ++b) {
+            if (C.slot_req[b] < 0 || st[b] == ST_RUNNING || st[b] == ST_IDLE) continue;
+            pmg_server::Req& r = S->reqs[C.slot_req[b]];
+            if ((rc = pmg_pool_take(C.pool, b, r.u, (pmg_stream_t)C.stream))) return rc;
+            took = true;
+            r.info = inf[b];
+            r.info.status = st[b];
+            r.done = true;
+            C.slot_req[b] = -1;
+            C.running--;
+            S->in_use -= C.footprint;
+            S->finished++;
+            ++done;
+        }
+        if (took) {
+            hipError_t e = hipStreamSynchronize(C.stream);
+            if (e != hipSuccess) return hip_fail(e, "server retire");
+        }
+    }
+    if (n_done) *n_done = done;
+    return PMG_OK;
+}
+
+int pmg_server_poll(pmg_server* S, long long ticket, pmg_info* info)
+{
+    if (!S || ticket < 0 || ticket >= (long long)S->reqs.size()) return fail(PMG_EINVAL, "bad ticket");
+    const pmg_server::Req& r = S->reqs[ticket];
+    if (!r.done) return 0;
+    if (info) *info = r.info;
+    return 1;
+}
+
+int pmg_server_stats_get(pmg_server* S, pmg_server_stats* st)
+{
+    if (!S || !st) return fail(PMG_EINVAL, "NULL argument");
+    st->queued = (int)S->queue.size();
+    int running = 0;
+    for (int c = 0; c < S->d.n_classes; ++c) running += S->cls[c].running;
+    st->running = running;
+    st->finished = S->finished;
+    st->bytes_in_use = S->in_use;
+    st->steps = S->steps;
+    return PMG_OK;
+}
+
+int pmg_server_destroy(pmg_server* S)
+{
+    if (!S) return PMG_OK;
+    for (int c = 0; c < PMG_SERVER_MAX_CLASSES; ++c) {
+        if (S->cls[c].pool) pmg_pool_destroy(S->cls[c].pool);
+        if (S->cls[c].stream) hipStreamDestroy(S->cls[c].stream);
+    }
+    delete S;
     return PMG_OK;
 }
 

@@ -13,6 +13,9 @@ struct SetupArgs {
     const double* coords[MAX_LEVELS];   // caller's coordinates per level
     double* detmin;                     // [nlev][B]
     int* pivot;                         // [B] nonzero if a zero pivot was met
+    int* sstatus;                       // [B] setup status
+    const int* slots;                   // nullable: workgroup -> problem index
+    int nslots;                         // workgroups to launch (B without slots)
     double* cr64[MAX_LEVELS][3];        // FP64 line factors per level and axis
     float* cr32[MAX_LEVELS][3];         // FP32 copies (nullptr if unused)
     double* G64[MAX_LEVELS];
@@ -27,7 +30,25 @@ struct SetupArgs {
     int smoother;
 };
 
+// Resumable state of one problem's outer solve (kept in the workspace, so a
+// solve can be split over several launches with identical arithmetic).
+enum { ST_RUNNING = 1, ST_IDLE = 2 };
+enum { PH_INIT = 0, PH_RESTART = 1, PH_ARNOLDI = 2 };
+struct SolveState {
+    int status;   // ST_RUNNING, ST_IDLE, or the final PMG_OK / PMG_E* code
+    int it;       // outer iterations so far
+    int j;        // FGMRES: position inside the current restart cycle
+    int phase;    // PH_*
+    double bn;    // ||b||
+    double rz;    // PCG: (r, z); FCG: (p, q) of the current direction
+};
+
 struct SolveArgs {
+    SolveState* st;     // [B] per-problem state
+    const int* sstatus; // [B] setup status (PMG_OK, PMG_EGEOM, PMG_EPIVOT)
+    const int* slots;   // nullable: workgroup -> problem index
+    int budget;         // outer iterations allowed in this launch
+    int fresh;          // 1: (re)start every problem from the setup status
     const double* b;
     double* x;
     double* V;          // [B][nv][N]
@@ -44,7 +65,8 @@ struct SolveArgs {
 hipError_t launch_setup(int dim, int p_fine, int nlev, int B, const SetupArgs& a,
                         pmg_info* info, hipStream_t s);
 hipError_t launch_rhs(int dim, int p, int B, const Hier<double>& H64, const double* f,
-                      const double* g, double* b, double* tmp, hipStream_t s);
+                      const double* g, double* b, double* tmp, hipStream_t s,
+                      const int* slots = nullptr, int nslots = 0);
 hipError_t launch_lift(int dim, int p, int B, const double* w, const double* g, double* u,
                        hipStream_t s);
 hipError_t launch_apply(int dim, int p, bool f32, int B, const void* H, const void* x,
@@ -59,6 +81,7 @@ hipError_t launch_line_smooth(int dim, int p, bool f32, int B, const void* H, in
                               const void* r, void* x, hipStream_t s);
 hipError_t launch_cycle(int dim, int p, bool f32, int B, const void* H, const void* r,
                         void* y, hipStream_t s);
+// grid = B workgroups (problem b = workgroup, or a.slots[workgroup])
 hipError_t launch_solve_f64(int dim, int p, bool f32, int B, const void* H, const SolveArgs& a,
                             hipStream_t s);
 hipError_t launch_solve_f32(int dim, int p, bool f32, int B, const void* H, const SolveArgs& a,
@@ -68,6 +91,11 @@ inline hipError_t launch_solve(int dim, int p, bool f32, int B, const void* H, c
 {
     return f32 ? launch_solve_f32(dim, p, f32, B, H, a, s) : launch_solve_f64(dim, p, f32, B, H, a, s);
 }
+hipError_t launch_pool_start(const int* slots, int n, const int* sstatus, SolveState* st,
+                             pmg_info* info, hipStream_t s);
+hipError_t launch_pool_idle(SolveState* st, int B, hipStream_t s);
+hipError_t launch_pool_take(int dim, int p, int slot, const double* w, const double* g, double* u,
+                            SolveState* st, hipStream_t s);
 hipError_t launch_line_coefs(int dim, int p, int B, const Hier<double>& H64, int smoother,
                              int dir, double* lo, double* di, double* up, hipStream_t s);
 

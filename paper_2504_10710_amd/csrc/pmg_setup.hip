@@ -23,12 +23,14 @@ __global__ void __launch_bounds__(NT) k_geom(const double* __restrict__ coords,
                                              const double* __restrict__ DT,
                                              double* __restrict__ G, float* __restrict__ G32,
                                              double* __restrict__ mass, double* __restrict__ X64,
-                                             double* __restrict__ detmin)
+                                             double* __restrict__ detmin, const int* slots,
+                                             int* pivot)
 {
     using S = Shape<P, DIM>;
     constexpr int n1 = S::n1, N = S::N, NC = S::NC;
     __shared__ double red[NT];
-    const long long b = blockIdx.x;
+    const long long b = slots ? slots[blockIdx.x] : blockIdx.x;
+    if (pivot && threadIdx.x == 0) pivot[b] = 0;
     const double* X = coords + b * DIM * N;
     double* Gb = G + b * NC * N;
     double dmin = INFINITY;
@@ -206,11 +208,11 @@ __global__ void __launch_bounds__(NT) k_lines(const double* __restrict__ G,
                                               const double* __restrict__ D, int smoother,
                                               double* cr0, double* cr1, double* cr2, float* f0,
                                               float* f1, float* f2, int* pivot,
-                                              double* cinv64, float* cinv32)
+                                              double* cinv64, float* cinv32, const int* slots)
 {
     using S = Shape<P, DIM>;
     constexpr int n = S::n, NL = S::NL, CRW = S::CRW, N = S::N, NC = S::NC;
-    const long long b = blockIdx.x;
+    const long long b = slots ? slots[blockIdx.x] : blockIdx.x;
     const double* Gb = G + b * NC * N;
     const double* Xb = X64 + b * DIM * N;
     int bad = 0;
@@ -279,10 +281,12 @@ __global__ void __launch_bounds__(NT) k_lines(const double* __restrict__ G,
 }
 
 __global__ void k_setup_finish(const double* __restrict__ detmin, const int* __restrict__ pivot,
-                               int nlev, int B, pmg_info* __restrict__ info)
+                               int nlev, int B, int n, const int* slots, pmg_info* __restrict__ info,
+                               int* sstatus)
 {
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int b = slots ? slots[i] : i;
     double m = INFINITY;
     for (int l = 0; l < nlev; ++l) m = fmin(m, detmin[(long long)l * B + b]);
     pmg_info r;
@@ -291,6 +295,7 @@ __global__ void k_setup_finish(const double* __restrict__ detmin, const int* __r
     r.relres = NAN;
     r.status = !(m > 0.0) ? PMG_EGEOM : (pivot[b] ? PMG_EPIVOT : PMG_OK);
     info[b] = r;
+    sstatus[b] = r.status;
 }
 
 // ================================================================== RHS
@@ -299,11 +304,11 @@ __global__ void k_setup_finish(const double* __restrict__ detmin, const int* __r
 template <int P, int DIM>
 __global__ void __launch_bounds__(NT) k_rhs(Hier<double> H, const double* __restrict__ f,
                                             const double* __restrict__ g, double* __restrict__ bo,
-                                            double* __restrict__ tmp)
+                                            double* __restrict__ tmp, const int* slots)
 {
     using S = Shape<P, DIM>;
     constexpr int N = S::N;
-    const long long b = blockIdx.x;
+    const long long b = slots ? slots[blockIdx.x] : blockIdx.x;
     const LevelData<double>& L = H.lev[S::LEV];
     double* v = tmp + b * N;
     for (int q = threadIdx.x; q < N; q += NT) v[q] = is_boundary<P, DIM>(q) ? g[b * N + q] : 0.0;
@@ -347,36 +352,83 @@ __global__ void __launch_bounds__(NT) k_line_coefs(Hier<double> H, int smoother,
 }
 
 
+// ================================================================== serving pools
+
+// Mark the listed slots as fresh solves (their setup status decides).
+__global__ void k_pool_start(const int* __restrict__ slots, int n, const int* __restrict__ sstatus,
+                             SolveState* __restrict__ st, pmg_info* __restrict__ info)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int b = slots[i];
+    SolveState s;
+    s.status = sstatus[b] == PMG_OK ? ST_RUNNING : sstatus[b];
+    s.it = 0;
+    s.j = 0;
+    s.phase = PH_INIT;
+    s.bn = 0.0;
+    s.rz = 0.0;
+    st[b] = s;
+    info[b].status = s.status;
+    info[b].iterations = 0;
+    info[b].relres = NAN;
+}
+
+__global__ void k_pool_idle(SolveState* __restrict__ st, int B)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    st[b].status = ST_IDLE;
+}
+
+// u = w inside, g on the boundary, for one slot; the slot becomes idle.
+template <int P, int DIM>
+__global__ void __launch_bounds__(NT) k_pool_take(int slot, const double* __restrict__ w,
+                                                  const double* __restrict__ g,
+                                                  double* __restrict__ u, SolveState* st)
+{
+    constexpr int N = Shape<P, DIM>::N;
+    const long long b = slot;
+    for (int q = threadIdx.x; q < N; q += NT)
+        u[q] = is_boundary<P, DIM>(q) ? g[b * N + q] : w[b * N + q];
+    if (threadIdx.x == 0) st[b].status = ST_IDLE;
+}
+
 hipError_t launch_setup(int dim, int p_fine, int nlev, int B, const SetupArgs& a, pmg_info* info,
                         hipStream_t s)
 {
-    hipError_t e = hipMemsetAsync(a.pivot, 0, sizeof(int) * B, s);
-    if (e != hipSuccess) return e;
+    hipError_t e;
+    const int nb = a.slots ? a.nslots : B;
+    if (nb <= 0) return hipSuccess;
     for (int l = 0; l < nlev; ++l) {
         const int p = 2 << l;
         double* mass = (p == p_fine) ? a.mass : nullptr;
-        PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_geom<P_, D_>), dim3(B), dim3(NT), 0, s,
+        PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_geom<P_, D_>), dim3(nb), dim3(NT), 0, s,
                                                    a.coords[l], a.rho[l], a.D64[l], a.DT64[l],
                                                    a.G64[l], a.G32[l], mass, a.X64[l],
-                                                   a.detmin + (long long)l * B));
+                                                   a.detmin + (long long)l * B, a.slots,
+                                                   l == 0 ? a.pivot : nullptr));
         if ((e = last()) != hipSuccess) return e;
-        PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_lines<P_, D_>), dim3(B), dim3(NT), 0, s,
+        PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_lines<P_, D_>), dim3(nb), dim3(NT), 0, s,
                                                    a.G64[l], a.X64[l], a.D64[l], a.smoother,
                                                    a.cr64[l][0], a.cr64[l][1], a.cr64[l][2],
                                                    a.cr32[l][0], a.cr32[l][1], a.cr32[l][2],
-                                                   a.pivot, a.cinv64, a.cinv32));
+                                                   a.pivot, a.cinv64, a.cinv32, a.slots));
         if ((e = last()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_setup_finish, dim3((B + 255) / 256), dim3(256), 0, s, a.detmin, a.pivot,
-                       nlev, B, info);
+    hipLaunchKernelGGL(k_setup_finish, dim3((nb + 255) / 256), dim3(256), 0, s, a.detmin, a.pivot,
+                       nlev, B, nb, a.slots, info, a.sstatus);
     return last();
 }
 
 hipError_t launch_rhs(int dim, int p, int B, const Hier<double>& H64, const double* f,
-                      const double* g, double* b, double* tmp, hipStream_t s)
+                      const double* g, double* b, double* tmp, hipStream_t s, const int* slots,
+                      int nslots)
 {
-    PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_rhs<P_, D_>), dim3(B), dim3(NT), 0, s, H64, f,
-                                               g, b, tmp));
+    const int nb = slots ? nslots : B;
+    if (nb <= 0) return hipSuccess;
+    PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_rhs<P_, D_>), dim3(nb), dim3(NT), 0, s, H64, f,
+                                               g, b, tmp, slots));
     return last();
 }
 
@@ -392,6 +444,28 @@ hipError_t launch_line_coefs(int dim, int p, int B, const Hier<double>& H64, int
 {
     PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_line_coefs<P_, D_>), dim3(B), dim3(NT), 0, s,
                                                H64, smoother, dir, lo, di, up));
+    return last();
+}
+
+hipError_t launch_pool_start(const int* slots, int n, const int* sstatus, SolveState* st,
+                             pmg_info* info, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pool_start, dim3((n + 255) / 256), dim3(256), 0, s, slots, n, sstatus, st, info);
+    return last();
+}
+
+hipError_t launch_pool_idle(SolveState* st, int B, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pool_idle, dim3((B + 255) / 256), dim3(256), 0, s, st, B);
+    return last();
+}
+
+hipError_t launch_pool_take(int dim, int p, int slot, const double* w, const double* g, double* u,
+                            SolveState* st, hipStream_t s)
+{
+    PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_pool_take<P_, D_>), dim3(1), dim3(NT), 0, s, slot,
+                                               w, g, u, st));
     return last();
 }
 

@@ -1,4 +1,7 @@
-// pmg_solve.hpp -- outer Krylov solve kernel (one problem per workgroup).
+// pmg_solve.hpp -- outer Krylov solve (one problem per workgroup), resumable:
+// the iteration state lives in the workspace, so one solve may run in one
+// launch (pmg_solve) or be advanced a few iterations per launch (the serving
+// pools) with exactly the same arithmetic.
 #pragma once
 
 #include <cmath>
@@ -6,8 +9,6 @@
 #include "pmg_dispatch.hpp"
 
 namespace pmg {
-
-// ================================================================== outer Krylov
 
 __device__ inline double wg_dot(const double* a, const double* b, int n, double* red)
 {
@@ -49,9 +50,10 @@ __device__ void apply64(const Hier<T>& H, const SolveArgs& A, int b, const doubl
                                            A.TR64 + (long long)b * DIM * S::N, x, nullptr, out);
 }
 
-// Right-preconditioned FGMRES with modified Gram-Schmidt and restarts, PCG or
-// flexible CG, one workgroup per problem; convergence is declared on the
-// true residual ||b - A x|| <= rtol ||b||.
+// Right-preconditioned flexible GMRES, modified Gram-Schmidt, restarted every
+// `restart` iterations; PCG; flexible CG.  Convergence is declared on the
+// true residual ||b - A x|| <= rtol ||b||.  At most A.budget iterations are
+// taken in this launch; the state is saved in A.st[b].
 template <class T, int P, int DIM>
 __global__ void __launch_bounds__(NT) k_solve(Hier<T> H, SolveArgs A)
 {
@@ -59,188 +61,230 @@ __global__ void __launch_bounds__(NT) k_solve(Hier<T> H, SolveArgs A)
     constexpr int N = S::N;
     __shared__ double red[NT];
     __shared__ double sh[4];
-    const int b = blockIdx.x;
+    const int b = A.slots ? A.slots[blockIdx.x] : (int)blockIdx.x;
     const double* bb = A.b + (long long)b * N;
     double* x = A.x + (long long)b * N;
     double* V = A.V + (long long)b * A.nv * N;
     double* Z = A.Z + (long long)b * A.restart * N;
     double* Hs = A.Hs + (long long)b * A.hs;
     pmg_info* info = A.info + b;
+    SolveState* stp = A.st + b;
     const int kr = A.restart;
 
-    wg_zero(x, N);
-    int status = info->status;
-    int it = 0;
-    double relres = NAN;
-    wg_barrier();
-    if (status != PMG_OK) {
-        if (threadIdx.x == 0) { info->iterations = 0; info->relres = NAN; }
-        return;
+    SolveState st = *stp;
+    if (A.fresh) {
+        st.status = A.sstatus[b] == PMG_OK ? ST_RUNNING : A.sstatus[b];
+        st.it = 0;
+        st.j = 0;
+        st.phase = PH_INIT;
+        st.bn = 0.0;
+        st.rz = 0.0;
     }
-    const double bn = sqrt(wg_dot(bb, bb, N, red));
-    if (!(bn > 0.0)) {
-        if (threadIdx.x == 0) {
-            info->status = bn == 0.0 ? PMG_OK : PMG_ENAN;
+    if (st.status != ST_RUNNING) {
+        if (A.fresh && threadIdx.x == 0) {
+            *stp = st;
+            info->status = st.status;
             info->iterations = 0;
-            info->relres = 0.0;
+            info->relres = NAN;
         }
+        if (A.fresh) wg_zero(x, N);
         return;
     }
-    const double tol = A.rtol * bn;
-    status = PMG_ENOTCONV;
+    double relres = info->relres;
+    int budget = A.budget;
+    const bool fgmres = A.krylov == PMG_FGMRES;
+    const bool flex = A.krylov == PMG_FCG;
 
-    if (A.krylov == PMG_FGMRES) {
+    if (st.phase == PH_INIT) {
+        wg_zero(x, N);
+        wg_barrier();
+        st.bn = sqrt(wg_dot(bb, bb, N, red));
+        if (!(st.bn > 0.0)) {
+            st.status = st.bn == 0.0 ? PMG_OK : PMG_ENAN;
+            relres = 0.0;
+            goto done;
+        }
+        if (fgmres) {
+            st.phase = PH_RESTART;
+        } else {
+            double* r = V;
+            double* z = V + N;
+            double* pp = V + 2LL * N;
+            double* q = V + 3LL * N;
+            wg_copy(r, bb, N);
+            wg_barrier();
+            precondition<T, P, DIM>(H, b, r, z);
+            wg_copy(pp, z, N);
+            wg_barrier();
+            if (flex) {
+                apply64<T, P, DIM>(H, A, b, pp, nullptr, q);
+                st.rz = wg_dot(pp, q, N, red);
+            } else {
+                st.rz = wg_dot(r, z, N, red);
+            }
+            relres = 1.0;
+            st.phase = PH_RESTART;
+        }
+    }
+
+    if (fgmres) {
         double* Hm = Hs;                         // (kr+1) x kr
         double* cs = Hs + (kr + 1) * kr;
         double* sn = cs + kr;
         double* gv = sn + kr;                    // kr + 1
         double* yv = gv + kr + 1;                // kr
-        while (true) {
-            apply64<T, P, DIM>(H, A, b, x, bb, V);
-            const double beta = sqrt(wg_dot(V, V, N, red));
-            relres = beta / bn;
-            if (!isfinite(beta)) { status = PMG_ENAN; break; }
-            if (beta <= tol) { status = PMG_OK; break; }
-            if (it >= A.max_iter) break;
-            for (int q = threadIdx.x; q < N; q += NT) V[q] /= beta;
-            if (threadIdx.x == 0) {
-                gv[0] = beta;
-                for (int i = 1; i <= kr; ++i) gv[i] = 0.0;
+        const double tol = A.rtol * st.bn;
+        for (;;) {
+            if (st.phase == PH_RESTART) {
+                apply64<T, P, DIM>(H, A, b, x, bb, V);
+                const double beta = sqrt(wg_dot(V, V, N, red));
+                relres = beta / st.bn;
+                if (!isfinite(beta)) { st.status = PMG_ENAN; goto done; }
+                if (beta <= tol) { st.status = PMG_OK; goto done; }
+                if (st.it >= A.max_iter) { st.status = PMG_ENOTCONV; goto done; }
+                for (int q = threadIdx.x; q < N; q += NT) V[q] /= beta;
+                if (threadIdx.x == 0) {
+                    gv[0] = beta;
+                    for (int i = 1; i <= kr; ++i) gv[i] = 0.0;
+                }
+                wg_barrier();
+                st.j = 0;
+                st.phase = PH_ARNOLDI;
             }
-            int used = 0;
-            bool fail = false;
-            for (int j = 0; j < kr; ++j) {
-                double* vj = V + (long long)j * N;
-                double* zj = Z + (long long)j * N;
-                double* w = V + (long long)(j + 1) * N;
-                precondition<T, P, DIM>(H, b, vj, zj);
-                apply64<T, P, DIM>(H, A, b, zj, nullptr, w);
-                for (int i = 0; i <= j; ++i) {
-                    const double* vi = V + (long long)i * N;
-                    const double hij = wg_dot(w, vi, N, red);
-                    for (int q = threadIdx.x; q < N; q += NT) w[q] -= hij * vi[q];
-                    if (threadIdx.x == 0) Hm[i * kr + j] = hij;
+            if (budget <= 0) break;
+            // one Arnoldi step
+            const int j = st.j;
+            double* vj = V + (long long)j * N;
+            double* zj = Z + (long long)j * N;
+            double* w = V + (long long)(j + 1) * N;
+            precondition<T, P, DIM>(H, b, vj, zj);
+            apply64<T, P, DIM>(H, A, b, zj, nullptr, w);
+            for (int i = 0; i <= j; ++i) {
+                const double* vi = V + (long long)i * N;
+                const double hij = wg_dot(w, vi, N, red);
+                for (int q = threadIdx.x; q < N; q += NT) w[q] -= hij * vi[q];
+                if (threadIdx.x == 0) Hm[i * kr + j] = hij;
+                wg_barrier();
+            }
+            const double hn = sqrt(wg_dot(w, w, N, red));
+            if (hn > 0.0)
+                for (int q = threadIdx.x; q < N; q += NT) w[q] /= hn;
+            if (threadIdx.x == 0) {
+                Hm[(j + 1) * kr + j] = hn;
+                for (int i = 0; i < j; ++i) {
+                    const double t = cs[i] * Hm[i * kr + j] + sn[i] * Hm[(i + 1) * kr + j];
+                    Hm[(i + 1) * kr + j] = -sn[i] * Hm[i * kr + j] + cs[i] * Hm[(i + 1) * kr + j];
+                    Hm[i * kr + j] = t;
+                }
+                const double a = Hm[j * kr + j], c = Hm[(j + 1) * kr + j];
+                const double rr = sqrt(a * a + c * c);
+                double est = -1.0;
+                if (rr > 0.0 && isfinite(rr)) {
+                    cs[j] = a / rr;
+                    sn[j] = c / rr;
+                    Hm[j * kr + j] = rr;
+                    Hm[(j + 1) * kr + j] = 0.0;
+                    gv[j + 1] = -sn[j] * gv[j];
+                    gv[j] = cs[j] * gv[j];
+                    est = fabs(gv[j + 1]);
+                }
+                sh[0] = est;
+                sh[1] = hn;
+            }
+            wg_barrier();
+            const double est = sh[0], hnb = sh[1];
+            wg_barrier();
+            ++st.it;
+            --budget;
+            const bool fail = !(est >= 0.0) || !isfinite(est);
+            const int used = fail ? j : j + 1;
+            st.j = j + 1;
+            if (fail || est <= tol || hnb == 0.0 || st.it >= A.max_iter || st.j == kr) {
+                // end of the restart cycle: x += Z y with H y = g
+                if (used > 0) {
+                    if (threadIdx.x == 0) {
+                        for (int i = used - 1; i >= 0; --i) {
+                            double s = gv[i];
+                            for (int k = i + 1; k < used; ++k) s -= Hm[i * kr + k] * yv[k];
+                            yv[i] = s / Hm[i * kr + i];
+                        }
+                    }
+                    wg_barrier();
+                    for (int q = threadIdx.x; q < N; q += NT) {
+                        double s = x[q];
+                        for (int i = 0; i < used; ++i) s += yv[i] * Z[(long long)i * N + q];
+                        x[q] = s;
+                    }
                     wg_barrier();
                 }
-                const double hn = sqrt(wg_dot(w, w, N, red));
-                if (hn > 0.0)
-                    for (int q = threadIdx.x; q < N; q += NT) w[q] /= hn;
-                if (threadIdx.x == 0) {
-                    Hm[(j + 1) * kr + j] = hn;
-                    for (int i = 0; i < j; ++i) {
-                        const double t = cs[i] * Hm[i * kr + j] + sn[i] * Hm[(i + 1) * kr + j];
-                        Hm[(i + 1) * kr + j] = -sn[i] * Hm[i * kr + j] + cs[i] * Hm[(i + 1) * kr + j];
-                        Hm[i * kr + j] = t;
-                    }
-                    const double a = Hm[j * kr + j], c = Hm[(j + 1) * kr + j];
-                    const double rr = sqrt(a * a + c * c);
-                    double est = -1.0;
-                    if (rr > 0.0 && isfinite(rr)) {
-                        cs[j] = a / rr;
-                        sn[j] = c / rr;
-                        Hm[j * kr + j] = rr;
-                        Hm[(j + 1) * kr + j] = 0.0;
-                        gv[j + 1] = -sn[j] * gv[j];
-                        gv[j] = cs[j] * gv[j];
-                        est = fabs(gv[j + 1]);
-                    }
-                    sh[0] = est;
-                    sh[1] = hn;
+                st.phase = PH_RESTART;
+                if (fail) {
+                    apply64<T, P, DIM>(H, A, b, x, bb, V);
+                    relres = sqrt(wg_dot(V, V, N, red)) / st.bn;
+                    st.status = isfinite(relres) ? (relres <= A.rtol ? PMG_OK : PMG_EBREAKDOWN) : PMG_ENAN;
+                    goto done;
                 }
-                wg_barrier();
-                const double est = sh[0], hnb = sh[1];
-                wg_barrier();
-                ++it;
-                if (est < 0.0) { fail = true; break; }
-                used = j + 1;
-                if (!isfinite(est)) { fail = true; break; }
-                if (est <= tol || hnb == 0.0 || it >= A.max_iter) break;
-            }
-            if (used > 0) {
-                if (threadIdx.x == 0) {
-                    for (int i = used - 1; i >= 0; --i) {
-                        double s = gv[i];
-                        for (int k = i + 1; k < used; ++k) s -= Hm[i * kr + k] * yv[k];
-                        yv[i] = s / Hm[i * kr + i];
-                    }
-                }
-                wg_barrier();
-                for (int q = threadIdx.x; q < N; q += NT) {
-                    double s = x[q];
-                    for (int i = 0; i < used; ++i) s += yv[i] * Z[(long long)i * N + q];
-                    x[q] = s;
-                }
-                wg_barrier();
-            }
-            if (fail) {
-                apply64<T, P, DIM>(H, A, b, x, bb, V);
-                relres = sqrt(wg_dot(V, V, N, red)) / bn;
-                status = isfinite(relres) ? (relres <= A.rtol ? PMG_OK : PMG_EBREAKDOWN) : PMG_ENAN;
-                break;
             }
         }
     } else {
         // CG family: V holds r, z, p, q, t
         double* r = V;
         double* z = V + N;
-        double* p = V + 2LL * N;
+        double* pp = V + 2LL * N;
         double* q = V + 3LL * N;
         double* t = V + 4LL * N;
-        const bool flex = A.krylov == PMG_FCG;
-        wg_copy(r, bb, N);
-        wg_barrier();
-        precondition<T, P, DIM>(H, b, r, z);
-        wg_copy(p, z, N);
-        wg_barrier();
-        double rz = wg_dot(r, z, N, red);
-        if (flex) apply64<T, P, DIM>(H, A, b, p, nullptr, q);
-        relres = 1.0;
-        while (true) {
-            if (!flex) apply64<T, P, DIM>(H, A, b, p, nullptr, q);
-            const double pq = wg_dot(p, q, N, red);
-            if (!(pq > 0.0)) { status = isfinite(pq) ? PMG_EBREAKDOWN : PMG_ENAN; break; }
-            const double al = (flex ? wg_dot(p, r, N, red) : rz) / pq;
+        const double tol = A.rtol * st.bn;
+        while (budget > 0) {
+            if (!flex) apply64<T, P, DIM>(H, A, b, pp, nullptr, q);
+            const double pq = flex ? st.rz : wg_dot(pp, q, N, red);
+            if (!(pq > 0.0)) { st.status = isfinite(pq) ? PMG_EBREAKDOWN : PMG_ENAN; goto done; }
+            const double al = (flex ? wg_dot(pp, r, N, red) : st.rz) / pq;
             for (int i = threadIdx.x; i < N; i += NT) {
-                x[i] += al * p[i];
+                x[i] += al * pp[i];
                 r[i] -= al * q[i];
             }
             wg_barrier();
-            ++it;
-            double rn = sqrt(wg_dot(r, r, N, red));
-            if (!isfinite(rn)) { status = PMG_ENAN; break; }
+            ++st.it;
+            --budget;
+            const double rn = sqrt(wg_dot(r, r, N, red));
+            if (!isfinite(rn)) { st.status = PMG_ENAN; goto done; }
+            relres = rn / st.bn;
             if (rn <= tol) {
                 apply64<T, P, DIM>(H, A, b, x, bb, t);
                 const double tn = sqrt(wg_dot(t, t, N, red));
-                relres = tn / bn;
-                if (tn <= tol) { status = PMG_OK; break; }
+                relres = tn / st.bn;
+                if (tn <= tol) { st.status = PMG_OK; goto done; }
                 wg_copy(r, t, N);
                 wg_barrier();
             }
-            relres = rn / bn;
-            if (it >= A.max_iter) break;
+            if (st.it >= A.max_iter) {
+                apply64<T, P, DIM>(H, A, b, x, bb, t);
+                relres = sqrt(wg_dot(t, t, N, red)) / st.bn;
+                st.status = PMG_ENOTCONV;
+                goto done;
+            }
             precondition<T, P, DIM>(H, b, r, z);
             if (flex) {
                 const double be = -wg_dot(z, q, N, red) / pq;
-                for (int i = threadIdx.x; i < N; i += NT) p[i] = z[i] + be * p[i];
+                for (int i = threadIdx.x; i < N; i += NT) pp[i] = z[i] + be * pp[i];
                 wg_barrier();
-                apply64<T, P, DIM>(H, A, b, p, nullptr, q);
+                apply64<T, P, DIM>(H, A, b, pp, nullptr, q);
+                st.rz = wg_dot(pp, q, N, red);
             } else {
                 const double rz2 = wg_dot(r, z, N, red);
-                const double be = rz2 / rz;
-                rz = rz2;
-                for (int i = threadIdx.x; i < N; i += NT) p[i] = z[i] + be * p[i];
+                const double be = rz2 / st.rz;
+                st.rz = rz2;
+                for (int i = threadIdx.x; i < N; i += NT) pp[i] = z[i] + be * pp[i];
                 wg_barrier();
             }
         }
-        if (status == PMG_ENOTCONV) {
-            apply64<T, P, DIM>(H, A, b, x, bb, t);
-            relres = sqrt(wg_dot(t, t, N, red)) / bn;
-        }
     }
+done:
     if (threadIdx.x == 0) {
-        info->status = status;
-        info->iterations = it;
+        *stp = st;
         info->relres = relres;
+        info->iterations = st.it;
+        info->status = st.status;
     }
 }
 
