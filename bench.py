@@ -42,6 +42,11 @@ def parse():
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget of the oracle CPU baseline (0 disables it)")
+    ap.add_argument("--serve", type=int, default=512, metavar="N",
+                    help="requests of the served mixed 2-D/3-D stream (0 skips serving)")
+    ap.add_argument("--serve-load", type=float, default=0.8,
+                    help="paced arrival rate as a fraction of the saturated throughput")
+    ap.add_argument("--mixed", type=int, default=1, help="also time the FP32-inner solve")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     return ap.parse_args()
@@ -108,28 +113,18 @@ def flops_per_solve(dim, p, gamma, m, iters, krylov, restart):
     return total
 
 
-def main():
-    args = parse()
-    if args.copy_calibration:
-        copy_calibration(args.copy_calibration)
-        return
-    if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not "
-                          "part of this build (independent problems shard by request across "
-                          "GPUs with no collectives)", "n_gpus": args.gpus}))
-        sys.exit(2)
-
+def run_batch(args, prec_name):
+    """Time `steps` whole-path steps of one batch; returns the measurements."""
     import numpy as np
     import torch
 
     from paper_2504_10710_amd import inputs, pmg
 
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
     B, p = args.batch, args.p
     dim = 2
     smoother = pmg.PMG_SMOOTHER_FEM if args.smoother == "fem" else pmg.PMG_SMOOTHER_GLL
-    prec = pmg.PMG_F32 if args.prec == "f32" else pmg.PMG_F64
+    prec = pmg.PMG_F32 if prec_name == "f32" else pmg.PMG_F64
     krylov = {"fgmres": pmg.PMG_FGMRES, "pcg": pmg.PMG_PCG, "fcg": pmg.PMG_FCG}[args.krylov]
     desc = pmg.make_desc(dim=dim, p_fine=p, batch=B, gamma=args.gamma, m=1, alpha=args.alpha,
                          smoother=smoother, inner_prec=prec, krylov=krylov,
@@ -153,7 +148,7 @@ def main():
     x = torch.empty_like(f)
     u = torch.empty_like(f)
     torch.cuda.synchronize()
-    print(f"[bench] inputs ready: B={B} p={p} ws={ws.numel() / 2**30:.2f} GiB "
+    print(f"[bench] {prec_name}: inputs ready: B={B} p={p} ws={ws.numel() / 2**30:.2f} GiB "
           f"({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
 
     stream = torch.cuda.current_stream()
@@ -175,7 +170,7 @@ def main():
     for i in range(args.warmup):
         step(False)
         torch.cuda.synchronize()
-        print(f"[bench] warmup step {i} done", file=sys.stderr, flush=True)
+        print(f"[bench] {prec_name}: warmup step {i} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for i in range(args.steps):
@@ -189,25 +184,54 @@ def main():
     solve_s = sum(solve_ms) / len(solve_ms) / 1e3
     ms_per_step = elapsed / args.steps * 1e3
     value = B * args.steps / elapsed
-    print(f"[bench] timed {args.steps} steps: {ms_per_step:.1f} ms/step, solve kernel "
+    print(f"[bench] {prec_name}: timed {args.steps} steps: {ms_per_step:.1f} ms/step, solve kernel "
           f"{solve_s * 1e3:.1f} ms, ok {ok}/{B}, its min/med/max {its.min()}/"
           f"{int(np.median(its))}/{its.max()}, max relres {nfo['relres'].max():.2e}",
           file=sys.stderr, flush=True)
-
     flops = sum(flops_per_solve(dim, p, args.gamma, 1, int(k), args.krylov, args.restart)
                 for k in its)
-    achieved = flops / solve_s / 1e12
+    return {"value": value, "ms_per_step": ms_per_step, "solve_s": solve_s, "its": its,
+            "ok": ok, "flops": flops, "max_relres": float(nfo["relres"].max()),
+            "probs": probs, "ps": ps}
+
+
+def main():
+    args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not "
+                          "part of this build (independent problems shard by request across "
+                          "GPUs with no collectives)", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    torch.cuda.set_device(0)
+    B, p, dim = args.batch, args.p, 2
+    r64 = run_batch(args, args.prec)
+    achieved = r64["flops"] / r64["solve_s"] / 1e12
     peak = PEAK_FP32_TFLOPS if args.prec == "f32" else PEAK_FP64_TFLOPS
     roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 5), "traffic": None,
                 "kernel": f"k_solve<{'float' if args.prec == 'f32' else 'double'}, {p}, 2>",
-                "flops_per_launch": flops}
-
-    cpu = None
-    if args.cpu_seconds > 0:
-        cpu = cpu_baseline(args, probs, ps)
+                "flops_per_launch": r64["flops"]}
+    mixed = None
+    if args.mixed and args.prec == "f64":
+        r32 = run_batch(args, "f32")
+        mixed = {"value": round(r32["value"], 3), "unit": "solves/s", "dtype": "f32 cycle + f64 Krylov",
+                 "ms_per_step": round(r32["ms_per_step"], 3),
+                 "iterations_median": int(np.median(r32["its"])), "converged": r32["ok"],
+                 "max_relres": r32["max_relres"],
+                 "achieved_tflops": round(r32["flops"] / r32["solve_s"] / 1e12, 4),
+                 "speedup_vs_f64": round(r32["value"] / r64["value"], 3)}
+    served = serve(args) if args.serve > 0 else None
+    cpu = cpu_baseline(args, r64["probs"], r64["ps"]) if args.cpu_seconds > 0 else None
 
     ndof = (p - 1) ** 2
+    value = r64["value"]
     line = {
         "metric": "solves/s to 1e-10 rel. residual",
         "value": round(value, 3),
@@ -215,7 +239,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": round(r64["ms_per_step"], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -226,11 +250,133 @@ def main():
                    "smoother": args.smoother, "krylov": args.krylov, "rtol": args.rtol,
                    "inner_precision": args.prec, "interior_dofs": ndof,
                    "dof_per_s": round(value * ndof, 1),
-                   "iterations_median": int(np.median(its)), "converged": ok},
+                   "iterations_median": int(np.median(r64["its"])), "converged": r64["ok"],
+                   "max_relres": r64["max_relres"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "mixed_precision": mixed,
+        "serving": served,
     }
     print(json.dumps(line), flush=True)
+
+
+SERVE_CLASSES = [  # (dim, p, slots)
+    (2, 16, 256), (2, 32, 256), (2, 64, 128), (2, 128, 128),
+    (3, 16, 128), (3, 32, 64), (3, 64, 16),
+]
+
+
+def serve(args):
+    """Served stream: continuous batching of mixed 2-D/3-D requests through the
+    library's server (mixed precision, graph-replayed steps, byte-budget
+    admission).  Pass 1 submits every request at once (saturated throughput);
+    pass 2 paces Poisson arrivals at serve_load x that throughput and reports
+    per-request latency (arrival to retirement)."""
+    import numpy as np
+    import torch
+
+    from paper_2504_10710_amd import inputs, pmg
+
+    dev = torch.device("cuda:0")
+    classes, bank = [], []
+    for dim, p, slots in SERVE_CLASSES:
+        if dim == 2:
+            classes.append(pmg.make_desc(dim=2, p_fine=p, batch=slots, gamma=1, alpha=0.16,
+                                         smoother=pmg.PMG_SMOOTHER_FEM, inner_prec=pmg.PMG_F32,
+                                         restart=30, max_iter=300, rtol=1e-10))
+        else:
+            classes.append(pmg.make_desc(dim=3, p_fine=p, batch=slots, gamma=1, alpha=0.16,
+                                         smoother=pmg.PMG_SMOOTHER_FEM, inner_prec=pmg.PMG_F32,
+                                         restart=20, max_iter=300, rtol=1e-10))
+    footprint = [pmg.pmg_pool_workspace_bytes(c) // c.batch for c in classes]
+    budget = int(sum(f * c.batch for f, c in zip(footprint, classes)) * 0.75)
+    sdesc = pmg.make_server_desc(classes, iters_per_step=4, budget_bytes=budget)
+    ws = torch.empty(pmg.pmg_server_workspace_bytes(sdesc), dtype=torch.uint8, device=dev)
+    # a bank of distinct seeded problems per class; request i of class c uses
+    # bank entry i mod K (every request still runs its own setup and solve)
+    K = 8
+    for ci, (dim, p, _) in enumerate(SERVE_CLASSES):
+        ps = inputs.halving_degrees(p, 2)
+        entries = []
+        for k in range(K):
+            prob = inputs.config2(1000 + 31 * ci + k) if dim == 2 else inputs.config3(1000 + 31 * ci + k)
+            coords = [torch.from_numpy(prob.coords(pmg.pmg_gll(q)[0])).to(dev).contiguous() for q in ps]
+            X = prob.coords(pmg.pmg_gll(p)[0])
+            entries.append((coords, torch.from_numpy(prob.f(X)).to(dev), torch.from_numpy(prob.g(X)).to(dev)))
+        bank.append(entries)
+    stream = inputs.served_stream(args.serve, seed=7)
+    cls_of = {(d, p): i for i, (d, p, _) in enumerate(SERVE_CLASSES)}
+    reqs = [cls_of[(d, p)] for d, p, _ in stream]
+    torch.cuda.synchronize()
+
+    def run(arrivals):
+        srv = pmg.pmg_server_create(sdesc, ws)
+        n = len(reqs)
+        outs, tickets, t_arr, t_done = [None] * n, [None] * n, np.zeros(n), np.zeros(n)
+        nxt, done, its, worst = 0, 0, [], 0.0
+        seen = [0] * len(SERVE_CLASSES)
+        t0 = time.perf_counter()
+        last_print = t0
+        while done < n:
+            if time.perf_counter() - last_print > 5.0:
+                last_print = time.perf_counter()
+                print(f"[bench] serving: {done}/{n} done, {nxt} arrived, "
+                      f"{pmg.pmg_server_stats_get(srv)}", file=sys.stderr, flush=True)
+            now = time.perf_counter() - t0
+            while nxt < n and arrivals[nxt] <= now:
+                c = reqs[nxt]
+                coords, f, g = bank[c][seen[c] % K]
+                seen[c] += 1
+                outs[nxt] = torch.empty_like(f)
+                tickets[nxt] = pmg.pmg_server_submit(srv, c, coords, f, g, outs[nxt])
+                t_arr[nxt] = max(arrivals[nxt], 0.0)
+                nxt += 1
+            st = pmg.pmg_server_stats_get(srv)
+            if st["running"] == 0 and st["queued"] == 0:
+                time.sleep(max(0.0, min(arrivals[nxt] - now, 0.01)) if nxt < n else 0.0)
+                continue
+            pmg.pmg_server_step(srv)
+            now = time.perf_counter() - t0
+            for i in range(nxt):
+                if t_done[i] == 0.0 and tickets[i] is not None:
+                    ok, info = pmg.pmg_server_poll(srv, tickets[i])
+                    if ok:
+                        t_done[i] = now
+                        done += 1
+                        its.append(int(info["iterations"]))
+                        if info["status"] != 0:
+                            worst = float("inf")
+                        else:
+                            worst = max(worst, float(info["relres"]))
+                        outs[i] = None
+        makespan = time.perf_counter() - t0
+        steps = pmg.pmg_server_stats_get(srv)["steps"]
+        pmg.pmg_server_destroy(srv)
+        lat = (t_done - t_arr) * 1e3
+        return makespan, lat, steps, worst, its
+
+    n = len(reqs)
+    mk, lat_sat, steps_sat, worst_sat, its = run(np.zeros(n))
+    thr = n / mk
+    rate = args.serve_load * thr
+    rng = np.random.default_rng(11)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    mk2, lat, steps, worst, _ = run(arrivals)
+    mix = {f"{d}d_p{p}": int(sum(1 for c in reqs if SERVE_CLASSES[c][:2] == (d, p)))
+           for d, p, _ in SERVE_CLASSES}
+    print(f"[bench] served: saturated {thr:.1f} req/s, paced at {rate:.1f} req/s: "
+          f"p50 {np.percentile(lat, 50):.1f} ms p99 {np.percentile(lat, 99):.1f} ms",
+          file=sys.stderr, flush=True)
+    return {"requests": n, "mix": mix, "inner_precision": "f32",
+            "saturated_solves_per_s": round(thr, 2),
+            "saturated_latency_ms": {"p50": round(float(np.percentile(lat_sat, 50)), 2),
+                                     "p99": round(float(np.percentile(lat_sat, 99)), 2)},
+            "paced_rate_per_s": round(rate, 2),
+            "paced_solves_per_s": round(n / mk2, 2),
+            "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2),
+                           "p99": round(float(np.percentile(lat, 99)), 2)},
+            "max_relres": worst, "iterations_median": int(np.median(its)),
+            "budget_bytes": budget, "steps": int(steps), "iters_per_step": 4}
 
 
 def cpu_baseline(args, probs, ps):

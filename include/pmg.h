@@ -72,7 +72,8 @@ enum { PMG_FGMRES = 0, PMG_PCG = 1, PMG_FCG = 2 };
  *   smoother   PMG_SMOOTHER_GLL: tridiagonal part of A_p along each line
  *              (Def. line preconditioners with half-bandwidth 1);
  *              PMG_SMOOTHER_FEM: tridiagonal line systems of the bilinear
- *              finite-element matrix on the GLL node mesh (2-D only)
+ *              (2-D) / trilinear (3-D) finite-element matrix on the GLL
+ *              node mesh
  *   inner_prec PMG_F64, or PMG_F32 for an FP32 gamma-cycle inside FP64
  *              Krylov (geometric factors and the outer solve stay FP64)
  *   krylov     PMG_FGMRES (right-preconditioned, modified Gram-Schmidt,

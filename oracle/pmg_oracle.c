@@ -514,10 +514,85 @@ static double fem_entry2(const or_level* L, int row, int col)
  * Axelsson incomplete bandwidth preconditioner): for every interior line
  * along axis dir, the tridiagonal part of R A P on the p-1 interior nodes of
  * the line; couplings to boundary nodes are dropped (Dirichlet nodes). */
+/* Entry of the trilinear finite-element stiffness matrix on the hexahedra
+ * whose corners are neighbouring GLL nodes (the 3-D analogue of the FEM line
+ * preconditioners): element integrals by the 2x2x2 Gauss rule on the
+ * trilinear map of each hexahedron. */
+static double fem_entry3(const or_level* L, int row, int col)
+{
+    int n1 = L->n1, N = L->N;
+    int r[3], c[3];
+    unrank(3, n1, row, r);
+    unrank(3, n1, col, c);
+    for (int a = 0; a < 3; ++a)
+        if (abs(r[a] - c[a]) > 1) return 0.0;
+    const double gp[2] = {0.5 - 0.5 / sqrt(3.0), 0.5 + 0.5 / sqrt(3.0)};
+    double s = 0.0;
+    for (int e0 = r[0] - 1; e0 <= r[0]; ++e0)
+        for (int e1 = r[1] - 1; e1 <= r[1]; ++e1)
+            for (int e2 = r[2] - 1; e2 <= r[2]; ++e2) {
+                int e[3] = {e0, e1, e2};
+                int ok = 1;
+                for (int a = 0; a < 3; ++a) {
+                    if (e[a] < 0 || e[a] >= n1 - 1) ok = 0;
+                    if (c[a] < e[a] || c[a] > e[a] + 1) ok = 0;
+                }
+                if (!ok) continue;
+                double X[8][3];
+                for (int v = 0; v < 8; ++v) {
+                    int cc[3] = {e0 + (v & 1), e1 + ((v >> 1) & 1), e2 + ((v >> 2) & 1)};
+                    int q = rank_(3, n1, cc);
+                    for (int a = 0; a < 3; ++a) X[v][a] = L->X[a * N + q];
+                }
+                int va = (r[0] - e0) + 2 * (r[1] - e1) + 4 * (r[2] - e2);
+                int vb = (c[0] - e0) + 2 * (c[1] - e1) + 4 * (c[2] - e2);
+                for (int g = 0; g < 8; ++g) {
+                    double u[3] = {gp[g & 1], gp[(g >> 1) & 1], gp[(g >> 2) & 1]};
+                    /* reference gradients of the 8 corner functions */
+                    double dN[8][3];
+                    for (int v = 0; v < 8; ++v) {
+                        double f[3], df[3];
+                        for (int a = 0; a < 3; ++a) {
+                            int bit = (v >> a) & 1;
+                            f[a] = bit ? u[a] : 1.0 - u[a];
+                            df[a] = bit ? 1.0 : -1.0;
+                        }
+                        dN[v][0] = df[0] * f[1] * f[2];
+                        dN[v][1] = f[0] * df[1] * f[2];
+                        dN[v][2] = f[0] * f[1] * df[2];
+                    }
+                    double J[3][3] = {{0}};   /* J[comp][ref axis] */
+                    for (int v = 0; v < 8; ++v)
+                        for (int comp = 0; comp < 3; ++comp)
+                            for (int a = 0; a < 3; ++a) J[comp][a] += X[v][comp] * dN[v][a];
+                    double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1])
+                               - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0])
+                               + J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+                    double inv[3][3];   /* inv[a][comp] = d ref_a / d x_comp */
+                    inv[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+                    inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+                    inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+                    inv[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+                    inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+                    inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+                    inv[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+                    inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+                    inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+                    double ga[3] = {0, 0, 0}, gb[3] = {0, 0, 0};
+                    for (int comp = 0; comp < 3; ++comp)
+                        for (int a = 0; a < 3; ++a) {
+                            ga[comp] += inv[a][comp] * dN[va][a];
+                            gb[comp] += inv[a][comp] * dN[vb][a];
+                        }
+                    s += 0.125 * fabs(det) * (ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2]);
+                }
+            }
+    return s;
+}
+
 static double fem_entry_any(int dim, const or_level* L, int row, int col)
 {
-    (void)dim;
-    return fem_entry2(L, row, col);
+    return dim == 2 ? fem_entry2(L, row, col) : fem_entry3(L, row, col);
 }
 
 static void level_lines(int dim, or_level* L, int dir, int smoother)
@@ -607,7 +682,7 @@ or_hier* or_hier_create(int dim, int nlev, const int* p, const double* const* co
                         int gamma, int m, double alpha, int smoother)
 {
     if ((dim != 2 && dim != 3) || nlev < 1 || nlev > OR_MAXLEV || gamma < 1 || m < 0
-        || smoother < 0 || smoother > 1 || (smoother == 1 && dim != 2))
+        || smoother < 0 || smoother > 1)
         return NULL;
     for (int l = 0; l < nlev; ++l)
         if (p[l] < 2 || (l > 0 && p[l] <= p[l - 1])) return NULL;
@@ -692,8 +767,7 @@ double or_entry(const or_hier* h, int l, int row, int col)
 
 double or_fem_entry(const or_hier* h, int l, int row, int col)
 {
-    if (h->dim != 2) return NAN;
-    return fem_entry2(&h->lev[l], row, col);
+    return fem_entry_any(h->dim, &h->lev[l], row, col);
 }
 
 int or_dense_interior(const or_hier* h, int l, double* A)

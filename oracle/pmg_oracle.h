@@ -80,7 +80,8 @@ typedef struct or_hier or_hier;
  * coords[l] holds dim*N_l doubles (all first coordinates, then all second,
  * ...), the physical positions of the level-l GLL nodes.  smoother = 0
  * selects the GLL line systems (Def. line preconditioners with A_p);
- * smoother = 1 the bilinear finite-element line systems (A~_p, 2-D only).
+ * smoother = 1 the bilinear (2-D) / trilinear (3-D) finite-element line
+ * systems (A~_p on the GLL node mesh).
  * Returns NULL on bad arguments, non-positive Jacobian, or a failed coarse
  * factorisation. */
 or_hier* or_hier_create(int dim, int nlev, const int* p,
@@ -106,8 +107,9 @@ void or_apply_all(const or_hier* h, int l, const double* x, double* y);
  * discreteBilinear (node indices). */
 double or_entry(const or_hier* h, int l, int row, int col);
 
-/* Entry A~_l[row, col] of the bilinear finite-element stiffness on the GLL
- * node mesh (FEM line preconditioners, Sec. 3.1); 2-D only (NaN otherwise). */
+/* Entry A~_l[row, col] of the bilinear (2-D) or trilinear (3-D)
+ * finite-element stiffness on the GLL node mesh (FEM line preconditioners,
+ * Sec. 3.1). */
 double or_fem_entry(const or_hier* h, int l, int row, int col);
 
 /* Dense interior matrix of level l (n_int x n_int, interior nodes in

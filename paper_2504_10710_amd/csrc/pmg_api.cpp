@@ -160,8 +160,6 @@ int check_desc(const pmg_desc* d)
     if (!(d->alpha > 0.0) || !std::isfinite(d->alpha)) return fail(PMG_EINVAL, "alpha must be > 0");
     if (d->smoother != PMG_SMOOTHER_GLL && d->smoother != PMG_SMOOTHER_FEM)
         return fail(PMG_EINVAL, "unknown smoother %d", d->smoother);
-    if (d->smoother == PMG_SMOOTHER_FEM && d->dim != 2)
-        return fail(PMG_EINVAL, "the FEM line smoother is 2-D only");
     if (d->inner_prec != PMG_F64 && d->inner_prec != PMG_F32)
         return fail(PMG_EINVAL, "unknown inner precision %d", d->inner_prec);
     if (d->krylov != PMG_FGMRES && d->krylov != PMG_PCG && d->krylov != PMG_FCG)
@@ -205,7 +203,7 @@ struct pmg_handle {
     size_t o_cr64[MAX_LEVELS][3], o_cr32[MAX_LEVELS][3];
     size_t o_X[MAX_LEVELS], o_R[MAX_LEVELS], o_Tm[MAX_LEVELS], o_TR[MAX_LEVELS];
     size_t o_mass, o_W1, o_W2, o_TR64, o_V, o_Z, o_Hs, o_detmin, o_pivot, o_cinv64, o_cinv32;
-    size_t o_sstatus, o_state;
+    size_t o_sstatus, o_state, o_hier64, o_hier32;
     // serving pools only: per-slot input staging, right-hand side, solution,
     // info, and the slot list of an admission
     bool pool = false;
@@ -280,6 +278,8 @@ void plan(pmg_handle* h)
     h->o_cinv32 = L.take(sizeof(float) * (size_t)B);
     h->o_sstatus = L.take(sizeof(int) * (size_t)B);
     h->o_state = L.take(sizeof(SolveState) * (size_t)B);
+    h->o_hier64 = L.take(sizeof(Hier<double>));
+    h->o_hier32 = L.take(sizeof(Hier<float>));
     if (h->pool) {
         for (int l = 0; l < h->nlev; ++l) {
             LevelShape s = level_shape(dim, l);
@@ -478,6 +478,14 @@ static int init_handle(const pmg_desc* desc, void* d_ws, size_t ws_bytes, bool p
     fill_hier<float>(h, h->H32, true);
     // FP64 views used by the FP64-only operations of an FP32 handle
     h->H64.lev[h->nlev - 1].TR = (double*)(h->ws + h->o_TR64);
+    // kernels read the hierarchy description from device memory
+    if ((e = hipMemcpyAsync(h->ws + h->o_hier64, &h->H64, sizeof(Hier<double>), hipMemcpyHostToDevice,
+                            s)) != hipSuccess ||
+        (e = hipMemcpyAsync(h->ws + h->o_hier32, &h->H32, sizeof(Hier<float>), hipMemcpyHostToDevice,
+                            s)) != hipSuccess) {
+        delete h;
+        return hip_fail(e, "hierarchy upload");
+    }
     *out = h;
     return PMG_OK;
 }
@@ -550,7 +558,12 @@ static int check_prec(pmg_handle* h, int prec, bool* f32)
 
 static const void* hier_of(pmg_handle* h, bool f32)
 {
-    return f32 ? (const void*)&h->H32 : (const void*)&h->H64;
+    return (const void*)(h->ws + (f32 ? h->o_hier32 : h->o_hier64));
+}
+
+static const Hier<double>* hier64_dev(pmg_handle* h)
+{
+    return (const Hier<double>*)(h->ws + h->o_hier64);
 }
 
 int pmg_rhs(pmg_handle* h, const double* d_f, const double* d_g, double* d_b, pmg_stream_t stream)
@@ -558,8 +571,9 @@ int pmg_rhs(pmg_handle* h, const double* d_f, const double* d_g, double* d_b, pm
     int rc = check_h(h);
     if (rc) return rc;
     if (!d_f || !d_g || !d_b) return fail(PMG_EINVAL, "NULL argument");
-    hipError_t e = launch_rhs(h->d.dim, h->d.p_fine, h->d.batch, h->H64, d_f, d_g, d_b,
-                              (double*)(h->ws + h->o_V), (hipStream_t)stream);
+    const long long vstride = h->nv * (long long)level_shape(h->d.dim, h->nlev - 1).N;
+    hipError_t e = launch_rhs(h->d.dim, h->d.p_fine, h->d.batch, hier64_dev(h), d_f, d_g, d_b,
+                              (double*)(h->ws + h->o_V), vstride, (hipStream_t)stream);
     return e == hipSuccess ? PMG_OK : hip_fail(e, "pmg_rhs");
 }
 
@@ -691,7 +705,7 @@ int pmg_line_coefs(pmg_handle* h, int level, int dir, double* d_lo, double* d_di
     if ((rc = check_h(h)) || (rc = check_level(h, level, 0))) return rc;
     if (dir < 0 || dir >= h->d.dim) return fail(PMG_EINVAL, "dir %d out of range", dir);
     if (!d_lo || !d_di || !d_up) return fail(PMG_EINVAL, "NULL argument");
-    hipError_t e = launch_line_coefs(h->d.dim, 2 << level, h->d.batch, h->H64, h->d.smoother, dir,
+    hipError_t e = launch_line_coefs(h->d.dim, 2 << level, h->d.batch, hier64_dev(h), h->d.smoother, dir,
                                      d_lo, d_di, d_up, (hipStream_t)stream);
     return e == hipSuccess ? PMG_OK : hip_fail(e, "pmg_line_coefs");
 }
@@ -836,9 +850,9 @@ int pmg_pool_admit(pmg_pool* P, int n, const int* slots, const double* const* d_
     pmg_info* info = (pmg_info*)(h->ws + h->o_info);
     e = launch_setup(dim, h->d.p_fine, h->nlev, B, a, info, s);
     if (e == hipSuccess)
-        e = launch_rhs(dim, h->d.p_fine, B, h->H64, (const double*)(h->ws + h->o_in_f),
+        e = launch_rhs(dim, h->d.p_fine, B, hier64_dev(h), (const double*)(h->ws + h->o_in_f),
                        (const double*)(h->ws + h->o_in_g), (double*)(h->ws + h->o_b),
-                       (double*)(h->ws + h->o_V), s, dslots, n);
+                       (double*)(h->ws + h->o_V), h->nv * (long long)N, s, dslots, n);
     if (e == hipSuccess)
         e = launch_pool_start(dslots, n, (const int*)(h->ws + h->o_sstatus),
                               (SolveState*)(h->ws + h->o_state), info, s);

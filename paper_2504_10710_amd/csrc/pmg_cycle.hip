@@ -6,8 +6,9 @@
 namespace pmg {
 
 template <class T, int P, int DIM>
-__global__ void __launch_bounds__(NT) k_cycle(Hier<T> H, const T* __restrict__ r, T* __restrict__ y)
+__global__ void __launch_bounds__(NT, 8) k_cycle(const Hier<T>* __restrict__ Hp, const T* __restrict__ r, T* __restrict__ y)
 {
+    const Hier<T>& H = *Hp;
     using S = Shape<P, DIM>;
     const long long b = blockIdx.x;
     gamma_cycle<T, P, DIM>(H, (int)b, r + b * S::N, y + b * S::N);
@@ -17,7 +18,7 @@ hipError_t launch_cycle(int dim, int p, bool f32, int B, const void* H, const vo
                         hipStream_t s)
 {
     PMG_TYPED(f32, PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_cycle<T_, P_, D_>), dim3(B),
-                                                              dim3(NT), 0, s, *(const Hier<T_>*)H,
+                                                              dim3(NT), 0, s, (const Hier<T_>*)H,
                                                               (const T_*)r, (T_*)y)));
     return last();
 }

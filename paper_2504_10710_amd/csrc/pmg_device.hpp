@@ -144,7 +144,7 @@ __device__ inline bool is_boundary(int q)
 // then (A x)(n) = sum_a sum_k D[k][n_a] f_a(n with axis a <- k) on interior
 // rows.  RESID: out = r - A x.  out has zero boundary rows.
 template <class T, int P, int DIM, bool RESID>
-__device__ void apply_level(const T* __restrict__ G, const T* __restrict__ D,
+__device__ __attribute__((noinline)) void apply_level(const T* __restrict__ G, const T* __restrict__ D,
                             const T* __restrict__ DT, T* __restrict__ TR,
                             const T* __restrict__ x, const T* __restrict__ r, T* __restrict__ out)
 {
@@ -234,7 +234,7 @@ __device__ inline void line_base(int dir, int line, int& base, int& st)
 //   up:   y_F = x_F - (l_F e_{F-1} + u_F e_{F+1}) / a_F         (x + P e)
 // FUSED: instead of storing z, x += alpha z.
 template <class T, int P, int DIM, bool FUSED>
-__device__ void line_cr(const T* __restrict__ cr, int dir, T* __restrict__ g,
+__device__ __attribute__((noinline)) void line_cr(const T* __restrict__ cr, int dir, T* __restrict__ g,
                         T* __restrict__ x, T alpha)
 {
     using S = Shape<P, DIM>;
@@ -365,7 +365,7 @@ __device__ void prolong_axis(const T* __restrict__ in, T* __restrict__ out, int 
 
 // rc = R_l rf with zero coarse boundary (Sec. 3.3, R = P^T)
 template <class T, int P, int DIM>
-__device__ void restrict_level(const T* rf, T* rc, const T* J, T* w1, T* w2)
+__device__ __attribute__((noinline)) void restrict_level(const T* rf, T* rc, const T* J, T* w1, T* w2)
 {
     constexpr int n1f = P + 1, n1c = P / 2 + 1;
     if (DIM == 2) {
@@ -380,7 +380,7 @@ __device__ void restrict_level(const T* rf, T* rc, const T* J, T* w1, T* w2)
 
 // xf += P_l ec
 template <class T, int P, int DIM>
-__device__ void prolong_level(const T* ec, T* xf, const T* J, const T* JT, T* w1, T* w2)
+__device__ __attribute__((noinline)) void prolong_level(const T* ec, T* xf, const T* J, const T* JT, T* w1, T* w2)
 {
     constexpr int n1f = P + 1, n1c = P / 2 + 1;
     if (DIM == 2) {
@@ -423,7 +423,7 @@ __device__ void smooth_step(const Hier<T>& H, int b, int dir, const T* r, T* x, 
 // m post-smoothing steps per axis in reverse axis order}; level 0 (p = 2,
 // one interior node) is solved exactly.
 template <class T, int P, int DIM>
-__device__ void gamma_cycle(const Hier<T>& H, int b, const T* r, T* x)
+__device__ __attribute__((noinline)) void gamma_cycle(const Hier<T>& H, int b, const T* r, T* x)
 {
     using S = Shape<P, DIM>;
     const LevelData<T>& L = lvl<T, P, DIM>(H);

@@ -64,8 +64,9 @@ struct SolveArgs {
 // All launchers return a hipError_t value (hipSuccess on success).
 hipError_t launch_setup(int dim, int p_fine, int nlev, int B, const SetupArgs& a,
                         pmg_info* info, hipStream_t s);
-hipError_t launch_rhs(int dim, int p, int B, const Hier<double>& H64, const double* f,
-                      const double* g, double* b, double* tmp, hipStream_t s,
+// tmp: per-problem scratch of N doubles at tmp + b * tmp_stride
+hipError_t launch_rhs(int dim, int p, int B, const Hier<double>* H64, const double* f,
+                      const double* g, double* b, double* tmp, long long tmp_stride, hipStream_t s,
                       const int* slots = nullptr, int nslots = 0);
 hipError_t launch_lift(int dim, int p, int B, const double* w, const double* g, double* u,
                        hipStream_t s);
@@ -96,7 +97,7 @@ hipError_t launch_pool_start(const int* slots, int n, const int* sstatus, SolveS
 hipError_t launch_pool_idle(SolveState* st, int B, hipStream_t s);
 hipError_t launch_pool_take(int dim, int p, int slot, const double* w, const double* g, double* u,
                             SolveState* st, hipStream_t s);
-hipError_t launch_line_coefs(int dim, int p, int B, const Hier<double>& H64, int smoother,
+hipError_t launch_line_coefs(int dim, int p, int B, const Hier<double>* H64, int smoother,
                              int dir, double* lo, double* di, double* up, hipStream_t s);
 
 }  // namespace pmg

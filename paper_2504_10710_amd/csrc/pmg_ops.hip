@@ -9,8 +9,9 @@ namespace pmg {
 // ================================================================== level operations
 
 template <class T, int P, int DIM>
-__global__ void __launch_bounds__(NT) k_apply(Hier<T> H, const T* __restrict__ x, T* __restrict__ y)
+__global__ void __launch_bounds__(NT) k_apply(const Hier<T>* __restrict__ Hp, const T* __restrict__ x, T* __restrict__ y)
 {
+    const Hier<T>& H = *Hp;
     using S = Shape<P, DIM>;
     const long long b = blockIdx.x;
     const LevelData<T>& L = H.lev[S::LEV];
@@ -19,8 +20,9 @@ __global__ void __launch_bounds__(NT) k_apply(Hier<T> H, const T* __restrict__ x
 }
 
 template <class T, int P, int DIM>
-__global__ void __launch_bounds__(NT) k_restrict(Hier<T> H, const T* __restrict__ rf, T* __restrict__ rc)
+__global__ void __launch_bounds__(NT) k_restrict(const Hier<T>* __restrict__ Hp, const T* __restrict__ rf, T* __restrict__ rc)
 {
+    const Hier<T>& H = *Hp;
     using S = Shape<P, DIM>;
     using C = Shape<P / 2, DIM>;
     const long long b = blockIdx.x;
@@ -30,8 +32,9 @@ __global__ void __launch_bounds__(NT) k_restrict(Hier<T> H, const T* __restrict_
 }
 
 template <class T, int P, int DIM>
-__global__ void __launch_bounds__(NT) k_prolong(Hier<T> H, const T* __restrict__ ec, T* __restrict__ xf)
+__global__ void __launch_bounds__(NT) k_prolong(const Hier<T>* __restrict__ Hp, const T* __restrict__ ec, T* __restrict__ xf)
 {
+    const Hier<T>& H = *Hp;
     using S = Shape<P, DIM>;
     using C = Shape<P / 2, DIM>;
     const long long b = blockIdx.x;
@@ -41,9 +44,10 @@ __global__ void __launch_bounds__(NT) k_prolong(Hier<T> H, const T* __restrict__
 }
 
 template <class T, int P, int DIM>
-__global__ void __launch_bounds__(NT) k_line_solve(Hier<T> H, int dir, const T* __restrict__ r,
+__global__ void __launch_bounds__(NT) k_line_solve(const Hier<T>* __restrict__ Hp, int dir, const T* __restrict__ r,
                                                    T* __restrict__ z)
 {
+    const Hier<T>& H = *Hp;
     using S = Shape<P, DIM>;
     const long long b = blockIdx.x;
     const LevelData<T>& L = H.lev[S::LEV];
@@ -55,9 +59,10 @@ __global__ void __launch_bounds__(NT) k_line_solve(Hier<T> H, int dir, const T* 
 }
 
 template <class T, int P, int DIM>
-__global__ void __launch_bounds__(NT) k_line_smooth(Hier<T> H, int dir, const T* __restrict__ r,
+__global__ void __launch_bounds__(NT) k_line_smooth(const Hier<T>* __restrict__ Hp, int dir, const T* __restrict__ r,
                                                     T* __restrict__ x)
 {
+    const Hier<T>& H = *Hp;
     using S = Shape<P, DIM>;
     const long long b = blockIdx.x;
     smooth_step<T, P, DIM>(H, (int)b, dir, r + b * S::N, x + b * S::N, false);
@@ -67,7 +72,7 @@ hipError_t launch_apply(int dim, int p, bool f32, int B, const void* H, const vo
                         hipStream_t s)
 {
     PMG_TYPED(f32, PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_apply<T_, P_, D_>), dim3(B),
-                                                              dim3(NT), 0, s, *(const Hier<T_>*)H,
+                                                              dim3(NT), 0, s, (const Hier<T_>*)H,
                                                               (const T_*)x, (T_*)y)));
     return last();
 }
@@ -76,7 +81,7 @@ hipError_t launch_restrict(int dim, int p, bool f32, int B, const void* H, const
                            void* rc, hipStream_t s)
 {
     PMG_TYPED(f32, PMG_DISPATCH_P4(dim, p, hipLaunchKernelGGL((k_restrict<T_, P_, D_>), dim3(B),
-                                                               dim3(NT), 0, s, *(const Hier<T_>*)H,
+                                                               dim3(NT), 0, s, (const Hier<T_>*)H,
                                                                (const T_*)rf, (T_*)rc)));
     return last();
 }
@@ -85,7 +90,7 @@ hipError_t launch_prolong(int dim, int p, bool f32, int B, const void* H, const 
                           void* xf, hipStream_t s)
 {
     PMG_TYPED(f32, PMG_DISPATCH_P4(dim, p, hipLaunchKernelGGL((k_prolong<T_, P_, D_>), dim3(B),
-                                                               dim3(NT), 0, s, *(const Hier<T_>*)H,
+                                                               dim3(NT), 0, s, (const Hier<T_>*)H,
                                                                (const T_*)ec, (T_*)xf)));
     return last();
 }
@@ -94,7 +99,7 @@ hipError_t launch_line_solve(int dim, int p, bool f32, int B, const void* H, int
                              const void* r, void* z, hipStream_t s)
 {
     PMG_TYPED(f32, PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_line_solve<T_, P_, D_>), dim3(B),
-                                                              dim3(NT), 0, s, *(const Hier<T_>*)H,
+                                                              dim3(NT), 0, s, (const Hier<T_>*)H,
                                                               dir, (const T_*)r, (T_*)z)));
     return last();
 }
@@ -103,7 +108,7 @@ hipError_t launch_line_smooth(int dim, int p, bool f32, int B, const void* H, in
                               const void* r, void* x, hipStream_t s)
 {
     PMG_TYPED(f32, PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_line_smooth<T_, P_, D_>), dim3(B),
-                                                              dim3(NT), 0, s, *(const Hier<T_>*)H,
+                                                              dim3(NT), 0, s, (const Hier<T_>*)H,
                                                               dir, (const T_*)r, (T_*)x)));
     return last();
 }

@@ -138,6 +138,82 @@ __device__ double fem_entry_2d(const double* __restrict__ X, int i, int j, int i
     return s;
 }
 
+// 3-D analogue: trilinear elements on the hexahedra of neighbouring GLL
+// nodes, 2x2x2 Gauss rule on each element's trilinear map; nodes c and c2
+// differ by at most one position per axis.
+template <int P>
+__device__ double fem_entry_3d(const double* __restrict__ X, const int* c, const int* c2)
+{
+    constexpr int n1 = P + 1, N = n1 * n1 * n1;
+    const double h = 0.5 / sqrt(3.0);
+    const double gq[2] = {0.5 - h, 0.5 + h};
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = (c[a] > c2[a] ? c[a] : c2[a]) - 1;
+        hi[a] = c[a] < c2[a] ? c[a] : c2[a];
+    }
+    double s = 0.0;
+    for (int e2 = lo[2]; e2 <= hi[2]; ++e2)
+        for (int e1 = lo[1]; e1 <= hi[1]; ++e1)
+            for (int e0 = lo[0]; e0 <= hi[0]; ++e0) {
+                if (e0 < 0 || e1 < 0 || e2 < 0 || e0 >= P || e1 >= P || e2 >= P) continue;
+                double cx[8][3];
+                for (int v = 0; v < 8; ++v) {
+                    const int q = (e0 + (v & 1)) + n1 * (e1 + ((v >> 1) & 1)) +
+                                  n1 * n1 * (e2 + ((v >> 2) & 1));
+                    for (int k = 0; k < 3; ++k) cx[v][k] = X[k * N + q];
+                }
+                const int va = (c[0] - e0) + 2 * (c[1] - e1) + 4 * (c[2] - e2);
+                const int vb = (c2[0] - e0) + 2 * (c2[1] - e1) + 4 * (c2[2] - e2);
+                for (int gi = 0; gi < 8; ++gi) {
+                    const double u[3] = {gq[gi & 1], gq[(gi >> 1) & 1], gq[(gi >> 2) & 1]};
+                    // gradient (d/du0, d/du1, d/du2) of the corner function v
+                    auto grad = [&](int v, double* g) {
+                        double f[3], df[3];
+                        for (int k = 0; k < 3; ++k) {
+                            const int bit = (v >> k) & 1;
+                            f[k] = bit ? u[k] : 1.0 - u[k];
+                            df[k] = bit ? 1.0 : -1.0;
+                        }
+                        g[0] = df[0] * f[1] * f[2];
+                        g[1] = f[0] * df[1] * f[2];
+                        g[2] = f[0] * f[1] * df[2];
+                    };
+                    double Jm[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // Jm[comp][ref axis]
+                    for (int v = 0; v < 8; ++v) {
+                        double g[3];
+                        grad(v, g);
+                        for (int k = 0; k < 3; ++k)
+                            for (int a = 0; a < 3; ++a) Jm[k][a] += cx[v][k] * g[a];
+                    }
+                    const double c00 = Jm[1][1] * Jm[2][2] - Jm[1][2] * Jm[2][1];
+                    const double c01 = Jm[1][2] * Jm[2][0] - Jm[1][0] * Jm[2][2];
+                    const double c02 = Jm[1][0] * Jm[2][1] - Jm[1][1] * Jm[2][0];
+                    const double det = Jm[0][0] * c00 + Jm[0][1] * c01 + Jm[0][2] * c02;
+                    double inv[3][3];  // inv[a][comp] = d u_a / d x_comp
+                    inv[0][0] = c00 / det;
+                    inv[1][0] = c01 / det;
+                    inv[2][0] = c02 / det;
+                    inv[0][1] = (Jm[0][2] * Jm[2][1] - Jm[0][1] * Jm[2][2]) / det;
+                    inv[1][1] = (Jm[0][0] * Jm[2][2] - Jm[0][2] * Jm[2][0]) / det;
+                    inv[2][1] = (Jm[0][1] * Jm[2][0] - Jm[0][0] * Jm[2][1]) / det;
+                    inv[0][2] = (Jm[0][1] * Jm[1][2] - Jm[0][2] * Jm[1][1]) / det;
+                    inv[1][2] = (Jm[0][2] * Jm[1][0] - Jm[0][0] * Jm[1][2]) / det;
+                    inv[2][2] = (Jm[0][0] * Jm[1][1] - Jm[0][1] * Jm[1][0]) / det;
+                    double ga[3], gb[3], pa[3] = {0, 0, 0}, pb[3] = {0, 0, 0};
+                    grad(va, ga);
+                    grad(vb, gb);
+                    for (int k = 0; k < 3; ++k)
+                        for (int a = 0; a < 3; ++a) {
+                            pa[k] += inv[a][k] * ga[a];
+                            pb[k] += inv[a][k] * gb[a];
+                        }
+                    s += 0.125 * fabs(det) * (pa[0] * pb[0] + pa[1] * pb[1] + pa[2] * pb[2]);
+                }
+            }
+    return s;
+}
+
 // Entry of A_p (eq. discreteBilinear) between node q (multi-index c) and its
 // neighbour along axis dir (offset dd = -1, 0 or +1 along that axis), read off
 // the tensor-product structure: the G_dd term along the line, plus the
@@ -190,6 +266,13 @@ __device__ void line_raw(const double* Gb, const double* Xb, const double* D, in
         a = fem_entry_2d<P>(Xb, c[0], c[1], c[0], c[1]);
         l = s > 0 ? fem_entry_2d<P>(Xb, c[0], c[1], c[0] - di, c[1] - dj) : 0.0;
         u = s < n - 1 ? fem_entry_2d<P>(Xb, c[0], c[1], c[0] + di, c[1] + dj) : 0.0;
+    } else if (smoother == PMG_SMOOTHER_FEM) {
+        int cl[3] = {c[0], c[1], c[2]}, cu[3] = {c[0], c[1], c[2]};
+        cl[dir] -= 1;
+        cu[dir] += 1;
+        a = fem_entry_3d<P>(Xb, c, c);
+        l = s > 0 ? fem_entry_3d<P>(Xb, c, cl) : 0.0;
+        u = s < n - 1 ? fem_entry_3d<P>(Xb, c, cu) : 0.0;
     } else {
         a = gll_entry<P, DIM>(Gb, D, q, c, dir, 0);
         l = s > 0 ? gll_entry<P, DIM>(Gb, D, q, c, dir, -1) : 0.0;
@@ -302,15 +385,17 @@ __global__ void k_setup_finish(const double* __restrict__ detmin, const int* __r
 
 // b = M f - A v on interior nodes, 0 on the boundary (Sec. 2.3)
 template <int P, int DIM>
-__global__ void __launch_bounds__(NT) k_rhs(Hier<double> H, const double* __restrict__ f,
+__global__ void __launch_bounds__(NT) k_rhs(const Hier<double>* __restrict__ Hp, const double* __restrict__ f,
                                             const double* __restrict__ g, double* __restrict__ bo,
-                                            double* __restrict__ tmp, const int* slots)
+                                            double* __restrict__ tmp, long long tmp_stride,
+                                            const int* slots)
 {
+    const Hier<double>& H = *Hp;
     using S = Shape<P, DIM>;
     constexpr int N = S::N;
     const long long b = slots ? slots[blockIdx.x] : blockIdx.x;
     const LevelData<double>& L = H.lev[S::LEV];
-    double* v = tmp + b * N;
+    double* v = tmp + b * tmp_stride;   // the problem's own scratch
     for (int q = threadIdx.x; q < N; q += NT) v[q] = is_boundary<P, DIM>(q) ? g[b * N + q] : 0.0;
     wg_barrier();
     double* out = bo + b * N;
@@ -331,9 +416,10 @@ __global__ void __launch_bounds__(NT) k_lift(const double* __restrict__ w,
 }
 
 template <int P, int DIM>
-__global__ void __launch_bounds__(NT) k_line_coefs(Hier<double> H, int smoother, int dir,
+__global__ void __launch_bounds__(NT) k_line_coefs(const Hier<double>* __restrict__ Hp, int smoother, int dir,
                                                    double* lo, double* di, double* up)
 {
+    const Hier<double>& H = *Hp;
     using S = Shape<P, DIM>;
     constexpr int n = S::n, NL = S::NL;
     const long long b = blockIdx.x;
@@ -421,14 +507,14 @@ hipError_t launch_setup(int dim, int p_fine, int nlev, int B, const SetupArgs& a
     return last();
 }
 
-hipError_t launch_rhs(int dim, int p, int B, const Hier<double>& H64, const double* f,
-                      const double* g, double* b, double* tmp, hipStream_t s, const int* slots,
-                      int nslots)
+hipError_t launch_rhs(int dim, int p, int B, const Hier<double>* H64, const double* f,
+                      const double* g, double* b, double* tmp, long long tmp_stride, hipStream_t s,
+                      const int* slots, int nslots)
 {
     const int nb = slots ? nslots : B;
     if (nb <= 0) return hipSuccess;
     PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_rhs<P_, D_>), dim3(nb), dim3(NT), 0, s, H64, f,
-                                               g, b, tmp, slots));
+                                               g, b, tmp, tmp_stride, slots));
     return last();
 }
 
@@ -439,7 +525,7 @@ hipError_t launch_lift(int dim, int p, int B, const double* w, const double* g, 
     return last();
 }
 
-hipError_t launch_line_coefs(int dim, int p, int B, const Hier<double>& H64, int smoother, int dir,
+hipError_t launch_line_coefs(int dim, int p, int B, const Hier<double>* H64, int smoother, int dir,
                              double* lo, double* di, double* up, hipStream_t s)
 {
     PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_line_coefs<P_, D_>), dim3(B), dim3(NT), 0, s,

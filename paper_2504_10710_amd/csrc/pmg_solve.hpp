@@ -55,8 +55,9 @@ __device__ void apply64(const Hier<T>& H, const SolveArgs& A, int b, const doubl
 // true residual ||b - A x|| <= rtol ||b||.  At most A.budget iterations are
 // taken in this launch; the state is saved in A.st[b].
 template <class T, int P, int DIM>
-__global__ void __launch_bounds__(NT) k_solve(Hier<T> H, SolveArgs A)
+__global__ void __launch_bounds__(NT, 8) k_solve(const Hier<T>* __restrict__ Hp, SolveArgs A)
 {
+    const Hier<T>& H = *Hp;
     using S = Shape<P, DIM>;
     constexpr int N = S::N;
     __shared__ double red[NT];

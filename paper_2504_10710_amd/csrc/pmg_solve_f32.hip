@@ -7,7 +7,7 @@ hipError_t launch_solve_f32(int dim, int p, bool f32, int B, const void* H, cons
                         hipStream_t s)
 {
     PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_solve<float, P_, D_>), dim3(B),
-                                                              dim3(NT), 0, s, *(const Hier<float>*)H,
+                                                              dim3(NT), 0, s, (const Hier<float>*)H,
                                                               a));
     return last();
 }

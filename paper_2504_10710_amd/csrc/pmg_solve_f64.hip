@@ -7,7 +7,7 @@ hipError_t launch_solve_f64(int dim, int p, bool f32, int B, const void* H, cons
                         hipStream_t s)
 {
     PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_solve<double, P_, D_>), dim3(B),
-                                                              dim3(NT), 0, s, *(const Hier<double>*)H,
+                                                              dim3(NT), 0, s, (const Hier<double>*)H,
                                                               a));
     return last();
 }

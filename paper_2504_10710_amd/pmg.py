@@ -34,6 +34,19 @@ class pmg_desc(ctypes.Structure):
                 ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double)]
 
 
+MAX_CLASSES = 8
+
+
+class pmg_server_desc(ctypes.Structure):
+    _fields_ = [("n_classes", ctypes.c_int), ("classes", pmg_desc * MAX_CLASSES),
+                ("iters_per_step", ctypes.c_int), ("budget_bytes", ctypes.c_size_t)]
+
+
+class pmg_server_stats(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_int), ("running", ctypes.c_int), ("finished", ctypes.c_int),
+                ("bytes_in_use", ctypes.c_size_t), ("steps", ctypes.c_longlong)]
+
+
 INFO_DTYPE = np.dtype([("status", np.int32), ("iterations", np.int32),
                        ("relres", np.float64), ("min_detj", np.float64)])
 INFO_BYTES = INFO_DTYPE.itemsize  # 24, the layout of pmg_info
@@ -73,6 +86,25 @@ def lib():
             "pmg_line_coefs": (i, [vp, i, i, vp, vp, vp, vp]),
             "pmg_geom": (i, [vp, i, vp, vp, vp]),
             "pmg_destroy": (i, [vp]),
+            "pmg_pool_workspace_bytes": (i, [ctypes.POINTER(pmg_desc), ctypes.POINTER(ctypes.c_size_t)]),
+            "pmg_pool_create": (i, [ctypes.POINTER(pmg_desc), i, vp, ctypes.c_size_t, vp,
+                                    ctypes.POINTER(vp)]),
+            "pmg_pool_admit": (i, [vp, i, ctypes.POINTER(i), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                   ctypes.POINTER(vp), vp]),
+            "pmg_pool_step": (i, [vp, vp]),
+            "pmg_pool_poll": (i, [vp, ctypes.POINTER(i), vp, vp]),
+            "pmg_pool_take": (i, [vp, i, vp, vp]),
+            "pmg_pool_destroy": (i, [vp]),
+            "pmg_server_workspace_bytes": (i, [ctypes.POINTER(pmg_server_desc),
+                                               ctypes.POINTER(ctypes.c_size_t)]),
+            "pmg_server_create": (i, [ctypes.POINTER(pmg_server_desc), vp, ctypes.c_size_t,
+                                      ctypes.POINTER(vp)]),
+            "pmg_server_submit": (i, [vp, i, ctypes.POINTER(vp), vp, vp, vp,
+                                      ctypes.POINTER(ctypes.c_longlong)]),
+            "pmg_server_step": (i, [vp, ctypes.POINTER(i)]),
+            "pmg_server_poll": (i, [vp, ctypes.c_longlong, vp]),
+            "pmg_server_stats_get": (i, [vp, ctypes.POINTER(pmg_server_stats)]),
+            "pmg_server_destroy": (i, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -87,7 +119,11 @@ def exported_symbols():
     return ["pmg_last_error", "pmg_num_levels", "pmg_gll", "pmg_interp", "pmg_workspace_bytes",
             "pmg_setup", "pmg_rhs", "pmg_lift", "pmg_apply", "pmg_restrict", "pmg_prolong_add",
             "pmg_line_solve", "pmg_line_smooth", "pmg_gamma_cycle", "pmg_solve",
-            "pmg_line_coefs", "pmg_geom", "pmg_destroy"]
+            "pmg_line_coefs", "pmg_geom", "pmg_destroy", "pmg_pool_workspace_bytes",
+            "pmg_pool_create", "pmg_pool_admit", "pmg_pool_step", "pmg_pool_poll", "pmg_pool_take",
+            "pmg_pool_destroy", "pmg_server_workspace_bytes", "pmg_server_create",
+            "pmg_server_submit", "pmg_server_step", "pmg_server_poll", "pmg_server_stats_get",
+            "pmg_server_destroy"]
 
 
 def _check(rc):
@@ -202,6 +238,108 @@ def pmg_geom(h, level, G, mass=None, stream=None):
 def pmg_destroy(h):
     if h:
         _check(lib().pmg_destroy(h))
+
+
+# ------------------------------------------------------------------ serving
+
+def pmg_pool_workspace_bytes(desc: pmg_desc) -> int:
+    n = ctypes.c_size_t(0)
+    _check(lib().pmg_pool_workspace_bytes(ctypes.byref(desc), ctypes.byref(n)))
+    return n.value
+
+
+def pmg_pool_create(desc, iters_per_step, ws, stream=None):
+    h = ctypes.c_void_p()
+    _check(lib().pmg_pool_create(ctypes.byref(desc), iters_per_step, _ptr(ws),
+                                 ws.numel() * ws.element_size(), _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def pmg_pool_admit(pool, slots, coords, fs, gs, stream=None):
+    """slots: list of slot ids; coords: per request a list of level tensors
+    (coarsest first); fs, gs: per request finest-level tensors."""
+    n = len(slots)
+    sl = (ctypes.c_int * n)(*slots)
+    cp = (ctypes.c_void_p * sum(len(c) for c in coords))(*[t.data_ptr() for c in coords for t in c])
+    fp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in fs])
+    gp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in gs])
+    _check(lib().pmg_pool_admit(pool, n, sl, cp, fp, gp, _stream(stream)))
+
+
+def pmg_pool_step(pool, stream=None):
+    _check(lib().pmg_pool_step(pool, _stream(stream)))
+
+
+def pmg_pool_poll(pool, nslots, stream=None):
+    st = (ctypes.c_int * nslots)()
+    info = np.zeros(nslots, dtype=INFO_DTYPE)
+    _check(lib().pmg_pool_poll(pool, st, ctypes.c_void_p(info.ctypes.data), _stream(stream)))
+    return np.array(st[:], dtype=np.int32), info
+
+
+def pmg_pool_take(pool, slot, u, stream=None):
+    _check(lib().pmg_pool_take(pool, slot, _ptr(u), _stream(stream)))
+
+
+def pmg_pool_destroy(pool):
+    if pool:
+        _check(lib().pmg_pool_destroy(pool))
+
+
+def make_server_desc(classes, iters_per_step=4, budget_bytes=1 << 40):
+    d = pmg_server_desc()
+    d.n_classes = len(classes)
+    for k, c in enumerate(classes):
+        d.classes[k] = c
+    d.iters_per_step = iters_per_step
+    d.budget_bytes = budget_bytes
+    return d
+
+
+def pmg_server_workspace_bytes(desc) -> int:
+    n = ctypes.c_size_t(0)
+    _check(lib().pmg_server_workspace_bytes(ctypes.byref(desc), ctypes.byref(n)))
+    return n.value
+
+
+def pmg_server_create(desc, ws):
+    h = ctypes.c_void_p()
+    _check(lib().pmg_server_create(ctypes.byref(desc), _ptr(ws), ws.numel() * ws.element_size(),
+                                   ctypes.byref(h)))
+    return h
+
+
+def pmg_server_submit(srv, cls, coords, f, g, u) -> int:
+    cp = (ctypes.c_void_p * len(coords))(*[t.data_ptr() for t in coords])
+    t = ctypes.c_longlong(-1)
+    _check(lib().pmg_server_submit(srv, cls, cp, _ptr(f), _ptr(g), _ptr(u), ctypes.byref(t)))
+    return t.value
+
+
+def pmg_server_step(srv) -> int:
+    n = ctypes.c_int(0)
+    _check(lib().pmg_server_step(srv, ctypes.byref(n)))
+    return n.value
+
+
+def pmg_server_poll(srv, ticket):
+    info = np.zeros(1, dtype=INFO_DTYPE)
+    rc = lib().pmg_server_poll(srv, ticket, ctypes.c_void_p(info.ctypes.data))
+    if rc < 0:
+        _check(rc)
+    return rc == 1, info[0]
+
+
+def pmg_server_stats_get(srv):
+    st = pmg_server_stats()
+    _check(lib().pmg_server_stats_get(srv, ctypes.byref(st)))
+    return {"queued": st.queued, "running": st.running, "finished": st.finished,
+            "bytes_in_use": st.bytes_in_use, "steps": st.steps}
+
+
+def pmg_server_destroy(srv):
+    if srv:
+        _check(lib().pmg_server_destroy(srv))
 
 
 def info_to_numpy(info_tensor) -> np.ndarray:

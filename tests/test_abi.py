@@ -37,7 +37,7 @@ def test_host_gll_matches_closed_forms():
 
 @pytest.mark.parametrize("kw,msg", [
     (dict(dim=4), "dim"), (dict(p_fine=12), "p_fine"), (dict(dim=3, p_fine=128), "p_fine"),
-    (dict(gamma=0), "gamma"), (dict(alpha=-1.0), "alpha"), (dict(dim=3, smoother=1), "FEM"),
+    (dict(gamma=0), "gamma"), (dict(alpha=-1.0), "alpha"), (dict(smoother=5), "smoother"),
     (dict(restart=0), "restart"), (dict(batch=0), "batch"), (dict(krylov=7), "Krylov")])
 def test_invalid_descriptions(kw, msg):
     with pytest.raises(pmg.PmgError) as e:

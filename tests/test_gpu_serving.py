@@ -1,0 +1,136 @@
+"""Serving: pools and the continuous-batching server against the one-shot
+batched solve.  A pooled solve runs exactly the arithmetic of pmg_solve (same
+resumable kernel, one workgroup per problem, fixed-order reductions), so
+results must be bit-identical however requests are batched, admitted or split
+into steps; admission must respect slots and the byte budget."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2504_10710_amd import inputs, pmg  # noqa: E402
+from tests.gpu_helpers import gpu_batch, problems  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _request_data(prob, p):
+    ps = inputs.halving_degrees(p, 2)
+    coords = [torch.from_numpy(prob.coords(pmg.pmg_gll(q)[0])).cuda().contiguous() for q in ps]
+    X = prob.coords(pmg.pmg_gll(p)[0])
+    f = torch.from_numpy(prob.f(X)).cuda()
+    g = torch.from_numpy(prob.g(X)).cuda()
+    return coords, f, g
+
+
+def _one_shot(probs, p, **kw):
+    s, f, g = gpu_batch(probs, p, **kw)
+    b = torch.empty_like(f)
+    x = torch.empty_like(f)
+    u = torch.empty_like(f)
+    pmg.pmg_rhs(s.h, f, g, b)
+    pmg.pmg_solve(s.h, b, x, s.info)
+    pmg.pmg_lift(s.h, x, g, u)
+    torch.cuda.synchronize()
+    return u.cpu().numpy(), s.info_host()
+
+
+def test_pool_matches_one_shot_solve():
+    p = 16
+    kw = dict(gamma=2, alpha=0.16, smoother=pmg.PMG_SMOOTHER_FEM)
+    probs = problems("cfg2", [20, 21, 22, 23])
+    ref_u, ref_info = _one_shot(probs, p, **kw)
+
+    desc = pmg.make_desc(dim=2, p_fine=p, batch=6, **kw)
+    ws = torch.empty(pmg.pmg_pool_workspace_bytes(desc), dtype=torch.uint8, device="cuda")
+    pool = pmg.pmg_pool_create(desc, 3, ws)
+    data = [_request_data(pr, p) for pr in probs]
+    outs = [torch.empty_like(d[1]) for d in data]
+    # two requests first, two more arrive while the first are running
+    pmg.pmg_pool_admit(pool, [4, 1], [data[0][0], data[1][0]], [data[0][1], data[1][1]],
+                       [data[0][2], data[1][2]])
+    pmg.pmg_pool_step(pool)
+    slot_of = {0: 4, 1: 1}
+    pmg.pmg_pool_admit(pool, [0, 2], [data[2][0], data[3][0]], [data[2][1], data[3][1]],
+                       [data[2][2], data[3][2]])
+    slot_of.update({2: 0, 3: 2})
+    done = {}
+    for _ in range(100):
+        pmg.pmg_pool_step(pool)
+        st, info = pmg.pmg_pool_poll(pool, 6)
+        for i, sl in slot_of.items():
+            if i not in done and st[sl] <= 0:
+                assert st[sl] == 0, (i, st[sl])
+                pmg.pmg_pool_take(pool, sl, outs[i])
+                done[i] = info[sl]
+        if len(done) == 4:
+            break
+    torch.cuda.synchronize()
+    assert len(done) == 4
+    st, _ = pmg.pmg_pool_poll(pool, 6)
+    assert np.all(st == 2)  # every slot idle again
+    for i in range(4):
+        assert np.array_equal(outs[i].cpu().numpy(), ref_u[i]), i
+        assert done[i]["iterations"] == ref_info["iterations"][i]
+        assert done[i]["relres"] == ref_info["relres"][i]
+    pmg.pmg_pool_destroy(pool)
+
+
+def test_server_mixed_classes_budget_and_bitwise_results():
+    classes = [
+        pmg.make_desc(dim=2, p_fine=16, batch=3, gamma=1, alpha=0.16,
+                      smoother=pmg.PMG_SMOOTHER_FEM, inner_prec=pmg.PMG_F32),
+        pmg.make_desc(dim=2, p_fine=32, batch=2, gamma=1, alpha=0.16,
+                      smoother=pmg.PMG_SMOOTHER_FEM, inner_prec=pmg.PMG_F32),
+        pmg.make_desc(dim=3, p_fine=8, batch=2, gamma=1, alpha=0.3,
+                      smoother=pmg.PMG_SMOOTHER_GLL, inner_prec=pmg.PMG_F32, restart=10),
+    ]
+    fp = [pmg.pmg_pool_workspace_bytes(c) // c.batch for c in classes]
+    budget = fp[0] * 2 + fp[1] + fp[2]       # forces queueing
+    sdesc = pmg.make_server_desc(classes, iters_per_step=2, budget_bytes=budget)
+    ws = torch.empty(pmg.pmg_server_workspace_bytes(sdesc), dtype=torch.uint8, device="cuda")
+    srv = pmg.pmg_server_create(sdesc, ws)
+
+    reqs = [(0, inputs.config2(30 + i), 16) for i in range(5)] + \
+           [(1, inputs.config2(40 + i), 32) for i in range(3)] + \
+           [(2, inputs.config3(50 + i), 8) for i in range(3)]
+    data, outs, tickets = [], [], []
+    order = [0, 5, 8, 1, 2, 6, 9, 3, 7, 10, 4]   # interleaved arrivals
+    pending = list(order)
+    max_bytes = 0
+    for step in range(400):
+        # two new requests arrive before every step
+        for _ in range(2):
+            if pending:
+                k = pending.pop(0)
+                c, prob, p = reqs[k]
+                d = _request_data(prob, p)
+                u = torch.empty_like(d[1])
+                data.append((k, d))
+                outs.append((k, u))
+                tickets.append((k, pmg.pmg_server_submit(srv, c, d[0], d[1], d[2], u)))
+        pmg.pmg_server_step(srv)
+        st = pmg.pmg_server_stats_get(srv)
+        max_bytes = max(max_bytes, st["bytes_in_use"])
+        assert st["bytes_in_use"] <= budget
+        if not pending and st["finished"] == len(reqs):
+            break
+    torch.cuda.synchronize()
+    assert pmg.pmg_server_stats_get(srv)["finished"] == len(reqs)
+    assert max_bytes > 0
+    res = {}
+    for (k, t), (_, u) in zip(tickets, outs):
+        ok, info = pmg.pmg_server_poll(srv, t)
+        assert ok and info["status"] == 0 and info["relres"] <= 1e-10, (k, info)
+        res[k] = (u.cpu().numpy(), info)
+    pmg.pmg_server_destroy(srv)
+    # each result equals the same problem solved alone in a one-shot batch
+    for c, desc in enumerate(classes):
+        ks = [k for k in range(len(reqs)) if reqs[k][0] == c]
+        for k in ks:
+            _, prob, p = reqs[k]
+            kw = dict(gamma=desc.gamma, alpha=desc.alpha, smoother=desc.smoother,
+                      inner_prec=desc.inner_prec, restart=desc.restart)
+            ref_u, ref_info = _one_shot([prob], p, **kw)
+            assert np.array_equal(res[k][0], ref_u[0]), k
+            assert res[k][1]["iterations"] == ref_info["iterations"][0]

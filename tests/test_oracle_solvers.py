@@ -242,6 +242,20 @@ def test_pcg_config1():
     assert np.abs(u - prob.exact(X)).max() < 1e-7
 
 
+@pytest.mark.parametrize("p", [8, 16])
+def test_iterations_bounded_3d_fem(p):
+    """3-D config-3 problems with the trilinear FEM line smoother, alpha = 0.16."""
+    its = []
+    for seed in range(3):
+        prob = inputs.config3(seed)
+        h, ps, coords = _hier(prob, p, gamma=1, alpha=0.16, smoother=1)
+        X = coords[-1]
+        x, st, it, hist = h.fgmres(h.rhs(prob.f(X), prob.g(X)), rtol=1e-10, maxit=100)
+        assert st == 0, (seed, it)
+        its.append(it)
+    assert max(its) <= 14, its
+
+
 @pytest.mark.parametrize("p", [16, 32, 64])
 def test_iterations_bounded_over_seeds(p):
     """Iteration counts stay bounded as deformation, RHS and Dirichlet data vary
@@ -256,6 +270,22 @@ def test_iterations_bounded_over_seeds(p):
         assert st == 0, (seed, it)
         its.append(it)
     assert max(its) <= 16 and max(its) <= 1.5 * np.median(its), its
+
+
+def test_fem_entries_3d():
+    """Trilinear FEM stiffness on the GLL node mesh of the unit cube: symmetric,
+    rows sum to zero, exact energy of trilinear functions."""
+    p = 4
+    prob = inputs.Problem(3, "deformed3d", {"beta": np.zeros(3), "amp": np.zeros(3),
+                                             "c": np.zeros((3, 3, 3))})
+    h, ps, coords = _hier(prob, p, p_coarse=p, smoother=1)
+    N = (p + 1) ** 3
+    A = np.array([[h.fem_entry(i, j) for j in range(N)] for i in range(N)])
+    np.testing.assert_allclose(A, A.T, atol=1e-13)
+    np.testing.assert_allclose(A.sum(axis=1), 0.0, atol=1e-12)
+    x, y, z = coords[-1]
+    for u, exact in [(x, 1.0), (x * y, 2.0 / 3.0), (x * y * z, 1.0 / 3.0), (x + y - z, 3.0)]:
+        np.testing.assert_allclose(u @ A @ u, exact, rtol=1e-13)
 
 
 def test_fem_entries():
