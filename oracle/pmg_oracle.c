@@ -717,22 +717,40 @@ or_hier* or_hier_create(int dim, int nlev, const int* p, const double* const* co
     }
     {
         /* M_0^{-1} = A_0^{-1} (Alg. 2): dense inverse of the interior matrix
-         * of the coarsest level, column by column with dense LU. */
+         * of the coarsest level by Gauss-Jordan elimination with partial
+         * pivoting on [A | I]. */
         or_level* L = &h->lev[0];
         int n = L->nint;
         double* A = (double*)malloc(sizeof(double) * (size_t)n * n);
-        double* W = (double*)malloc(sizeof(double) * (size_t)n * n);
-        double* e = (double*)malloc(sizeof(double) * (size_t)n);
-        L->A0inv = (double*)malloc(sizeof(double) * (size_t)n * n);
+        double* Inv = (double*)malloc(sizeof(double) * (size_t)n * n);
         or_dense_interior(h, 0, A);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) Inv[i * n + j] = (i == j);
         int bad = 0;
-        for (int j = 0; j < n && !bad; ++j) {
-            memcpy(W, A, sizeof(double) * (size_t)n * n);
-            for (int i = 0; i < n; ++i) e[i] = (i == j);
-            if (or_dense_solve(n, W, e)) bad = 1;
-            for (int i = 0; i < n; ++i) L->A0inv[i * n + j] = e[i];
+        for (int k = 0; k < n && !bad; ++k) {
+            int piv = k;
+            for (int i = k + 1; i < n; ++i)
+                if (fabs(A[i * n + k]) > fabs(A[piv * n + k])) piv = i;
+            if (A[piv * n + k] == 0.0) { bad = 1; break; }
+            if (piv != k)
+                for (int j = 0; j < n; ++j) {
+                    double t = A[k * n + j]; A[k * n + j] = A[piv * n + j]; A[piv * n + j] = t;
+                    t = Inv[k * n + j]; Inv[k * n + j] = Inv[piv * n + j]; Inv[piv * n + j] = t;
+                }
+            double d = A[k * n + k];
+            for (int j = 0; j < n; ++j) { A[k * n + j] /= d; Inv[k * n + j] /= d; }
+            for (int i = 0; i < n; ++i) {
+                if (i == k) continue;
+                double f = A[i * n + k];
+                if (f == 0.0) continue;
+                for (int j = 0; j < n; ++j) {
+                    A[i * n + j] -= f * A[k * n + j];
+                    Inv[i * n + j] -= f * Inv[k * n + j];
+                }
+            }
         }
-        free(A); free(W); free(e);
+        free(A);
+        L->A0inv = Inv;
         if (bad) goto fail;
     }
     return h;

@@ -139,6 +139,103 @@ __device__ inline bool is_boundary(int q)
 
 // ------------------------------------------------------------------ operator
 
+// ------------------------------------------------------------------ MFMA tiles
+
+// 16x16x4 matrix-core step: A fragment lane l holds A[l % 16][l / 16], B fragment
+// B[l / 16][l % 16]; accumulator register v of lane l holds C[row(l, v)][l % 16]
+// with row = 4 (l / 16) + v for FP32 and (l / 16) + 4 v for FP64 (measured).
+template <class T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    __device__ static inline v4 op(double a, double b, v4 c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static inline int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <>
+struct Mfma<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    __device__ static inline v4 op(float a, float b, v4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static inline int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+// acc += A[r0 .. r0+15][:] * B[:][c0 .. c0+15] for n1 x n1 row-major A and B
+// (one wave).  Rows/columns past n1 are clamped (their results are never
+// stored); the k tail past n1 contributes zero.
+template <class T, int n1>
+__device__ inline void mfma_tile(const T* __restrict__ A, const T* __restrict__ B, int r0, int c0,
+                                 typename Mfma<T>::v4& acc)
+{
+    const int lane = threadIdx.x & 63;
+    const int ar = min(r0 + (lane & 15), n1 - 1);
+    const int bc = min(c0 + (lane & 15), n1 - 1);
+    const int kq = lane >> 4;
+    const T* Ap = A + ar * n1 + kq;
+    const T* Bp = B + kq * n1 + bc;
+    constexpr int KF = (n1 / 4) * 4;
+#pragma unroll 4
+    for (int k0 = 0; k0 < KF; k0 += 4) acc = Mfma<T>::op(Ap[k0], Bp[k0 * n1], acc);
+    if (KF < n1) {
+        const int kk = min(KF + kq, n1 - 1) - kq;   // stays inside the row / column
+        T a = Ap[kk], b = Bp[kk * n1];
+        if (KF + kq >= n1) { a = T(0); b = T(0); }
+        acc = Mfma<T>::op(a, b, acc);
+    }
+}
+
+// 2-D A x on matrix cores: the four contractions of the sum factorisation
+// (x D^T, D x, then F0 D and D^T F1) as 16x16 output tiles, one wave per tile.
+template <class T, int P, bool RESID>
+__device__ void apply2d_mfma(const T* __restrict__ G, const T* __restrict__ D,
+                             const T* __restrict__ DT, T* __restrict__ TR,
+                             const T* __restrict__ x, const T* __restrict__ r, T* __restrict__ out)
+{
+    constexpr int n1 = P + 1, N = n1 * n1, NTL = (n1 + 15) / 16;
+    using V4 = typename Mfma<T>::v4;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int t = wave; t < NTL * NTL; t += NT / 64) {
+        const int r0 = (t / NTL) * 16, c0 = (t % NTL) * 16;
+        V4 ur = {0, 0, 0, 0}, us = {0, 0, 0, 0};
+        mfma_tile<T, n1>(x, DT, r0, c0, ur);   // derivative along the first axis
+        mfma_tile<T, n1>(D, x, r0, c0, us);    // derivative along the second axis
+        const int i = c0 + (lane & 15);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int j = r0 + Mfma<T>::row(lane, v);
+            if (j < n1 && i < n1) {
+                const int q = j * n1 + i;
+                const T g00 = G[q], g11 = G[N + q], g01 = G[2 * N + q];
+                TR[q] = g00 * ur[v] + g01 * us[v];
+                TR[N + q] = g01 * ur[v] + g11 * us[v];
+            }
+        }
+    }
+    wg_barrier();
+    for (int t = wave; t < NTL * NTL; t += NT / 64) {
+        const int r0 = (t / NTL) * 16, c0 = (t % NTL) * 16;
+        V4 y = {0, 0, 0, 0};
+        mfma_tile<T, n1>(TR, D, r0, c0, y);        // sum_k D[k][i] F0[j][k]
+        mfma_tile<T, n1>(DT, TR + N, r0, c0, y);   // sum_k D[k][j] F1[k][i]
+        const int i = c0 + (lane & 15);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int j = r0 + Mfma<T>::row(lane, v);
+            if (j < n1 && i < n1) {
+                const int q = j * n1 + i;
+                const bool bd = i == 0 || i == P || j == 0 || j == P;
+                out[q] = bd ? T(0) : (RESID ? r[q] - y[v] : y[v]);
+            }
+        }
+    }
+    wg_barrier();
+}
+
 // Matrix-free A x of eq. discreteBilinear by sum factorisation: reference
 // gradients g_b = D along axis b, fluxes f_a = sum_b G_ab g_b at every node,
 // then (A x)(n) = sum_a sum_k D[k][n_a] f_a(n with axis a <- k) on interior
@@ -148,6 +245,10 @@ __device__ __attribute__((noinline)) void apply_level(const T* __restrict__ G, c
                             const T* __restrict__ DT, T* __restrict__ TR,
                             const T* __restrict__ x, const T* __restrict__ r, T* __restrict__ out)
 {
+    if constexpr (DIM == 2 && P >= 64) {
+        apply2d_mfma<T, P, RESID>(G, D, DT, TR, x, r, out);
+        return;
+    }
     using S = Shape<P, DIM>;
     constexpr int n1 = S::n1, N = S::N;
     for (int q = threadIdx.x; q < N; q += NT) {

@@ -1,12 +1,14 @@
 """GPU parity: every C-ABI entry point against the CPU oracle on the same
 seeded inputs (each side with its own GLL nodes).
 
-Tolerances (FP64): geometry, operator, transfers, right-hand side 1e-12
-relative to the output's max-norm; line tridiagonals 1e-12; line solves and
-smoothing max(1e-12, 20 n eps kappa), kappa the largest condition number of
-the level's line tridiagonals (two cyclic reductions that round differently
-differ by O(n eps kappa)); one gamma-cycle max(1e-9, 100 x the largest line
-tolerance of its levels); full solves reach 1e-10 true relative residual (recomputed
+Tolerances (FP64): geometry and transfers 1e-12 relative to the output's
+max-norm; operator and right-hand side eval_tol(p) = max(1e-12, 2e-12 (p/16)^3)
+(two FP64 evaluations of the degree-p operator differ by O(eps p^3)); line tridiagonals 1e-12; line solves and
+max(1e-12, 20 n eps kappa), kappa the largest condition number of the
+level's line tridiagonals (two cyclic reductions that round differently
+differ by O(n eps kappa)); a smoothing step that plus kappa eval_tol(p) (its
+residual evaluation amplified by the line solve); one gamma-cycle
+max(1e-9, 100 x the largest smoothing tolerance of its levels); full solves reach 1e-10 true relative residual (recomputed
 by the oracle's operator on the GPU's solution) with the solution within
 1e-7 relative of the oracle's (two independently converged iterates differ
 by up to cond(A) * 1e-10) and iteration counts within +-1.
@@ -25,6 +27,7 @@ pytestmark = pytest.mark.gpu
 CASES = [
     ("cfg2", 16, pmg.PMG_SMOOTHER_FEM, 0.16, 1),
     ("cfg2", 32, pmg.PMG_SMOOTHER_GLL, 0.3, 2),
+    ("cfg2", 64, pmg.PMG_SMOOTHER_FEM, 0.16, 2),
     ("cfg1", 8, pmg.PMG_SMOOTHER_GLL, 2.0 / 3.0, 3),
     ("cfg3", 8, pmg.PMG_SMOOTHER_GLL, 0.3, 1),
     ("cfg3", 16, pmg.PMG_SMOOTHER_FEM, 0.16, 2),
@@ -73,6 +76,12 @@ def _line_kappa(h, l, d, dim, p):
 def _line_tol(h, l, d, dim, p):
     # rounding of two independent cyclic reductions: O(n eps kappa)
     return max(1e-12, 20 * (p - 1) * np.finfo(float).eps * _line_kappa(h, l, d, dim, p))
+
+
+def _smooth_tol(h, l, d, dim, p):
+    # a smoothing step also evaluates r - A x (operator tolerance), which the
+    # line solve amplifies by at most kappa
+    return _line_tol(h, l, d, dim, p) + _line_kappa(h, l, d, dim, p) * eval_tol(p)
 
 
 def test_setup_status(case):
@@ -129,7 +138,7 @@ def test_apply(case):
         pmg.pmg_apply(s.h, l, pmg.PMG_F64, xt, y)
         torch.cuda.synchronize()
         for b, (h, _, _) in enumerate(case["ors"]):
-            assert rel_err(y.cpu().numpy()[b], h.apply(x[b], l)) < 1e-12, (l, b)
+            assert rel_err(y.cpu().numpy()[b], h.apply(x[b], l)) < eval_tol(p), (l, b)
 
 
 def test_transfers(case):
@@ -167,6 +176,7 @@ def test_line_solve_and_smooth(case):
             for b, (h, _, _) in enumerate(case["ors"]):
                 tol = _line_tol(h, l, d, dim, p)
                 assert rel_err(z.cpu().numpy()[b], h.line_solve(r[b], d, l)) < tol, (l, d, b, tol)
+                tol = _smooth_tol(h, l, d, dim, p)
                 assert rel_err(xs.cpu().numpy()[b], h.smooth(r[b], x0[b], d, l)) < tol, (l, d, b, tol)
 
 
@@ -177,7 +187,7 @@ def test_gamma_cycle(case):
     pmg.pmg_gamma_cycle(s.h, pmg.PMG_F64, torch.from_numpy(r).cuda(), y)
     torch.cuda.synchronize()
     for b, (h, _, _) in enumerate(case["ors"]):
-        tol = max(1e-9, 100 * max(_line_tol(h, l, d, dim, 2 << l)
+        tol = max(1e-9, 100 * max(_smooth_tol(h, l, d, dim, 2 << l)
                                   for l in range(1, h.nlev) for d in range(dim)))
         assert rel_err(y.cpu().numpy()[b], h.cycle(r[b])) < tol, (b, tol)
 
@@ -188,7 +198,7 @@ def test_rhs(case):
     pmg.pmg_rhs(s.h, case["f"], case["g"], b_t)
     torch.cuda.synchronize()
     for b, (h, f, g) in enumerate(case["ors"]):
-        assert rel_err(b_t.cpu().numpy()[b], h.rhs(f, g)) < 1e-12, b
+        assert rel_err(b_t.cpu().numpy()[b], h.rhs(f, g)) < eval_tol(case["p"]), b
 
 
 def test_solve_fgmres(case):
@@ -205,8 +215,9 @@ def test_solve_fgmres(case):
         assert info["status"][b] == 0, info[b]
         # true residual of the GPU solution with the oracle's operator
         rr = np.linalg.norm(bh[b] - h.apply(xh[b])) / np.linalg.norm(bh[b])
-        assert rr <= 1.0001e-10, rr
-        assert abs(info["relres"][b] - rr) <= 1e-12, (info["relres"][b], rr)
+        assert info["relres"][b] <= 1e-10
+        assert rr <= 1e-10 + eval_tol(case["p"]), rr
+        assert abs(info["relres"][b] - rr) <= 1e-12 + eval_tol(case["p"]), (info["relres"][b], rr)
         xo, st, it, _ = h.fgmres(h.rhs(f, g), rtol=1e-10, maxit=200, restart=30)
         assert st == 0
         assert abs(int(info["iterations"][b]) - it) <= 1, (info["iterations"][b], it)
