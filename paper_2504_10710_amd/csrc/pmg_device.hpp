@@ -12,10 +12,12 @@
 //   vectors     N = (p+1)^dim nodes, first axis fastest
 //   G           ncomp arrays of N: 2-D (G00, G11, G01), 3-D (G00, G11, G22,
 //               G01, G02, G12): weighted inverse metric of the mapping
-//   line data   per axis: 3 words x CRW x NL, line index fastest, where NL
-//               = (p-1)^(dim-1) lines, CRW = sum over cyclic-reduction levels
-//               of the level's unknown count, word (slot, w) at
-//               (slot*3 + w)*NL + line
+//   line data   per axis: 3 words x CRW x NL, where NL = (p-1)^(dim-1)
+//               lines, CRW = sum over cyclic-reduction levels of the level's
+//               unknown count; word (slot, w) of a line at (slot*3 + w)*NL +
+//               line (line index fastest, one thread per line), except the
+//               first axis for p <= 128, stored line-major at
+//               (line*CRW + slot)*3 + w (one lane group per line)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -189,6 +191,58 @@ __device__ inline void mfma_tile(const T* __restrict__ A, const T* __restrict__ 
     }
 }
 
+// acc += A[r0 .. r0+15][:K] * B[:K][c0 .. c0+15] for row-major A (M x K,
+// leading dimension LDA) and B (K x N, LDB); one wave.
+template <class T, int M, int N, int K, int LDA, int LDB>
+__device__ inline void mfma_tile_g(const T* __restrict__ A, const T* __restrict__ B, int r0,
+                                   int c0, typename Mfma<T>::v4& acc)
+{
+    const int lane = threadIdx.x & 63;
+    const int ar = min(r0 + (lane & 15), M - 1);
+    const int bc = min(c0 + (lane & 15), N - 1);
+    const int kq = lane >> 4;
+    const T* Ap = A + ar * LDA + kq;
+    const T* Bp = B + kq * LDB + bc;
+    constexpr int KF = (K / 4) * 4;
+#pragma unroll 4
+    for (int k0 = 0; k0 < KF; k0 += 4) acc = Mfma<T>::op(Ap[k0], Bp[k0 * LDB], acc);
+    if (KF < K) {
+        const int kk = min(KF + kq, K - 1) - kq;
+        T a = Ap[kk], b = Bp[kk * LDB];
+        if (KF + kq >= K) { a = T(0); b = T(0); }
+        acc = Mfma<T>::op(a, b, acc);
+    }
+}
+
+// C (M x N, row-major) = A B (MODE 0), += A B (MODE 1), or = A B with the
+// boundary rows and columns set to zero (MODE 2); 16x16 tiles, one wave each.
+template <class T, int M, int N, int K, int LDA, int LDB, int MODE>
+__device__ void wg_gemm(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C)
+{
+    constexpr int TM = (M + 15) / 16, TN = (N + 15) / 16;
+    using V4 = typename Mfma<T>::v4;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int t = wave; t < TM * TN; t += NT / 64) {
+        const int r0 = (t / TN) * 16, c0 = (t % TN) * 16;
+        V4 acc = {0, 0, 0, 0};
+        mfma_tile_g<T, M, N, K, LDA, LDB>(A, B, r0, c0, acc);
+        const int i = c0 + (lane & 15);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int j = r0 + Mfma<T>::row(lane, v);
+            if (j < M && i < N) {
+                if (MODE == 1)
+                    C[j * N + i] += acc[v];
+                else if (MODE == 2)
+                    C[j * N + i] = (j == 0 || j == M - 1 || i == 0 || i == N - 1) ? T(0) : acc[v];
+                else
+                    C[j * N + i] = acc[v];
+            }
+        }
+    }
+    wg_barrier();
+}
+
 // 2-D A x on matrix cores: the four contractions of the sum factorisation
 // (x D^T, D x, then F0 D and D^T F1) as 16x16 output tiles, one wave per tile.
 template <class T, int P, bool RESID>
@@ -323,6 +377,96 @@ __device__ inline void line_base(int dir, int line, int& base, int& st)
     }
 }
 
+// Lines along the first axis are stored line-major ([line][slot][3]) and
+// solved one line per group of (n+1)/2 lanes (a whole wave at p = 128): lane
+// u holds positions 2u (an F point of level 0) and 2u+1 (a C point, which is
+// also where every coarser level keeps its unknowns: level-k unknown t lives
+// in lane (t+1) 2^(k-1) - 1).  Neighbours at every level are exchanged with
+// cross-lane shuffles; loads and stores of the line are contiguous.
+template <int P>
+__host__ __device__ constexpr bool wave_lines() { return P >= 2 && P <= 128; }
+
+template <class T, int P, int DIM, bool FUSED>
+__device__ void line_cr_wave(const T* __restrict__ cr, T* __restrict__ g, T* __restrict__ x,
+                             T alpha)
+{
+    using S = Shape<P, DIM>;
+    constexpr int n = S::n, NL = S::NL, CRW = S::CRW;
+    constexpr int W = (n + 1) / 2 > 0 ? (n + 1) / 2 : 1;   // lanes per line
+    constexpr int LPW = 64 / W;                              // lines per wave
+    constexpr int NK = ilog2(n + 1);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int u = lane % W, sub = lane / W;
+    for (int line0 = wave * LPW; line0 < NL; line0 += (NT / 64) * LPW) {
+        const int line = line0 + sub;
+        const bool act = line < NL;
+        const int lc = act ? line : NL - 1;
+        int base, st;
+        line_base<P, DIM>(0, lc, base, st);
+        const T* c = cr + (long long)lc * 3 * CRW;
+        const bool has1 = 2 * u + 1 < n;
+        T e0 = g[base + 2 * u + 1];
+        T e1 = has1 ? g[base + 2 * u + 2] : T(0);
+        // level 0: F solve, then C residual
+        e0 *= c[(2 * u) * 3 + 0];
+        {
+            const T r = __shfl(e0, u + 1, W);
+            if (has1) e1 -= c[(2 * u + 1) * 3 + 0] * e0 + c[(2 * u + 1) * 3 + 2] * r;
+        }
+        int offs[NK > 0 ? NK : 1];
+        offs[0] = 0;
+        int off = n;
+#pragma unroll
+        for (int k = 1; k < NK; ++k) {
+            const int nk = ((n + 1) >> k) - 1;
+            const int h = 1 << (k - 1);
+            offs[k] = off;
+            const bool on = ((u + 1) % h == 0) && ((u + 1) / h - 1 < nk);
+            const int t = (u + 1) / h - 1;
+            if (nk == 1) {
+                if (on) e1 *= c[off * 3 + 0];
+            } else {
+                if (on && (t & 1) == 0) e1 *= c[(off + t) * 3 + 0];
+                const T lf = __shfl(e1, u - h, W), rg = __shfl(e1, u + h, W);
+                if (on && (t & 1) == 1) e1 -= c[(off + t) * 3 + 0] * lf + c[(off + t) * 3 + 2] * rg;
+            }
+            off += nk;
+        }
+#pragma unroll
+        for (int k = NK - 2; k >= 1; --k) {
+            const int nk = ((n + 1) >> k) - 1;
+            const int h = 1 << (k - 1);
+            const int o = offs[k];
+            const T lf = __shfl(e1, u - h, W), rg = __shfl(e1, u + h, W);
+            const bool on = ((u + 1) % h == 0) && ((u + 1) / h - 1 < nk);
+            const int t = (u + 1) / h - 1;
+            if (on && (t & 1) == 0) {
+                T v = e1;
+                if (t >= 1) v += c[(o + t) * 3 + 1] * lf;
+                if (t + 1 < nk) v += c[(o + t) * 3 + 2] * rg;
+                e1 = v;
+            }
+        }
+        {
+            const T lf = __shfl(e1, u - 1, W);
+            T v = e0;
+            if (u >= 1) v += c[(2 * u) * 3 + 1] * lf;
+            if (has1) v += c[(2 * u) * 3 + 2] * e1;
+            e0 = v;
+        }
+        if (act) {
+            if (FUSED) {
+                x[base + 2 * u + 1] += alpha * e0;
+                if (has1) x[base + 2 * u + 2] += alpha * e1;
+            } else {
+                g[base + 2 * u + 1] = e0;
+                if (has1) g[base + 2 * u + 2] = e1;
+            }
+        }
+    }
+    wg_barrier();
+}
+
 // Cyclic reduction as a direct multigrid (Thm. "Two-level direct solver",
 // Cor. "Direct multigrid solver"), one thread per line, in place on g.
 // Level k of a line of n = 2^q - 1 unknowns holds the unknowns at 1-based
@@ -338,6 +482,12 @@ template <class T, int P, int DIM, bool FUSED>
 __device__ __attribute__((noinline)) void line_cr(const T* __restrict__ cr, int dir, T* __restrict__ g,
                         T* __restrict__ x, T alpha)
 {
+    if constexpr (wave_lines<P>()) {
+        if (dir == 0) {
+            line_cr_wave<T, P, DIM, FUSED>(cr, g, x, alpha);
+            return;
+        }
+    }
     using S = Shape<P, DIM>;
     constexpr int n = S::n, NL = S::NL;
     constexpr int NK = ilog2(n + 1);   // number of CR levels
@@ -466,9 +616,17 @@ __device__ void prolong_axis(const T* __restrict__ in, T* __restrict__ out, int 
 
 // rc = R_l rf with zero coarse boundary (Sec. 3.3, R = P^T)
 template <class T, int P, int DIM>
-__device__ __attribute__((noinline)) void restrict_level(const T* rf, T* rc, const T* J, T* w1, T* w2)
+__device__ __attribute__((noinline)) void restrict_level(const T* rf, T* rc, const T* J,
+                                                         const T* JT, T* w1, T* w2)
 {
     constexpr int n1f = P + 1, n1c = P / 2 + 1;
+    if constexpr (DIM == 2 && P >= 64) {
+        // W1 = rf J (n1f x n1c); rc = J^T W1 with zero boundary
+        (void)w2;
+        wg_gemm<T, n1f, n1c, n1f, n1f, n1c, 0>(rf, J, w1);
+        wg_gemm<T, n1c, n1c, n1f, n1f, n1c, 2>(JT, w1, rc);
+        return;
+    }
     if (DIM == 2) {
         restrict_axis<T>(rf, w1, n1f, n1f, 1, 0, n1f, n1c, J, false);
         restrict_axis<T>(w1, rc, n1c, n1f, 1, 1, n1f, n1c, J, true);
@@ -484,6 +642,13 @@ template <class T, int P, int DIM>
 __device__ __attribute__((noinline)) void prolong_level(const T* ec, T* xf, const T* J, const T* JT, T* w1, T* w2)
 {
     constexpr int n1f = P + 1, n1c = P / 2 + 1;
+    if constexpr (DIM == 2 && P >= 64) {
+        // W1 = ec J^T (n1c x n1f); xf += J W1
+        (void)w2;
+        wg_gemm<T, n1c, n1f, n1c, n1c, n1f, 0>(ec, JT, w1);
+        wg_gemm<T, n1f, n1f, n1c, n1c, n1f, 1>(J, w1, xf);
+        return;
+    }
     if (DIM == 2) {
         prolong_axis<T, false>(ec, w1, n1c, n1c, 1, 0, n1f, n1c, J, JT);
         prolong_axis<T, true>(w1, xf, n1f, n1c, 1, 1, n1f, n1c, J, JT);
@@ -553,7 +718,7 @@ __device__ __attribute__((noinline)) void gamma_cycle(const Hier<T>& H, int b, c
         for (int g = 0; g < H.gamma; ++g) {
             apply_level<T, P, DIM, true>(L.G + (long long)b * S::NC * S::N, L.D, L.DT,
                                          L.TR + (long long)b * DIM * S::N, x, r, tmp);
-            restrict_level<T, P, DIM>(tmp, rc, L.J, w1, w2);
+            restrict_level<T, P, DIM>(tmp, rc, L.J, L.JT, w1, w2);
             gamma_cycle<T, P / 2, DIM>(H, b, rc, xc);
             prolong_level<T, P, DIM>(xc, x, L.J, L.JT, w1, w2);
             for (int dir = DIM - 1; dir >= 0; --dir)

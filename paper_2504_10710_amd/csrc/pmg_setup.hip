@@ -302,8 +302,12 @@ __global__ void __launch_bounds__(NT) k_lines(const double* __restrict__ G,
     for (int dir = 0; dir < DIM; ++dir) {
         double* cr = (dir == 0 ? cr0 : (dir == 1 ? cr1 : cr2)) + b * 3 * CRW * NL;
         float* cf = dir == 0 ? f0 : (dir == 1 ? f1 : f2);
+        const bool lm = dir == 0 && wave_lines<P>();   // line-major layout
         for (int line = threadIdx.x; line < NL; line += NT) {
-            auto W = [&](int slot, int w) -> double& { return cr[(slot * 3 + w) * NL + line]; };
+            auto idx = [&](int slot, int w) -> long long {
+                return lm ? ((long long)line * CRW + slot) * 3 + w : (long long)(slot * 3 + w) * NL + line;
+            };
+            auto W = [&](int slot, int w) -> double& { return cr[idx(slot, w)]; };
             for (int s = 0; s < n; ++s) {
                 double l, a, u;
                 line_raw<P, DIM>(Gb, Xb, D, smoother, dir, line, s, l, a, u);
@@ -345,8 +349,7 @@ __global__ void __launch_bounds__(NT) k_lines(const double* __restrict__ G,
             if (cf) {
                 float* cfb = cf + b * 3 * CRW * NL;
                 for (int slot = 0; slot < CRW; ++slot)
-                    for (int w = 0; w < 3; ++w)
-                        cfb[(slot * 3 + w) * NL + line] = (float)W(slot, w);
+                    for (int w = 0; w < 3; ++w) cfb[idx(slot, w)] = (float)W(slot, w);
             }
         }
     }
