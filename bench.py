@@ -31,7 +31,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--batch", type=int, default=2048)
     ap.add_argument("--p", type=int, default=128)
     ap.add_argument("--gamma", type=int, default=1)
     ap.add_argument("--alpha", type=float, default=0.16)
