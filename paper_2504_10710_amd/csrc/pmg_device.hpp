@@ -85,19 +85,40 @@ struct Hier {
 
 __device__ inline void wg_barrier() { __syncthreads(); }
 
+// The workspace pointers reach device code through structures in memory, so
+// the compiler cannot prove that they address global memory and would emit
+// flat accesses, which are waited for together with LDS traffic.  Hot code
+// converts them once with gmem() so that loads and stores are global ones.
 template <class T>
-__device__ inline void wg_copy(T* __restrict__ dst, const T* __restrict__ src, int n)
+__device__ inline __attribute__((address_space(1))) T* gmem(T* p)
 {
+    return (__attribute__((address_space(1))) T*)p;
+}
+template <class T>
+__device__ inline __attribute__((address_space(1))) T* gmem(__attribute__((address_space(1))) T* p)
+{
+    return p;
+}
+
+template <class T>
+__device__ inline void wg_copy(T* __restrict__ dst_, const T* __restrict__ src_, int n)
+{
+    const auto dst = gmem(dst_);
+    const auto src = gmem(src_);
     for (int i = threadIdx.x; i < n; i += NT) dst[i] = src[i];
 }
 
 template <class T>
-__device__ inline void wg_zero(T* dst, int n)
+__device__ inline void wg_zero(T* dst_, int n)
 {
+    const auto dst = gmem(dst_);
     for (int i = threadIdx.x; i < n; i += NT) dst[i] = T(0);
 }
 
-// Deterministic workgroup sum: fixed per-thread order, fixed tree.
+// Deterministic workgroup reductions: every thread first folds its own
+// elements in a fixed order, then a fixed binary tree over the NT partial
+// results in LDS (red: NT doubles).  The result does not depend on timing or
+// on other workgroups.
 __device__ inline double wg_sum(double v, double* red)
 {
     red[threadIdx.x] = v;
@@ -107,7 +128,7 @@ __device__ inline double wg_sum(double v, double* red)
         if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    double r = red[0];
+    const double r = red[0];
     __syncthreads();
     return r;
 }
@@ -121,7 +142,7 @@ __device__ inline double wg_min(double v, double* red)
         if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
         __syncthreads();
     }
-    double r = red[0];
+    const double r = red[0];
     __syncthreads();
     return r;
 }
@@ -167,126 +188,163 @@ struct Mfma<float> {
     __device__ static inline int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
-// acc += A[r0 .. r0+15][:] * B[:][c0 .. c0+15] for n1 x n1 row-major A and B
-// (one wave).  Rows/columns past n1 are clamped (their results are never
-// stored); the k tail past n1 contributes zero.
-template <class T, int n1>
-__device__ inline void mfma_tile(const T* __restrict__ A, const T* __restrict__ B, int r0, int c0,
-                                 typename Mfma<T>::v4& acc)
+// Two independent 16x16 matrix-core products on one wave, accumulated over
+// k = 0 .. K-1: c0 += A0 B0 and c1 += A1 B1.  a0 / a1 point at the lane's A
+// element (row r + lane % 16, column lane / 16), b0 / b1 at its B element
+// (row lane / 16, column c + lane % 16); SA* and SB* are the element strides
+// between consecutive k.  The operand loads of the next PF k-steps are issued
+// before the current matrix-core steps so that their latency overlaps the
+// matrix core; the k tail past the last multiple of 4 contributes zero.
+template <class T, int K, int SA0, int SB0, int SA1, int SB1, class PA0, class PB0, class PA1,
+          class PB1>
+__device__ inline void mfma2(PA0 a0_, PB0 b0_, PA1 a1_, PB1 b1_,
+                             typename Mfma<T>::v4& c0, typename Mfma<T>::v4& c1)
 {
-    const int lane = threadIdx.x & 63;
-    const int ar = min(r0 + (lane & 15), n1 - 1);
-    const int bc = min(c0 + (lane & 15), n1 - 1);
-    const int kq = lane >> 4;
-    const T* Ap = A + ar * n1 + kq;
-    const T* Bp = B + kq * n1 + bc;
-    constexpr int KF = (n1 / 4) * 4;
-#pragma unroll 4
-    for (int k0 = 0; k0 < KF; k0 += 4) acc = Mfma<T>::op(Ap[k0], Bp[k0 * n1], acc);
-    if (KF < n1) {
-        const int kk = min(KF + kq, n1 - 1) - kq;   // stays inside the row / column
-        T a = Ap[kk], b = Bp[kk * n1];
-        if (KF + kq >= n1) { a = T(0); b = T(0); }
-        acc = Mfma<T>::op(a, b, acc);
+    const auto a0 = gmem(a0_);
+    const auto b0 = gmem(b0_);
+    const auto a1 = gmem(a1_);
+    const auto b1 = gmem(b1_);
+    constexpr int KS = K / 4;
+    constexpr int PF = 2;
+    T x0[PF], y0[PF], x1[PF], y1[PF];
+#pragma unroll
+    for (int u = 0; u < PF; ++u)
+        if (u < KS) {
+            x0[u] = a0[4 * u * SA0];
+            y0[u] = b0[4 * u * SB0];
+            x1[u] = a1[4 * u * SA1];
+            y1[u] = b1[4 * u * SB1];
+        }
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        const int u = s % PF;
+        const T p0 = x0[u], q0 = y0[u], p1 = x1[u], q1 = y1[u];
+        if (s + PF < KS) {
+            x0[u] = a0[4 * (s + PF) * SA0];
+            y0[u] = b0[4 * (s + PF) * SB0];
+            x1[u] = a1[4 * (s + PF) * SA1];
+            y1[u] = b1[4 * (s + PF) * SB1];
+        }
+        c0 = Mfma<T>::op(p0, q0, c0);
+        c1 = Mfma<T>::op(p1, q1, c1);
     }
-}
-
-// acc += A[r0 .. r0+15][:K] * B[:K][c0 .. c0+15] for row-major A (M x K,
-// leading dimension LDA) and B (K x N, LDB); one wave.
-template <class T, int M, int N, int K, int LDA, int LDB>
-__device__ inline void mfma_tile_g(const T* __restrict__ A, const T* __restrict__ B, int r0,
-                                   int c0, typename Mfma<T>::v4& acc)
-{
-    const int lane = threadIdx.x & 63;
-    const int ar = min(r0 + (lane & 15), M - 1);
-    const int bc = min(c0 + (lane & 15), N - 1);
-    const int kq = lane >> 4;
-    const T* Ap = A + ar * LDA + kq;
-    const T* Bp = B + kq * LDB + bc;
-    constexpr int KF = (K / 4) * 4;
-#pragma unroll 4
-    for (int k0 = 0; k0 < KF; k0 += 4) acc = Mfma<T>::op(Ap[k0], Bp[k0 * LDB], acc);
-    if (KF < K) {
-        const int kk = min(KF + kq, K - 1) - kq;
-        T a = Ap[kk], b = Bp[kk * LDB];
-        if (KF + kq >= K) { a = T(0); b = T(0); }
-        acc = Mfma<T>::op(a, b, acc);
+    if constexpr (K % 4 != 0) {
+        const int kq = (threadIdx.x & 63) >> 4;
+        const bool in = 4 * KS + kq < K;
+        const int kk = (in ? 4 * KS + kq : K - 1) - kq;   // stays inside the row / column
+        T p0 = a0[kk * SA0], q0 = b0[kk * SB0], p1 = a1[kk * SA1], q1 = b1[kk * SB1];
+        if (!in) { p0 = T(0); q0 = T(0); p1 = T(0); q1 = T(0); }
+        c0 = Mfma<T>::op(p0, q0, c0);
+        c1 = Mfma<T>::op(p1, q1, c1);
     }
 }
 
 // C (M x N, row-major) = A B (MODE 0), += A B (MODE 1), or = A B with the
-// boundary rows and columns set to zero (MODE 2); 16x16 tiles, one wave each.
+// boundary rows and columns set to zero (MODE 2), for row-major A (M x K,
+// leading dimension LDA) and B (K x N, LDB).  Each wave computes a 16 x 32
+// block as two 16x16 tiles that share their A rows; rows and columns past
+// M, N are clamped in the loads and never stored.
 template <class T, int M, int N, int K, int LDA, int LDB, int MODE>
-__device__ void wg_gemm(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C)
+__device__ void wg_gemm(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C_)
 {
-    constexpr int TM = (M + 15) / 16, TN = (N + 15) / 16;
+    const auto C = gmem(C_);
+    constexpr int TM = (M + 15) / 16, TN2 = (N + 31) / 32;
     using V4 = typename Mfma<T>::v4;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int t = wave; t < TM * TN; t += NT / 64) {
-        const int r0 = (t / TN) * 16, c0 = (t % TN) * 16;
-        V4 acc = {0, 0, 0, 0};
-        mfma_tile_g<T, M, N, K, LDA, LDB>(A, B, r0, c0, acc);
-        const int i = c0 + (lane & 15);
+    const int lr = lane & 15, kq = lane >> 4;
+    for (int t = wave; t < TM * TN2; t += NT / 64) {
+        const int r0 = (t / TN2) * 16, c0 = (t % TN2) * 32;
+        const int ar = min(r0 + lr, M - 1);
+        const int bc0 = min(c0 + lr, N - 1), bc1 = min(c0 + 16 + lr, N - 1);
+        V4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+        const T* ap = A + ar * LDA + kq;
+        mfma2<T, K, 1, LDB, 1, LDB>(ap, B + kq * LDB + bc0, ap, B + kq * LDB + bc1, acc0, acc1);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int j = r0 + Mfma<T>::row(lane, v);
-            if (j < M && i < N) {
-                if (MODE == 1)
-                    C[j * N + i] += acc[v];
-                else if (MODE == 2)
-                    C[j * N + i] = (j == 0 || j == M - 1 || i == 0 || i == N - 1) ? T(0) : acc[v];
-                else
-                    C[j * N + i] = acc[v];
+        for (int h = 0; h < 2; ++h) {
+            const int i = c0 + 16 * h + lr;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int j = r0 + Mfma<T>::row(lane, v);
+                const T a = h ? acc1[v] : acc0[v];
+                if (j < M && i < N) {
+                    if (MODE == 1)
+                        C[j * N + i] += a;
+                    else if (MODE == 2)
+                        C[j * N + i] = (j == 0 || j == M - 1 || i == 0 || i == N - 1) ? T(0) : a;
+                    else
+                        C[j * N + i] = a;
+                }
             }
         }
     }
     wg_barrier();
 }
 
-// 2-D A x on matrix cores: the four contractions of the sum factorisation
-// (x D^T, D x, then F0 D and D^T F1) as 16x16 output tiles, one wave per tile.
+// 2-D A x on matrix cores.  Pass 1: the reference gradients x D^T and D x at
+// the nodes with both indices in 1..P as 16x16 tiles (one wave computes both
+// gradients of a tile), combined into the fluxes at once; row 0 and column 0
+// on the vector units.  Pass 2: F0 D + D^T F1 on the same tiles (two
+// accumulators, added at the end); the boundary rows and columns are zero.
 template <class T, int P, bool RESID>
-__device__ void apply2d_mfma(const T* __restrict__ G, const T* __restrict__ D,
-                             const T* __restrict__ DT, T* __restrict__ TR,
-                             const T* __restrict__ x, const T* __restrict__ r, T* __restrict__ out)
+__device__ void apply2d_mfma(const T* __restrict__ G_, const T* __restrict__ D_,
+                             const T* __restrict__ DT_, T* __restrict__ TR_,
+                             const T* __restrict__ x_, const T* __restrict__ r_, T* __restrict__ out_)
 {
-    constexpr int n1 = P + 1, N = n1 * n1, NTL = (n1 + 15) / 16;
+    const auto G = gmem(G_);
+    const auto D = gmem(D_);
+    const auto DT = gmem(DT_);
+    const auto TR = gmem(TR_);
+    const auto x = gmem(x_);
+    const auto r = gmem(r_);
+    const auto out = gmem(out_);
+    static_assert(P % 16 == 0, "tiles cover rows 1..P");
+    constexpr int n1 = P + 1, N = n1 * n1, NTL = P / 16;
     using V4 = typename Mfma<T>::v4;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, kq = lane >> 4;
     for (int t = wave; t < NTL * NTL; t += NT / 64) {
-        const int r0 = (t / NTL) * 16, c0 = (t % NTL) * 16;
+        const int r0 = 1 + (t / NTL) * 16, c0 = 1 + (t % NTL) * 16;
         V4 ur = {0, 0, 0, 0}, us = {0, 0, 0, 0};
-        mfma_tile<T, n1>(x, DT, r0, c0, ur);   // derivative along the first axis
-        mfma_tile<T, n1>(D, x, r0, c0, us);    // derivative along the second axis
-        const int i = c0 + (lane & 15);
+        mfma2<T, n1, 1, n1, 1, n1>(x + (r0 + lr) * n1 + kq, DT + kq * n1 + c0 + lr,
+                                   D + (r0 + lr) * n1 + kq, x + kq * n1 + c0 + lr, ur, us);
+        const int i = c0 + lr;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int j = r0 + Mfma<T>::row(lane, v);
-            if (j < n1 && i < n1) {
-                const int q = j * n1 + i;
-                const T g00 = G[q], g11 = G[N + q], g01 = G[2 * N + q];
-                TR[q] = g00 * ur[v] + g01 * us[v];
-                TR[N + q] = g01 * ur[v] + g11 * us[v];
-            }
+            const int q = (r0 + Mfma<T>::row(lane, v)) * n1 + i;
+            const T g00 = G[q], g11 = G[N + q], g01 = G[2 * N + q];
+            TR[q] = g00 * ur[v] + g01 * us[v];
+            TR[N + q] = g01 * ur[v] + g11 * us[v];
         }
+    }
+    for (int e = threadIdx.x; e < 2 * P + 1; e += NT) {
+        const int j = e <= P ? 0 : e - P, i = e <= P ? e : 0;
+        T ur = 0, us = 0;
+        for (int k = 0; k < n1; ++k) {
+            ur += x[j * n1 + k] * DT[k * n1 + i];
+            us += D[j * n1 + k] * x[k * n1 + i];
+        }
+        const int q = j * n1 + i;
+        const T g00 = G[q], g11 = G[N + q], g01 = G[2 * N + q];
+        TR[q] = g00 * ur + g01 * us;
+        TR[N + q] = g01 * ur + g11 * us;
     }
     wg_barrier();
     for (int t = wave; t < NTL * NTL; t += NT / 64) {
-        const int r0 = (t / NTL) * 16, c0 = (t % NTL) * 16;
-        V4 y = {0, 0, 0, 0};
-        mfma_tile<T, n1>(TR, D, r0, c0, y);        // sum_k D[k][i] F0[j][k]
-        mfma_tile<T, n1>(DT, TR + N, r0, c0, y);   // sum_k D[k][j] F1[k][i]
-        const int i = c0 + (lane & 15);
+        const int r0 = 1 + (t / NTL) * 16, c0 = 1 + (t % NTL) * 16;
+        V4 y0 = {0, 0, 0, 0}, y1 = {0, 0, 0, 0};
+        // sum_k F0[j][k] D[k][i] and sum_k D^T[j][k] F1[k][i]
+        mfma2<T, n1, 1, n1, 1, n1>(TR + (r0 + lr) * n1 + kq, D + kq * n1 + c0 + lr,
+                                   DT + (r0 + lr) * n1 + kq, TR + N + kq * n1 + c0 + lr, y0, y1);
+        const int i = c0 + lr;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int j = r0 + Mfma<T>::row(lane, v);
-            if (j < n1 && i < n1) {
-                const int q = j * n1 + i;
-                const bool bd = i == 0 || i == P || j == 0 || j == P;
-                out[q] = bd ? T(0) : (RESID ? r[q] - y[v] : y[v]);
-            }
+            const int q = j * n1 + i;
+            const T y = y0[v] + y1[v];
+            out[q] = (i == P || j == P) ? T(0) : (RESID ? r[q] - y : y);
         }
     }
+    for (int e = threadIdx.x; e < 2 * P + 1; e += NT) out[e <= P ? e : (e - P) * n1] = T(0);
     wg_barrier();
 }
 
@@ -295,21 +353,30 @@ __device__ void apply2d_mfma(const T* __restrict__ G, const T* __restrict__ D,
 // then (A x)(n) = sum_a sum_k D[k][n_a] f_a(n with axis a <- k) on interior
 // rows.  RESID: out = r - A x.  out has zero boundary rows.
 template <class T, int P, int DIM, bool RESID>
-__device__ __attribute__((noinline)) void apply_level(const T* __restrict__ G, const T* __restrict__ D,
-                            const T* __restrict__ DT, T* __restrict__ TR,
-                            const T* __restrict__ x, const T* __restrict__ r, T* __restrict__ out)
+__device__ __attribute__((noinline)) void apply_level(const T* __restrict__ G_,
+                                                      const T* __restrict__ D_,
+                                                      const T* __restrict__ DT_, T* __restrict__ TR_,
+                                                      const T* __restrict__ x_,
+                                                      const T* __restrict__ r_, T* __restrict__ out_)
 {
     if constexpr (DIM == 2 && P >= 64) {
-        apply2d_mfma<T, P, RESID>(G, D, DT, TR, x, r, out);
+        apply2d_mfma<T, P, RESID>(G_, D_, DT_, TR_, x_, r_, out_);
         return;
     }
+    const auto G = gmem(G_);
+    const auto D = gmem(D_);
+    const auto DT = gmem(DT_);
+    const auto TR = gmem(TR_);
+    const auto x = gmem(x_);
+    const auto r = gmem(r_);
+    const auto out = gmem(out_);
     using S = Shape<P, DIM>;
     constexpr int n1 = S::n1, N = S::N;
     for (int q = threadIdx.x; q < N; q += NT) {
         int c[3] = {q % n1, (q / n1) % n1, DIM == 3 ? q / (n1 * n1) : 0};
         T g[DIM];
         {
-            const T* xr = x + (q - c[0]);
+            const auto xr = x + (q - c[0]);
             T s = 0;
 #pragma unroll 8
             for (int k = 0; k < n1; ++k) s += DT[k * n1 + c[0]] * xr[k];
@@ -318,8 +385,8 @@ __device__ __attribute__((noinline)) void apply_level(const T* __restrict__ G, c
 #pragma unroll
         for (int a = 1; a < DIM; ++a) {
             const int st = a == 1 ? n1 : n1 * n1;
-            const T* xr = x + (q - c[a] * st);
-            const T* Dr = D + c[a] * n1;
+            const auto xr = x + (q - c[a] * st);
+            const auto Dr = D + c[a] * n1;
             T s = 0;
 #pragma unroll 8
             for (int k = 0; k < n1; ++k) s += Dr[k] * xr[k * st];
@@ -342,14 +409,14 @@ __device__ __attribute__((noinline)) void apply_level(const T* __restrict__ G, c
         int c[3] = {q % n1, (q / n1) % n1, DIM == 3 ? q / (n1 * n1) : 0};
         T y = 0;
         {
-            const T* fr = TR + (q - c[0]);
+            const auto fr = TR + (q - c[0]);
 #pragma unroll 8
             for (int k = 0; k < n1; ++k) y += D[k * n1 + c[0]] * fr[k];
         }
 #pragma unroll
         for (int a = 1; a < DIM; ++a) {
             const int st = a == 1 ? n1 : n1 * n1;
-            const T* fr = TR + a * N + (q - c[a] * st);
+            const auto fr = TR + a * N + (q - c[a] * st);
 #pragma unroll 8
             for (int k = 0; k < n1; ++k) y += D[k * n1 + c[a]] * fr[k * st];
         }
@@ -387,9 +454,12 @@ template <int P>
 __host__ __device__ constexpr bool wave_lines() { return P >= 2 && P <= 128; }
 
 template <class T, int P, int DIM, bool FUSED>
-__device__ void line_cr_wave(const T* __restrict__ cr, T* __restrict__ g, T* __restrict__ x,
+__device__ void line_cr_wave(const T* __restrict__ cr_, T* __restrict__ g_, T* __restrict__ x_,
                              T alpha)
 {
+    const auto cr = gmem(cr_);
+    const auto g = gmem(g_);
+    const auto x = gmem(x_);
     using S = Shape<P, DIM>;
     constexpr int n = S::n, NL = S::NL, CRW = S::CRW;
     constexpr int W = (n + 1) / 2 > 0 ? (n + 1) / 2 : 1;   // lanes per line
@@ -403,7 +473,7 @@ __device__ void line_cr_wave(const T* __restrict__ cr, T* __restrict__ g, T* __r
         const int lc = act ? line : NL - 1;
         int base, st;
         line_base<P, DIM>(0, lc, base, st);
-        const T* c = cr + (long long)lc * 3 * CRW;
+        const auto c = cr + (long long)lc * 3 * CRW;
         const bool has1 = 2 * u + 1 < n;
         T e0 = g[base + 2 * u + 1];
         T e1 = has1 ? g[base + 2 * u + 2] : T(0);
@@ -479,15 +549,18 @@ __device__ void line_cr_wave(const T* __restrict__ cr, T* __restrict__ g, T* __r
 //   up:   y_F = x_F - (l_F e_{F-1} + u_F e_{F+1}) / a_F         (x + P e)
 // FUSED: instead of storing z, x += alpha z.
 template <class T, int P, int DIM, bool FUSED>
-__device__ __attribute__((noinline)) void line_cr(const T* __restrict__ cr, int dir, T* __restrict__ g,
-                        T* __restrict__ x, T alpha)
+__device__ __attribute__((noinline)) void line_cr(const T* __restrict__ cr_, int dir,
+                                                  T* __restrict__ g_, T* __restrict__ x_, T alpha)
 {
     if constexpr (wave_lines<P>()) {
         if (dir == 0) {
-            line_cr_wave<T, P, DIM, FUSED>(cr, g, x, alpha);
+            line_cr_wave<T, P, DIM, FUSED>(cr_, g_, x_, alpha);
             return;
         }
     }
+    const auto cr = gmem(cr_);
+    const auto g = gmem(g_);
+    const auto x = gmem(x_);
     using S = Shape<P, DIM>;
     constexpr int n = S::n, NL = S::NL;
     constexpr int NK = ilog2(n + 1);   // number of CR levels
@@ -556,10 +629,13 @@ __device__ __attribute__((noinline)) void line_cr(const T* __restrict__ cr, int 
 // One axis of the restriction R = (J x J [x J])^T: out(.., o_a, ..) =
 // sum_t J[t][o_a] in(.., t, ..), in has extent n1f along a, out n1c.
 template <class T>
-__device__ void restrict_axis(const T* __restrict__ in, T* __restrict__ out, int e0, int e1,
-                              int e2, int a, int n1f, int n1c, const T* __restrict__ J,
+__device__ void restrict_axis(const T* __restrict__ in_, T* __restrict__ out_, int e0, int e1,
+                              int e2, int a, int n1f, int n1c, const T* __restrict__ J_,
                               bool zero_boundary)
 {
+    const auto in = gmem(in_);
+    const auto out = gmem(out_);
+    const auto J = gmem(J_);
     int eo[3] = {e0, e1, e2};
     eo[a] = n1c;
     int ei[3] = {e0, e1, e2};
@@ -576,7 +652,7 @@ __device__ void restrict_axis(const T* __restrict__ in, T* __restrict__ out, int
         }
         int ii[3] = {o0, o1, o2};
         ii[a] = 0;
-        const T* src = in + ii[0] + ei[0] * (ii[1] + ei[1] * ii[2]);
+        const auto src = in + ii[0] + ei[0] * (ii[1] + ei[1] * ii[2]);
         T s = 0;
         for (int t = 0; t < n1f; ++t) s += J[t * n1c + oa] * src[t * sti];
         out[q] = s;
@@ -587,10 +663,14 @@ __device__ void restrict_axis(const T* __restrict__ in, T* __restrict__ out, int
 // One axis of the prolongation P = J x J [x J]: out(.., o_a, ..) =
 // sum_t J[o_a][t] in(.., t, ..), in has extent n1c along a, out n1f.
 template <class T, bool ADD>
-__device__ void prolong_axis(const T* __restrict__ in, T* __restrict__ out, int e0, int e1,
-                             int e2, int a, int n1f, int n1c, const T* __restrict__ J,
-                             const T* __restrict__ JT)
+__device__ void prolong_axis(const T* __restrict__ in_, T* __restrict__ out_, int e0, int e1,
+                             int e2, int a, int n1f, int n1c, const T* __restrict__ J_,
+                             const T* __restrict__ JT_)
 {
+    const auto in = gmem(in_);
+    const auto out = gmem(out_);
+    const auto J = gmem(J_);
+    const auto JT = gmem(JT_);
     int eo[3] = {e0, e1, e2};
     eo[a] = n1f;
     int ei[3] = {e0, e1, e2};
@@ -601,7 +681,7 @@ __device__ void prolong_axis(const T* __restrict__ in, T* __restrict__ out, int 
         int o0 = q % eo[0], o1 = (q / eo[0]) % eo[1], o2 = q / (eo[0] * eo[1]);
         int ii[3] = {o0, o1, o2};
         ii[a] = 0;
-        const T* src = in + ii[0] + ei[0] * (ii[1] + ei[1] * ii[2]);
+        const auto src = in + ii[0] + ei[0] * (ii[1] + ei[1] * ii[2]);
         T s = 0;
         if (a == 0) {
             for (int t = 0; t < n1c; ++t) s += JT[t * n1f + o0] * src[t * sti];
@@ -697,7 +777,9 @@ __device__ __attribute__((noinline)) void gamma_cycle(const Hier<T>& H, int b, c
         // one interior node: M_0^{-1} = A_0^{-1} is a division
         constexpr int c = DIM == 2 ? 4 : 13;
         const T ia = H.cinv[b];
-        for (int q = threadIdx.x; q < S::N; q += NT) x[q] = q == c ? r[c] * ia : T(0);
+        const auto xg = gmem(x);
+        const auto rg = gmem(r);
+        for (int q = threadIdx.x; q < S::N; q += NT) xg[q] = q == c ? rg[c] * ia : T(0);
         wg_barrier();
     } else {
         using C = Shape<P / 2, DIM>;

@@ -10,8 +10,10 @@
 
 namespace pmg {
 
-__device__ inline double wg_dot(const double* a, const double* b, int n, double* red)
+__device__ inline double wg_dot(const double* a_, const double* b_, int n, double* red)
 {
+    const auto a = gmem(a_);
+    const auto b = gmem(b_);
     double s = 0.0;
     for (int i = threadIdx.x; i < n; i += NT) s += a[i] * b[i];
     return wg_sum(s, red);
@@ -28,10 +30,18 @@ __device__ void precondition(const Hier<T>& H, int b, const double* v, double* z
         const LevelData<T>& L = H.lev[S::LEV];
         T* r = L.R + (long long)b * S::N;
         T* x = L.X + (long long)b * S::N;
-        for (int q = threadIdx.x; q < S::N; q += NT) r[q] = (T)v[q];
+        {
+            const auto rg = gmem(r);
+            const auto vg = gmem(v);
+            for (int q = threadIdx.x; q < S::N; q += NT) rg[q] = (T)vg[q];
+        }
         wg_barrier();
         gamma_cycle<T, P, DIM>(H, b, r, x);
-        for (int q = threadIdx.x; q < S::N; q += NT) z[q] = (double)x[q];
+        {
+            const auto zg = gmem(z);
+            const auto xg = gmem((const T*)x);
+            for (int q = threadIdx.x; q < S::N; q += NT) zg[q] = (double)xg[q];
+        }
         wg_barrier();
     }
 }
@@ -50,8 +60,37 @@ __device__ void apply64(const Hier<T>& H, const SolveArgs& A, int b, const doubl
                                            A.TR64 + (long long)b * DIM * S::N, x, nullptr, out);
 }
 
-// Right-preconditioned flexible GMRES, modified Gram-Schmidt, restarted every
-// `restart` iterations; PCG; flexible CG.  Convergence is declared on the
+// Modified Gram-Schmidt for column j of the Arnoldi process: for i = 0..j,
+// h_i = <w, v_i> and w -= h_i v_i, in that order.  The subtraction of v_i
+// and the partial products of the next inner product (with v_{i+1}, or
+// <w, w> after the last one) share one pass over w, so each basis vector
+// costs one pass and one reduction.  Returns ||w|| after orthogonalisation;
+// H[i * ldh] = h_i.
+__device__ inline double mgs_column(double* w_, const double* V_, long long N, int j, double* H,
+                                    int ldh, double* red)
+{
+    const auto w = gmem(w_);
+    const auto V = gmem(V_);
+    double d = 0.0;
+    for (long long q = threadIdx.x; q < N; q += NT) d += w[q] * V[q];
+    double h = wg_sum(d, red);
+    for (int i = 0; i <= j; ++i) {
+        const auto vi = V + i * N;
+        const auto vn = V + (i + 1) * N;
+        d = 0.0;
+        for (long long q = threadIdx.x; q < N; q += NT) {
+            const double wq = w[q] - h * vi[q];
+            w[q] = wq;
+            d += wq * (i < j ? vn[q] : wq);
+        }
+        if (threadIdx.x == 0) H[i * ldh] = h;
+        h = wg_sum(d, red);
+    }
+    return sqrt(h);
+}
+
+// Right-preconditioned flexible GMRES (Arnoldi by modified Gram-Schmidt),
+// restarted every `restart` iterations; PCG; flexible CG.  Convergence is declared on the
 // true residual ||b - A x|| <= rtol ||b||.  At most A.budget iterations are
 // taken in this launch; the state is saved in A.st[b].
 template <class T, int P, int DIM>
@@ -143,7 +182,10 @@ __global__ void __launch_bounds__(NT, 8) k_solve(const Hier<T>* __restrict__ Hp,
                 if (!isfinite(beta)) { st.status = PMG_ENAN; goto done; }
                 if (beta <= tol) { st.status = PMG_OK; goto done; }
                 if (st.it >= A.max_iter) { st.status = PMG_ENOTCONV; goto done; }
-                for (int q = threadIdx.x; q < N; q += NT) V[q] /= beta;
+                {
+                    const auto Vg = gmem(V);
+                    for (int q = threadIdx.x; q < N; q += NT) Vg[q] /= beta;
+                }
                 if (threadIdx.x == 0) {
                     gv[0] = beta;
                     for (int i = 1; i <= kr; ++i) gv[i] = 0.0;
@@ -160,16 +202,11 @@ __global__ void __launch_bounds__(NT, 8) k_solve(const Hier<T>* __restrict__ Hp,
             double* w = V + (long long)(j + 1) * N;
             precondition<T, P, DIM>(H, b, vj, zj);
             apply64<T, P, DIM>(H, A, b, zj, nullptr, w);
-            for (int i = 0; i <= j; ++i) {
-                const double* vi = V + (long long)i * N;
-                const double hij = wg_dot(w, vi, N, red);
-                for (int q = threadIdx.x; q < N; q += NT) w[q] -= hij * vi[q];
-                if (threadIdx.x == 0) Hm[i * kr + j] = hij;
-                wg_barrier();
+            const double hn = mgs_column(w, V, N, j, Hm + j, kr, red);
+            if (hn > 0.0) {
+                const auto wg = gmem(w);
+                for (int q = threadIdx.x; q < N; q += NT) wg[q] /= hn;
             }
-            const double hn = sqrt(wg_dot(w, w, N, red));
-            if (hn > 0.0)
-                for (int q = threadIdx.x; q < N; q += NT) w[q] /= hn;
             if (threadIdx.x == 0) {
                 Hm[(j + 1) * kr + j] = hn;
                 for (int i = 0; i < j; ++i) {
@@ -211,10 +248,12 @@ __global__ void __launch_bounds__(NT, 8) k_solve(const Hier<T>* __restrict__ Hp,
                         }
                     }
                     wg_barrier();
+                    const auto xg = gmem(x);
+                    const auto Zg = gmem((const double*)Z);
                     for (int q = threadIdx.x; q < N; q += NT) {
-                        double s = x[q];
-                        for (int i = 0; i < used; ++i) s += yv[i] * Z[(long long)i * N + q];
-                        x[q] = s;
+                        double s = xg[q];
+                        for (int i = 0; i < used; ++i) s += yv[i] * Zg[(long long)i * N + q];
+                        xg[q] = s;
                     }
                     wg_barrier();
                 }
@@ -240,9 +279,13 @@ __global__ void __launch_bounds__(NT, 8) k_solve(const Hier<T>* __restrict__ Hp,
             const double pq = flex ? st.rz : wg_dot(pp, q, N, red);
             if (!(pq > 0.0)) { st.status = isfinite(pq) ? PMG_EBREAKDOWN : PMG_ENAN; goto done; }
             const double al = (flex ? wg_dot(pp, r, N, red) : st.rz) / pq;
-            for (int i = threadIdx.x; i < N; i += NT) {
-                x[i] += al * pp[i];
-                r[i] -= al * q[i];
+            {
+                const auto xg = gmem(x), rg = gmem(r);
+                const auto pg = gmem((const double*)pp), qg = gmem((const double*)q);
+                for (int i = threadIdx.x; i < N; i += NT) {
+                    xg[i] += al * pg[i];
+                    rg[i] -= al * qg[i];
+                }
             }
             wg_barrier();
             ++st.it;
@@ -267,7 +310,9 @@ __global__ void __launch_bounds__(NT, 8) k_solve(const Hier<T>* __restrict__ Hp,
             precondition<T, P, DIM>(H, b, r, z);
             if (flex) {
                 const double be = -wg_dot(z, q, N, red) / pq;
-                for (int i = threadIdx.x; i < N; i += NT) pp[i] = z[i] + be * pp[i];
+                const auto pg = gmem(pp);
+                const auto zg = gmem((const double*)z);
+                for (int i = threadIdx.x; i < N; i += NT) pg[i] = zg[i] + be * pg[i];
                 wg_barrier();
                 apply64<T, P, DIM>(H, A, b, pp, nullptr, q);
                 st.rz = wg_dot(pp, q, N, red);
@@ -275,7 +320,9 @@ __global__ void __launch_bounds__(NT, 8) k_solve(const Hier<T>* __restrict__ Hp,
                 const double rz2 = wg_dot(r, z, N, red);
                 const double be = rz2 / st.rz;
                 st.rz = rz2;
-                for (int i = threadIdx.x; i < N; i += NT) pp[i] = z[i] + be * pp[i];
+                const auto pg = gmem(pp);
+                const auto zg = gmem((const double*)z);
+                for (int i = threadIdx.x; i < N; i += NT) pg[i] = zg[i] + be * pg[i];
                 wg_barrier();
             }
         }
