@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--serve-load", type=float, default=0.8,
                     help="paced arrival rate as a fraction of the saturated throughput")
     ap.add_argument("--mixed", type=int, default=1, help="also time the FP32-inner solve")
+    ap.add_argument("--components", type=int, default=1,
+                    help="also time the operator and line-solve kernels alone")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     return ap.parse_args()
@@ -195,6 +197,106 @@ def run_batch(args, prec_name):
             "probs": probs, "ps": ps}
 
 
+def cr_words(n):
+    return n if n <= 1 else n + cr_words(n // 2)
+
+
+def components(args, probs, ps):
+    """Rooflines of the two hot operations of the path, each launched alone
+    through the library on the same batch (finest level): the sum-factorised
+    operator (matrix cores; algorithmic flops) and the cyclic-reduction line
+    solve (HBM; algorithmic bytes).  Durations come from HIP events on the
+    launch stream around `reps` back-to-back launches."""
+    import numpy as np
+    import torch
+
+    from paper_2504_10710_amd import pmg
+
+    dev = torch.device("cuda:0")
+    B, p, dim, reps = args.batch, args.p, 2, 10
+    n1, n = p + 1, p - 1
+    N = n1 ** dim
+    coords = []
+    for q in ps:
+        xi = pmg.pmg_gll(q)[0]
+        coords.append(torch.from_numpy(np.stack([pr.coords(xi) for pr in probs[:B]])).to(dev))
+    out = {}
+    stream = torch.cuda.current_stream()
+    for prec_name in ("f64", "f32"):
+        prec = pmg.PMG_F32 if prec_name == "f32" else pmg.PMG_F64
+        tname = "float" if prec_name == "f32" else "double"
+        esz = 4 if prec_name == "f32" else 8
+        desc = pmg.make_desc(dim=dim, p_fine=p, batch=B, gamma=args.gamma, alpha=args.alpha,
+                             smoother=pmg.PMG_SMOOTHER_FEM, inner_prec=prec)
+        s = pmg.Solver(desc, coords)
+        L = s.nlev - 1
+        dt = torch.float32 if prec_name == "f32" else torch.float64
+        gen = torch.Generator(device=dev).manual_seed(5)
+        x = torch.randn(B, N, dtype=dt, device=dev, generator=gen)
+        y = torch.empty_like(x)
+
+        def timed(fn):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps / 1e3
+
+        t_apply = timed(lambda: pmg.pmg_apply(s.h, L, prec, x, y))
+        fl = (8 * n1 + 7) * N * B          # four n1^3 contractions + pointwise fluxes
+        peak = PEAK_FP32_TFLOPS if prec_name == "f32" else PEAK_FP64_TFLOPS
+        out[f"k_apply<{tname}, {p}, 2>"] = {
+            "bound": "mfma", "achieved": round(fl / t_apply / 1e12, 3), "peak": peak,
+            "unit": "TFLOP/s", "frac": round(fl / t_apply / 1e12 / peak, 4),
+            "avg_ms": round(t_apply * 1e3, 4), "flops_per_problem": fl // B,
+            "algorithmic_bytes_per_problem": (1 + 3 + 1) * N * esz}
+        crw = cr_words(n)
+        nb = (2 * n ** dim + 3 * crw * n ** (dim - 1)) * esz   # r in, z out, CR factors
+        for d, nm in ((0, "x"), (1, "y")):
+            t = timed(lambda: pmg.pmg_line_solve(s.h, L, d, prec, x, y))
+            gbs = nb * B / t / 1e9
+            out[f"k_line_solve<{tname}, {p}, 2> {nm}-lines"] = {
+                "bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s",
+                "frac": round(gbs / 8000.0, 4), "avg_ms": round(t * 1e3, 4),
+                "algorithmic_bytes_per_problem": nb}
+        del s
+        torch.cuda.synchronize()
+        print(f"[bench] components {prec_name}: " + ", ".join(
+            f"{k} {v['achieved']} {v['unit']}" for k, v in out.items() if tname in k),
+            file=sys.stderr, flush=True)
+    return out
+
+
+def measured_traffic(kernel, batch):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if
+    it was taken on the current kernel sources at this batch size; else None."""
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2504_10710_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    digest = h.hexdigest()[:16]
+    for f in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
+        rec = {}
+        with open(f) as fh:
+            for line in fh:
+                if line.startswith("traffic-record:"):
+                    for kv in line.split(":", 1)[1].split(";"):
+                        if "=" in kv:
+                            k, v = kv.split("=", 1)
+                            rec[k.strip()] = v.strip()
+        if rec.get("kernel") == kernel and rec.get("batch") == str(batch) and \
+                rec.get("sources") == digest:
+            return float(rec["bytes_per_launch"]), os.path.basename(f)
+    return None, digest
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -214,10 +316,12 @@ def main():
     r64 = run_batch(args, args.prec)
     achieved = r64["flops"] / r64["solve_s"] / 1e12
     peak = PEAK_FP32_TFLOPS if args.prec == "f32" else PEAK_FP64_TFLOPS
+    kname = f"k_solve<{'float' if args.prec == 'f32' else 'double'}, {p}, 2>"
+    traffic, src = measured_traffic(kname, B)
     roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 5), "traffic": None,
-                "kernel": f"k_solve<{'float' if args.prec == 'f32' else 'double'}, {p}, 2>",
-                "flops_per_launch": r64["flops"]}
+                "frac": round(achieved / peak, 5), "traffic": traffic,
+                "traffic_source": src if traffic is not None else None,
+                "kernel": kname, "flops_per_launch": r64["flops"]}
     mixed = None
     if args.mixed and args.prec == "f64":
         r32 = run_batch(args, "f32")
@@ -227,6 +331,7 @@ def main():
                  "max_relres": r32["max_relres"],
                  "achieved_tflops": round(r32["flops"] / r32["solve_s"] / 1e12, 4),
                  "speedup_vs_f64": round(r32["value"] / r64["value"], 3)}
+    comps = components(args, r64["probs"], r64["ps"]) if args.components else None
     served = serve(args) if args.serve > 0 else None
     cpu = cpu_baseline(args, r64["probs"], r64["ps"]) if args.cpu_seconds > 0 else None
 
@@ -253,6 +358,7 @@ def main():
                    "iterations_median": int(np.median(r64["its"])), "converged": r64["ok"],
                    "max_relres": r64["max_relres"]},
         "roofline": roofline,
+        "kernels": comps,
         "cpu_baseline": cpu,
         "mixed_precision": mixed,
         "serving": served,

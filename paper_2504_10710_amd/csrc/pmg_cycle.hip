@@ -6,7 +6,7 @@
 namespace pmg {
 
 template <class T, int P, int DIM>
-__global__ void __launch_bounds__(NT, 8) k_cycle(const Hier<T>* __restrict__ Hp, const T* __restrict__ r, T* __restrict__ y)
+__global__ void __launch_bounds__(NT, 4) k_cycle(const Hier<T>* __restrict__ Hp, const T* __restrict__ r, T* __restrict__ y)
 {
     const Hier<T>& H = *Hp;
     using S = Shape<P, DIM>;

@@ -44,7 +44,7 @@ __global__ void __launch_bounds__(NT) k_prolong(const Hier<T>* __restrict__ Hp, 
 }
 
 template <class T, int P, int DIM>
-__global__ void __launch_bounds__(NT) k_line_solve(const Hier<T>* __restrict__ Hp, int dir, const T* __restrict__ r,
+__global__ void __launch_bounds__(NT, 8) k_line_solve(const Hier<T>* __restrict__ Hp, int dir, const T* __restrict__ r,
                                                    T* __restrict__ z)
 {
     const Hier<T>& H = *Hp;

@@ -94,7 +94,7 @@ __device__ inline double mgs_column(double* w_, const double* V_, long long N, i
 // true residual ||b - A x|| <= rtol ||b||.  At most A.budget iterations are
 // taken in this launch; the state is saved in A.st[b].
 template <class T, int P, int DIM>
-__global__ void __launch_bounds__(NT, 8) k_solve(const Hier<T>* __restrict__ Hp, SolveArgs A)
+__global__ void __launch_bounds__(NT, 4) k_solve(const Hier<T>* __restrict__ Hp, SolveArgs A)
 {
     const Hier<T>& H = *Hp;
     using S = Shape<P, DIM>;
