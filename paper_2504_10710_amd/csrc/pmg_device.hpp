@@ -26,6 +26,9 @@ namespace pmg {
 
 constexpr int NT = 256;          // threads per workgroup
 constexpr int MAX_LEVELS = 9;
+// smallest 2-D degree whose operator and transfers run on the matrix cores
+// (16x16 tiles over rows and columns 1..p); below it the vector units
+constexpr int MFMA_MIN_P = 32;
 
 __host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 __host__ __device__ constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
@@ -280,11 +283,108 @@ __device__ void wg_gemm(const T* __restrict__ A, const T* __restrict__ B, T* __r
     wg_barrier();
 }
 
+// Register-blocked form of mfma2 for BR x BC tiles per product: c0[i][j] +=
+// A0_i B0_j and c1[i][j] += A1_i B1_j over k = 0 .. K-1, where A_i are the
+// row strips 16 i apart (row-major, leading dimension LDA*, unit stride in
+// k) and B_j the column strips 16 j apart (row-major, leading dimension
+// LDB*, stride LDB* in k).  Pointers as in mfma2 (the lane's element of the
+// first strip).  Each operand fragment feeds BR or BC matrix-core steps, so
+// a block needs BR + BC loads per product and k-step instead of 2 BR BC.
+// c0 and c1 may be the same array (both products then accumulate into it).
+template <class T, int K, int LDA0, int LDB0, int LDA1, int LDB1, int BR, int BC, class PA0,
+          class PB0, class PA1, class PB1>
+__device__ inline void mfma_blocks(PA0 a0_, PB0 b0_, PA1 a1_, PB1 b1_,
+                                   typename Mfma<T>::v4 (&c0)[BR][BC],
+                                   typename Mfma<T>::v4 (&c1)[BR][BC])
+{
+    const auto a0 = gmem(a0_);
+    const auto b0 = gmem(b0_);
+    const auto a1 = gmem(a1_);
+    const auto b1 = gmem(b1_);
+    constexpr int KS = K / 4;
+    constexpr int PF = 2;
+    T xa0[PF][BR], xb0[PF][BC], xa1[PF][BR], xb1[PF][BC];
+#pragma unroll
+    for (int u = 0; u < PF; ++u)
+        if (u < KS) {
+#pragma unroll
+            for (int i = 0; i < BR; ++i) {
+                xa0[u][i] = a0[i * 16 * LDA0 + 4 * u];
+                xa1[u][i] = a1[i * 16 * LDA1 + 4 * u];
+            }
+#pragma unroll
+            for (int j = 0; j < BC; ++j) {
+                xb0[u][j] = b0[j * 16 + 4 * u * LDB0];
+                xb1[u][j] = b1[j * 16 + 4 * u * LDB1];
+            }
+        }
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        const int u = s % PF;
+        T pa0[BR], pb0[BC], pa1[BR], pb1[BC];
+#pragma unroll
+        for (int i = 0; i < BR; ++i) {
+            pa0[i] = xa0[u][i];
+            pa1[i] = xa1[u][i];
+        }
+#pragma unroll
+        for (int j = 0; j < BC; ++j) {
+            pb0[j] = xb0[u][j];
+            pb1[j] = xb1[u][j];
+        }
+        if (s + PF < KS) {
+#pragma unroll
+            for (int i = 0; i < BR; ++i) {
+                xa0[u][i] = a0[i * 16 * LDA0 + 4 * (s + PF)];
+                xa1[u][i] = a1[i * 16 * LDA1 + 4 * (s + PF)];
+            }
+#pragma unroll
+            for (int j = 0; j < BC; ++j) {
+                xb0[u][j] = b0[j * 16 + 4 * (s + PF) * LDB0];
+                xb1[u][j] = b1[j * 16 + 4 * (s + PF) * LDB1];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < BR; ++i)
+#pragma unroll
+            for (int j = 0; j < BC; ++j) c0[i][j] = Mfma<T>::op(pa0[i], pb0[j], c0[i][j]);
+#pragma unroll
+        for (int i = 0; i < BR; ++i)
+#pragma unroll
+            for (int j = 0; j < BC; ++j) c1[i][j] = Mfma<T>::op(pa1[i], pb1[j], c1[i][j]);
+    }
+    if constexpr (K % 4 != 0) {
+        const int kq = (threadIdx.x & 63) >> 4;
+        const bool in = 4 * KS + kq < K;
+        const int kk = (in ? 4 * KS + kq : K - 1) - kq;   // stays inside the row / column
+        T pa0[BR], pb0[BC], pa1[BR], pb1[BC];
+#pragma unroll
+        for (int i = 0; i < BR; ++i) {
+            pa0[i] = in ? a0[i * 16 * LDA0 + kk] : T(0);
+            pa1[i] = in ? a1[i * 16 * LDA1 + kk] : T(0);
+        }
+#pragma unroll
+        for (int j = 0; j < BC; ++j) {
+            pb0[j] = in ? b0[j * 16 + kk * LDB0] : T(0);
+            pb1[j] = in ? b1[j * 16 + kk * LDB1] : T(0);
+        }
+#pragma unroll
+        for (int i = 0; i < BR; ++i)
+#pragma unroll
+            for (int j = 0; j < BC; ++j) c0[i][j] = Mfma<T>::op(pa0[i], pb0[j], c0[i][j]);
+#pragma unroll
+        for (int i = 0; i < BR; ++i)
+#pragma unroll
+            for (int j = 0; j < BC; ++j) c1[i][j] = Mfma<T>::op(pa1[i], pb1[j], c1[i][j]);
+    }
+}
+
 // 2-D A x on matrix cores.  Pass 1: the reference gradients x D^T and D x at
-// the nodes with both indices in 1..P as 16x16 tiles (one wave computes both
-// gradients of a tile), combined into the fluxes at once; row 0 and column 0
-// on the vector units.  Pass 2: F0 D + D^T F1 on the same tiles (two
-// accumulators, added at the end); the boundary rows and columns are zero.
+// the nodes with both indices in 1..P, one wave per block of BLK x BLK
+// 16x16 tiles (both gradients of the block), combined into the fluxes at
+// once; row 0 and column 0 on the vector units.  Pass 2: F0 D + D^T F1 on
+// the same blocks, both products accumulating into one set of tiles; the
+// boundary rows and columns are zero.
 template <class T, int P, bool RESID>
 __device__ void apply2d_mfma(const T* __restrict__ G_, const T* __restrict__ D_,
                              const T* __restrict__ DT_, T* __restrict__ TR_,
@@ -298,23 +398,37 @@ __device__ void apply2d_mfma(const T* __restrict__ G_, const T* __restrict__ D_,
     const auto r = gmem(r_);
     const auto out = gmem(out_);
     static_assert(P % 16 == 0, "tiles cover rows 1..P");
-    constexpr int n1 = P + 1, N = n1 * n1, NTL = P / 16;
+    constexpr int BLK = P >= 64 ? 2 : 1;           // tiles per block side
+    constexpr int n1 = P + 1, N = n1 * n1, NB = P / (16 * BLK);
     using V4 = typename Mfma<T>::v4;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lr = lane & 15, kq = lane >> 4;
-    for (int t = wave; t < NTL * NTL; t += NT / 64) {
-        const int r0 = 1 + (t / NTL) * 16, c0 = 1 + (t % NTL) * 16;
-        V4 ur = {0, 0, 0, 0}, us = {0, 0, 0, 0};
-        mfma2<T, n1, 1, n1, 1, n1>(x + (r0 + lr) * n1 + kq, DT + kq * n1 + c0 + lr,
-                                   D + (r0 + lr) * n1 + kq, x + kq * n1 + c0 + lr, ur, us);
-        const int i = c0 + lr;
+    for (int t = wave; t < NB * NB; t += NT / 64) {
+        const int r0 = 1 + (t / NB) * 16 * BLK, c0 = 1 + (t % NB) * 16 * BLK;
+        V4 ur[BLK][BLK], us[BLK][BLK];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int q = (r0 + Mfma<T>::row(lane, v)) * n1 + i;
-            const T g00 = G[q], g11 = G[N + q], g01 = G[2 * N + q];
-            TR[q] = g00 * ur[v] + g01 * us[v];
-            TR[N + q] = g01 * ur[v] + g11 * us[v];
-        }
+        for (int i = 0; i < BLK; ++i)
+#pragma unroll
+            for (int j = 0; j < BLK; ++j) {
+                ur[i][j] = V4{0, 0, 0, 0};
+                us[i][j] = V4{0, 0, 0, 0};
+            }
+        mfma_blocks<T, n1, n1, n1, n1, n1, BLK, BLK>(x + (r0 + lr) * n1 + kq, DT + kq * n1 + c0 + lr,
+                                                     D + (r0 + lr) * n1 + kq, x + kq * n1 + c0 + lr,
+                                                     ur, us);
+#pragma unroll
+        for (int i = 0; i < BLK; ++i)
+#pragma unroll
+            for (int j = 0; j < BLK; ++j) {
+                const int col = c0 + 16 * j + lr;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int q = (r0 + 16 * i + Mfma<T>::row(lane, v)) * n1 + col;
+                    const T g00 = G[q], g11 = G[N + q], g01 = G[2 * N + q];
+                    TR[q] = g00 * ur[i][j][v] + g01 * us[i][j][v];
+                    TR[N + q] = g01 * ur[i][j][v] + g11 * us[i][j][v];
+                }
+            }
     }
     for (int e = threadIdx.x; e < 2 * P + 1; e += NT) {
         const int j = e <= P ? 0 : e - P, i = e <= P ? e : 0;
@@ -329,20 +443,29 @@ __device__ void apply2d_mfma(const T* __restrict__ G_, const T* __restrict__ D_,
         TR[N + q] = g01 * ur + g11 * us;
     }
     wg_barrier();
-    for (int t = wave; t < NTL * NTL; t += NT / 64) {
-        const int r0 = 1 + (t / NTL) * 16, c0 = 1 + (t % NTL) * 16;
-        V4 y0 = {0, 0, 0, 0}, y1 = {0, 0, 0, 0};
-        // sum_k F0[j][k] D[k][i] and sum_k D^T[j][k] F1[k][i]
-        mfma2<T, n1, 1, n1, 1, n1>(TR + (r0 + lr) * n1 + kq, D + kq * n1 + c0 + lr,
-                                   DT + (r0 + lr) * n1 + kq, TR + N + kq * n1 + c0 + lr, y0, y1);
-        const int i = c0 + lr;
+    for (int t = wave; t < NB * NB; t += NT / 64) {
+        const int r0 = 1 + (t / NB) * 16 * BLK, c0 = 1 + (t % NB) * 16 * BLK;
+        V4 y[BLK][BLK];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int j = r0 + Mfma<T>::row(lane, v);
-            const int q = j * n1 + i;
-            const T y = y0[v] + y1[v];
-            out[q] = (i == P || j == P) ? T(0) : (RESID ? r[q] - y : y);
-        }
+        for (int i = 0; i < BLK; ++i)
+#pragma unroll
+            for (int j = 0; j < BLK; ++j) y[i][j] = V4{0, 0, 0, 0};
+        // sum_k F0[j][k] D[k][i] and sum_k D^T[j][k] F1[k][i]
+        mfma_blocks<T, n1, n1, n1, n1, n1, BLK, BLK>(TR + (r0 + lr) * n1 + kq, D + kq * n1 + c0 + lr,
+                                                     DT + (r0 + lr) * n1 + kq,
+                                                     TR + N + kq * n1 + c0 + lr, y, y);
+#pragma unroll
+        for (int i = 0; i < BLK; ++i)
+#pragma unroll
+            for (int jj = 0; jj < BLK; ++jj) {
+                const int col = c0 + 16 * jj + lr;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = r0 + 16 * i + Mfma<T>::row(lane, v);
+                    const int q = row * n1 + col;
+                    out[q] = (col == P || row == P) ? T(0) : (RESID ? r[q] - y[i][jj][v] : y[i][jj][v]);
+                }
+            }
     }
     for (int e = threadIdx.x; e < 2 * P + 1; e += NT) out[e <= P ? e : (e - P) * n1] = T(0);
     wg_barrier();
@@ -359,7 +482,7 @@ __device__ __attribute__((noinline)) void apply_level(const T* __restrict__ G_,
                                                       const T* __restrict__ x_,
                                                       const T* __restrict__ r_, T* __restrict__ out_)
 {
-    if constexpr (DIM == 2 && P >= 64) {
+    if constexpr (DIM == 2 && P >= MFMA_MIN_P) {
         apply2d_mfma<T, P, RESID>(G_, D_, DT_, TR_, x_, r_, out_);
         return;
     }
@@ -700,7 +823,7 @@ __device__ __attribute__((noinline)) void restrict_level(const T* rf, T* rc, con
                                                          const T* JT, T* w1, T* w2)
 {
     constexpr int n1f = P + 1, n1c = P / 2 + 1;
-    if constexpr (DIM == 2 && P >= 64) {
+    if constexpr (DIM == 2 && P >= MFMA_MIN_P) {
         // W1 = rf J (n1f x n1c); rc = J^T W1 with zero boundary
         (void)w2;
         wg_gemm<T, n1f, n1c, n1f, n1f, n1c, 0>(rf, J, w1);
@@ -722,7 +845,7 @@ template <class T, int P, int DIM>
 __device__ __attribute__((noinline)) void prolong_level(const T* ec, T* xf, const T* J, const T* JT, T* w1, T* w2)
 {
     constexpr int n1f = P + 1, n1c = P / 2 + 1;
-    if constexpr (DIM == 2 && P >= 64) {
+    if constexpr (DIM == 2 && P >= MFMA_MIN_P) {
         // W1 = ec J^T (n1c x n1f); xf += J W1
         (void)w2;
         wg_gemm<T, n1c, n1f, n1c, n1c, n1f, 0>(ec, JT, w1);
