@@ -696,12 +696,12 @@ __device__ __attribute__((noinline)) void line_cr(const T* __restrict__ cr_, int
 #pragma unroll
         for (int k = 0; k < NK - 1; ++k) {
             const int nk = (n + 1) / (1 << k) - 1;
-#pragma unroll 4
+#pragma unroll 8
             for (int t = 0; t < nk; t += 2) {
                 int s = ((t + 1) << k) - 1;
                 g[node(s)] *= W(off + t, 0);
             }
-#pragma unroll 4
+#pragma unroll 8
             for (int t = 1; t < nk; t += 2) {
                 int s = ((t + 1) << k) - 1;
                 int sl = (t << k) - 1, sr = ((t + 2) << k) - 1;
@@ -718,7 +718,7 @@ __device__ __attribute__((noinline)) void line_cr(const T* __restrict__ cr_, int
             const int nk = (n + 1) / (1 << k) - 1;
             off -= nk;
             if (FUSED && k == 0) {
-#pragma unroll 4
+#pragma unroll 8
                 for (int t = 0; t < nk; ++t) {
                     int s = t;
                     T v;
@@ -732,7 +732,7 @@ __device__ __attribute__((noinline)) void line_cr(const T* __restrict__ cr_, int
                     x[node(s)] += alpha * v;
                 }
             } else {
-#pragma unroll 4
+#pragma unroll 8
                 for (int t = 0; t < nk; t += 2) {
                     int s = ((t + 1) << k) - 1;
                     T v = g[node(s)];
