@@ -255,9 +255,13 @@ int pmg_pool_destroy(pmg_pool* pool);
 /* A server owns one pool per shape class and admits queued requests in
  * arrival order whenever a slot of their class is free and the summed
  * footprint (per-slot workspace bytes) of the admitted, unfinished requests
- * stays within budget_bytes.  Each pmg_server_step admits, launches one step
- * of every non-empty pool (each pool on its own stream, so the classes'
- * kernels overlap on the device), waits, and retires finished requests. */
+ * stays within budget_bytes.  Each class runs on its own stream and
+ * advances independently: pmg_server_step retires the finished requests of
+ * every class whose previous step has completed (waiting up to about 2 ms for
+ * one if none has), admits queued requests into idle classes, and launches
+ * the next step of every idle class with running slots, then returns without
+ * waiting for those steps.  Fast classes are therefore not held by slow ones,
+ * and the classes' kernels overlap on the device.  Call it repeatedly. */
 #define PMG_SERVER_MAX_CLASSES 8
 typedef struct {
     int n_classes;

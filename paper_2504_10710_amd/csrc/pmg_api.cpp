@@ -2,11 +2,13 @@
 // workspace layout, host-side 1-D GLL tables, kernel launches.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "pmg_internal.hpp"
@@ -959,6 +961,12 @@ struct pmg_server {
         std::vector<long long> slot_req;   // ticket per slot, -1 free
         int running = 0;
         int nlev = 0;
+        // a step in flight: its slot states and infos arrive in pinned host
+        // buffers, `done` is recorded after the copies
+        bool inflight = false;
+        hipEvent_t done = nullptr;
+        SolveState* hst = nullptr;
+        pmg_info* hinfo = nullptr;
     };
     Class cls[PMG_SERVER_MAX_CLASSES];
     std::vector<Req> reqs;           // indexed by ticket
@@ -1022,6 +1030,15 @@ int pmg_server_create(const pmg_server_desc* d, void* d_ws, size_t ws_bytes, pmg
             return rc;
         }
         base += (b + 4095) & ~size_t(4095);
+        const int B = d->classes[c].batch;
+        if ((e = hipEventCreateWithFlags(&C.done, hipEventDisableTiming)) != hipSuccess ||
+            (e = hipHostMalloc((void**)&C.hst, sizeof(SolveState) * B, hipHostMallocDefault)) !=
+                hipSuccess ||
+            (e = hipHostMalloc((void**)&C.hinfo, sizeof(pmg_info) * B, hipHostMallocDefault)) !=
+                hipSuccess) {
+            pmg_server_destroy(S);
+            return hip_fail(e, "server host buffers");
+        }
         C.footprint = b / d->classes[c].batch;
         C.slot_req.assign(d->classes[c].batch, -1);
         C.nlev = ilog2(d->classes[c].p_fine);
@@ -1049,12 +1066,69 @@ int pmg_server_submit(pmg_server* S, int c, const double* const* d_coords, const
     return PMG_OK;
 }
 
+// Retire the finished slots of a class whose step has completed (its slot
+// states are in C.hst): lift their solutions into the callers' buffers and
+// free slots and budget.
+static int server_retire(pmg_server* S, pmg_server::Class& C, int* done)
+{
+    int rc;
+    const int B = (int)C.slot_req.size();
+    std::vector<int> taken;
+    for (int b = 0; b < B; ++b) {
+        if (C.slot_req[b] < 0) continue;
+        const int st = C.hst[b].status;
+        if (st == ST_RUNNING || st == ST_IDLE) continue;
+        pmg_server::Req& r = S->reqs[C.slot_req[b]];
+        if ((rc = pmg_pool_take(C.pool, b, r.u, (pmg_stream_t)C.stream))) return rc;
+        r.info = C.hinfo[b];
+        r.info.status = st;
+        taken.push_back(b);
+    }
+    if (taken.empty()) return PMG_OK;
+    hipError_t e = hipStreamSynchronize(C.stream);   // only the lifts are queued
+    if (e != hipSuccess) return hip_fail(e, "server retire");
+    for (int b : taken) {
+        S->reqs[C.slot_req[b]].done = true;
+        C.slot_req[b] = -1;
+        C.running--;
+        S->in_use -= C.footprint;
+        S->finished++;
+        ++*done;
+    }
+    return PMG_OK;
+}
+
 int pmg_server_step(pmg_server* S, int* n_done)
 {
     if (!S) return fail(PMG_EINVAL, "server is NULL");
     int rc;
     const int nc = S->d.n_classes;
-    // 1. admissions in arrival order, within slots and the byte budget
+    int done = 0;
+    // 1. collect the classes whose step has completed; if none has and some
+    //    are in flight, wait a little for one (bounded, so that the caller
+    //    can keep submitting arrivals)
+    const auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        bool any_inflight = false, any_ready = false;
+        for (int c = 0; c < nc; ++c) {
+            pmg_server::Class& C = S->cls[c];
+            if (!C.inflight) continue;
+            hipError_t q = hipEventQuery(C.done);
+            if (q == hipErrorNotReady) {
+                any_inflight = true;
+                continue;
+            }
+            if (q != hipSuccess) return hip_fail(q, "server step");
+            C.inflight = false;
+            any_ready = true;
+            if ((rc = server_retire(S, C, &done))) return rc;
+        }
+        if (any_ready || !any_inflight) break;
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2)) break;
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+    // 2. admissions in arrival order into idle classes, within slots and the
+    //    byte budget (a request of a class whose step is in flight waits)
     std::vector<std::vector<int>> slots(nc);
     std::vector<std::vector<const double*>> coords(nc), fs(nc), gs(nc);
     std::vector<long long> keep;
@@ -1062,7 +1136,7 @@ int pmg_server_step(pmg_server* S, int* n_done)
         pmg_server::Req& r = S->reqs[t];
         pmg_server::Class& C = S->cls[r.cls];
         int free_slot = -1;
-        if (S->in_use + C.footprint <= S->d.budget_bytes) {
+        if (!C.inflight && S->in_use + C.footprint <= S->d.budget_bytes) {
             for (int b = 0; b < (int)C.slot_req.size(); ++b)
                 if (C.slot_req[b] < 0) { free_slot = b; break; }
         }
@@ -1083,41 +1157,24 @@ int pmg_server_step(pmg_server* S, int* n_done)
                                  coords[c].data(), fs[c].data(), gs[c].data(),
                                  (pmg_stream_t)S->cls[c].stream)))
             return rc;
-    // 2. one step of every class with running slots (classes overlap on the device)
-    for (int c = 0; c < nc; ++c)
-        if (S->cls[c].running > 0 &&
-            (rc = pmg_pool_step(S->cls[c].pool, (pmg_stream_t)S->cls[c].stream)))
-            return rc;
-    S->steps++;
-    // 3. retire finished requests
-    int done = 0;
+    // 3. launch a step of every idle class with running slots; each class runs
+    //    on its own stream, so fast classes are not held by slow ones
     for (int c = 0; c < nc; ++c) {
         pmg_server::Class& C = S->cls[c];
-        if (C.running == 0) continue;
-        const int B = (int)C.slot_req.size();
-        std::vector<int> st(B);
-        std::vector<pmg_info> inf(B);
-        if ((rc = pmg_pool_poll(C.pool, st.data(), inf.data(), (pmg_stream_t)C.stream))) return rc;
-        bool took = false;
-        for (int b = 0; b < B; ++b) {
-            if (C.slot_req[b] < 0 || st[b] == ST_RUNNING || st[b] == ST_IDLE) continue;
-            pmg_server::Req& r = S->reqs[C.slot_req[b]];
-            if ((rc = pmg_pool_take(C.pool, b, r.u, (pmg_stream_t)C.stream))) return rc;
-            took = true;
-            r.info = inf[b];
-            r.info.status = st[b];
-            r.done = true;
-            C.slot_req[b] = -1;
-            C.running--;
-            S->in_use -= C.footprint;
-            S->finished++;
-            ++done;
-        }
-        if (took) {
-            hipError_t e = hipStreamSynchronize(C.stream);
-            if (e != hipSuccess) return hip_fail(e, "server retire");
-        }
+        if (C.inflight || C.running == 0) continue;
+        if ((rc = pmg_pool_step(C.pool, (pmg_stream_t)C.stream))) return rc;
+        pmg_handle* h = C.pool->h;
+        const int B = h->d.batch;
+        hipError_t e = hipMemcpyAsync(C.hst, h->ws + h->o_state, sizeof(SolveState) * B,
+                                      hipMemcpyDeviceToHost, C.stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(C.hinfo, h->ws + h->o_info, sizeof(pmg_info) * B,
+                               hipMemcpyDeviceToHost, C.stream);
+        if (e == hipSuccess) e = hipEventRecord(C.done, C.stream);
+        if (e != hipSuccess) return hip_fail(e, "server launch");
+        C.inflight = true;
     }
+    S->steps++;
     if (n_done) *n_done = done;
     return PMG_OK;
 }
@@ -1148,8 +1205,13 @@ int pmg_server_destroy(pmg_server* S)
 {
     if (!S) return PMG_OK;
     for (int c = 0; c < PMG_SERVER_MAX_CLASSES; ++c) {
-        if (S->cls[c].pool) pmg_pool_destroy(S->cls[c].pool);
-        if (S->cls[c].stream) hipStreamDestroy(S->cls[c].stream);
+        pmg_server::Class& C = S->cls[c];
+        if (C.stream) hipStreamSynchronize(C.stream);
+        if (C.pool) pmg_pool_destroy(C.pool);
+        if (C.done) hipEventDestroy(C.done);
+        if (C.hst) hipHostFree(C.hst);
+        if (C.hinfo) hipHostFree(C.hinfo);
+        if (C.stream) hipStreamDestroy(C.stream);
     }
     delete S;
     return PMG_OK;

@@ -98,7 +98,7 @@ def test_server_mixed_classes_budget_and_bitwise_results():
     order = [0, 5, 8, 1, 2, 6, 9, 3, 7, 10, 4]   # interleaved arrivals
     pending = list(order)
     max_bytes = 0
-    for step in range(400):
+    for step in range(20000):
         # two new requests arrive before every step
         for _ in range(2):
             if pending:
