@@ -366,9 +366,9 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-SERVE_CLASSES = [  # (dim, p, slots)
-    (2, 16, 512), (2, 32, 512), (2, 64, 256), (2, 128, 256),
-    (3, 16, 256), (3, 32, 128), (3, 64, 128),
+SERVE_CLASSES = [  # (dim, p, slots, inner precision)
+    (2, 16, 512, "f32"), (2, 32, 512, "f32"), (2, 64, 256, "f32"), (2, 128, 256, "f32"),
+    (3, 16, 256, "f32"), (3, 32, 128, "f32"), (3, 64, 128, "f64"),
 ]
 
 
@@ -385,15 +385,11 @@ def serve(args):
 
     dev = torch.device("cuda:0")
     classes, bank = [], []
-    for dim, p, slots in SERVE_CLASSES:
-        if dim == 2:
-            classes.append(pmg.make_desc(dim=2, p_fine=p, batch=slots, gamma=1, alpha=0.16,
-                                         smoother=pmg.PMG_SMOOTHER_FEM, inner_prec=pmg.PMG_F32,
-                                         restart=30, max_iter=300, rtol=1e-10))
-        else:
-            classes.append(pmg.make_desc(dim=3, p_fine=p, batch=slots, gamma=1, alpha=0.16,
-                                         smoother=pmg.PMG_SMOOTHER_FEM, inner_prec=pmg.PMG_F32,
-                                         restart=20, max_iter=300, rtol=1e-10))
+    for dim, p, slots, prec in SERVE_CLASSES:
+        classes.append(pmg.make_desc(dim=dim, p_fine=p, batch=slots, gamma=1, alpha=0.16,
+                                     smoother=pmg.PMG_SMOOTHER_FEM,
+                                     inner_prec=pmg.PMG_F32 if prec == "f32" else pmg.PMG_F64,
+                                     restart=30 if dim == 2 else 20, max_iter=300, rtol=1e-10))
     footprint = [pmg.pmg_pool_workspace_bytes(c) // c.batch for c in classes]
     budget = int(sum(f * c.batch for f, c in zip(footprint, classes)) * 0.75)
     sdesc = pmg.make_server_desc(classes, iters_per_step=4, budget_bytes=budget)
@@ -401,7 +397,7 @@ def serve(args):
     # a bank of distinct seeded problems per class; request i of class c uses
     # bank entry i mod K (every request still runs its own setup and solve)
     K = 8
-    for ci, (dim, p, _) in enumerate(SERVE_CLASSES):
+    for ci, (dim, p, _, _) in enumerate(SERVE_CLASSES):
         ps = inputs.halving_degrees(p, 2)
         entries = []
         for k in range(K):
@@ -411,7 +407,7 @@ def serve(args):
             entries.append((coords, torch.from_numpy(prob.f(X)).to(dev), torch.from_numpy(prob.g(X)).to(dev)))
         bank.append(entries)
     stream = inputs.served_stream(args.serve, seed=7)
-    cls_of = {(d, p): i for i, (d, p, _) in enumerate(SERVE_CLASSES)}
+    cls_of = {(d, p): i for i, (d, p, _, _) in enumerate(SERVE_CLASSES)}
     reqs = [cls_of[(d, p)] for d, p, _ in stream]
     torch.cuda.synchronize()
 
@@ -469,7 +465,7 @@ def serve(args):
         one-shot batched pmg_solve per class over all of that class's
         requests (setup, lifting, solve, lift), classes back to back."""
         t0 = time.perf_counter()
-        for ci, (dim, p, _) in enumerate(SERVE_CLASSES):
+        for ci, (dim, p, _, _) in enumerate(SERVE_CLASSES):
             cnt = sum(1 for c in reqs if c == ci)
             if cnt == 0:
                 continue
@@ -508,11 +504,12 @@ def serve(args):
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n))
     mk2, lat, steps, worst, _ = run(arrivals)
     mix = {f"{d}d_p{p}": int(sum(1 for c in reqs if SERVE_CLASSES[c][:2] == (d, p)))
-           for d, p, _ in SERVE_CLASSES}
+           for d, p, _, _ in SERVE_CLASSES}
     print(f"[bench] served: saturated {thr:.1f} req/s, paced at {rate:.1f} req/s: "
           f"p50 {np.percentile(lat, 50):.1f} ms p99 {np.percentile(lat, 99):.1f} ms",
           file=sys.stderr, flush=True)
-    return {"requests": n, "mix": mix, "inner_precision": "f32",
+    return {"requests": n, "mix": mix,
+            "inner_precision": {f"{d}d_p{p}": pr for d, p, _, pr in SERVE_CLASSES},
             "saturated_solves_per_s": round(thr, 2),
             "plain_fp64_batched_solves_per_s": round(plain_thr, 2),
             "speedup_vs_plain_fp64": round(thr / plain_thr, 3),

@@ -291,12 +291,14 @@ __device__ void wg_gemm(const T* __restrict__ A, const T* __restrict__ B, T* __r
 // first strip).  Each operand fragment feeds BR or BC matrix-core steps, so
 // a block needs BR + BC loads per product and k-step instead of 2 BR BC.
 // c0 and c1 may be the same array (both products then accumulate into it).
-template <class T, int K, int LDA0, int LDB0, int LDA1, int LDB1, int BR, int BC, class PA0,
-          class PB0, class PA1, class PB1>
+// NP = 1 computes only the first product (a1, b1, c1 unused).
+template <class T, int K, int LDA0, int LDB0, int LDA1, int LDB1, int BR, int BC, int NP = 2,
+          class PA0, class PB0, class PA1, class PB1>
 __device__ inline void mfma_blocks(PA0 a0_, PB0 b0_, PA1 a1_, PB1 b1_,
                                    typename Mfma<T>::v4 (&c0)[BR][BC],
                                    typename Mfma<T>::v4 (&c1)[BR][BC])
 {
+    static_assert(NP == 1 || NP == 2, "one or two products");
     const auto a0 = gmem(a0_);
     const auto b0 = gmem(b0_);
     const auto a1 = gmem(a1_);
@@ -310,12 +312,12 @@ __device__ inline void mfma_blocks(PA0 a0_, PB0 b0_, PA1 a1_, PB1 b1_,
 #pragma unroll
             for (int i = 0; i < BR; ++i) {
                 xa0[u][i] = a0[i * 16 * LDA0 + 4 * u];
-                xa1[u][i] = a1[i * 16 * LDA1 + 4 * u];
+                if constexpr (NP == 2) xa1[u][i] = a1[i * 16 * LDA1 + 4 * u];
             }
 #pragma unroll
             for (int j = 0; j < BC; ++j) {
                 xb0[u][j] = b0[j * 16 + 4 * u * LDB0];
-                xb1[u][j] = b1[j * 16 + 4 * u * LDB1];
+                if constexpr (NP == 2) xb1[u][j] = b1[j * 16 + 4 * u * LDB1];
             }
         }
 #pragma unroll
@@ -325,33 +327,35 @@ __device__ inline void mfma_blocks(PA0 a0_, PB0 b0_, PA1 a1_, PB1 b1_,
 #pragma unroll
         for (int i = 0; i < BR; ++i) {
             pa0[i] = xa0[u][i];
-            pa1[i] = xa1[u][i];
+            if constexpr (NP == 2) pa1[i] = xa1[u][i];
         }
 #pragma unroll
         for (int j = 0; j < BC; ++j) {
             pb0[j] = xb0[u][j];
-            pb1[j] = xb1[u][j];
+            if constexpr (NP == 2) pb1[j] = xb1[u][j];
         }
         if (s + PF < KS) {
 #pragma unroll
             for (int i = 0; i < BR; ++i) {
                 xa0[u][i] = a0[i * 16 * LDA0 + 4 * (s + PF)];
-                xa1[u][i] = a1[i * 16 * LDA1 + 4 * (s + PF)];
+                if constexpr (NP == 2) xa1[u][i] = a1[i * 16 * LDA1 + 4 * (s + PF)];
             }
 #pragma unroll
             for (int j = 0; j < BC; ++j) {
                 xb0[u][j] = b0[j * 16 + 4 * (s + PF) * LDB0];
-                xb1[u][j] = b1[j * 16 + 4 * (s + PF) * LDB1];
+                if constexpr (NP == 2) xb1[u][j] = b1[j * 16 + 4 * (s + PF) * LDB1];
             }
         }
 #pragma unroll
         for (int i = 0; i < BR; ++i)
 #pragma unroll
             for (int j = 0; j < BC; ++j) c0[i][j] = Mfma<T>::op(pa0[i], pb0[j], c0[i][j]);
+        if constexpr (NP == 2) {
 #pragma unroll
-        for (int i = 0; i < BR; ++i)
+            for (int i = 0; i < BR; ++i)
 #pragma unroll
-            for (int j = 0; j < BC; ++j) c1[i][j] = Mfma<T>::op(pa1[i], pb1[j], c1[i][j]);
+                for (int j = 0; j < BC; ++j) c1[i][j] = Mfma<T>::op(pa1[i], pb1[j], c1[i][j]);
+        }
     }
     if constexpr (K % 4 != 0) {
         const int kq = (threadIdx.x & 63) >> 4;
@@ -361,21 +365,23 @@ __device__ inline void mfma_blocks(PA0 a0_, PB0 b0_, PA1 a1_, PB1 b1_,
 #pragma unroll
         for (int i = 0; i < BR; ++i) {
             pa0[i] = in ? a0[i * 16 * LDA0 + kk] : T(0);
-            pa1[i] = in ? a1[i * 16 * LDA1 + kk] : T(0);
+            if constexpr (NP == 2) pa1[i] = in ? a1[i * 16 * LDA1 + kk] : T(0);
         }
 #pragma unroll
         for (int j = 0; j < BC; ++j) {
             pb0[j] = in ? b0[j * 16 + kk * LDB0] : T(0);
-            pb1[j] = in ? b1[j * 16 + kk * LDB1] : T(0);
+            if constexpr (NP == 2) pb1[j] = in ? b1[j * 16 + kk * LDB1] : T(0);
         }
 #pragma unroll
         for (int i = 0; i < BR; ++i)
 #pragma unroll
             for (int j = 0; j < BC; ++j) c0[i][j] = Mfma<T>::op(pa0[i], pb0[j], c0[i][j]);
+        if constexpr (NP == 2) {
 #pragma unroll
-        for (int i = 0; i < BR; ++i)
+            for (int i = 0; i < BR; ++i)
 #pragma unroll
-            for (int j = 0; j < BC; ++j) c1[i][j] = Mfma<T>::op(pa1[i], pb1[j], c1[i][j]);
+                for (int j = 0; j < BC; ++j) c1[i][j] = Mfma<T>::op(pa1[i], pb1[j], c1[i][j]);
+        }
     }
 }
 
@@ -471,6 +477,183 @@ __device__ void apply2d_mfma(const T* __restrict__ G_, const T* __restrict__ D_,
     wg_barrier();
 }
 
+// 3-D A x on matrix cores, node q = i + n1 j + n1^2 k.  The four passes are
+// 16x16-tile products over index ranges 1..P (blocks of BLK x BLK tiles per
+// wave); index 0 of the gradients is filled on the vector units and the
+// output's boundary faces are zero.
+//   1a  g2(k, i) = sum_m D[k][m] x(i, j, m)        for each j   -> TR2
+//   1b  g0(j, i) = sum_m x(m, j, k) D[i][m],
+//       g1(j, i) = sum_m D[j][m] x(i, m, k)        for each k;
+//       fluxes f_a = sum_b G_ab g_b at once        -> TR0, TR1, TR2
+//   2a  y(k, i)  = sum_m D[m][k] f2(i, j, m)       for interior j -> out
+//   2b  y(j, i) += sum_m f0(m, j, k) D[m][i] + D[m][j] f1(i, m, k)
+//                                                 for interior k -> out
+template <class T, int P, bool RESID>
+__device__ void apply3d_mfma(const T* __restrict__ G_, const T* __restrict__ D_,
+                             const T* __restrict__ DT_, T* __restrict__ TR_,
+                             const T* __restrict__ x_, const T* __restrict__ r_, T* __restrict__ out_)
+{
+    const auto G = gmem(G_);
+    const auto D = gmem(D_);
+    const auto DT = gmem(DT_);
+    const auto TR = gmem(TR_);
+    const auto x = gmem(x_);
+    const auto r = gmem(r_);
+    const auto out = gmem(out_);
+    static_assert(P % 16 == 0, "tiles cover indices 1..P");
+    constexpr int BLK = P >= 64 ? 2 : 1;
+    constexpr int n1 = P + 1, S2 = n1 * n1, N = S2 * n1, NB = P / (16 * BLK), NBB = NB * NB;
+    using V4 = typename Mfma<T>::v4;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, kq = lane >> 4;
+    const auto F0 = TR, F1 = TR + N, F2 = TR + 2 * N;
+
+    // ---- 1a: z-gradient into F2
+    for (int t = wave; t < n1 * NBB; t += NT / 64) {
+        const int j = t / NBB, bb = t % NBB;
+        const int r0 = 1 + (bb / NB) * 16 * BLK, c0 = 1 + (bb % NB) * 16 * BLK;   // k, i
+        V4 acc[BLK][BLK];
+#pragma unroll
+        for (int a = 0; a < BLK; ++a)
+#pragma unroll
+            for (int b = 0; b < BLK; ++b) acc[a][b] = V4{0, 0, 0, 0};
+        const auto bp = x + n1 * j + kq * S2 + c0 + lr;
+        mfma_blocks<T, n1, n1, S2, n1, S2, BLK, BLK, 1>(D + (r0 + lr) * n1 + kq, bp, D, bp, acc, acc);
+#pragma unroll
+        for (int a = 0; a < BLK; ++a)
+#pragma unroll
+            for (int b = 0; b < BLK; ++b) {
+                const int i = c0 + 16 * b + lr;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int k = r0 + 16 * a + Mfma<T>::row(lane, v);
+                    F2[i + n1 * j + S2 * k] = acc[a][b][v];
+                }
+            }
+    }
+    for (int e = threadIdx.x; e < n1 * (2 * P + 1); e += NT) {
+        const int j = e / (2 * P + 1), tt = e % (2 * P + 1);
+        const int k = tt <= P ? 0 : tt - P, i = tt <= P ? tt : 0;
+        T g2 = 0;
+        for (int m = 0; m < n1; ++m) g2 += D[k * n1 + m] * x[i + n1 * j + S2 * m];
+        F2[i + n1 * j + S2 * k] = g2;
+    }
+    wg_barrier();
+
+    // ---- 1b: x- and y-gradients per z-slab, fluxes
+    for (int t = wave; t < n1 * NBB; t += NT / 64) {
+        const int k = t / NBB, bb = t % NBB;
+        const int r0 = 1 + (bb / NB) * 16 * BLK, c0 = 1 + (bb % NB) * 16 * BLK;   // j, i
+        const auto xk = x + S2 * k;
+        V4 g0[BLK][BLK], g1[BLK][BLK];
+#pragma unroll
+        for (int a = 0; a < BLK; ++a)
+#pragma unroll
+            for (int b = 0; b < BLK; ++b) {
+                g0[a][b] = V4{0, 0, 0, 0};
+                g1[a][b] = V4{0, 0, 0, 0};
+            }
+        mfma_blocks<T, n1, n1, n1, n1, n1, BLK, BLK>(xk + (r0 + lr) * n1 + kq, DT + kq * n1 + c0 + lr,
+                                                     D + (r0 + lr) * n1 + kq, xk + kq * n1 + c0 + lr,
+                                                     g0, g1);
+#pragma unroll
+        for (int a = 0; a < BLK; ++a)
+#pragma unroll
+            for (int b = 0; b < BLK; ++b) {
+                const int i = c0 + 16 * b + lr;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int q = i + n1 * (r0 + 16 * a + Mfma<T>::row(lane, v)) + S2 * k;
+                    const T u0 = g0[a][b][v], u1 = g1[a][b][v], u2 = F2[q];
+                    const T G00 = G[q], G11 = G[N + q], G22 = G[2 * N + q];
+                    const T G01 = G[3 * N + q], G02 = G[4 * N + q], G12 = G[5 * N + q];
+                    F0[q] = G00 * u0 + G01 * u1 + G02 * u2;
+                    F1[q] = G01 * u0 + G11 * u1 + G12 * u2;
+                    F2[q] = G02 * u0 + G12 * u1 + G22 * u2;
+                }
+            }
+    }
+    for (int e = threadIdx.x; e < n1 * (2 * P + 1); e += NT) {
+        const int k = e / (2 * P + 1), tt = e % (2 * P + 1);
+        const int j = tt <= P ? 0 : tt - P, i = tt <= P ? tt : 0;
+        T u0 = 0, u1 = 0;
+        for (int m = 0; m < n1; ++m) {
+            u0 += x[m + n1 * j + S2 * k] * DT[m * n1 + i];
+            u1 += D[j * n1 + m] * x[i + n1 * m + S2 * k];
+        }
+        const int q = i + n1 * j + S2 * k;
+        const T u2 = F2[q];
+        const T G00 = G[q], G11 = G[N + q], G22 = G[2 * N + q];
+        const T G01 = G[3 * N + q], G02 = G[4 * N + q], G12 = G[5 * N + q];
+        F0[q] = G00 * u0 + G01 * u1 + G02 * u2;
+        F1[q] = G01 * u0 + G11 * u1 + G12 * u2;
+        F2[q] = G02 * u0 + G12 * u1 + G22 * u2;
+    }
+    wg_barrier();
+
+    // ---- 2a: z-part of the divergence on interior y-rows
+    for (int t = wave; t < (P - 1) * NBB; t += NT / 64) {
+        const int j = 1 + t / NBB, bb = t % NBB;
+        const int r0 = 1 + (bb / NB) * 16 * BLK, c0 = 1 + (bb % NB) * 16 * BLK;   // k, i
+        V4 acc[BLK][BLK];
+#pragma unroll
+        for (int a = 0; a < BLK; ++a)
+#pragma unroll
+            for (int b = 0; b < BLK; ++b) acc[a][b] = V4{0, 0, 0, 0};
+        const auto bp = F2 + n1 * j + kq * S2 + c0 + lr;
+        mfma_blocks<T, n1, n1, S2, n1, S2, BLK, BLK, 1>(DT + (r0 + lr) * n1 + kq, bp, DT, bp, acc, acc);
+#pragma unroll
+        for (int a = 0; a < BLK; ++a)
+#pragma unroll
+            for (int b = 0; b < BLK; ++b) {
+                const int i = c0 + 16 * b + lr;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int k = r0 + 16 * a + Mfma<T>::row(lane, v);
+                    if (i < P && k < P) out[i + n1 * j + S2 * k] = acc[a][b][v];
+                }
+            }
+    }
+    wg_barrier();
+
+    // ---- 2b: x- and y-parts on interior z-slabs, residual
+    for (int t = wave; t < (P - 1) * NBB; t += NT / 64) {
+        const int k = 1 + t / NBB, bb = t % NBB;
+        const int r0 = 1 + (bb / NB) * 16 * BLK, c0 = 1 + (bb % NB) * 16 * BLK;   // j, i
+        V4 y[BLK][BLK];
+#pragma unroll
+        for (int a = 0; a < BLK; ++a)
+#pragma unroll
+            for (int b = 0; b < BLK; ++b) y[a][b] = V4{0, 0, 0, 0};
+        const auto f0k = F0 + S2 * k, f1k = F1 + S2 * k;
+        mfma_blocks<T, n1, n1, n1, n1, n1, BLK, BLK>(f0k + (r0 + lr) * n1 + kq, D + kq * n1 + c0 + lr,
+                                                     DT + (r0 + lr) * n1 + kq,
+                                                     f1k + kq * n1 + c0 + lr, y, y);
+#pragma unroll
+        for (int a = 0; a < BLK; ++a)
+#pragma unroll
+            for (int b = 0; b < BLK; ++b) {
+                const int i = c0 + 16 * b + lr;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int j = r0 + 16 * a + Mfma<T>::row(lane, v);
+                    if (i < P && j < P) {
+                        const int q = i + n1 * j + S2 * k;
+                        const T yy = y[a][b][v] + out[q];
+                        out[q] = RESID ? r[q] - yy : yy;
+                    }
+                }
+            }
+    }
+    // boundary faces
+    for (int e = threadIdx.x; e < 6 * S2; e += NT) {
+        const int f = e / S2, a = e % S2, u = a % n1, w = a / n1, c = (f & 1) ? P : 0;
+        const int q = f < 2 ? c + n1 * u + S2 * w : (f < 4 ? u + n1 * c + S2 * w : u + n1 * w + S2 * c);
+        out[q] = T(0);
+    }
+    wg_barrier();
+}
+
 // Matrix-free A x of eq. discreteBilinear by sum factorisation: reference
 // gradients g_b = D along axis b, fluxes f_a = sum_b G_ab g_b at every node,
 // then (A x)(n) = sum_a sum_k D[k][n_a] f_a(n with axis a <- k) on interior
@@ -484,6 +667,10 @@ __device__ __attribute__((noinline)) void apply_level(const T* __restrict__ G_,
 {
     if constexpr (DIM == 2 && P >= MFMA_MIN_P) {
         apply2d_mfma<T, P, RESID>(G_, D_, DT_, TR_, x_, r_, out_);
+        return;
+    }
+    if constexpr (DIM == 3 && P >= MFMA_MIN_P) {
+        apply3d_mfma<T, P, RESID>(G_, D_, DT_, TR_, x_, r_, out_);
         return;
     }
     const auto G = gmem(G_);
