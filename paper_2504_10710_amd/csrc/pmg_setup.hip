@@ -19,8 +19,8 @@ namespace pmg {
 template <int P, int DIM>
 __global__ void __launch_bounds__(NT) k_geom(const double* __restrict__ coords,
                                              const double* __restrict__ rho,
-                                             const double* __restrict__ D,
-                                             const double* __restrict__ DT,
+                                             const double* __restrict__ D_,
+                                             const double* __restrict__ DT_,
                                              double* __restrict__ G, float* __restrict__ G32,
                                              double* __restrict__ mass, double* __restrict__ X64,
                                              double* __restrict__ detmin, const int* slots,
@@ -31,25 +31,16 @@ __global__ void __launch_bounds__(NT) k_geom(const double* __restrict__ coords,
     __shared__ double red[NT];
     const long long b = slots ? slots[blockIdx.x] : blockIdx.x;
     if (pivot && threadIdx.x == 0) pivot[b] = 0;
-    const double* X = coords + b * DIM * N;
-    double* Gb = G + b * NC * N;
+    const auto X = gmem(coords + b * DIM * N);
+    const auto D = gmem(D_);
+    const auto DT = gmem(DT_);
+    const auto Gb = gmem(G + b * NC * N);
+    const auto G32b = G32 ? gmem(G32 + b * NC * N) : nullptr;
+    const auto massb = mass ? gmem(mass + b * N) : nullptr;
+    const auto Xo = gmem(X64 + b * DIM * N);
     double dmin = INFINITY;
-    for (int q = threadIdx.x; q < N; q += NT) {
-        int c[3] = {q % n1, (q / n1) % n1, DIM == 3 ? q / (n1 * n1) : 0};
-        double Jm[3][3];
-        for (int comp = 0; comp < DIM; ++comp) {
-            const double* Xc = X + comp * N;
-            for (int a = 0; a < DIM; ++a) {
-                const int st = a == 0 ? 1 : (a == 1 ? n1 : n1 * n1);
-                const double* xr = Xc + (q - c[a] * st);
-                double s = 0.0;
-                if (a == 0)
-                    for (int k = 0; k < n1; ++k) s += DT[k * n1 + c[0]] * xr[k];
-                else
-                    for (int k = 0; k < n1; ++k) s += D[c[a] * n1 + k] * xr[k * st];
-                Jm[comp][a] = s;
-            }
-        }
+    // everything after the Jacobian is pointwise: Jm[comp][a] = dx_comp/dxi_a at node q
+    auto point = [&](int q, const int (&c)[3], const double (&Jm)[3][3]) {
         double det, inv[3][3];
         if (DIM == 2) {
             det = Jm[0][0] * Jm[1][1] - Jm[0][1] * Jm[1][0];
@@ -84,10 +75,61 @@ __global__ void __launch_bounds__(NT) k_geom(const double* __restrict__ coords,
                 for (int comp = 0; comp < DIM; ++comp) s += inv[a][comp] * inv[bb][comp];
                 int gi = gidx(DIM, a, bb);
                 Gb[gi * N + q] = phi * s;
-                if (G32) G32[b * NC * N + gi * N + q] = (float)(phi * s);
+                if (G32b) G32b[gi * N + q] = (float)(phi * s);
             }
-        if (mass) mass[b * N + q] = phi;
-        for (int comp = 0; comp < DIM; ++comp) X64[b * DIM * N + comp * N + q] = X[comp * N + q];
+        if (massb) massb[q] = phi;
+        for (int comp = 0; comp < DIM; ++comp) Xo[comp * N + q] = X[comp * N + q];
+    };
+    // Jacobian by plain dot products (every node, or the first row and column)
+    auto valu = [&](int q) {
+        int c[3] = {q % n1, (q / n1) % n1, DIM == 3 ? q / (n1 * n1) : 0};
+        double Jm[3][3] = {};
+        for (int comp = 0; comp < DIM; ++comp) {
+            const auto Xc = X + comp * N;
+            for (int a = 0; a < DIM; ++a) {
+                const int st = a == 0 ? 1 : (a == 1 ? n1 : n1 * n1);
+                const auto xr = Xc + (q - c[a] * st);
+                double s = 0.0;
+                if (a == 0)
+                    for (int k = 0; k < n1; ++k) s += DT[k * n1 + c[0]] * xr[k];
+                else
+                    for (int k = 0; k < n1; ++k) s += D[c[a] * n1 + k] * xr[k * st];
+                Jm[comp][a] = s;
+            }
+        }
+        point(q, c, Jm);
+    };
+    if constexpr (DIM == 2 && P >= MFMA_MIN_P) {
+        // the four derivatives x D^T, D x, y D^T, D y on matrix-core tiles
+        // over rows and columns 1..P; row 0 and column 0 on the vector units
+        using V4 = Mfma<double>::v4;
+        constexpr int NB = P / 16;
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const int lr = lane & 15, kq = lane >> 4;
+        for (int t = wave; t < NB * NB; t += NT / 64) {
+            const int r0 = 1 + (t / NB) * 16, c0 = 1 + (t % NB) * 16;
+            V4 xr[1][1] = {{V4{0, 0, 0, 0}}}, xs[1][1] = {{V4{0, 0, 0, 0}}};
+            V4 yr[1][1] = {{V4{0, 0, 0, 0}}}, ys[1][1] = {{V4{0, 0, 0, 0}}};
+            mfma_blocks<double, n1, n1, n1, n1, n1, 1, 1>(X + (r0 + lr) * n1 + kq, DT + kq * n1 + c0 + lr,
+                                                          D + (r0 + lr) * n1 + kq, X + kq * n1 + c0 + lr,
+                                                          xr, xs);
+            mfma_blocks<double, n1, n1, n1, n1, n1, 1, 1>(X + N + (r0 + lr) * n1 + kq,
+                                                          DT + kq * n1 + c0 + lr, D + (r0 + lr) * n1 + kq,
+                                                          X + N + kq * n1 + c0 + lr, yr, ys);
+            const int i = c0 + lr;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int j = r0 + Mfma<double>::row(lane, v);
+                const int c[3] = {i, j, 0};
+                const double Jm[3][3] = {{xr[0][0][v], xs[0][0][v], 0.0},
+                                         {yr[0][0][v], ys[0][0][v], 0.0},
+                                         {0.0, 0.0, 0.0}};
+                point(j * n1 + i, c, Jm);
+            }
+        }
+        for (int e = threadIdx.x; e < 2 * P + 1; e += NT) valu(e <= P ? e : (e - P) * n1);
+    } else {
+        for (int q = threadIdx.x; q < N; q += NT) valu(q);
     }
     double m = wg_min(dmin, red);
     if (threadIdx.x == 0) detmin[b] = m;
@@ -299,22 +341,29 @@ __global__ void __launch_bounds__(NT) k_lines(const double* __restrict__ G,
     const double* Gb = G + b * NC * N;
     const double* Xb = X64 + b * DIM * N;
     int bad = 0;
-    for (int dir = 0; dir < DIM; ++dir) {
-        double* cr = (dir == 0 ? cr0 : (dir == 1 ? cr1 : cr2)) + b * 3 * CRW * NL;
-        float* cf = dir == 0 ? f0 : (dir == 1 ? f1 : f2);
+    auto crp = [&](int dir) { return (dir == 0 ? cr0 : (dir == 1 ? cr1 : cr2)) + b * 3 * CRW * NL; };
+    auto idx = [&](int dir, int line, int slot, int w) -> long long {
         const bool lm = dir == 0 && wave_lines<P>();   // line-major layout
-        for (int line = threadIdx.x; line < NL; line += NT) {
-            auto idx = [&](int slot, int w) -> long long {
-                return lm ? ((long long)line * CRW + slot) * 3 + w : (long long)(slot * 3 + w) * NL + line;
-            };
-            auto W = [&](int slot, int w) -> double& { return cr[idx(slot, w)]; };
-            for (int s = 0; s < n; ++s) {
-                double l, a, u;
-                line_raw<P, DIM>(Gb, Xb, D, smoother, dir, line, s, l, a, u);
-                W(s, 0) = l;
-                W(s, 1) = a;
-                W(s, 2) = u;
-            }
+        return lm ? ((long long)line * CRW + slot) * 3 + w : (long long)(slot * 3 + w) * NL + line;
+    };
+    // 1. the raw tridiagonals of every line of every axis, one entry per work item
+    for (int e = threadIdx.x; e < DIM * NL * n; e += NT) {
+        const int dir = e / (NL * n), line = (e / n) % NL, sq = e % n;
+        double l, a, u;
+        line_raw<P, DIM>(Gb, Xb, D, smoother, dir, line, sq, l, a, u);
+        double* cr = crp(dir);
+        cr[idx(dir, line, sq, 0)] = l;
+        cr[idx(dir, line, sq, 1)] = a;
+        cr[idx(dir, line, sq, 2)] = u;
+    }
+    wg_barrier();
+    // 2. cyclic-reduction factors, one line per thread over all axes
+    for (int e = threadIdx.x; e < DIM * NL; e += NT) {
+        const int dir = e / NL, line = e % NL;
+        double* cr = crp(dir);
+        float* cf = dir == 0 ? f0 : (dir == 1 ? f1 : f2);
+        auto W = [&](int slot, int w) -> double& { return cr[idx(dir, line, slot, w)]; };
+        {
             int off = 0, nk = n;
             while (nk > 1) {
                 const int nc = nk / 2;
@@ -349,7 +398,7 @@ __global__ void __launch_bounds__(NT) k_lines(const double* __restrict__ G,
             if (cf) {
                 float* cfb = cf + b * 3 * CRW * NL;
                 for (int slot = 0; slot < CRW; ++slot)
-                    for (int w = 0; w < 3; ++w) cfb[idx(slot, w)] = (float)W(slot, w);
+                    for (int w = 0; w < 3; ++w) cfb[idx(dir, line, slot, w)] = (float)W(slot, w);
             }
         }
     }
