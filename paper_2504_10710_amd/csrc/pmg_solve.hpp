@@ -66,6 +66,40 @@ __device__ void apply64(const Hier<T>& H, const SolveArgs& A, int b, const doubl
 // <w, w> after the last one) share one pass over w, so each basis vector
 // costs one pass and one reduction.  Returns ||w|| after orthogonalisation;
 // H[i * ldh] = h_i.
+// One pass of the column: w -= h v_i and this thread's part of <w, v_next>
+// (or of <w, w> after the last basis vector).  The three vectors are distinct
+// (restrict), so the loads of several elements can be issued together.
+__device__ inline double mgs_pass(double* __restrict__ w_, const double* __restrict__ vi_,
+                                  const double* __restrict__ vn_, double h, int N)
+{
+    const auto w = gmem(w_);
+    const auto vi = gmem(vi_);
+    const auto vn = gmem(vn_);
+    double d = 0.0;
+#pragma unroll 4
+    for (int q = threadIdx.x; q < N; q += NT) {
+        const double wq = w[q] - h * vi[q];
+        w[q] = wq;
+        d += wq * vn[q];
+    }
+    return d;
+}
+
+__device__ inline double mgs_pass_last(double* __restrict__ w_, const double* __restrict__ vi_,
+                                       double h, int N)
+{
+    const auto w = gmem(w_);
+    const auto vi = gmem(vi_);
+    double d = 0.0;
+#pragma unroll 4
+    for (int q = threadIdx.x; q < N; q += NT) {
+        const double wq = w[q] - h * vi[q];
+        w[q] = wq;
+        d += wq * wq;
+    }
+    return d;
+}
+
 __device__ inline double mgs_column(double* w_, const double* V_, long long N, int j, double* H,
                                     int ldh, double* red)
 {
@@ -75,14 +109,8 @@ __device__ inline double mgs_column(double* w_, const double* V_, long long N, i
     for (long long q = threadIdx.x; q < N; q += NT) d += w[q] * V[q];
     double h = wg_sum(d, red);
     for (int i = 0; i <= j; ++i) {
-        const auto vi = V + i * N;
-        const auto vn = V + (i + 1) * N;
-        d = 0.0;
-        for (long long q = threadIdx.x; q < N; q += NT) {
-            const double wq = w[q] - h * vi[q];
-            w[q] = wq;
-            d += wq * (i < j ? vn[q] : wq);
-        }
+        d = i < j ? mgs_pass(w_, V_ + i * N, V_ + (i + 1) * N, h, (int)N)
+                  : mgs_pass_last(w_, V_ + i * N, h, (int)N);
         if (threadIdx.x == 0) H[i * ldh] = h;
         h = wg_sum(d, red);
     }
