@@ -15,8 +15,17 @@ __device__ inline double wg_dot(const double* a_, const double* b_, int n, doubl
     const auto a = gmem(a_);
     const auto b = gmem(b_);
     double s = 0.0;
+#pragma unroll 4
     for (int i = threadIdx.x; i < n; i += NT) s += a[i] * b[i];
     return wg_sum(s, red);
+}
+
+// v /= d
+__device__ inline void wg_scale_div(double* __restrict__ v_, double d, int n)
+{
+    const auto v = gmem(v_);
+#pragma unroll 4
+    for (int i = threadIdx.x; i < n; i += NT) v[i] = v[i] / d;
 }
 
 // z = M^{-1} v with the gamma-cycle in T (FP64 in/out)
@@ -210,10 +219,7 @@ __global__ void __launch_bounds__(NT, 4) k_solve(const Hier<T>* __restrict__ Hp,
                 if (!isfinite(beta)) { st.status = PMG_ENAN; goto done; }
                 if (beta <= tol) { st.status = PMG_OK; goto done; }
                 if (st.it >= A.max_iter) { st.status = PMG_ENOTCONV; goto done; }
-                {
-                    const auto Vg = gmem(V);
-                    for (int q = threadIdx.x; q < N; q += NT) Vg[q] /= beta;
-                }
+                wg_scale_div(V, beta, N);
                 if (threadIdx.x == 0) {
                     gv[0] = beta;
                     for (int i = 1; i <= kr; ++i) gv[i] = 0.0;
@@ -231,10 +237,7 @@ __global__ void __launch_bounds__(NT, 4) k_solve(const Hier<T>* __restrict__ Hp,
             precondition<T, P, DIM>(H, b, vj, zj);
             apply64<T, P, DIM>(H, A, b, zj, nullptr, w);
             const double hn = mgs_column(w, V, N, j, Hm + j, kr, red);
-            if (hn > 0.0) {
-                const auto wg = gmem(w);
-                for (int q = threadIdx.x; q < N; q += NT) wg[q] /= hn;
-            }
+            if (hn > 0.0) wg_scale_div(w, hn, N);
             if (threadIdx.x == 0) {
                 Hm[(j + 1) * kr + j] = hn;
                 for (int i = 0; i < j; ++i) {
