@@ -255,8 +255,12 @@ def components(args, probs, ps):
             "avg_ms": round(t_apply * 1e3, 4), "flops_per_problem": fl // B,
             "algorithmic_bytes_per_problem": (1 + 3 + 1) * N * esz}
         crw = cr_words(n)
-        nb = (2 * n ** dim + 3 * crw * n ** (dim - 1)) * esz   # r in, z out, CR factors
         for d, nm in ((0, "x"), (1, "y")):
+            # r in, z out, and the line data: first-axis lines read their raw
+            # tridiagonal (3 words per unknown, operators built on the fly),
+            # the others the stored factors of every CR level (3 CRW words)
+            words = 3 * n if d == 0 else 3 * crw
+            nb = (2 * n ** dim + words * n ** (dim - 1)) * esz
             t = timed(lambda: pmg.pmg_line_solve(s.h, L, d, prec, x, y))
             gbs = nb * B / t / 1e9
             out[f"k_line_solve<{tname}, {p}, 2> {nm}-lines"] = {

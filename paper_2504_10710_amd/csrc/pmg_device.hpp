@@ -754,12 +754,20 @@ __device__ inline void line_base(int dir, int line, int& base, int& st)
     }
 }
 
-// Lines along the first axis are stored line-major ([line][slot][3]) and
-// solved one line per group of (n+1)/2 lanes (a whole wave at p = 128): lane
-// u holds positions 2u (an F point of level 0) and 2u+1 (a C point, which is
-// also where every coarser level keeps its unknowns: level-k unknown t lives
-// in lane (t+1) 2^(k-1) - 1).  Neighbours at every level are exchanged with
-// cross-lane shuffles; loads and stores of the line are contiguous.
+// Lines along the first axis (p <= 128) are solved one line per group of
+// (n+1)/2 lanes (a whole wave at p = 128) with the cyclic-reduction operators
+// built on the fly (Prop. "line-solver cost", matrix-free variant, Remark on
+// its memory footprint): only the line's tridiagonal (l, a, u) is stored
+// ([line][position][3], contiguous).  Lane u holds positions 2u (an F point
+// of level 0) and 2u+1 (a C point, which is also where every coarser level
+// keeps its unknowns: level-k unknown t lives in lane (t+1) 2^(k-1) - 1).
+// Going down, each F point turns its row into (1/a, l/a, u/a) and each C point
+// forms its row of the coarse matrix D - C A^{-1} B (stencil of the proof of
+// Prop. "line coarse space") from its F neighbours' values, exchanged with
+// cross-lane shuffles; every lane keeps the (l/a, u/a) of the two F points it
+// owns (level 0 and the level where its C unknown becomes F) for the way up.
+// The whole hierarchy lives in registers: O(n) memory and O(n) work per line,
+// instead of the paper's O(n^2) for the on-the-fly variant.
 template <int P>
 __host__ __device__ constexpr bool wave_lines() { return P >= 2 && P <= 128; }
 
@@ -777,6 +785,7 @@ __device__ void line_cr_wave(const T* __restrict__ cr_, T* __restrict__ g_, T* _
     constexpr int NK = ilog2(n + 1);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int u = lane % W, sub = lane / W;
+    const bool has1 = 2 * u + 1 < n;
     for (int line0 = wave * LPW; line0 < NL; line0 += (NT / 64) * LPW) {
         const int line = line0 + sub;
         const bool act = line < NL;
@@ -784,54 +793,77 @@ __device__ void line_cr_wave(const T* __restrict__ cr_, T* __restrict__ g_, T* _
         int base, st;
         line_base<P, DIM>(0, lc, base, st);
         const auto c = cr + (long long)lc * 3 * CRW;
-        const bool has1 = 2 * u + 1 < n;
+        // level 0 rows of positions 2u (F) and 2u+1 (C)
+        const T lF = c[(2 * u) * 3 + 0], aF = c[(2 * u) * 3 + 1], uF = c[(2 * u) * 3 + 2];
+        T cl = has1 ? c[(2 * u + 1) * 3 + 0] : T(0);
+        T ca = has1 ? c[(2 * u + 1) * 3 + 1] : T(1);
+        T cu = has1 ? c[(2 * u + 1) * 3 + 2] : T(0);
         T e0 = g[base + 2 * u + 1];
         T e1 = has1 ? g[base + 2 * u + 2] : T(0);
-        // level 0: F solve, then C residual
-        e0 *= c[(2 * u) * 3 + 0];
+        // level 0 down: F solve, then C residual and C's coarse row
+        const T iF = T(1) / aF;
+        const T pl0 = lF * iF, pu0 = uF * iF;
+        e0 *= iF;
         {
-            const T r = __shfl(e0, u + 1, W);
-            if (has1) e1 -= c[(2 * u + 1) * 3 + 0] * e0 + c[(2 * u + 1) * 3 + 2] * r;
+            const T xr = __shfl(e0, u + 1, W), plr = __shfl(pl0, u + 1, W),
+                    pur = __shfl(pu0, u + 1, W);
+            if (has1) {
+                e1 -= cl * e0 + cu * xr;
+                const T na = ca - cl * pu0 - cu * plr;
+                const T nl = -cl * pl0, nu = -cu * pur;
+                cl = nl;
+                ca = na;
+                cu = nu;
+            }
         }
-        int offs[NK > 0 ? NK : 1];
-        offs[0] = 0;
-        int off = n;
+        T plF = T(0), puF = T(0);   // row of this lane's C unknown where it becomes F
 #pragma unroll
         for (int k = 1; k < NK; ++k) {
             const int nk = ((n + 1) >> k) - 1;
-            const int h = 1 << (k - 1);
-            offs[k] = off;
-            const bool on = ((u + 1) % h == 0) && ((u + 1) / h - 1 < nk);
-            const int t = (u + 1) / h - 1;
+            const int hs = 1 << (k - 1);
+            const bool on = ((u + 1) % hs == 0) && ((u + 1) / hs - 1 < nk);
+            const int t = (u + 1) / hs - 1;
             if (nk == 1) {
-                if (on) e1 *= c[off * 3 + 0];
+                if (on) e1 /= ca;
             } else {
-                if (on && (t & 1) == 0) e1 *= c[(off + t) * 3 + 0];
-                const T lf = __shfl(e1, u - h, W), rg = __shfl(e1, u + h, W);
-                if (on && (t & 1) == 1) e1 -= c[(off + t) * 3 + 0] * lf + c[(off + t) * 3 + 2] * rg;
+                if (on && (t & 1) == 0) {
+                    const T ia = T(1) / ca;
+                    plF = cl * ia;
+                    puF = cu * ia;
+                    e1 *= ia;
+                }
+                const T lf = __shfl(e1, u - hs, W), rg = __shfl(e1, u + hs, W);
+                const T pul = __shfl(puF, u - hs, W), pll = __shfl(plF, u - hs, W);
+                const T plr = __shfl(plF, u + hs, W), pur = __shfl(puF, u + hs, W);
+                if (on && (t & 1) == 1) {
+                    e1 -= cl * lf + cu * rg;
+                    const T na = ca - cl * pul - cu * plr;
+                    const T nl = -cl * pll, nu = -cu * pur;
+                    cl = nl;
+                    ca = na;
+                    cu = nu;
+                }
             }
-            off += nk;
         }
 #pragma unroll
         for (int k = NK - 2; k >= 1; --k) {
             const int nk = ((n + 1) >> k) - 1;
-            const int h = 1 << (k - 1);
-            const int o = offs[k];
-            const T lf = __shfl(e1, u - h, W), rg = __shfl(e1, u + h, W);
-            const bool on = ((u + 1) % h == 0) && ((u + 1) / h - 1 < nk);
-            const int t = (u + 1) / h - 1;
+            const int hs = 1 << (k - 1);
+            const T lf = __shfl(e1, u - hs, W), rg = __shfl(e1, u + hs, W);
+            const bool on = ((u + 1) % hs == 0) && ((u + 1) / hs - 1 < nk);
+            const int t = (u + 1) / hs - 1;
             if (on && (t & 1) == 0) {
                 T v = e1;
-                if (t >= 1) v += c[(o + t) * 3 + 1] * lf;
-                if (t + 1 < nk) v += c[(o + t) * 3 + 2] * rg;
+                if (t >= 1) v -= plF * lf;
+                if (t + 1 < nk) v -= puF * rg;
                 e1 = v;
             }
         }
         {
             const T lf = __shfl(e1, u - 1, W);
             T v = e0;
-            if (u >= 1) v += c[(2 * u) * 3 + 1] * lf;
-            if (has1) v += c[(2 * u) * 3 + 2] * e1;
+            if (u >= 1) v -= pl0 * lf;
+            if (has1) v -= pu0 * e1;
             e0 = v;
         }
         if (act) {

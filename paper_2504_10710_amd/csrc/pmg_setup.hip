@@ -326,7 +326,9 @@ __device__ void line_raw(const double* Gb, const double* Xb, const double* D, in
 // Level-k slots first receive the raw (l, a, u) of the level-k matrix; the
 // coarse matrix D - C A^{-1} B of Prop. "line coarse space" (stencil of its
 // proof) fills the level-(k+1) slots; then the F slots are turned into
-// (1/a, -l/a, -u/a).  All in FP64, cast to FP32 when requested.
+// (1/a, -l/a, -u/a).  First-axis lines solved in the wave layout keep their
+// level-0 rows raw (their solver builds the operators on the fly); all their
+// pivots are still checked here.  All in FP64, cast to FP32 when requested.
 template <int P, int DIM>
 __global__ void __launch_bounds__(NT) k_lines(const double* __restrict__ G,
                                               const double* __restrict__ X64,
@@ -379,6 +381,9 @@ __global__ void __launch_bounds__(NT) k_lines(const double* __restrict__ G,
                 for (int t = 0; t < nk; t += 2) {
                     const double a = W(off + t, 1);
                     if (a == 0.0 || !isfinite(a)) bad = 1;
+                    // first-axis lines in the wave layout keep level 0 raw:
+                    // their solver builds every level's operators on the fly
+                    if (off == 0 && dir == 0 && wave_lines<P>()) continue;
                     const double ia = 1.0 / a;
                     const double l = W(off + t, 0), u = W(off + t, 2);
                     W(off + t, 0) = ia;
@@ -391,9 +396,11 @@ __global__ void __launch_bounds__(NT) k_lines(const double* __restrict__ G,
             {
                 const double a = W(off, 1);
                 if (a == 0.0 || !isfinite(a)) bad = 1;
-                W(off, 0) = 1.0 / a;
-                W(off, 1) = 0.0;
-                W(off, 2) = 0.0;
+                if (!(off == 0 && dir == 0 && wave_lines<P>())) {
+                    W(off, 0) = 1.0 / a;
+                    W(off, 1) = 0.0;
+                    W(off, 2) = 0.0;
+                }
             }
             if (cf) {
                 float* cfb = cf + b * 3 * CRW * NL;
