@@ -256,10 +256,11 @@ def components(args, probs, ps):
             "algorithmic_bytes_per_problem": (1 + 3 + 1) * N * esz}
         crw = cr_words(n)
         for d, nm in ((0, "x"), (1, "y")):
-            # r in, z out, and the line data: first-axis lines read their raw
-            # tridiagonal (3 words per unknown, operators built on the fly),
-            # the others the stored factors of every CR level (3 CRW words)
-            words = 3 * n if d == 0 else 3 * crw
+            # r in, z out, and the line data: lines solved by lane groups
+            # (2-D, p <= 128) read their raw tridiagonal (3 words per unknown,
+            # operators built on the fly), others the stored factors of every
+            # CR level (3 CRW words)
+            words = 3 * n if (d == 0 or dim == 2) and p <= 128 else 3 * crw
             nb = (2 * n ** dim + words * n ** (dim - 1)) * esz
             t = timed(lambda: pmg.pmg_line_solve(s.h, L, d, prec, x, y))
             gbs = nb * B / t / 1e9

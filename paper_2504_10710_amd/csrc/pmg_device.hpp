@@ -16,8 +16,9 @@
 //               lines, CRW = sum over cyclic-reduction levels of the level's
 //               unknown count; word (slot, w) of a line at (slot*3 + w)*NL +
 //               line (line index fastest, one thread per line), except the
-//               first axis for p <= 128, stored line-major at
-//               (line*CRW + slot)*3 + w (one lane group per line)
+//               first axis (and the second in 2-D) for p <= 128: line-major
+//               (line*CRW + slot)*3 + w, one lane group per line, holding
+//               only the raw rows of level 0 (operators built on the fly)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -771,6 +772,83 @@ __device__ inline void line_base(int dir, int line, int& base, int& st)
 template <int P>
 __host__ __device__ constexpr bool wave_lines() { return P >= 2 && P <= 128; }
 
+// Solve one line held by a lane group of W lanes (lane u: e0 = position 2u,
+// e1 = position 2u+1) with its tridiagonal rows c[s*3 + {0,1,2}] = (l, a, u).
+template <class T, int n, int W, class PC>
+__device__ inline void cr_wave_solve(PC c, int u, bool has1, T& e0, T& e1)
+{
+    constexpr int NK = ilog2(n + 1);
+    const T lF = c[(2 * u) * 3 + 0], aF = c[(2 * u) * 3 + 1], uF = c[(2 * u) * 3 + 2];
+    T cl = has1 ? c[(2 * u + 1) * 3 + 0] : T(0);
+    T ca = has1 ? c[(2 * u + 1) * 3 + 1] : T(1);
+    T cu = has1 ? c[(2 * u + 1) * 3 + 2] : T(0);
+    // level 0 down: F solve, then C residual and C's coarse row
+    const T iF = T(1) / aF;
+    const T pl0 = lF * iF, pu0 = uF * iF;
+    e0 *= iF;
+    {
+        const T xr = __shfl(e0, u + 1, W), plr = __shfl(pl0, u + 1, W), pur = __shfl(pu0, u + 1, W);
+        if (has1) {
+            e1 -= cl * e0 + cu * xr;
+            const T na = ca - cl * pu0 - cu * plr;
+            const T nl = -cl * pl0, nu = -cu * pur;
+            cl = nl;
+            ca = na;
+            cu = nu;
+        }
+    }
+    T plF = T(0), puF = T(0);   // row of this lane's C unknown where it becomes F
+#pragma unroll
+    for (int k = 1; k < NK; ++k) {
+        const int nk = ((n + 1) >> k) - 1;
+        const int hs = 1 << (k - 1);
+        const bool on = ((u + 1) % hs == 0) && ((u + 1) / hs - 1 < nk);
+        const int t = (u + 1) / hs - 1;
+        if (nk == 1) {
+            if (on) e1 /= ca;
+        } else {
+            if (on && (t & 1) == 0) {
+                const T ia = T(1) / ca;
+                plF = cl * ia;
+                puF = cu * ia;
+                e1 *= ia;
+            }
+            const T lf = __shfl(e1, u - hs, W), rg = __shfl(e1, u + hs, W);
+            const T pul = __shfl(puF, u - hs, W), pll = __shfl(plF, u - hs, W);
+            const T plr = __shfl(plF, u + hs, W), pur = __shfl(puF, u + hs, W);
+            if (on && (t & 1) == 1) {
+                e1 -= cl * lf + cu * rg;
+                const T na = ca - cl * pul - cu * plr;
+                const T nl = -cl * pll, nu = -cu * pur;
+                cl = nl;
+                ca = na;
+                cu = nu;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = NK - 2; k >= 1; --k) {
+        const int nk = ((n + 1) >> k) - 1;
+        const int hs = 1 << (k - 1);
+        const T lf = __shfl(e1, u - hs, W), rg = __shfl(e1, u + hs, W);
+        const bool on = ((u + 1) % hs == 0) && ((u + 1) / hs - 1 < nk);
+        const int t = (u + 1) / hs - 1;
+        if (on && (t & 1) == 0) {
+            T v = e1;
+            if (t >= 1) v -= plF * lf;
+            if (t + 1 < nk) v -= puF * rg;
+            e1 = v;
+        }
+    }
+    {
+        const T lf = __shfl(e1, u - 1, W);
+        T v = e0;
+        if (u >= 1) v -= pl0 * lf;
+        if (has1) v -= pu0 * e1;
+        e0 = v;
+    }
+}
+
 template <class T, int P, int DIM, bool FUSED>
 __device__ void line_cr_wave(const T* __restrict__ cr_, T* __restrict__ g_, T* __restrict__ x_,
                              T alpha)
@@ -782,7 +860,6 @@ __device__ void line_cr_wave(const T* __restrict__ cr_, T* __restrict__ g_, T* _
     constexpr int n = S::n, NL = S::NL, CRW = S::CRW;
     constexpr int W = (n + 1) / 2 > 0 ? (n + 1) / 2 : 1;   // lanes per line
     constexpr int LPW = 64 / W;                              // lines per wave
-    constexpr int NK = ilog2(n + 1);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int u = lane % W, sub = lane / W;
     const bool has1 = 2 * u + 1 < n;
@@ -792,80 +869,9 @@ __device__ void line_cr_wave(const T* __restrict__ cr_, T* __restrict__ g_, T* _
         const int lc = act ? line : NL - 1;
         int base, st;
         line_base<P, DIM>(0, lc, base, st);
-        const auto c = cr + (long long)lc * 3 * CRW;
-        // level 0 rows of positions 2u (F) and 2u+1 (C)
-        const T lF = c[(2 * u) * 3 + 0], aF = c[(2 * u) * 3 + 1], uF = c[(2 * u) * 3 + 2];
-        T cl = has1 ? c[(2 * u + 1) * 3 + 0] : T(0);
-        T ca = has1 ? c[(2 * u + 1) * 3 + 1] : T(1);
-        T cu = has1 ? c[(2 * u + 1) * 3 + 2] : T(0);
         T e0 = g[base + 2 * u + 1];
         T e1 = has1 ? g[base + 2 * u + 2] : T(0);
-        // level 0 down: F solve, then C residual and C's coarse row
-        const T iF = T(1) / aF;
-        const T pl0 = lF * iF, pu0 = uF * iF;
-        e0 *= iF;
-        {
-            const T xr = __shfl(e0, u + 1, W), plr = __shfl(pl0, u + 1, W),
-                    pur = __shfl(pu0, u + 1, W);
-            if (has1) {
-                e1 -= cl * e0 + cu * xr;
-                const T na = ca - cl * pu0 - cu * plr;
-                const T nl = -cl * pl0, nu = -cu * pur;
-                cl = nl;
-                ca = na;
-                cu = nu;
-            }
-        }
-        T plF = T(0), puF = T(0);   // row of this lane's C unknown where it becomes F
-#pragma unroll
-        for (int k = 1; k < NK; ++k) {
-            const int nk = ((n + 1) >> k) - 1;
-            const int hs = 1 << (k - 1);
-            const bool on = ((u + 1) % hs == 0) && ((u + 1) / hs - 1 < nk);
-            const int t = (u + 1) / hs - 1;
-            if (nk == 1) {
-                if (on) e1 /= ca;
-            } else {
-                if (on && (t & 1) == 0) {
-                    const T ia = T(1) / ca;
-                    plF = cl * ia;
-                    puF = cu * ia;
-                    e1 *= ia;
-                }
-                const T lf = __shfl(e1, u - hs, W), rg = __shfl(e1, u + hs, W);
-                const T pul = __shfl(puF, u - hs, W), pll = __shfl(plF, u - hs, W);
-                const T plr = __shfl(plF, u + hs, W), pur = __shfl(puF, u + hs, W);
-                if (on && (t & 1) == 1) {
-                    e1 -= cl * lf + cu * rg;
-                    const T na = ca - cl * pul - cu * plr;
-                    const T nl = -cl * pll, nu = -cu * pur;
-                    cl = nl;
-                    ca = na;
-                    cu = nu;
-                }
-            }
-        }
-#pragma unroll
-        for (int k = NK - 2; k >= 1; --k) {
-            const int nk = ((n + 1) >> k) - 1;
-            const int hs = 1 << (k - 1);
-            const T lf = __shfl(e1, u - hs, W), rg = __shfl(e1, u + hs, W);
-            const bool on = ((u + 1) % hs == 0) && ((u + 1) / hs - 1 < nk);
-            const int t = (u + 1) / hs - 1;
-            if (on && (t & 1) == 0) {
-                T v = e1;
-                if (t >= 1) v -= plF * lf;
-                if (t + 1 < nk) v -= puF * rg;
-                e1 = v;
-            }
-        }
-        {
-            const T lf = __shfl(e1, u - 1, W);
-            T v = e0;
-            if (u >= 1) v -= pl0 * lf;
-            if (has1) v -= pu0 * e1;
-            e0 = v;
-        }
+        cr_wave_solve<T, n, W>(cr + (long long)lc * 3 * CRW, u, has1, e0, e1);
         if (act) {
             if (FUSED) {
                 x[base + 2 * u + 1] += alpha * e0;
@@ -877,6 +883,70 @@ __device__ void line_cr_wave(const T* __restrict__ cr_, T* __restrict__ g_, T* _
         }
     }
     wg_barrier();
+}
+
+// LDS strip shared by the second-axis line solves of every level (one
+// allocation per kernel): 16 lines of up to 127 unknowns, padded rows.
+constexpr int LINE_STRIP_WORDS = 127 * 17;
+__device__ inline void* line_strip_lds()
+{
+    __shared__ double buf[LINE_STRIP_WORDS];
+    return buf;
+}
+
+// Second-axis lines of a 2-D level (strided in memory) in strips of 16
+// adjacent lines: the strip's right-hand sides are read row by row
+// (coalesced) into LDS, each line is solved by a lane group as above, and the
+// solutions go back row by row.  The lines' tridiagonals are stored
+// line-major like the first axis'.
+template <class T, int P, bool FUSED>
+__device__ void line_cr_wave_y(const T* __restrict__ cr_, T* __restrict__ g_, T* __restrict__ x_,
+                               T alpha)
+{
+    const auto cr = gmem(cr_);
+    const auto g = gmem(g_);
+    const auto x = gmem(x_);
+    using S = Shape<P, 2>;
+    constexpr int n1 = S::n1, n = S::n, NL = S::NL, CRW = S::CRW;
+    constexpr int W = (n + 1) / 2 > 0 ? (n + 1) / 2 : 1;
+    constexpr int LPW = 64 / W;
+    constexpr int SW = 16, LD = SW + 1;                      // lines per strip, LDS row
+    static_assert(n * LD * sizeof(T) <= sizeof(double) * LINE_STRIP_WORDS, "strip fits");
+    const auto strip = (__attribute__((address_space(3))) T*)line_strip_lds();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int u = lane % W, sub = lane / W;
+    const bool has1 = 2 * u + 1 < n;
+    for (int l0 = 0; l0 < NL; l0 += SW) {
+        for (int e = threadIdx.x; e < n * SW; e += NT) {
+            const int r = e / SW, ci = e % SW, line = l0 + ci;
+            strip[r * LD + ci] = line < NL ? g[(r + 1) * n1 + line + 1] : T(0);
+        }
+        wg_barrier();
+        for (int s0 = wave * LPW; s0 < SW; s0 += (NT / 64) * LPW) {
+            const int sl = s0 + sub;                   // line within the strip
+            const int sc = min(sl, SW - 1);            // lane groups past the strip
+            const int lc = min(l0 + sc, NL - 1);       // compute on a copy, store nothing
+            T e0 = strip[(2 * u) * LD + sc];
+            T e1 = has1 ? strip[(2 * u + 1) * LD + sc] : T(0);
+            cr_wave_solve<T, n, W>(cr + (long long)lc * 3 * CRW, u, has1, e0, e1);
+            if (sl < SW) {
+                strip[(2 * u) * LD + sl] = e0;
+                if (has1) strip[(2 * u + 1) * LD + sl] = e1;
+            }
+        }
+        wg_barrier();
+        for (int e = threadIdx.x; e < n * SW; e += NT) {
+            const int r = e / SW, ci = e % SW, line = l0 + ci;
+            if (line < NL) {
+                const int q = (r + 1) * n1 + line + 1;
+                if (FUSED)
+                    x[q] += alpha * strip[r * LD + ci];
+                else
+                    g[q] = strip[r * LD + ci];
+            }
+        }
+        wg_barrier();
+    }
 }
 
 // Cyclic reduction as a direct multigrid (Thm. "Two-level direct solver",
@@ -897,6 +967,10 @@ __device__ __attribute__((noinline)) void line_cr(const T* __restrict__ cr_, int
     if constexpr (wave_lines<P>()) {
         if (dir == 0) {
             line_cr_wave<T, P, DIM, FUSED>(cr_, g_, x_, alpha);
+            return;
+        }
+        if (DIM == 2 && dir == 1) {
+            line_cr_wave_y<T, P, FUSED>(cr_, g_, x_, alpha);
             return;
         }
     }

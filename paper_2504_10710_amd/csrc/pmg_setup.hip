@@ -345,7 +345,7 @@ __global__ void __launch_bounds__(NT) k_lines(const double* __restrict__ G,
     int bad = 0;
     auto crp = [&](int dir) { return (dir == 0 ? cr0 : (dir == 1 ? cr1 : cr2)) + b * 3 * CRW * NL; };
     auto idx = [&](int dir, int line, int slot, int w) -> long long {
-        const bool lm = dir == 0 && wave_lines<P>();   // line-major layout
+        const bool lm = (dir == 0 || (DIM == 2 && dir == 1)) && wave_lines<P>();   // line-major
         return lm ? ((long long)line * CRW + slot) * 3 + w : (long long)(slot * 3 + w) * NL + line;
     };
     // 1. the raw tridiagonals of every line of every axis, one entry per work item
@@ -383,7 +383,7 @@ __global__ void __launch_bounds__(NT) k_lines(const double* __restrict__ G,
                     if (a == 0.0 || !isfinite(a)) bad = 1;
                     // first-axis lines in the wave layout keep level 0 raw:
                     // their solver builds every level's operators on the fly
-                    if (off == 0 && dir == 0 && wave_lines<P>()) continue;
+                    if (off == 0 && (dir == 0 || (DIM == 2 && dir == 1)) && wave_lines<P>()) continue;
                     const double ia = 1.0 / a;
                     const double l = W(off + t, 0), u = W(off + t, 2);
                     W(off + t, 0) = ia;
@@ -396,7 +396,7 @@ __global__ void __launch_bounds__(NT) k_lines(const double* __restrict__ G,
             {
                 const double a = W(off, 1);
                 if (a == 0.0 || !isfinite(a)) bad = 1;
-                if (!(off == 0 && dir == 0 && wave_lines<P>())) {
+                if (!(off == 0 && (dir == 0 || (DIM == 2 && dir == 1)) && wave_lines<P>())) {
                     W(off, 0) = 1.0 / a;
                     W(off, 1) = 0.0;
                     W(off, 2) = 0.0;
