@@ -15,10 +15,10 @@
 //   line data   per axis: 3 words x CRW x NL, where NL = (p-1)^(dim-1)
 //               lines, CRW = sum over cyclic-reduction levels of the level's
 //               unknown count; word (slot, w) of a line at (slot*3 + w)*NL +
-//               line (line index fastest, one thread per line), except the
-//               first axis (and the second in 2-D) for p <= 128: line-major
-//               (line*CRW + slot)*3 + w, one lane group per line, holding
-//               only the raw rows of level 0 (operators built on the fly)
+//               line (line index fastest, one thread per line), except for
+//               p <= 128: line-major (line*CRW + slot)*3 + w, one lane group
+//               per line, holding only the raw rows of level 0 (operators
+//               built on the fly)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -885,8 +885,9 @@ __device__ void line_cr_wave(const T* __restrict__ cr_, T* __restrict__ g_, T* _
     wg_barrier();
 }
 
-// LDS strip shared by the second-axis line solves of every level (one
-// allocation per kernel): 16 lines of up to 127 unknowns, padded rows.
+// LDS strip shared by the strided line solves of every level (one
+// allocation per kernel): up to 16 lines of 127 unknowns or 32 of 63, padded
+// rows.
 constexpr int LINE_STRIP_WORDS = 127 * 17;
 __device__ inline void* line_strip_lds()
 {
@@ -894,58 +895,66 @@ __device__ inline void* line_strip_lds()
     return buf;
 }
 
-// Second-axis lines of a 2-D level (strided in memory) in strips of 16
-// adjacent lines: the strip's right-hand sides are read row by row
-// (coalesced) into LDS, each line is solved by a lane group as above, and the
-// solutions go back row by row.  The lines' tridiagonals are stored
-// line-major like the first axis'.
-template <class T, int P, bool FUSED>
-__device__ void line_cr_wave_y(const T* __restrict__ cr_, T* __restrict__ g_, T* __restrict__ x_,
-                               T alpha)
+// Lines along the second axis (and the third in 3-D), strided in memory, in
+// strips of SW adjacent lines (consecutive first-axis positions at one value
+// of the remaining coordinate): the strip's right-hand sides are read row by
+// row (coalesced) into LDS, each line is solved by a lane group as above,
+// and the solutions go back row by row.  Line index = (i-1) + n (o-1) for
+// first-axis position i and outer coordinate o, as everywhere else; the
+// lines' tridiagonals are stored line-major like the first axis'.
+template <class T, int P, int DIM, bool FUSED>
+__device__ void line_cr_wave_strided(const T* __restrict__ cr_, int dir, T* __restrict__ g_,
+                                     T* __restrict__ x_, T alpha)
 {
     const auto cr = gmem(cr_);
     const auto g = gmem(g_);
     const auto x = gmem(x_);
-    using S = Shape<P, 2>;
-    constexpr int n1 = S::n1, n = S::n, NL = S::NL, CRW = S::CRW;
+    using S = Shape<P, DIM>;
+    constexpr int n1 = S::n1, n = S::n, CRW = S::CRW;
     constexpr int W = (n + 1) / 2 > 0 ? (n + 1) / 2 : 1;
     constexpr int LPW = 64 / W;
-    constexpr int SW = 16, LD = SW + 1;                      // lines per strip, LDS row
+    constexpr int SW = n > 63 ? 16 : 32, LD = SW + 1;        // lines per strip, LDS row
+    constexpr int NO = DIM == 2 ? 1 : n;                     // values of the outer coordinate
     static_assert(n * LD * sizeof(T) <= sizeof(double) * LINE_STRIP_WORDS, "strip fits");
     const auto strip = (__attribute__((address_space(3))) T*)line_strip_lds();
+    const int RS = dir == 1 ? n1 : n1 * n1;                  // stride along the line
+    const int OS = DIM == 2 ? 0 : (dir == 1 ? n1 * n1 : n1); // stride of the outer coordinate
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int u = lane % W, sub = lane / W;
     const bool has1 = 2 * u + 1 < n;
-    for (int l0 = 0; l0 < NL; l0 += SW) {
-        for (int e = threadIdx.x; e < n * SW; e += NT) {
-            const int r = e / SW, ci = e % SW, line = l0 + ci;
-            strip[r * LD + ci] = line < NL ? g[(r + 1) * n1 + line + 1] : T(0);
-        }
-        wg_barrier();
-        for (int s0 = wave * LPW; s0 < SW; s0 += (NT / 64) * LPW) {
-            const int sl = s0 + sub;                   // line within the strip
-            const int sc = min(sl, SW - 1);            // lane groups past the strip
-            const int lc = min(l0 + sc, NL - 1);       // compute on a copy, store nothing
-            T e0 = strip[(2 * u) * LD + sc];
-            T e1 = has1 ? strip[(2 * u + 1) * LD + sc] : T(0);
-            cr_wave_solve<T, n, W>(cr + (long long)lc * 3 * CRW, u, has1, e0, e1);
-            if (sl < SW) {
-                strip[(2 * u) * LD + sl] = e0;
-                if (has1) strip[(2 * u + 1) * LD + sl] = e1;
+    for (int o = 0; o < NO; ++o) {
+        const int ob = DIM == 2 ? 0 : (o + 1) * OS;
+        for (int l0 = 0; l0 < n; l0 += SW) {
+            for (int e = threadIdx.x; e < n * SW; e += NT) {
+                const int r = e / SW, ci = e % SW, i = l0 + ci;
+                strip[r * LD + ci] = i < n ? g[ob + (r + 1) * RS + i + 1] : T(0);
             }
-        }
-        wg_barrier();
-        for (int e = threadIdx.x; e < n * SW; e += NT) {
-            const int r = e / SW, ci = e % SW, line = l0 + ci;
-            if (line < NL) {
-                const int q = (r + 1) * n1 + line + 1;
-                if (FUSED)
-                    x[q] += alpha * strip[r * LD + ci];
-                else
-                    g[q] = strip[r * LD + ci];
+            wg_barrier();
+            for (int s0 = wave * LPW; s0 < SW; s0 += (NT / 64) * LPW) {
+                const int sl = s0 + sub;                   // line within the strip
+                const int sc = min(sl, SW - 1);            // lane groups past the strip
+                const int lc = min(l0 + sc, n - 1) + n * o;   // compute on a copy, store nothing
+                T e0 = strip[(2 * u) * LD + sc];
+                T e1 = has1 ? strip[(2 * u + 1) * LD + sc] : T(0);
+                cr_wave_solve<T, n, W>(cr + (long long)lc * 3 * CRW, u, has1, e0, e1);
+                if (sl < SW) {
+                    strip[(2 * u) * LD + sl] = e0;
+                    if (has1) strip[(2 * u + 1) * LD + sl] = e1;
+                }
             }
+            wg_barrier();
+            for (int e = threadIdx.x; e < n * SW; e += NT) {
+                const int r = e / SW, ci = e % SW, i = l0 + ci;
+                if (i < n) {
+                    const int q = ob + (r + 1) * RS + i + 1;
+                    if (FUSED)
+                        x[q] += alpha * strip[r * LD + ci];
+                    else
+                        g[q] = strip[r * LD + ci];
+                }
+            }
+            wg_barrier();
         }
-        wg_barrier();
     }
 }
 
@@ -969,10 +978,8 @@ __device__ __attribute__((noinline)) void line_cr(const T* __restrict__ cr_, int
             line_cr_wave<T, P, DIM, FUSED>(cr_, g_, x_, alpha);
             return;
         }
-        if (DIM == 2 && dir == 1) {
-            line_cr_wave_y<T, P, FUSED>(cr_, g_, x_, alpha);
-            return;
-        }
+        line_cr_wave_strided<T, P, DIM, FUSED>(cr_, dir, g_, x_, alpha);
+        return;
     }
     const auto cr = gmem(cr_);
     const auto g = gmem(g_);

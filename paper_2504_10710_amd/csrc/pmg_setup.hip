@@ -326,9 +326,10 @@ __device__ void line_raw(const double* Gb, const double* Xb, const double* D, in
 // Level-k slots first receive the raw (l, a, u) of the level-k matrix; the
 // coarse matrix D - C A^{-1} B of Prop. "line coarse space" (stencil of its
 // proof) fills the level-(k+1) slots; then the F slots are turned into
-// (1/a, -l/a, -u/a).  First-axis lines solved in the wave layout keep their
-// level-0 rows raw (their solver builds the operators on the fly); all their
-// pivots are still checked here.  All in FP64, cast to FP32 when requested.
+// (1/a, -l/a, -u/a).  For p <= 128 the lines are solved by lane groups and
+// keep their level-0 rows raw (their solver builds the operators on the
+// fly); all pivots are still checked here.  All in FP64, cast to FP32 when
+// requested.
 template <int P, int DIM>
 __global__ void __launch_bounds__(NT) k_lines(const double* __restrict__ G,
                                               const double* __restrict__ X64,
@@ -345,7 +346,7 @@ __global__ void __launch_bounds__(NT) k_lines(const double* __restrict__ G,
     int bad = 0;
     auto crp = [&](int dir) { return (dir == 0 ? cr0 : (dir == 1 ? cr1 : cr2)) + b * 3 * CRW * NL; };
     auto idx = [&](int dir, int line, int slot, int w) -> long long {
-        const bool lm = (dir == 0 || (DIM == 2 && dir == 1)) && wave_lines<P>();   // line-major
+        const bool lm = wave_lines<P>();   // line-major, raw level 0
         return lm ? ((long long)line * CRW + slot) * 3 + w : (long long)(slot * 3 + w) * NL + line;
     };
     // 1. the raw tridiagonals of every line of every axis, one entry per work item
@@ -383,7 +384,7 @@ __global__ void __launch_bounds__(NT) k_lines(const double* __restrict__ G,
                     if (a == 0.0 || !isfinite(a)) bad = 1;
                     // first-axis lines in the wave layout keep level 0 raw:
                     // their solver builds every level's operators on the fly
-                    if (off == 0 && (dir == 0 || (DIM == 2 && dir == 1)) && wave_lines<P>()) continue;
+                    if (off == 0 && wave_lines<P>()) continue;
                     const double ia = 1.0 / a;
                     const double l = W(off + t, 0), u = W(off + t, 2);
                     W(off + t, 0) = ia;
@@ -396,7 +397,7 @@ __global__ void __launch_bounds__(NT) k_lines(const double* __restrict__ G,
             {
                 const double a = W(off, 1);
                 if (a == 0.0 || !isfinite(a)) bad = 1;
-                if (!(off == 0 && (dir == 0 || (DIM == 2 && dir == 1)) && wave_lines<P>())) {
+                if (!(off == 0 && wave_lines<P>())) {
                     W(off, 0) = 1.0 / a;
                     W(off, 1) = 0.0;
                     W(off, 2) = 0.0;
