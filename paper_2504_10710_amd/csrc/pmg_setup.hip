@@ -256,6 +256,84 @@ __device__ double fem_entry_3d(const double* __restrict__ X, const int* c, const
     return s;
 }
 
+// All line couplings of interior node c at once for the trilinear FEM
+// matrix: out = {a, l_0, u_0, l_1, u_1, l_2, u_2}, the diagonal entry and the
+// entries coupling c to c - e_k and c + e_k.  Same element integrals as
+// fem_entry_3d, but each element's Gauss-point geometry is computed once for
+// the seven entries (the elements are visited in the same order).
+template <int P>
+__device__ void fem_node_3d(const double* __restrict__ X, const int* c, double* out)
+{
+    constexpr int n1 = P + 1, N = n1 * n1 * n1;
+    const double h = 0.5 / sqrt(3.0);
+    const double gq[2] = {0.5 - h, 0.5 + h};
+    for (int i = 0; i < 7; ++i) out[i] = 0.0;
+    for (int e2 = c[2] - 1; e2 <= c[2]; ++e2)
+        for (int e1 = c[1] - 1; e1 <= c[1]; ++e1)
+            for (int e0 = c[0] - 1; e0 <= c[0]; ++e0) {
+                if (e0 < 0 || e1 < 0 || e2 < 0 || e0 >= P || e1 >= P || e2 >= P) continue;
+                double cx[8][3];
+                for (int v = 0; v < 8; ++v) {
+                    const int q = (e0 + (v & 1)) + n1 * (e1 + ((v >> 1) & 1)) +
+                                  n1 * n1 * (e2 + ((v >> 2) & 1));
+                    for (int k = 0; k < 3; ++k) cx[v][k] = X[k * N + q];
+                }
+                const int va = (c[0] - e0) + 2 * (c[1] - e1) + 4 * (c[2] - e2);
+                for (int gi = 0; gi < 8; ++gi) {
+                    const double u[3] = {gq[gi & 1], gq[(gi >> 1) & 1], gq[(gi >> 2) & 1]};
+                    auto grad = [&](int v, double* g) {
+                        double f[3], df[3];
+                        for (int k = 0; k < 3; ++k) {
+                            const int bit = (v >> k) & 1;
+                            f[k] = bit ? u[k] : 1.0 - u[k];
+                            df[k] = bit ? 1.0 : -1.0;
+                        }
+                        g[0] = df[0] * f[1] * f[2];
+                        g[1] = f[0] * df[1] * f[2];
+                        g[2] = f[0] * f[1] * df[2];
+                    };
+                    double Jm[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // Jm[comp][ref axis]
+                    for (int v = 0; v < 8; ++v) {
+                        double g[3];
+                        grad(v, g);
+                        for (int k = 0; k < 3; ++k)
+                            for (int a = 0; a < 3; ++a) Jm[k][a] += cx[v][k] * g[a];
+                    }
+                    const double c00 = Jm[1][1] * Jm[2][2] - Jm[1][2] * Jm[2][1];
+                    const double c01 = Jm[1][2] * Jm[2][0] - Jm[1][0] * Jm[2][2];
+                    const double c02 = Jm[1][0] * Jm[2][1] - Jm[1][1] * Jm[2][0];
+                    const double det = Jm[0][0] * c00 + Jm[0][1] * c01 + Jm[0][2] * c02;
+                    double inv[3][3];  // inv[a][comp] = d u_a / d x_comp
+                    inv[0][0] = c00 / det;
+                    inv[1][0] = c01 / det;
+                    inv[2][0] = c02 / det;
+                    inv[0][1] = (Jm[0][2] * Jm[2][1] - Jm[0][1] * Jm[2][2]) / det;
+                    inv[1][1] = (Jm[0][0] * Jm[2][2] - Jm[0][2] * Jm[2][0]) / det;
+                    inv[2][1] = (Jm[0][1] * Jm[2][0] - Jm[0][0] * Jm[2][1]) / det;
+                    inv[0][2] = (Jm[0][1] * Jm[1][2] - Jm[0][2] * Jm[1][1]) / det;
+                    inv[1][2] = (Jm[0][2] * Jm[1][0] - Jm[0][0] * Jm[1][2]) / det;
+                    inv[2][2] = (Jm[0][0] * Jm[1][1] - Jm[0][1] * Jm[1][0]) / det;
+                    const double w = 0.125 * fabs(det);
+                    auto phys = [&](int v, double* pg) {
+                        double gg[3];
+                        grad(v, gg);
+                        for (int k = 0; k < 3; ++k) pg[k] = 0.0;
+                        for (int k = 0; k < 3; ++k)
+                            for (int a = 0; a < 3; ++a) pg[k] += inv[a][k] * gg[a];
+                    };
+                    double pa[3];
+                    phys(va, pa);
+                    out[0] += w * (pa[0] * pa[0] + pa[1] * pa[1] + pa[2] * pa[2]);
+                    for (int a = 0; a < 3; ++a) {
+                        const int bit = (va >> a) & 1;   // 1: c - e_a is a corner, 0: c + e_a
+                        double pb[3];
+                        phys(va ^ (1 << a), pb);
+                        out[1 + 2 * a + (bit ? 0 : 1)] += w * (pa[0] * pb[0] + pa[1] * pb[1] + pa[2] * pb[2]);
+                    }
+                }
+            }
+}
+
 // Entry of A_p (eq. discreteBilinear) between node q (multi-index c) and its
 // neighbour along axis dir (offset dd = -1, 0 or +1 along that axis), read off
 // the tensor-product structure: the G_dd term along the line, plus the
@@ -349,8 +427,27 @@ __global__ void __launch_bounds__(NT) k_lines(const double* __restrict__ G,
         const bool lm = wave_lines<P>();   // line-major, raw level 0
         return lm ? ((long long)line * CRW + slot) * 3 + w : (long long)(slot * 3 + w) * NL + line;
     };
-    // 1. the raw tridiagonals of every line of every axis, one entry per work item
+    // 1. the raw tridiagonals of every line of every axis, one entry per work
+    //    item (3-D FEM: one interior node per work item, all axes at once)
+    if constexpr (DIM == 3) {
+        if (smoother == PMG_SMOOTHER_FEM) {
+            for (int e = threadIdx.x; e < n * n * n; e += NT) {
+                const int c[3] = {e % n + 1, (e / n) % n + 1, e / (n * n) + 1};
+                double v[7];
+                fem_node_3d<P>(Xb, c, v);
+                for (int dir = 0; dir < 3; ++dir) {
+                    const int o1 = dir == 0 ? c[1] : c[0], o2 = dir == 2 ? c[1] : c[2];
+                    const int line = (o1 - 1) + n * (o2 - 1), sq = c[dir] - 1;
+                    double* cr = crp(dir);
+                    cr[idx(dir, line, sq, 0)] = sq > 0 ? v[1 + 2 * dir] : 0.0;
+                    cr[idx(dir, line, sq, 1)] = v[0];
+                    cr[idx(dir, line, sq, 2)] = sq < n - 1 ? v[2 + 2 * dir] : 0.0;
+                }
+            }
+        }
+    }
     for (int e = threadIdx.x; e < DIM * NL * n; e += NT) {
+        if (DIM == 3 && smoother == PMG_SMOOTHER_FEM) break;
         const int dir = e / (NL * n), line = (e / n) % NL, sq = e % n;
         double l, a, u;
         line_raw<P, DIM>(Gb, Xb, D, smoother, dir, line, sq, l, a, u);
