@@ -323,7 +323,9 @@ def main():
     peak = PEAK_FP32_TFLOPS if args.prec == "f32" else PEAK_FP64_TFLOPS
     kname = f"k_solve<{'float' if args.prec == 'f32' else 'double'}, {p}, 2>"
     traffic, src = measured_traffic(kname, B)
-    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
+    # the solve's flops are mostly matrix-core contractions (operator and
+    # transfers); MI355X's dense FP64 MFMA peak equals its FP64 vector peak
+    roofline = {"bound": "mfma", "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 5), "traffic": traffic,
                 "traffic_source": src if traffic is not None else None,
                 "kernel": kname, "flops_per_launch": r64["flops"]}
