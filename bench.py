@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget of the oracle CPU baseline (0 disables it)")
-    ap.add_argument("--serve", type=int, default=512, metavar="N",
+    ap.add_argument("--serve", type=int, default=4096, metavar="N",
                     help="requests of the served mixed 2-D/3-D stream (0 skips serving)")
     ap.add_argument("--serve-load", type=float, default=0.8,
                     help="paced arrival rate as a fraction of the saturated throughput")
