@@ -276,18 +276,25 @@ def components(args, probs, ps):
     return out
 
 
-def measured_traffic(kernel, batch):
-    """HBM bytes per launch of `kernel` from the committed counter summary, if
-    it was taken on the current kernel sources at this batch size; else None."""
+def sources_digest(root=ROOT):
+    """SHA-256 (first 16 hex digits) of the kernel sources under csrc/."""
     import glob
     import hashlib
 
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2504_10710_amd", "csrc", "*"))):
+    for f in sorted(glob.glob(os.path.join(root, "paper_2504_10710_amd", "csrc", "*"))):
         with open(f, "rb") as fh:
             h.update(fh.read())
-    digest = h.hexdigest()[:16]
-    for f in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, batch, root=ROOT):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if
+    it was taken on the current kernel sources at this batch size; else None."""
+    import glob
+
+    digest = sources_digest(root)
+    for f in glob.glob(os.path.join(root, "profiles", "*.md")):
         rec = {}
         with open(f) as fh:
             for line in fh:
