@@ -404,3 +404,43 @@ def test_error_statuses():
     pmg.pmg_solve(s2.h, bt2, x2, s2.info)
     torch.cuda.synchronize()
     assert s2.info_host()["status"][0] == pmg.PMG_EGEOM
+
+
+@pytest.mark.parametrize("dim,p", [(2, 128), (3, 32)])
+def test_line_solve_full_width(dim, p):
+    """Line solves on the largest lane-group lines: 2-D p = 128 (127 unknowns,
+    one wave per line, second axis through 16-line LDS strips) and 3-D p = 32
+    (second and third axes through 32-line strips), FP64 and FP32, against the
+    oracle's literal cyclic reduction."""
+    kind = "cfg2" if dim == 2 else "cfg3"
+    probs = problems(kind, [5, 6])
+    s, f, g = gpu_batch(probs, p, gamma=1, alpha=0.16, smoother=pmg.PMG_SMOOTHER_FEM)
+    torch.cuda.synchronize()
+    ors = [oracle_of(pr, p, gamma=1, alpha=0.16, smoother=1) for pr in probs]
+    L = s.nlev - 1
+    r = _rand_interior(dim, p, len(probs), 77)
+    for d in range(dim):
+        z = torch.empty((len(probs), (p + 1) ** dim), dtype=torch.float64, device="cuda")
+        pmg.pmg_line_solve(s.h, L, d, pmg.PMG_F64, torch.from_numpy(r).cuda(), z)
+        torch.cuda.synchronize()
+        for b, (h, _, _) in enumerate(ors):
+            zo = h.line_solve(r[b], d, L)
+            tol = _line_tol(h, L, d, dim, p)
+            err = rel_err(z.cpu().numpy()[b], zo)
+            print(f"[line solve] dim={dim} p={p} dir={d} b={b} rel err {err:.2e} tol {tol:.1e}",
+                  flush=True)
+            assert err < tol, (d, b, err, tol)
+    # FP32 lines: the same solve to single precision (kappa-scaled)
+    s32, _, _ = gpu_batch(probs, p, gamma=1, alpha=0.16, smoother=pmg.PMG_SMOOTHER_FEM,
+                          inner_prec=pmg.PMG_F32)
+    r32 = torch.from_numpy(r.astype(np.float32)).cuda()
+    for d in range(dim):
+        z = torch.empty((len(probs), (p + 1) ** dim), dtype=torch.float32, device="cuda")
+        pmg.pmg_line_solve(s32.h, L, d, pmg.PMG_F32, r32, z)
+        torch.cuda.synchronize()
+        for b, (h, _, _) in enumerate(ors):
+            zo = h.line_solve(r[b], d, L)
+            kap = _line_kappa(h, L, d, dim, p)
+            tol = max(1e-5, 20 * (p - 1) * np.finfo(np.float32).eps * kap)
+            err = rel_err(z.cpu().numpy()[b].astype(np.float64), zo)
+            assert err < tol, (d, b, err, tol)
