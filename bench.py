@@ -380,10 +380,15 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-SERVE_CLASSES = [  # (dim, p, slots, inner precision)
-    (2, 16, 512, "f32"), (2, 32, 512, "f32"), (2, 64, 256, "f32"), (2, 128, 256, "f32"),
-    (3, 16, 256, "f32"), (3, 32, 128, "f32"), (3, 64, 128, "f64"),
+# (dim, p, slots, inner precision).  A class with 1024 slots can fill the chip
+# by itself (256 CUs x 4 resident one-problem workgroups); 3-D p = 64 slots
+# cost 194 MB each, so that class holds 768 (149 GB).
+SERVE_CLASSES = [
+    (2, 16, 1024, "f32"), (2, 32, 1024, "f32"), (2, 64, 1024, "f32"), (2, 128, 1024, "f32"),
+    (3, 16, 1024, "f32"), (3, 32, 1024, "f32"), (3, 64, 768, "f64"),
 ]
+SERVE_BUDGET_FRAC = 0.8     # admission budget: this share of the slot pools' bytes
+SERVE_ITERS_PER_STEP = 4    # outer iterations of every running solve per server step
 
 
 def serve(args):
@@ -398,6 +403,7 @@ def serve(args):
     from paper_2504_10710_amd import inputs, pmg
 
     dev = torch.device("cuda:0")
+    torch.cuda.empty_cache()         # the batch runs' workspaces go back first
     classes, bank = [], []
     for dim, p, slots, prec in SERVE_CLASSES:
         classes.append(pmg.make_desc(dim=dim, p_fine=p, batch=slots, gamma=1, alpha=0.16,
@@ -405,9 +411,8 @@ def serve(args):
                                      inner_prec=pmg.PMG_F32 if prec == "f32" else pmg.PMG_F64,
                                      restart=30 if dim == 2 else 20, max_iter=300, rtol=1e-10))
     footprint = [pmg.pmg_pool_workspace_bytes(c) // c.batch for c in classes]
-    budget = int(sum(f * c.batch for f, c in zip(footprint, classes)) * 0.75)
-    sdesc = pmg.make_server_desc(classes, iters_per_step=4, budget_bytes=budget)
-    ws = torch.empty(pmg.pmg_server_workspace_bytes(sdesc), dtype=torch.uint8, device=dev)
+    budget = int(sum(f * c.batch for f, c in zip(footprint, classes)) * SERVE_BUDGET_FRAC)
+    sdesc = pmg.make_server_desc(classes, iters_per_step=SERVE_ITERS_PER_STEP, budget_bytes=budget)
     # a bank of distinct seeded problems per class; request i of class c uses
     # bank entry i mod K (every request still runs its own setup and solve)
     K = 8
@@ -430,7 +435,7 @@ def serve(args):
         n = len(reqs)
         outs, tickets, t_arr, t_done = [None] * n, [None] * n, np.zeros(n), np.zeros(n)
         nxt, done, its, worst = 0, 0, [], 0.0
-        open_ = set()
+        open_, req_of = set(), {}
         seen = [0] * len(SERVE_CLASSES)
         t0 = time.perf_counter()
         last_print = t0
@@ -446,6 +451,7 @@ def serve(args):
                 seen[c] += 1
                 outs[nxt] = torch.empty_like(f)
                 tickets[nxt] = pmg.pmg_server_submit(srv, c, coords, f, g, outs[nxt])
+                req_of[tickets[nxt]] = nxt
                 t_arr[nxt] = max(arrivals[nxt], 0.0)
                 open_.add(nxt)
                 nxt += 1
@@ -456,33 +462,39 @@ def serve(args):
             if pmg.pmg_server_step(srv) == 0:
                 continue
             now = time.perf_counter() - t0
-            for i in list(open_):
-                ok, info = pmg.pmg_server_poll(srv, tickets[i])
-                if ok:
-                    open_.discard(i)
-                    t_done[i] = now
-                    done += 1
-                    its.append(int(info["iterations"]))
-                    if info["status"] != 0:
-                        worst = float("inf")
-                    else:
-                        worst = max(worst, float(info["relres"]))
-                    outs[i] = None
+            for t in pmg.pmg_server_drain(srv, n):
+                i = req_of[int(t)]
+                ok, info = pmg.pmg_server_poll(srv, int(t))
+                assert ok and i in open_
+                open_.discard(i)
+                t_done[i] = now
+                done += 1
+                its.append(int(info["iterations"]))
+                if info["status"] != 0:
+                    worst = float("inf")
+                else:
+                    worst = max(worst, float(info["relres"]))
+                outs[i] = None
         makespan = time.perf_counter() - t0
         steps = pmg.pmg_server_stats_get(srv)["steps"]
         pmg.pmg_server_destroy(srv)
         lat = (t_done - t_arr) * 1e3
-        return makespan, lat, steps, worst, its
+        last = {f"{d}d_p{p}": round(float(max((t_done[i] for i in range(n) if reqs[i] == c),
+                                              default=0.0)), 4)
+                for c, (d, p, _, _) in enumerate(SERVE_CLASSES)}
+        return makespan, lat, steps, worst, its, last
 
     def plain_fp64():
         """The same request mix solved the plain way: FP64 inner cycle, one
         one-shot batched pmg_solve per class over all of that class's
         requests (setup, lifting, solve, lift), classes back to back."""
         t0 = time.perf_counter()
+        per_class = {}
         for ci, (dim, p, _, _) in enumerate(SERVE_CLASSES):
             cnt = sum(1 for c in reqs if c == ci)
             if cnt == 0:
                 continue
+            tc = time.perf_counter()
             d = classes[ci]
             desc = pmg.make_desc(dim=dim, p_fine=p, batch=cnt, gamma=d.gamma, alpha=d.alpha,
                                  smoother=d.smoother, inner_prec=pmg.PMG_F64, restart=d.restart,
@@ -504,19 +516,24 @@ def serve(args):
             assert np.all(nfo["status"] == 0), (dim, p)
             pmg.pmg_destroy(h)
             del wsp
-        return len(reqs) / (time.perf_counter() - t0)
+            per_class[f"{dim}d_p{p}"] = round(time.perf_counter() - tc, 4)
+        return len(reqs) / (time.perf_counter() - t0), per_class
 
     n = len(reqs)
     plain_fp64()                     # warm-up (module load, graph-free path)
-    plain_thr = plain_fp64()
-    print(f"[bench] served mix, plain FP64 batched per class: {plain_thr:.1f} solves/s",
+    plain_thr, plain_cls = plain_fp64()
+    print(f"[bench] served mix, plain FP64 batched per class: {plain_thr:.1f} solves/s "
+          f"(seconds per class: {plain_cls})", file=sys.stderr, flush=True)
+    torch.cuda.empty_cache()         # the plain batches' workspaces go back before the pools
+    ws = torch.empty(pmg.pmg_server_workspace_bytes(sdesc), dtype=torch.uint8, device=dev)
+    mk, lat_sat, steps_sat, worst_sat, its, last_sat = run(np.zeros(n))
+    print(f"[bench] served saturated: last completion per class (s): {last_sat}",
           file=sys.stderr, flush=True)
-    mk, lat_sat, steps_sat, worst_sat, its = run(np.zeros(n))
     thr = n / mk
     rate = args.serve_load * thr
     rng = np.random.default_rng(11)
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n))
-    mk2, lat, steps, worst, _ = run(arrivals)
+    mk2, lat, steps, worst, _, _ = run(arrivals)
     mix = {f"{d}d_p{p}": int(sum(1 for c in reqs if SERVE_CLASSES[c][:2] == (d, p)))
            for d, p, _, _ in SERVE_CLASSES}
     print(f"[bench] served: saturated {thr:.1f} req/s, paced at {rate:.1f} req/s: "
@@ -526,6 +543,8 @@ def serve(args):
             "inner_precision": {f"{d}d_p{p}": pr for d, p, _, pr in SERVE_CLASSES},
             "saturated_solves_per_s": round(thr, 2),
             "plain_fp64_batched_solves_per_s": round(plain_thr, 2),
+            "plain_seconds_per_class": plain_cls,
+            "saturated_last_done_s": last_sat,
             "speedup_vs_plain_fp64": round(thr / plain_thr, 3),
             "saturated_latency_ms": {"p50": round(float(np.percentile(lat_sat, 50)), 2),
                                      "p99": round(float(np.percentile(lat_sat, 99)), 2)},
@@ -534,7 +553,7 @@ def serve(args):
             "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2),
                            "p99": round(float(np.percentile(lat, 99)), 2)},
             "max_relres": worst, "iterations_median": int(np.median(its)),
-            "budget_bytes": budget, "steps": int(steps), "iters_per_step": 4}
+            "budget_bytes": budget, "steps": int(steps), "iters_per_step": SERVE_ITERS_PER_STEP}
 
 
 def cpu_baseline(args, probs, ps):

@@ -261,7 +261,9 @@ int pmg_pool_destroy(pmg_pool* pool);
  * one if none has), admits queued requests into idle classes, and launches
  * the next step of every idle class with running slots, then returns without
  * waiting for those steps.  Fast classes are therefore not held by slow ones,
- * and the classes' kernels overlap on the device.  Call it repeatedly. */
+ * and the classes' kernels overlap on the device.  Admissions and launches
+ * are issued class by class in decreasing per-slot footprint, so the longest
+ * solves start first.  Call it repeatedly. */
 #define PMG_SERVER_MAX_CLASSES 8
 typedef struct {
     int n_classes;
@@ -290,6 +292,11 @@ int pmg_server_submit(pmg_server* srv, int cls, const double* const* d_coords,
 int pmg_server_step(pmg_server* srv, int* n_done);
 /* 1 if the request has finished (info filled, d_u written), 0 if pending. */
 int pmg_server_poll(pmg_server* srv, long long ticket, pmg_info* info);
+/* Move up to max tickets of requests retired since the previous drain, in
+ * retirement order, into tickets[] (host array of max entries); *n receives
+ * how many.  Entries not moved stay for the next call.  Lets a caller find
+ * its finished requests without polling every open ticket. */
+int pmg_server_drain(pmg_server* srv, long long* tickets, int max, int* n);
 int pmg_server_stats_get(pmg_server* srv, pmg_server_stats* stats);
 int pmg_server_destroy(pmg_server* srv);
 

@@ -2,6 +2,7 @@
 // workspace layout, host-side 1-D GLL tables, kernel launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -971,6 +972,8 @@ struct pmg_server {
     Class cls[PMG_SERVER_MAX_CLASSES];
     std::vector<Req> reqs;           // indexed by ticket
     std::vector<long long> queue;    // arrival order
+    std::vector<long long> retired;  // tickets retired and not yet drained
+    std::vector<int> order;          // classes by per-slot footprint, largest first
     size_t in_use = 0;
     long long steps = 0;
     int finished = 0;
@@ -1043,6 +1046,11 @@ int pmg_server_create(const pmg_server_desc* d, void* d_ws, size_t ws_bytes, pmg
         C.slot_req.assign(d->classes[c].batch, -1);
         C.nlev = ilog2(d->classes[c].p_fine);
     }
+    // the heaviest problems are the longest single solves: their admissions
+    // and steps are issued first so that they start first on the device
+    for (int c = 0; c < d->n_classes; ++c) S->order.push_back(c);
+    std::stable_sort(S->order.begin(), S->order.end(),
+                     [S](int a, int b) { return S->cls[a].footprint > S->cls[b].footprint; });
     *out = S;
     return PMG_OK;
 }
@@ -1089,6 +1097,7 @@ static int server_retire(pmg_server* S, pmg_server::Class& C, int* done)
     if (e != hipSuccess) return hip_fail(e, "server retire");
     for (int b : taken) {
         S->reqs[C.slot_req[b]].done = true;
+        S->retired.push_back(C.slot_req[b]);
         C.slot_req[b] = -1;
         C.running--;
         S->in_use -= C.footprint;
@@ -1151,7 +1160,7 @@ int pmg_server_step(pmg_server* S, int* n_done)
         gs[r.cls].push_back(r.g);
     }
     S->queue.swap(keep);
-    for (int c = 0; c < nc; ++c)
+    for (int c : S->order)
         if (!slots[c].empty() &&
             (rc = pmg_pool_admit(S->cls[c].pool, (int)slots[c].size(), slots[c].data(),
                                  coords[c].data(), fs[c].data(), gs[c].data(),
@@ -1159,7 +1168,7 @@ int pmg_server_step(pmg_server* S, int* n_done)
             return rc;
     // 3. launch a step of every idle class with running slots; each class runs
     //    on its own stream, so fast classes are not held by slow ones
-    for (int c = 0; c < nc; ++c) {
+    for (int c : S->order) {
         pmg_server::Class& C = S->cls[c];
         if (C.inflight || C.running == 0) continue;
         if ((rc = pmg_pool_step(C.pool, (pmg_stream_t)C.stream))) return rc;
@@ -1186,6 +1195,16 @@ int pmg_server_poll(pmg_server* S, long long ticket, pmg_info* info)
     if (!r.done) return 0;
     if (info) *info = r.info;
     return 1;
+}
+
+int pmg_server_drain(pmg_server* S, long long* tickets, int max, int* n)
+{
+    if (!S || !n || max < 0 || (max > 0 && !tickets)) return fail(PMG_EINVAL, "bad argument");
+    const int k = (int)std::min<size_t>((size_t)max, S->retired.size());
+    std::copy(S->retired.begin(), S->retired.begin() + k, tickets);
+    S->retired.erase(S->retired.begin(), S->retired.begin() + k);
+    *n = k;
+    return PMG_OK;
 }
 
 int pmg_server_stats_get(pmg_server* S, pmg_server_stats* st)

@@ -103,6 +103,7 @@ def lib():
                                       ctypes.POINTER(ctypes.c_longlong)]),
             "pmg_server_step": (i, [vp, ctypes.POINTER(i)]),
             "pmg_server_poll": (i, [vp, ctypes.c_longlong, vp]),
+            "pmg_server_drain": (i, [vp, vp, i, ctypes.POINTER(i)]),
             "pmg_server_stats_get": (i, [vp, ctypes.POINTER(pmg_server_stats)]),
             "pmg_server_destroy": (i, [vp]),
         }
@@ -122,7 +123,8 @@ def exported_symbols():
             "pmg_line_coefs", "pmg_geom", "pmg_destroy", "pmg_pool_workspace_bytes",
             "pmg_pool_create", "pmg_pool_admit", "pmg_pool_step", "pmg_pool_poll", "pmg_pool_take",
             "pmg_pool_destroy", "pmg_server_workspace_bytes", "pmg_server_create",
-            "pmg_server_submit", "pmg_server_step", "pmg_server_poll", "pmg_server_stats_get",
+            "pmg_server_submit", "pmg_server_step", "pmg_server_poll", "pmg_server_drain",
+            "pmg_server_stats_get",
             "pmg_server_destroy"]
 
 
@@ -328,6 +330,14 @@ def pmg_server_poll(srv, ticket):
     if rc < 0:
         _check(rc)
     return rc == 1, info[0]
+
+
+def pmg_server_drain(srv, max_n=4096):
+    """Tickets retired since the previous drain (numpy int64 array)."""
+    buf = np.empty(max_n, dtype=np.int64)
+    n = ctypes.c_int(0)
+    _check(lib().pmg_server_drain(srv, ctypes.c_void_p(buf.ctypes.data), max_n, ctypes.byref(n)))
+    return buf[:n.value].copy()
 
 
 def pmg_server_stats_get(srv):

@@ -98,6 +98,7 @@ def test_server_mixed_classes_budget_and_bitwise_results():
     order = [0, 5, 8, 1, 2, 6, 9, 3, 7, 10, 4]   # interleaved arrivals
     pending = list(order)
     max_bytes = 0
+    drained = []
     for step in range(20000):
         # two new requests arrive before every step
         for _ in range(2):
@@ -110,6 +111,10 @@ def test_server_mixed_classes_budget_and_bitwise_results():
                 outs.append((k, u))
                 tickets.append((k, pmg.pmg_server_submit(srv, c, d[0], d[1], d[2], u)))
         pmg.pmg_server_step(srv)
+        got = pmg.pmg_server_drain(srv, 4)
+        for t in got:                       # drained tickets have finished
+            assert pmg.pmg_server_poll(srv, int(t))[0]
+        drained += [int(t) for t in got]
         st = pmg.pmg_server_stats_get(srv)
         max_bytes = max(max_bytes, st["bytes_in_use"])
         assert st["bytes_in_use"] <= budget
@@ -118,6 +123,10 @@ def test_server_mixed_classes_budget_and_bitwise_results():
     torch.cuda.synchronize()
     assert pmg.pmg_server_stats_get(srv)["finished"] == len(reqs)
     assert max_bytes > 0
+    # every ticket is drained exactly once (the rest of the list after the loop)
+    drained += [int(t) for t in pmg.pmg_server_drain(srv, 64)]
+    assert sorted(drained) == sorted(t for _, t in tickets)
+    assert len(pmg.pmg_server_drain(srv, 64)) == 0
     res = {}
     for (k, t), (_, u) in zip(tickets, outs):
         ok, info = pmg.pmg_server_poll(srv, t)
