@@ -25,7 +25,7 @@
 
 namespace pmg {
 
-constexpr int NT = 256;          // threads per workgroup
+constexpr int NT = 512;          // threads per workgroup (one problem each)
 constexpr int MAX_LEVELS = 9;
 // smallest 2-D degree whose operator and transfers run on the matrix cores
 // (16x16 tiles over rows and columns 1..p); below it the vector units

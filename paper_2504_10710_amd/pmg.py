@@ -374,7 +374,7 @@ class Solver:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h:
+        if h and pmg_destroy is not None:      # module globals go at interpreter exit
             pmg_destroy(h)
             self.h = None
 
