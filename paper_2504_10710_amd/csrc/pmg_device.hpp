@@ -245,10 +245,12 @@ __device__ inline void mfma2(PA0 a0_, PB0 b0_, PA1 a1_, PB1 b1_,
 
 // C (M x N, row-major) = A B (MODE 0), += A B (MODE 1), or = A B with the
 // boundary rows and columns set to zero (MODE 2), for row-major A (M x K,
-// leading dimension LDA) and B (K x N, LDB).  Each wave computes a 16 x 32
+// leading dimension LDA) and B (K x N, LDB).  ATR: A is given by its
+// transpose (K x M, row-major, leading dimension LDA), which the 16 lanes of
+// a k-step read as 16 consecutive words.  Each wave computes a 16 x 32
 // block as two 16x16 tiles that share their A rows; rows and columns past
 // M, N are clamped in the loads and never stored.
-template <class T, int M, int N, int K, int LDA, int LDB, int MODE>
+template <class T, int M, int N, int K, int LDA, int LDB, int MODE, bool ATR = false>
 __device__ void wg_gemm(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C_)
 {
     const auto C = gmem(C_);
@@ -261,8 +263,9 @@ __device__ void wg_gemm(const T* __restrict__ A, const T* __restrict__ B, T* __r
         const int ar = min(r0 + lr, M - 1);
         const int bc0 = min(c0 + lr, N - 1), bc1 = min(c0 + 16 + lr, N - 1);
         V4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-        const T* ap = A + ar * LDA + kq;
-        mfma2<T, K, 1, LDB, 1, LDB>(ap, B + kq * LDB + bc0, ap, B + kq * LDB + bc1, acc0, acc1);
+        constexpr int SA = ATR ? LDA : 1;
+        const T* ap = ATR ? A + kq * LDA + ar : A + ar * LDA + kq;
+        mfma2<T, K, SA, LDB, SA, LDB>(ap, B + kq * LDB + bc0, ap, B + kq * LDB + bc1, acc0, acc1);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int i = c0 + 16 * h + lr;
@@ -286,15 +289,18 @@ __device__ void wg_gemm(const T* __restrict__ A, const T* __restrict__ B, T* __r
 
 // Register-blocked form of mfma2 for BR x BC tiles per product: c0[i][j] +=
 // A0_i B0_j and c1[i][j] += A1_i B1_j over k = 0 .. K-1, where A_i are the
-// row strips 16 i apart (row-major, leading dimension LDA*, unit stride in
-// k) and B_j the column strips 16 j apart (row-major, leading dimension
-// LDB*, stride LDB* in k).  Pointers as in mfma2 (the lane's element of the
-// first strip).  Each operand fragment feeds BR or BC matrix-core steps, so
-// a block needs BR + BC loads per product and k-step instead of 2 BR BC.
-// c0 and c1 may be the same array (both products then accumulate into it).
-// NP = 1 computes only the first product (a1, b1, c1 unused).
+// row strips 16 i apart (row stride LDA*, k stride KA*) and B_j the column
+// strips 16 j apart (row-major, leading dimension LDB*, stride LDB* in k).
+// A row-major A has LDA = its leading dimension and KA = 1; an A read from
+// its stored transpose has LDA = 1 and KA = the transpose's leading
+// dimension, so that the 16 lanes of a k-step read 16 consecutive words.
+// Pointers as in mfma2 (the lane's element of the first strip).  Each
+// operand fragment feeds BR or BC matrix-core steps, so a block needs
+// BR + BC loads per product and k-step instead of 2 BR BC.  c0 and c1 may be
+// the same array (both products then accumulate into it).  NP = 1 computes
+// only the first product (a1, b1, c1 unused).
 template <class T, int K, int LDA0, int LDB0, int LDA1, int LDB1, int BR, int BC, int NP = 2,
-          class PA0, class PB0, class PA1, class PB1>
+          int KA0 = 1, int KA1 = 1, class PA0, class PB0, class PA1, class PB1>
 __device__ inline void mfma_blocks(PA0 a0_, PB0 b0_, PA1 a1_, PB1 b1_,
                                    typename Mfma<T>::v4 (&c0)[BR][BC],
                                    typename Mfma<T>::v4 (&c1)[BR][BC])
@@ -312,8 +318,8 @@ __device__ inline void mfma_blocks(PA0 a0_, PB0 b0_, PA1 a1_, PB1 b1_,
         if (u < KS) {
 #pragma unroll
             for (int i = 0; i < BR; ++i) {
-                xa0[u][i] = a0[i * 16 * LDA0 + 4 * u];
-                if constexpr (NP == 2) xa1[u][i] = a1[i * 16 * LDA1 + 4 * u];
+                xa0[u][i] = a0[i * 16 * LDA0 + 4 * u * KA0];
+                if constexpr (NP == 2) xa1[u][i] = a1[i * 16 * LDA1 + 4 * u * KA1];
             }
 #pragma unroll
             for (int j = 0; j < BC; ++j) {
@@ -338,8 +344,8 @@ __device__ inline void mfma_blocks(PA0 a0_, PB0 b0_, PA1 a1_, PB1 b1_,
         if (s + PF < KS) {
 #pragma unroll
             for (int i = 0; i < BR; ++i) {
-                xa0[u][i] = a0[i * 16 * LDA0 + 4 * (s + PF)];
-                if constexpr (NP == 2) xa1[u][i] = a1[i * 16 * LDA1 + 4 * (s + PF)];
+                xa0[u][i] = a0[i * 16 * LDA0 + 4 * (s + PF) * KA0];
+                if constexpr (NP == 2) xa1[u][i] = a1[i * 16 * LDA1 + 4 * (s + PF) * KA1];
             }
 #pragma unroll
             for (int j = 0; j < BC; ++j) {
@@ -365,8 +371,8 @@ __device__ inline void mfma_blocks(PA0 a0_, PB0 b0_, PA1 a1_, PB1 b1_,
         T pa0[BR], pb0[BC], pa1[BR], pb1[BC];
 #pragma unroll
         for (int i = 0; i < BR; ++i) {
-            pa0[i] = in ? a0[i * 16 * LDA0 + kk] : T(0);
-            if constexpr (NP == 2) pa1[i] = in ? a1[i * 16 * LDA1 + kk] : T(0);
+            pa0[i] = in ? a0[i * 16 * LDA0 + kk * KA0] : T(0);
+            if constexpr (NP == 2) pa1[i] = in ? a1[i * 16 * LDA1 + kk * KA1] : T(0);
         }
 #pragma unroll
         for (int j = 0; j < BC; ++j) {
@@ -420,9 +426,10 @@ __device__ void apply2d_mfma(const T* __restrict__ G_, const T* __restrict__ D_,
                 ur[i][j] = V4{0, 0, 0, 0};
                 us[i][j] = V4{0, 0, 0, 0};
             }
-        mfma_blocks<T, n1, n1, n1, n1, n1, BLK, BLK>(x + (r0 + lr) * n1 + kq, DT + kq * n1 + c0 + lr,
-                                                     D + (r0 + lr) * n1 + kq, x + kq * n1 + c0 + lr,
-                                                     ur, us);
+        mfma_blocks<T, n1, n1, n1, 1, n1, BLK, BLK, 2, 1, n1>(x + (r0 + lr) * n1 + kq,
+                                                              DT + kq * n1 + c0 + lr,
+                                                              DT + kq * n1 + r0 + lr,
+                                                              x + kq * n1 + c0 + lr, ur, us);
 #pragma unroll
         for (int i = 0; i < BLK; ++i)
 #pragma unroll
@@ -458,9 +465,10 @@ __device__ void apply2d_mfma(const T* __restrict__ G_, const T* __restrict__ D_,
 #pragma unroll
             for (int j = 0; j < BLK; ++j) y[i][j] = V4{0, 0, 0, 0};
         // sum_k F0[j][k] D[k][i] and sum_k D^T[j][k] F1[k][i]
-        mfma_blocks<T, n1, n1, n1, n1, n1, BLK, BLK>(TR + (r0 + lr) * n1 + kq, D + kq * n1 + c0 + lr,
-                                                     DT + (r0 + lr) * n1 + kq,
-                                                     TR + N + kq * n1 + c0 + lr, y, y);
+        mfma_blocks<T, n1, n1, n1, 1, n1, BLK, BLK, 2, 1, n1>(TR + (r0 + lr) * n1 + kq,
+                                                              D + kq * n1 + c0 + lr,
+                                                              D + kq * n1 + r0 + lr,
+                                                              TR + N + kq * n1 + c0 + lr, y, y);
 #pragma unroll
         for (int i = 0; i < BLK; ++i)
 #pragma unroll
@@ -519,7 +527,8 @@ __device__ void apply3d_mfma(const T* __restrict__ G_, const T* __restrict__ D_,
 #pragma unroll
             for (int b = 0; b < BLK; ++b) acc[a][b] = V4{0, 0, 0, 0};
         const auto bp = x + n1 * j + kq * S2 + c0 + lr;
-        mfma_blocks<T, n1, n1, S2, n1, S2, BLK, BLK, 1>(D + (r0 + lr) * n1 + kq, bp, D, bp, acc, acc);
+        mfma_blocks<T, n1, 1, S2, 1, S2, BLK, BLK, 1, n1, n1>(DT + kq * n1 + r0 + lr, bp, DT, bp,
+                                                              acc, acc);
 #pragma unroll
         for (int a = 0; a < BLK; ++a)
 #pragma unroll
@@ -554,9 +563,10 @@ __device__ void apply3d_mfma(const T* __restrict__ G_, const T* __restrict__ D_,
                 g0[a][b] = V4{0, 0, 0, 0};
                 g1[a][b] = V4{0, 0, 0, 0};
             }
-        mfma_blocks<T, n1, n1, n1, n1, n1, BLK, BLK>(xk + (r0 + lr) * n1 + kq, DT + kq * n1 + c0 + lr,
-                                                     D + (r0 + lr) * n1 + kq, xk + kq * n1 + c0 + lr,
-                                                     g0, g1);
+        mfma_blocks<T, n1, n1, n1, 1, n1, BLK, BLK, 2, 1, n1>(xk + (r0 + lr) * n1 + kq,
+                                                              DT + kq * n1 + c0 + lr,
+                                                              DT + kq * n1 + r0 + lr,
+                                                              xk + kq * n1 + c0 + lr, g0, g1);
 #pragma unroll
         for (int a = 0; a < BLK; ++a)
 #pragma unroll
@@ -602,7 +612,8 @@ __device__ void apply3d_mfma(const T* __restrict__ G_, const T* __restrict__ D_,
 #pragma unroll
             for (int b = 0; b < BLK; ++b) acc[a][b] = V4{0, 0, 0, 0};
         const auto bp = F2 + n1 * j + kq * S2 + c0 + lr;
-        mfma_blocks<T, n1, n1, S2, n1, S2, BLK, BLK, 1>(DT + (r0 + lr) * n1 + kq, bp, DT, bp, acc, acc);
+        mfma_blocks<T, n1, 1, S2, 1, S2, BLK, BLK, 1, n1, n1>(D + kq * n1 + r0 + lr, bp, D, bp,
+                                                              acc, acc);
 #pragma unroll
         for (int a = 0; a < BLK; ++a)
 #pragma unroll
@@ -627,9 +638,10 @@ __device__ void apply3d_mfma(const T* __restrict__ G_, const T* __restrict__ D_,
 #pragma unroll
             for (int b = 0; b < BLK; ++b) y[a][b] = V4{0, 0, 0, 0};
         const auto f0k = F0 + S2 * k, f1k = F1 + S2 * k;
-        mfma_blocks<T, n1, n1, n1, n1, n1, BLK, BLK>(f0k + (r0 + lr) * n1 + kq, D + kq * n1 + c0 + lr,
-                                                     DT + (r0 + lr) * n1 + kq,
-                                                     f1k + kq * n1 + c0 + lr, y, y);
+        mfma_blocks<T, n1, n1, n1, 1, n1, BLK, BLK, 2, 1, n1>(f0k + (r0 + lr) * n1 + kq,
+                                                              D + kq * n1 + c0 + lr,
+                                                              D + kq * n1 + r0 + lr,
+                                                              f1k + kq * n1 + c0 + lr, y, y);
 #pragma unroll
         for (int a = 0; a < BLK; ++a)
 #pragma unroll
@@ -1127,7 +1139,7 @@ __device__ __attribute__((noinline)) void restrict_level(const T* rf, T* rc, con
         // W1 = rf J (n1f x n1c); rc = J^T W1 with zero boundary
         (void)w2;
         wg_gemm<T, n1f, n1c, n1f, n1f, n1c, 0>(rf, J, w1);
-        wg_gemm<T, n1c, n1c, n1f, n1f, n1c, 2>(JT, w1, rc);
+        wg_gemm<T, n1c, n1c, n1f, n1c, n1c, 2, true>(J, w1, rc);
         return;
     }
     if (DIM == 2) {
@@ -1149,7 +1161,7 @@ __device__ __attribute__((noinline)) void prolong_level(const T* ec, T* xf, cons
         // W1 = ec J^T (n1c x n1f); xf += J W1
         (void)w2;
         wg_gemm<T, n1c, n1f, n1c, n1c, n1f, 0>(ec, JT, w1);
-        wg_gemm<T, n1f, n1f, n1c, n1c, n1f, 1>(J, w1, xf);
+        wg_gemm<T, n1f, n1f, n1c, n1f, n1f, 1, true>(JT, w1, xf);
         return;
     }
     if (DIM == 2) {
