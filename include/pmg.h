@@ -170,7 +170,7 @@ int pmg_prolong_add(pmg_handle* h, int level, int prec, const void* d_ec, void* 
 /* d_z = B_{l,dir}^{-1} d_r: every interior line along axis dir solved by the
  * cyclic reduction of Thm. "Two-level direct solver" / Cor. "Direct
  * multigrid solver" (block Jacobi over lines, Def. line preconditioners);
- * boundary entries of d_z are 0. */
+ * boundary entries of d_z are 0.  d_r and d_z must not overlap. */
 int pmg_line_solve(pmg_handle* h, int level, int dir, int prec, const void* d_r,
                    void* d_z, pmg_stream_t stream);
 

@@ -889,8 +889,9 @@ __device__ void line_cr_wave(const T* __restrict__ cr_, T* __restrict__ g_, T* _
                 x[base + 2 * u + 1] += alpha * e0;
                 if (has1) x[base + 2 * u + 2] += alpha * e1;
             } else {
-                g[base + 2 * u + 1] = e0;
-                if (has1) g[base + 2 * u + 2] = e1;
+                const auto z = x_ ? x : g;
+                z[base + 2 * u + 1] = e0;
+                if (has1) z[base + 2 * u + 2] = e1;
             }
         }
     }
@@ -962,7 +963,7 @@ __device__ void line_cr_wave_strided(const T* __restrict__ cr_, int dir, T* __re
                     if (FUSED)
                         x[q] += alpha * strip[r * LD + ci];
                     else
-                        g[q] = strip[r * LD + ci];
+                        (x_ ? x : g)[q] = strip[r * LD + ci];
                 }
             }
             wg_barrier();
@@ -980,7 +981,9 @@ __device__ void line_cr_wave_strided(const T* __restrict__ cr_, int dir, T* __re
 //   down: x_F = g_F / a_F;  g_C -= l_C x_{C-1} + u_C x_{C+1}   (R (g - M x))
 //   coarsest: x = g / a
 //   up:   y_F = x_F - (l_F e_{F-1} + u_F e_{F+1}) / a_F         (x + P e)
-// FUSED: instead of storing z, x += alpha z.
+// FUSED: instead of storing z, x += alpha z.  Not fused, lines solved by
+// lane groups (wave_lines) store z into x when x is given (g is then only
+// read), else in place; the thread-per-line form is in place only.
 template <class T, int P, int DIM, bool FUSED>
 __device__ __attribute__((noinline)) void line_cr(const T* __restrict__ cr_, int dir,
                                                   T* __restrict__ g_, T* __restrict__ x_, T alpha)

@@ -53,9 +53,18 @@ __global__ void __launch_bounds__(NT, 8) k_line_solve(const Hier<T>* __restrict_
     const LevelData<T>& L = H.lev[S::LEV];
     T* zb = z + b * S::N;
     const T* rb = r + b * S::N;
-    for (int q = threadIdx.x; q < S::N; q += NT) zb[q] = is_boundary<P, DIM>(q) ? T(0) : rb[q];
-    wg_barrier();
-    line_cr<T, P, DIM, false>(L.cr[dir] + b * 3 * S::CRW * S::NL, dir, zb, nullptr, T(0));
+    if constexpr (wave_lines<P>()) {
+        // lane-group lines read r and write z: one pass over each, and the
+        // boundary of z set to zero (the lines cover every interior node)
+        for (int q = threadIdx.x; q < S::N; q += NT)
+            if (is_boundary<P, DIM>(q)) zb[q] = T(0);
+        line_cr<T, P, DIM, false>(L.cr[dir] + b * 3 * S::CRW * S::NL, dir, const_cast<T*>(rb), zb,
+                                  T(0));
+    } else {
+        for (int q = threadIdx.x; q < S::N; q += NT) zb[q] = is_boundary<P, DIM>(q) ? T(0) : rb[q];
+        wg_barrier();
+        line_cr<T, P, DIM, false>(L.cr[dir] + b * 3 * S::CRW * S::NL, dir, zb, nullptr, T(0));
+    }
 }
 
 template <class T, int P, int DIM>
