@@ -444,3 +444,44 @@ def test_line_solve_full_width(dim, p):
             tol = max(1e-5, 20 * (p - 1) * np.finfo(np.float32).eps * kap)
             err = rel_err(z.cpu().numpy()[b].astype(np.float64), zo)
             assert err < tol, (d, b, err, tol)
+
+
+@pytest.mark.parametrize("dim,p", [(2, 128), (3, 32), (3, 64)])
+def test_apply_transfers_mfma(dim, p):
+    """Operator and transfers on their matrix-core paths at the finest level
+    (2-D p = 128: 2x2-tile blocks; 3-D p = 32 single tiles, p = 64 2x2 blocks;
+    D, D^T and J, J^T read from their stored transposes), FP64 and FP32,
+    element by element against the oracle on random interior inputs."""
+    kind = "cfg2" if dim == 2 else "cfg3"
+    probs = problems(kind, [3, 4])
+    B = len(probs)
+    s, _, _ = gpu_batch(probs, p, gamma=1, alpha=0.16, smoother=pmg.PMG_SMOOTHER_FEM)
+    s32, _, _ = gpu_batch(probs, p, gamma=1, alpha=0.16, smoother=pmg.PMG_SMOOTHER_FEM,
+                          inner_prec=pmg.PMG_F32)
+    torch.cuda.synchronize()
+    ors = [oracle_of(pr, p, gamma=1, alpha=0.16, smoother=1)[0] for pr in probs]
+    L = s.nlev - 1
+    pc = p // 2
+    x = _rand_interior(dim, p, B, 91)
+    rng = np.random.default_rng(92)
+    rf = rng.standard_normal((B, (p + 1) ** dim))
+    ec = _rand_interior(dim, pc, B, 93)
+    xf0 = rng.standard_normal((B, (p + 1) ** dim))
+    for prec, dt, tol_a, tol_t in ((pmg.PMG_F64, torch.float64, eval_tol(p), 1e-12),
+                                   (pmg.PMG_F32, torch.float32, 1e-5, 1e-5)):
+        h = s.h if prec == pmg.PMG_F64 else s32.h
+        xt = torch.from_numpy(x).to(dt).cuda()
+        y = torch.empty_like(xt)
+        pmg.pmg_apply(h, L, prec, xt, y)
+        rc = torch.empty((B, (pc + 1) ** dim), dtype=dt, device="cuda")
+        pmg.pmg_restrict(h, L, prec, torch.from_numpy(rf).to(dt).cuda(), rc)
+        xf = torch.from_numpy(xf0).to(dt).cuda()
+        pmg.pmg_prolong_add(h, L, prec, torch.from_numpy(ec).to(dt).cuda(), xf)
+        torch.cuda.synchronize()
+        for b, ho in enumerate(ors):
+            ea = rel_err(y.cpu().double().numpy()[b], ho.apply(x[b], L))
+            er = rel_err(rc.cpu().double().numpy()[b], ho.restrict(rf[b], L))
+            ep = rel_err(xf.cpu().double().numpy()[b], ho.prolong_add(ec[b], xf0[b], L))
+            print(f"[mfma ops] dim={dim} p={p} prec={prec} b={b}: apply {ea:.2e} restrict {er:.2e} "
+                  f"prolong {ep:.2e}", flush=True)
+            assert ea < tol_a and er < tol_t and ep < tol_t, (prec, b, ea, er, ep)
