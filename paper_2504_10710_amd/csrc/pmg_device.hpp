@@ -1192,8 +1192,15 @@ __device__ void smooth_step(const Hier<T>& H, int b, int dir, const T* r, T* x, 
     using S = Shape<P, DIM>;
     const LevelData<T>& L = lvl<T, P, DIM>(H);
     T* tmp = L.Tm + (long long)b * S::N;
+    if (x_is_zero && wave_lines<P>()) {
+        // the residual is r itself; lane-group lines only read their
+        // right-hand side, so they take it from r without a copy
+        line_cr<T, P, DIM, true>(L.cr[dir] + (long long)b * 3 * S::CRW * S::NL, dir,
+                                 const_cast<T*>(r), x, H.alpha);
+        return;
+    }
     if (x_is_zero) {
-        wg_copy(tmp, r, S::N);
+        wg_copy(tmp, r, S::N);   // the thread-per-line form works in place
         wg_barrier();
     } else {
         apply_level<T, P, DIM, true>(L.G + (long long)b * S::NC * S::N, L.D, L.DT,
