@@ -863,7 +863,7 @@ __device__ inline void cr_wave_solve(PC c, int u, bool has1, T& e0, T& e1)
 
 template <class T, int P, int DIM, bool FUSED>
 __device__ void line_cr_wave(const T* __restrict__ cr_, T* __restrict__ g_, T* __restrict__ x_,
-                             T alpha)
+                             T alpha, bool assign)
 {
     const auto cr = gmem(cr_);
     const auto g = gmem(g_);
@@ -886,8 +886,9 @@ __device__ void line_cr_wave(const T* __restrict__ cr_, T* __restrict__ g_, T* _
         cr_wave_solve<T, n, W>(cr + (long long)lc * 3 * CRW, u, has1, e0, e1);
         if (act) {
             if (FUSED) {
-                x[base + 2 * u + 1] += alpha * e0;
-                if (has1) x[base + 2 * u + 2] += alpha * e1;
+                const int q0 = base + 2 * u + 1;
+                x[q0] = (assign ? T(0) : x[q0]) + alpha * e0;
+                if (has1) x[q0 + 1] = (assign ? T(0) : x[q0 + 1]) + alpha * e1;
             } else {
                 const auto z = x_ ? x : g;
                 z[base + 2 * u + 1] = e0;
@@ -917,7 +918,7 @@ __device__ inline void* line_strip_lds()
 // lines' tridiagonals are stored line-major like the first axis'.
 template <class T, int P, int DIM, bool FUSED>
 __device__ void line_cr_wave_strided(const T* __restrict__ cr_, int dir, T* __restrict__ g_,
-                                     T* __restrict__ x_, T alpha)
+                                     T* __restrict__ x_, T alpha, bool assign)
 {
     const auto cr = gmem(cr_);
     const auto g = gmem(g_);
@@ -961,7 +962,7 @@ __device__ void line_cr_wave_strided(const T* __restrict__ cr_, int dir, T* __re
                 if (i < n) {
                     const int q = ob + (r + 1) * RS + i + 1;
                     if (FUSED)
-                        x[q] += alpha * strip[r * LD + ci];
+                        x[q] = (assign ? T(0) : x[q]) + alpha * strip[r * LD + ci];
                     else
                         (x_ ? x : g)[q] = strip[r * LD + ci];
                 }
@@ -981,19 +982,21 @@ __device__ void line_cr_wave_strided(const T* __restrict__ cr_, int dir, T* __re
 //   down: x_F = g_F / a_F;  g_C -= l_C x_{C-1} + u_C x_{C+1}   (R (g - M x))
 //   coarsest: x = g / a
 //   up:   y_F = x_F - (l_F e_{F-1} + u_F e_{F+1}) / a_F         (x + P e)
-// FUSED: instead of storing z, x += alpha z.  Not fused, lines solved by
+// FUSED: instead of storing z, x += alpha z (x = alpha z with assign, lane
+// groups only: x is then not read).  Not fused, lines solved by
 // lane groups (wave_lines) store z into x when x is given (g is then only
 // read), else in place; the thread-per-line form is in place only.
 template <class T, int P, int DIM, bool FUSED>
 __device__ __attribute__((noinline)) void line_cr(const T* __restrict__ cr_, int dir,
-                                                  T* __restrict__ g_, T* __restrict__ x_, T alpha)
+                                                  T* __restrict__ g_, T* __restrict__ x_, T alpha,
+                                                  bool assign = false)
 {
     if constexpr (wave_lines<P>()) {
         if (dir == 0) {
-            line_cr_wave<T, P, DIM, FUSED>(cr_, g_, x_, alpha);
+            line_cr_wave<T, P, DIM, FUSED>(cr_, g_, x_, alpha, assign);
             return;
         }
-        line_cr_wave_strided<T, P, DIM, FUSED>(cr_, dir, g_, x_, alpha);
+        line_cr_wave_strided<T, P, DIM, FUSED>(cr_, dir, g_, x_, alpha, assign);
         return;
     }
     const auto cr = gmem(cr_);
@@ -1194,9 +1197,10 @@ __device__ void smooth_step(const Hier<T>& H, int b, int dir, const T* r, T* x, 
     T* tmp = L.Tm + (long long)b * S::N;
     if (x_is_zero && wave_lines<P>()) {
         // the residual is r itself; lane-group lines only read their
-        // right-hand side, so they take it from r without a copy
+        // right-hand side, so they take it from r without a copy, and they
+        // assign x = alpha z on the interior (x's boundary is already zero)
         line_cr<T, P, DIM, true>(L.cr[dir] + (long long)b * 3 * S::CRW * S::NL, dir,
-                                 const_cast<T*>(r), x, H.alpha);
+                                 const_cast<T*>(r), x, H.alpha, true);
         return;
     }
     if (x_is_zero) {
@@ -1234,7 +1238,14 @@ __device__ __attribute__((noinline)) void gamma_cycle(const Hier<T>& H, int b, c
         T* tmp = L.Tm + (long long)b * S::N;
         T* w1 = H.W1 + (long long)b * H.w1;
         T* w2 = H.W2 ? H.W2 + (long long)b * H.w2 : nullptr;
-        wg_zero(x, S::N);
+        if (wave_lines<P>() && H.m > 0) {
+            // the first smoothing step assigns every interior node
+            const auto xg = gmem(x);
+            for (int q = threadIdx.x; q < S::N; q += NT)
+                if (is_boundary<P, DIM>(q)) xg[q] = T(0);
+        } else {
+            wg_zero(x, S::N);
+        }
         wg_barrier();
         bool zero = true;
         for (int dir = 0; dir < DIM; ++dir)

@@ -485,3 +485,25 @@ def test_apply_transfers_mfma(dim, p):
             print(f"[mfma ops] dim={dim} p={p} prec={prec} b={b}: apply {ea:.2e} restrict {er:.2e} "
                   f"prolong {ep:.2e}", flush=True)
             assert ea < tol_a and er < tol_t and ep < tol_t, (prec, b, ea, er, ep)
+
+
+@pytest.mark.parametrize("dim,p,m,gamma", [(2, 32, 0, 2), (2, 32, 2, 1), (3, 16, 0, 1), (3, 16, 2, 2)])
+def test_gamma_cycle_smoothing_counts(dim, p, m, gamma):
+    """Cycles with no smoothing (m = 0: coarse corrections only, the iterate
+    starts from zero) and with two smoothing steps per axis, against the
+    oracle's cycle."""
+    kind = "cfg2" if dim == 2 else "cfg3"
+    probs = problems(kind, [7, 8])
+    s, _, _ = gpu_batch(probs, p, gamma=gamma, m=m, alpha=0.16, smoother=pmg.PMG_SMOOTHER_FEM)
+    ors = [oracle_of(pr, p, gamma=gamma, m=m, alpha=0.16, smoother=1)[0] for pr in probs]
+    r = _rand_interior(dim, p, len(probs), 51)
+    y = torch.empty((len(probs), (p + 1) ** dim), dtype=torch.float64, device="cuda")
+    pmg.pmg_gamma_cycle(s.h, pmg.PMG_F64, torch.from_numpy(r).cuda(), y)
+    torch.cuda.synchronize()
+    for b, h in enumerate(ors):
+        tol = max(1e-9, 100 * max(_smooth_tol(h, l, d, dim, 2 << l)
+                                  for l in range(1, h.nlev) for d in range(dim)))
+        err = rel_err(y.cpu().numpy()[b], h.cycle(r[b]))
+        print(f"[cycle m={m} gamma={gamma}] dim={dim} p={p} b={b}: rel err {err:.2e} tol {tol:.1e}",
+              flush=True)
+        assert err < tol, (b, err, tol)
