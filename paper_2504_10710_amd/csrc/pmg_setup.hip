@@ -457,6 +457,36 @@ __global__ void __launch_bounds__(NT) k_lines(const double* __restrict__ G,
         cr[idx(dir, line, sq, 2)] = u;
     }
     wg_barrier();
+    if constexpr (wave_lines<P>()) {
+        // 2'. lane-group lines keep only their raw rows: the solver builds
+        //     every CR level from them.  Every level's pivots are checked by
+        //     solving each line with a right-hand side of ones (a zero or
+        //     non-finite pivot makes the solution non-finite), and the FP32
+        //     copy is of the raw rows alone.
+        constexpr int W = (n + 1) / 2 > 0 ? (n + 1) / 2 : 1;   // lanes per line
+        constexpr int LPW = 64 / W;
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        const int u = lane % W, sub = lane / W;
+        const bool has1 = 2 * u + 1 < n;
+        for (int dir = 0; dir < DIM; ++dir) {
+            const auto cr = gmem((const double*)crp(dir));
+            for (int line0 = wave * LPW; line0 < NL; line0 += (NT / 64) * LPW) {
+                const int line = line0 + sub;
+                const int lc = line < NL ? line : NL - 1;
+                double e0 = 1.0, e1 = has1 ? 1.0 : 0.0;
+                cr_wave_solve<double, n, W>(cr + (long long)lc * 3 * CRW, u, has1, e0, e1);
+                if (line < NL && !(isfinite(e0) && isfinite(e1))) bad = 1;
+            }
+            float* cf = dir == 0 ? f0 : (dir == 1 ? f1 : f2);
+            if (cf) {
+                const auto cfb = gmem(cf + b * 3 * CRW * NL);
+                for (int e = threadIdx.x; e < NL * 3 * n; e += NT) {
+                    const long long o = (long long)(e / (3 * n)) * 3 * CRW + e % (3 * n);
+                    cfb[o] = (float)cr[o];
+                }
+            }
+        }
+    } else {
     // 2. cyclic-reduction factors, one line per thread over all axes
     for (int e = threadIdx.x; e < DIM * NL; e += NT) {
         const int dir = e / NL, line = e % NL;
@@ -506,6 +536,7 @@ __global__ void __launch_bounds__(NT) k_lines(const double* __restrict__ G,
                     for (int w = 0; w < 3; ++w) cfb[idx(dir, line, slot, w)] = (float)W(slot, w);
             }
         }
+    }
     }
     if (P == 2 && threadIdx.x == 0) {
         // level 0: the exact coarse solve uses A_0 itself (eq. discreteBilinear),
