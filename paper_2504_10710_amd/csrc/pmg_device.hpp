@@ -247,21 +247,27 @@ __device__ inline void mfma2(PA0 a0_, PB0 b0_, PA1 a1_, PB1 b1_,
 // boundary rows and columns set to zero (MODE 2), for row-major A (M x K,
 // leading dimension LDA) and B (K x N, LDB).  ATR: A is given by its
 // transpose (K x M, row-major, leading dimension LDA), which the 16 lanes of
-// a k-step read as 16 consecutive words.  Each wave computes a 16 x 32
-// block as two 16x16 tiles that share their A rows; rows and columns past
-// M, N are clamped in the loads and never stored.
-template <class T, int M, int N, int K, int LDA, int LDB, int MODE, bool ATR = false>
-__device__ void wg_gemm(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C_)
+// a k-step read as 16 consecutive words.  NS > 1: NS products C_s = A B_s
+// with B_s = B + s SB and C_s = C + s SC (one A), and MODE 2 also zeroes the
+// first and last slab (the boundary faces of a 3-D box).  Each wave computes
+// a 16 x 32 block as two 16x16 tiles that share their A rows; rows and
+// columns past M, N are clamped in the loads and never stored.
+template <class T, int M, int N, int K, int LDA, int LDB, int MODE, bool ATR = false, int NS = 1,
+          int SB = 0, int SC = 0>
+__device__ void wg_gemm(const T* __restrict__ A, const T* __restrict__ B_, T* __restrict__ C_)
 {
     const auto C = gmem(C_);
     constexpr int TM = (M + 15) / 16, TN2 = (N + 31) / 32;
     using V4 = typename Mfma<T>::v4;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lr = lane & 15, kq = lane >> 4;
-    for (int t = wave; t < TM * TN2; t += NT / 64) {
-        const int r0 = (t / TN2) * 16, c0 = (t % TN2) * 32;
+    for (int t = wave; t < NS * TM * TN2; t += NT / 64) {
+        const int sl = t / (TM * TN2), tt = t % (TM * TN2);
+        const int r0 = (tt / TN2) * 16, c0 = (tt % TN2) * 32;
         const int ar = min(r0 + lr, M - 1);
         const int bc0 = min(c0 + lr, N - 1), bc1 = min(c0 + 16 + lr, N - 1);
+        const T* B = B_ + (long long)sl * SB;
+        const auto Cs = C + (long long)sl * SC;
         V4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
         constexpr int SA = ATR ? LDA : 1;
         const T* ap = ATR ? A + kq * LDA + ar : A + ar * LDA + kq;
@@ -275,11 +281,14 @@ __device__ void wg_gemm(const T* __restrict__ A, const T* __restrict__ B, T* __r
                 const T a = h ? acc1[v] : acc0[v];
                 if (j < M && i < N) {
                     if (MODE == 1)
-                        C[j * N + i] += a;
+                        Cs[j * N + i] += a;
                     else if (MODE == 2)
-                        C[j * N + i] = (j == 0 || j == M - 1 || i == 0 || i == N - 1) ? T(0) : a;
+                        Cs[j * N + i] = (j == 0 || j == M - 1 || i == 0 || i == N - 1 ||
+                                         (NS > 1 && (sl == 0 || sl == NS - 1)))
+                                            ? T(0)
+                                            : a;
                     else
-                        C[j * N + i] = a;
+                        Cs[j * N + i] = a;
                 }
             }
         }
@@ -1148,6 +1157,15 @@ __device__ __attribute__((noinline)) void restrict_level(const T* rf, T* rc, con
         wg_gemm<T, n1c, n1c, n1f, n1c, n1c, 2, true>(J, w1, rc);
         return;
     }
+    if constexpr (DIM == 3 && P >= MFMA_MIN_P) {
+        // third axis:  W1 = J^T RF, RF as n1f x n1f^2       -> [k'][j][i]
+        // first axis:  W2 = W1 J, W1 as (n1c n1f) x n1f      -> [k'][j][i']
+        // second axis: rc_k' = J^T W2_k' for every slab k', boundary faces zero
+        wg_gemm<T, n1c, n1f * n1f, n1f, n1c, n1f * n1f, 0, true>(J, rf, w1);
+        wg_gemm<T, n1c * n1f, n1c, n1f, n1f, n1c, 0>(w1, J, w2);
+        wg_gemm<T, n1c, n1c, n1f, n1c, n1c, 2, true, n1c, n1f * n1c, n1c * n1c>(J, w2, rc);
+        return;
+    }
     if (DIM == 2) {
         restrict_axis<T>(rf, w1, n1f, n1f, 1, 0, n1f, n1c, J, false);
         restrict_axis<T>(w1, rc, n1c, n1f, 1, 1, n1f, n1c, J, true);
@@ -1168,6 +1186,15 @@ __device__ __attribute__((noinline)) void prolong_level(const T* ec, T* xf, cons
         (void)w2;
         wg_gemm<T, n1c, n1f, n1c, n1c, n1f, 0>(ec, JT, w1);
         wg_gemm<T, n1f, n1f, n1c, n1f, n1f, 1, true>(JT, w1, xf);
+        return;
+    }
+    if constexpr (DIM == 3 && P >= MFMA_MIN_P) {
+        // third axis:  W1 = J EC, EC as n1c x n1c^2           -> [k][j'][i']
+        // first axis:  W2 = W1 J^T, W1 as (n1f n1c) x n1c     -> [k][j'][i]
+        // second axis: xf_k += J W2_k for every slab k
+        wg_gemm<T, n1f, n1c * n1c, n1c, n1f, n1c * n1c, 0, true>(JT, ec, w1);
+        wg_gemm<T, n1f * n1c, n1f, n1c, n1c, n1f, 0>(w1, JT, w2);
+        wg_gemm<T, n1f, n1f, n1c, n1f, n1f, 1, true, n1f, n1c * n1f, n1f * n1f>(JT, w2, xf);
         return;
     }
     if (DIM == 2) {
