@@ -382,13 +382,14 @@ def main():
 
 # (dim, p, slots, inner precision).  A class with 1024 slots can fill the chip
 # by itself (256 CUs x 2 resident one-problem workgroups, twice over); 3-D
-# p = 64 slots cost 196 MB each, so that class holds 768 (151 GB).
+# p = 64 slots cost 178 MB each (FP64 cycle: the FP32 one leaves one problem
+# in eight needing half again as many iterations), so that class holds 768.
 SERVE_CLASSES = [
     (2, 16, 1024, "f32"), (2, 32, 1024, "f32"), (2, 64, 1024, "f32"), (2, 128, 1024, "f32"),
-    (3, 16, 1024, "f32"), (3, 32, 1024, "f32"), (3, 64, 768, "f32"),
+    (3, 16, 1024, "f32"), (3, 32, 1024, "f32"), (3, 64, 768, "f64"),
 ]
 SERVE_BUDGET_FRAC = 0.8     # admission budget: this share of the slot pools' bytes
-SERVE_ITERS_PER_STEP = 8    # outer iterations of every running solve per server step
+SERVE_ITERS_PER_STEP = 16   # outer iterations of every running solve per server step
 
 
 def serve(args):
