@@ -69,7 +69,10 @@ def copy_calibration(mib):
 
 
 def flops_per_solve(dim, p, gamma, m, iters, krylov, restart):
-    """Algorithmic flop count of one solve (model stated in the design doc)."""
+    """Algorithmic flop count of one solve: per level visit the operator's
+    contractions and flux products, the line sweeps' cyclic reduction, the
+    transfers and the vector updates; per outer iteration the FP64 operator
+    and the Krylov vector work."""
     def level_costs(pl):
         n1 = pl + 1
         N = n1 ** dim
@@ -315,9 +318,9 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not "
-                          "part of this build (independent problems shard by request across "
-                          "GPUs with no collectives)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; it has no multi-GPU "
+                          "mode (independent problems shard by request across GPUs with no "
+                          "collectives)", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import numpy as np
