@@ -456,7 +456,8 @@ __device__ void apply2d_mfma(const T* __restrict__ G_, const T* __restrict__ D_,
     for (int e = threadIdx.x; e < 2 * P + 1; e += NT) {
         const int j = e <= P ? 0 : e - P, i = e <= P ? e : 0;
         T ur = 0, us = 0;
-        for (int k = 0; k < n1; ++k) {
+#pragma unroll 8
+        for (int k = 0; k < n1; ++k) {   // loads of eight terms in flight
             ur += x[j * n1 + k] * DT[k * n1 + i];
             us += D[j * n1 + k] * x[k * n1 + i];
         }
@@ -554,6 +555,7 @@ __device__ void apply3d_mfma(const T* __restrict__ G_, const T* __restrict__ D_,
         const int j = e / (2 * P + 1), tt = e % (2 * P + 1);
         const int k = tt <= P ? 0 : tt - P, i = tt <= P ? tt : 0;
         T g2 = 0;
+#pragma unroll 8
         for (int m = 0; m < n1; ++m) g2 += D[k * n1 + m] * x[i + n1 * j + S2 * m];
         F2[i + n1 * j + S2 * k] = g2;
     }
@@ -597,6 +599,7 @@ __device__ void apply3d_mfma(const T* __restrict__ G_, const T* __restrict__ D_,
         const int k = e / (2 * P + 1), tt = e % (2 * P + 1);
         const int j = tt <= P ? 0 : tt - P, i = tt <= P ? tt : 0;
         T u0 = 0, u1 = 0;
+#pragma unroll 8
         for (int m = 0; m < n1; ++m) {
             u0 += x[m + n1 * j + S2 * k] * DT[m * n1 + i];
             u1 += D[j * n1 + m] * x[i + n1 * m + S2 * k];
