@@ -225,8 +225,9 @@ typedef struct pmg_pool pmg_pool;
  * staging, right-hand side, solution and info). */
 int pmg_pool_workspace_bytes(const pmg_desc* desc, size_t* bytes);
 
-/* Create a pool in the caller's workspace; every slot starts idle.  The pool
- * keeps using `stream` for its graph; iters_per_step >= 1. */
+/* Create a pool in the caller's workspace; every slot starts idle.  With a
+ * non-null `stream` the step (one launch of the resumable solve) is captured
+ * into a graph on it here, so that steps only replay it; iters_per_step >= 1. */
 int pmg_pool_create(const pmg_desc* desc, int iters_per_step, void* d_ws, size_t ws_bytes,
                     pmg_stream_t stream, pmg_pool** out);
 
@@ -263,7 +264,12 @@ int pmg_pool_destroy(pmg_pool* pool);
  * waiting for those steps.  Fast classes are therefore not held by slow ones,
  * and the classes' kernels overlap on the device.  Admissions and launches
  * are issued class by class in decreasing per-slot footprint, so the longest
- * solves start first.  Call it repeatedly. */
+ * solves start first, and a class is admitted into only while the classes of
+ * larger footprint run fewer requests than the device holds solve
+ * workgroups at once (CUs x resident workgroups per CU): the heaviest work
+ * fills the device by itself and lighter classes use what it leaves free.
+ * The finished requests of a class are lifted into their d_u by one launch.
+ * Call it repeatedly. */
 #define PMG_SERVER_MAX_CLASSES 8
 typedef struct {
     int n_classes;

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -211,6 +212,7 @@ struct pmg_handle {
     // info, and the slot list of an admission
     bool pool = false;
     size_t o_in_coords[MAX_LEVELS], o_in_f, o_in_g, o_b, o_x, o_info, o_slots;
+    size_t o_take_slots, o_take_outs;   // slot and destination lists of a batched lift
     long long w1, w2, nv, hs;
     size_t total;
     // host copies of the tables uploaded at setup (kept alive for async copies)
@@ -294,6 +296,8 @@ void plan(pmg_handle* h)
         h->o_x = L.take(sizeof(double) * (size_t)B * f.N);
         h->o_info = L.take(sizeof(pmg_info) * (size_t)B);
         h->o_slots = L.take(sizeof(int) * (size_t)B);
+        h->o_take_slots = L.take(sizeof(int) * (size_t)B);
+        h->o_take_outs = L.take(sizeof(double*) * (size_t)B);
     }
     h->total = L.take(0) + 256;
 }
@@ -788,6 +792,8 @@ int pmg_pool_workspace_bytes(const pmg_desc* desc, size_t* bytes)
     return PMG_OK;
 }
 
+static void pool_capture(pmg_pool* P, hipStream_t s);
+
 int pmg_pool_create(const pmg_desc* desc, int iters_per_step, void* d_ws, size_t ws_bytes,
                     pmg_stream_t stream, pmg_pool** out)
 {
@@ -805,6 +811,9 @@ int pmg_pool_create(const pmg_desc* desc, int iters_per_step, void* d_ws, size_t
     pmg_pool* P = new pmg_pool();
     P->h = h;
     P->iters = iters_per_step;
+    // the step graph is captured now, so that the first step of a serving
+    // loop does not pay for its instantiation
+    if (s) pool_capture(P, s);
     *out = P;
     return PMG_OK;
 }
@@ -865,15 +874,15 @@ int pmg_pool_admit(pmg_pool* P, int n, const int* slots, const double* const* d_
     return e == hipSuccess ? PMG_OK : hip_fail(e, "admission kernels");
 }
 
-int pmg_pool_step(pmg_pool* P, pmg_stream_t stream)
+// Capture the step (one launch of the resumable solve) into a graph on
+// stream s; on failure the pool launches directly.
+static void pool_capture(pmg_pool* P, hipStream_t s)
 {
-    if (!P) return fail(PMG_EINVAL, "pool is NULL");
     pmg_handle* h = P->h;
-    hipStream_t s = (hipStream_t)stream;
     SolveArgs a = pool_solve_args(P);
     const void* H = hier_of(h, h->f32);
     hipError_t e;
-    if (s && !P->exec) {
+    {
         // capture the step once; replays reuse it
         e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
@@ -895,6 +904,17 @@ int pmg_pool_step(pmg_pool* P, pmg_stream_t stream)
         }
         (void)hipGetLastError();
     }
+}
+
+int pmg_pool_step(pmg_pool* P, pmg_stream_t stream)
+{
+    if (!P) return fail(PMG_EINVAL, "pool is NULL");
+    pmg_handle* h = P->h;
+    hipStream_t s = (hipStream_t)stream;
+    SolveArgs a = pool_solve_args(P);
+    const void* H = hier_of(h, h->f32);
+    hipError_t e;
+    if (s && !P->exec) pool_capture(P, s);
     if (P->exec)
         e = hipGraphLaunch(P->exec, s);
     else
@@ -930,6 +950,26 @@ int pmg_pool_take(pmg_pool* P, int slot, double* d_u, pmg_stream_t stream)
     return e == hipSuccess ? PMG_OK : hip_fail(e, "pool take");
 }
 
+// Lift n finished slots at once: h_slots / h_outs are pinned host arrays
+// that stay unchanged until the stream has copied them.
+static int pool_take_many(pmg_pool* P, int n, const int* h_slots, double* const* h_outs,
+                          hipStream_t s)
+{
+    pmg_handle* h = P->h;
+    if (n <= 0) return PMG_OK;
+    int* ds = (int*)(h->ws + h->o_take_slots);
+    double** dout = (double**)(h->ws + h->o_take_outs);
+    hipError_t e = hipMemcpyAsync(ds, h_slots, sizeof(int) * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dout, h_outs, sizeof(double*) * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = launch_pool_take_many(h->d.dim, h->d.p_fine, n, ds, dout,
+                                  (const double*)(h->ws + h->o_x),
+                                  (const double*)(h->ws + h->o_in_g),
+                                  (SolveState*)(h->ws + h->o_state), s);
+    return e == hipSuccess ? PMG_OK : hip_fail(e, "pool take");
+}
+
 int pmg_pool_destroy(pmg_pool* P)
 {
     if (!P) return PMG_OK;
@@ -959,6 +999,7 @@ struct pmg_server {
         pmg_pool* pool = nullptr;
         hipStream_t stream = nullptr;
         size_t footprint = 0;        // bytes per slot
+        int resident = 0;            // solve workgroups the device holds at once
         std::vector<long long> slot_req;   // ticket per slot, -1 free
         int running = 0;
         int nlev = 0;
@@ -968,6 +1009,8 @@ struct pmg_server {
         hipEvent_t done = nullptr;
         SolveState* hst = nullptr;
         pmg_info* hinfo = nullptr;
+        int* htake = nullptr;          // pinned slot / destination lists of a lift
+        double** hout = nullptr;
     };
     Class cls[PMG_SERVER_MAX_CLASSES];
     std::vector<Req> reqs;           // indexed by ticket
@@ -1038,6 +1081,10 @@ int pmg_server_create(const pmg_server_desc* d, void* d_ws, size_t ws_bytes, pmg
             (e = hipHostMalloc((void**)&C.hst, sizeof(SolveState) * B, hipHostMallocDefault)) !=
                 hipSuccess ||
             (e = hipHostMalloc((void**)&C.hinfo, sizeof(pmg_info) * B, hipHostMallocDefault)) !=
+                hipSuccess ||
+            (e = hipHostMalloc((void**)&C.htake, sizeof(int) * B, hipHostMallocDefault)) !=
+                hipSuccess ||
+            (e = hipHostMalloc((void**)&C.hout, sizeof(double*) * B, hipHostMallocDefault)) !=
                 hipSuccess) {
             pmg_server_destroy(S);
             return hip_fail(e, "server host buffers");
@@ -1045,6 +1092,20 @@ int pmg_server_create(const pmg_server_desc* d, void* d_ws, size_t ws_bytes, pmg
         C.footprint = b / d->classes[c].batch;
         C.slot_req.assign(d->classes[c].batch, -1);
         C.nlev = ilog2(d->classes[c].p_fine);
+    }
+    // resident solve workgroups per class: CUs x workgroups per CU
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 0;
+        for (int c = 0; c < d->n_classes; ++c) {
+            const pmg_desc& cd = d->classes[c];
+            const int per = cd.inner_prec == PMG_F32 ? solve_blocks_per_cu_f32(cd.dim, cd.p_fine)
+                                                     : solve_blocks_per_cu_f64(cd.dim, cd.p_fine);
+            S->cls[c].resident = cus > 0 && per > 0 ? cus * per : INT_MAX;
+        }
+        (void)hipGetLastError();
     }
     // the heaviest problems are the longest single solves: their admissions
     // and steps are issued first so that they start first on the device
@@ -1087,12 +1148,15 @@ static int server_retire(pmg_server* S, pmg_server::Class& C, int* done)
         const int st = C.hst[b].status;
         if (st == ST_RUNNING || st == ST_IDLE) continue;
         pmg_server::Req& r = S->reqs[C.slot_req[b]];
-        if ((rc = pmg_pool_take(C.pool, b, r.u, (pmg_stream_t)C.stream))) return rc;
+        C.htake[taken.size()] = b;
+        C.hout[taken.size()] = r.u;
         r.info = C.hinfo[b];
         r.info.status = st;
         taken.push_back(b);
     }
     if (taken.empty()) return PMG_OK;
+    // one launch lifts every finished slot of the class
+    if ((rc = pool_take_many(C.pool, (int)taken.size(), C.htake, C.hout, C.stream))) return rc;
     hipError_t e = hipStreamSynchronize(C.stream);   // only the lifts are queued
     if (e != hipSuccess) return hip_fail(e, "server retire");
     for (int b : taken) {
@@ -1137,7 +1201,12 @@ int pmg_server_step(pmg_server* S, int* n_done)
         std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
     // 2. admissions in arrival order into idle classes, within slots and the
-    //    byte budget (a request of a class whose step is in flight waits)
+    //    byte budget (a request of a class whose step is in flight waits).
+    //    A class is admitted into only while the classes of larger
+    //    footprint run fewer requests than the device holds solve
+    //    workgroups at once: the heaviest work fills the device by itself
+    //    (no other class's working set in the caches beside it), lighter
+    //    classes fill what it leaves free.
     std::vector<std::vector<int>> slots(nc);
     std::vector<std::vector<const double*>> coords(nc), fs(nc), gs(nc);
     std::vector<long long> keep;
@@ -1145,7 +1214,12 @@ int pmg_server_step(pmg_server* S, int* n_done)
         pmg_server::Req& r = S->reqs[t];
         pmg_server::Class& C = S->cls[r.cls];
         int free_slot = -1;
-        if (!C.inflight && S->in_use + C.footprint <= S->d.budget_bytes) {
+        int heavier = 0;
+        for (int k : S->order) {
+            if (k == r.cls) break;
+            heavier += S->cls[k].running;
+        }
+        if (!C.inflight && S->in_use + C.footprint <= S->d.budget_bytes && heavier < C.resident) {
             for (int b = 0; b < (int)C.slot_req.size(); ++b)
                 if (C.slot_req[b] < 0) { free_slot = b; break; }
         }
@@ -1230,6 +1304,8 @@ int pmg_server_destroy(pmg_server* S)
         if (C.done) hipEventDestroy(C.done);
         if (C.hst) hipHostFree(C.hst);
         if (C.hinfo) hipHostFree(C.hinfo);
+        if (C.htake) hipHostFree(C.htake);
+        if (C.hout) hipHostFree(C.hout);
         if (C.stream) hipStreamDestroy(C.stream);
     }
     delete S;

@@ -87,6 +87,9 @@ hipError_t launch_solve_f64(int dim, int p, bool f32, int B, const void* H, cons
                             hipStream_t s);
 hipError_t launch_solve_f32(int dim, int p, bool f32, int B, const void* H, const SolveArgs& a,
                             hipStream_t s);
+// resident workgroups per CU of the solve kernel (0 if unknown)
+int solve_blocks_per_cu_f64(int dim, int p);
+int solve_blocks_per_cu_f32(int dim, int p);
 inline hipError_t launch_solve(int dim, int p, bool f32, int B, const void* H, const SolveArgs& a,
                                hipStream_t s)
 {
@@ -97,6 +100,8 @@ hipError_t launch_pool_start(const int* slots, int n, const int* sstatus, SolveS
 hipError_t launch_pool_idle(SolveState* st, int B, hipStream_t s);
 hipError_t launch_pool_take(int dim, int p, int slot, const double* w, const double* g, double* u,
                             SolveState* st, hipStream_t s);
+hipError_t launch_pool_take_many(int dim, int p, int n, const int* slots, double* const* outs,
+                                 const double* w, const double* g, SolveState* st, hipStream_t s);
 hipError_t launch_line_coefs(int dim, int p, int B, const Hier<double>* H64, int smoother,
                              int dir, double* lo, double* di, double* up, hipStream_t s);
 

@@ -668,6 +668,21 @@ __global__ void __launch_bounds__(NT) k_pool_take(int slot, const double* __rest
     if (threadIdx.x == 0) st[b].status = ST_IDLE;
 }
 
+// The same for n slots at once: workgroup i lifts slot slots[i] into outs[i].
+template <int P, int DIM>
+__global__ void __launch_bounds__(NT) k_pool_take_many(const int* __restrict__ slots,
+                                                       double* const* __restrict__ outs,
+                                                       const double* __restrict__ w,
+                                                       const double* __restrict__ g, SolveState* st)
+{
+    constexpr int N = Shape<P, DIM>::N;
+    const long long b = slots[blockIdx.x];
+    double* u = outs[blockIdx.x];
+    for (int q = threadIdx.x; q < N; q += NT)
+        u[q] = is_boundary<P, DIM>(q) ? g[b * N + q] : w[b * N + q];
+    if (threadIdx.x == 0) st[b].status = ST_IDLE;
+}
+
 hipError_t launch_setup(int dim, int p_fine, int nlev, int B, const SetupArgs& a, pmg_info* info,
                         hipStream_t s)
 {
@@ -740,6 +755,15 @@ hipError_t launch_pool_take(int dim, int p, int slot, const double* w, const dou
 {
     PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_pool_take<P_, D_>), dim3(1), dim3(NT), 0, s, slot,
                                                w, g, u, st));
+    return last();
+}
+
+hipError_t launch_pool_take_many(int dim, int p, int n, const int* slots, double* const* outs,
+                                 const double* w, const double* g, SolveState* st, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_pool_take_many<P_, D_>), dim3(n), dim3(NT), 0, s,
+                                               slots, outs, w, g, st));
     return last();
 }
 

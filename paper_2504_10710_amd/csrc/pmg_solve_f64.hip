@@ -12,4 +12,12 @@ hipError_t launch_solve_f64(int dim, int p, bool f32, int B, const void* H, cons
     return last();
 }
 
+int solve_blocks_per_cu_f64(int dim, int p)
+{
+    int nb = 0;
+    PMG_DISPATCH_P(dim, p, (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                               &nb, k_solve<double, P_, D_>, NT, 0));
+    return nb;
+}
+
 }  // namespace pmg
