@@ -213,6 +213,7 @@ struct pmg_handle {
     bool pool = false;
     size_t o_in_coords[MAX_LEVELS], o_in_f, o_in_g, o_b, o_x, o_info, o_slots;
     size_t o_take_slots, o_take_outs;   // slot and destination lists of a batched lift
+    size_t o_jobs;                      // copy jobs of an admission (inputs into slots)
     long long w1, w2, nv, hs;
     size_t total;
     // host copies of the tables uploaded at setup (kept alive for async copies)
@@ -298,6 +299,7 @@ void plan(pmg_handle* h)
         h->o_slots = L.take(sizeof(int) * (size_t)B);
         h->o_take_slots = L.take(sizeof(int) * (size_t)B);
         h->o_take_outs = L.take(sizeof(double*) * (size_t)B);
+        h->o_jobs = L.take(sizeof(CopyJob) * (size_t)B * (h->nlev + 2));
     }
     h->total = L.take(0) + 256;
 }
@@ -746,10 +748,11 @@ int pmg_destroy(pmg_handle* h)
 struct pmg_pool {
     pmg_handle* h = nullptr;
     int iters = 1;
+    CopyJob* hjobs = nullptr;   // pinned staging of an admission's copy jobs
+    int* hslots = nullptr;      // pinned staging of an admission's slot list
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t graph_stream = nullptr;
-    std::vector<std::vector<int>> pending;   // slot lists whose async upload may be in flight
 };
 
 static SolveArgs pool_solve_args(pmg_pool* P)
@@ -811,6 +814,14 @@ int pmg_pool_create(const pmg_desc* desc, int iters_per_step, void* d_ws, size_t
     pmg_pool* P = new pmg_pool();
     P->h = h;
     P->iters = iters_per_step;
+    const size_t njobs = (size_t)desc->batch * (h->nlev + 2);
+    if ((e = hipHostMalloc((void**)&P->hjobs, sizeof(CopyJob) * njobs, hipHostMallocDefault)) !=
+            hipSuccess ||
+        (e = hipHostMalloc((void**)&P->hslots, sizeof(int) * desc->batch, hipHostMallocDefault)) !=
+            hipSuccess) {
+        pmg_pool_destroy(P);
+        return hip_fail(e, "pool staging");
+    }
     // the step graph is captured now, so that the first step of a serving
     // loop does not pay for its instantiation
     if (s) pool_capture(P, s);
@@ -829,30 +840,32 @@ int pmg_pool_admit(pmg_pool* P, int n, const int* slots, const double* const* d_
         return fail(PMG_EINVAL, "bad admission arguments");
     hipStream_t s = (hipStream_t)stream;
     const int N = level_shape(dim, h->nlev - 1).N;
-    hipError_t e = hipSuccess;
-    for (int i = 0; i < n && e == hipSuccess; ++i) {
+    // the copies of every admitted request (coordinates per level, f, g)
+    // into their slots' staging, as one launch of copy jobs; the pinned
+    // staging is free again because every admission ends with a
+    // synchronisation of its stream
+    int nj = 0;
+    for (int i = 0; i < n; ++i) {
         const int b = slots[i];
         if (b < 0 || b >= B) return fail(PMG_EINVAL, "slot %d out of range", b);
-        for (int l = 0; l < h->nlev && e == hipSuccess; ++l) {
-            const size_t bytes = sizeof(double) * dim * level_shape(dim, l).N;
-            if (!d_coords[(size_t)i * h->nlev + l]) return fail(PMG_EINVAL, "NULL coordinates");
-            e = hipMemcpyAsync(h->ws + h->o_in_coords[l] + bytes * b, d_coords[(size_t)i * h->nlev + l],
-                               bytes, hipMemcpyDeviceToDevice, s);
+        for (int l = 0; l < h->nlev; ++l) {
+            const long long cnt = (long long)dim * level_shape(dim, l).N;
+            const double* src = d_coords[(size_t)i * h->nlev + l];
+            if (!src) return fail(PMG_EINVAL, "NULL coordinates");
+            P->hjobs[nj++] = {src, (double*)(h->ws + h->o_in_coords[l]) + cnt * b, cnt};
         }
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(h->ws + h->o_in_f + sizeof(double) * N * b, d_f[i], sizeof(double) * N,
-                               hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(h->ws + h->o_in_g + sizeof(double) * N * b, d_g[i], sizeof(double) * N,
-                               hipMemcpyDeviceToDevice, s);
+        if (!d_f[i] || !d_g[i]) return fail(PMG_EINVAL, "NULL right-hand side or boundary data");
+        P->hjobs[nj++] = {d_f[i], (double*)(h->ws + h->o_in_f) + (long long)N * b, N};
+        P->hjobs[nj++] = {d_g[i], (double*)(h->ws + h->o_in_g) + (long long)N * b, N};
+        P->hslots[i] = b;
     }
+    CopyJob* djobs = (CopyJob*)(h->ws + h->o_jobs);
+    hipError_t e = hipMemcpyAsync(djobs, P->hjobs, sizeof(CopyJob) * nj, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_copy_jobs(nj, djobs, s);
     if (e != hipSuccess) return hip_fail(e, "admission copies");
-    P->pending.emplace_back(slots, slots + n);
-    const int* hs = P->pending.back().data();
     int* dslots = (int*)(h->ws + h->o_slots);
-    // each admission gets its own span of the device slot list
     static_assert(sizeof(int) == 4, "int");
-    e = hipMemcpyAsync(dslots, hs, sizeof(int) * n, hipMemcpyHostToDevice, s);
+    e = hipMemcpyAsync(dslots, P->hslots, sizeof(int) * n, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "slot list upload");
     SetupArgs a;
     setup_args(h, a);
@@ -868,9 +881,8 @@ int pmg_pool_admit(pmg_pool* P, int n, const int* slots, const double* const* d_
     if (e == hipSuccess)
         e = launch_pool_start(dslots, n, (const int*)(h->ws + h->o_sstatus),
                               (SolveState*)(h->ws + h->o_state), info, s);
-    // the slot list is read by the kernels above before any later upload
+    // the staging and the device slot list are reused by the next admission
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    P->pending.clear();
     return e == hipSuccess ? PMG_OK : hip_fail(e, "admission kernels");
 }
 
@@ -975,6 +987,8 @@ int pmg_pool_destroy(pmg_pool* P)
     if (!P) return PMG_OK;
     if (P->exec) hipGraphExecDestroy(P->exec);
     if (P->graph) hipGraphDestroy(P->graph);
+    if (P->hjobs) (void)hipHostFree(P->hjobs);
+    if (P->hslots) (void)hipHostFree(P->hslots);
     delete P->h;
     delete P;
     return PMG_OK;

@@ -102,6 +102,13 @@ hipError_t launch_pool_take(int dim, int p, int slot, const double* w, const dou
                             SolveState* st, hipStream_t s);
 hipError_t launch_pool_take_many(int dim, int p, int n, const int* slots, double* const* outs,
                                  const double* w, const double* g, SolveState* st, hipStream_t s);
+// one contiguous copy of n doubles; a batch of them runs as one launch
+struct CopyJob {
+    const double* src;
+    double* dst;
+    long long n;
+};
+hipError_t launch_copy_jobs(int n, const CopyJob* jobs, hipStream_t s);
 hipError_t launch_line_coefs(int dim, int p, int B, const Hier<double>* H64, int smoother,
                              int dir, double* lo, double* di, double* up, hipStream_t s);
 

@@ -758,6 +758,22 @@ hipError_t launch_pool_take(int dim, int p, int slot, const double* w, const dou
     return last();
 }
 
+// Workgroup i performs copy job i.
+__global__ void __launch_bounds__(NT) k_copy_jobs(const CopyJob* __restrict__ jobs)
+{
+    const CopyJob j = jobs[blockIdx.x];
+    const auto src = gmem(j.src);
+    const auto dst = gmem(j.dst);
+    for (long long q = threadIdx.x; q < j.n; q += NT) dst[q] = src[q];
+}
+
+hipError_t launch_copy_jobs(int n, const CopyJob* jobs, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_jobs, dim3(n), dim3(NT), 0, s, jobs);
+    return last();
+}
+
 hipError_t launch_pool_take_many(int dim, int p, int n, const int* slots, double* const* outs,
                                  const double* w, const double* g, SolveState* st, hipStream_t s)
 {
