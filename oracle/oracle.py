@@ -51,8 +51,12 @@ def lib():
             "or_thomas": (ctypes.c_int, [ctypes.c_int, _D, _D, _D, _D, _D]),
             "or_dense_solve": (ctypes.c_int, [ctypes.c_int, _D, _D]),
             "or_cr_coarse": (None, [ctypes.c_int, _D, _D, _D, _D, _D, _D]),
+            "or_bcr_solve": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _D, _D, _D, _D, _D]),
+            "or_bcr_coarse": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _D, _D, _D, _D, _D, _D]),
             "or_hier_create": (vp, [ctypes.c_int, ctypes.c_int, _I, ctypes.POINTER(_D),
-                                    ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int]),
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                    ctypes.c_int]),
+            "or_line_band": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, _D]),
             "or_hier_destroy": (None, [vp]),
             "or_nodes": (ctypes.c_int, [vp, ctypes.c_int]),
             "or_geom": (ctypes.c_double, [vp, ctypes.c_int, _D, _D]),
@@ -158,6 +162,36 @@ def cr_coarse(l, a, u):
     return l0, a0, u0
 
 
+def bcr_solve(Lb, Ab, Ub, g):
+    """Block cyclic reduction: Lb, Ab, Ub are (nb, m, m), g is (nb*m,)."""
+    Ab = np.ascontiguousarray(Ab, dtype=np.float64)
+    nb, m, _ = Ab.shape
+    Lb = np.ascontiguousarray(Lb, dtype=np.float64)
+    Ub = np.ascontiguousarray(Ub, dtype=np.float64)
+    g = _f64(g)
+    y = np.zeros(nb * m)
+    if lib().or_bcr_solve(nb, m, _p(Lb), _p(Ab), _p(Ub), _p(g), _p(y)) != 0:
+        raise ZeroDivisionError("singular block in block cyclic reduction")
+    return y
+
+
+def bcr_coarse(Lb, Ab, Ub):
+    Ab = np.ascontiguousarray(Ab, dtype=np.float64)
+    nb, m, _ = Ab.shape
+    Lb = np.ascontiguousarray(Lb, dtype=np.float64)
+    Ub = np.ascontiguousarray(Ub, dtype=np.float64)
+    nc = nb // 2
+    L0, A0, U0 = (np.zeros((nc, m, m)) for _ in range(3))
+    if lib().or_bcr_coarse(nb, m, _p(Lb), _p(Ab), _p(Ub), _p(L0), _p(A0), _p(U0)) != 0:
+        raise ZeroDivisionError("singular block")
+    return L0, A0, U0
+
+
+# line-system and restriction choices of the hierarchy (pmg_oracle.h)
+SMOOTHER_GLL, SMOOTHER_FEM, SMOOTHER_GLL_BAND2, SMOOTHER_GLL_FULL = 0, 1, 2, 3
+RESTRICT_TRANSPOSE, RESTRICT_INTERP = 0, 1
+
+
 # ---------------------------------------------------------------- hierarchy
 
 class Hier:
@@ -167,7 +201,8 @@ class Hier:
     (dim, N_l) array of physical node positions of level l.
     """
 
-    def __init__(self, dim, plist, coords, gamma=7, m=1, alpha=2.0 / 3.0, smoother=0):
+    def __init__(self, dim, plist, coords, gamma=7, m=1, alpha=2.0 / 3.0, smoother=0,
+                 restriction=RESTRICT_TRANSPOSE):
         self.dim = int(dim)
         self.plist = [int(p) for p in plist]
         self.nlev = len(self.plist)
@@ -175,10 +210,11 @@ class Hier:
         cp = (_D * self.nlev)(*[_p(c) for c in self._coords])
         pl = (ctypes.c_int * self.nlev)(*self.plist)
         self.h = lib().or_hier_create(self.dim, self.nlev, pl, cp, int(gamma), int(m),
-                                      float(alpha), int(smoother))
+                                      float(alpha), int(smoother), int(restriction))
         if not self.h:
             raise ValueError("or_hier_create failed (bad arguments or det J <= 0)")
         self.gamma, self.m, self.alpha = gamma, m, alpha
+        self.smoother, self.restriction = int(smoother), int(restriction)
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -243,6 +279,15 @@ class Hier:
         lo, di, up = np.zeros(n), np.zeros(n), np.zeros(n)
         lib().or_line_coefs(self.h, l, dir, _p(lo), _p(di), _p(up))
         return lo, di, up
+
+    def line_band(self, dir, l=-1):
+        """Half-bandwidth-2 line entries (lines, n, 5) of the band-2 smoother."""
+        l = l % self.nlev
+        n = self.plist[l] - 1
+        out = np.zeros(n ** self.dim * 5)
+        if lib().or_line_band(self.h, l, dir, _p(out)) != 0:
+            raise ValueError("hierarchy has no banded line systems")
+        return out.reshape(n ** (self.dim - 1), n, 5)
 
     def line_solve(self, r, dir, l=-1):
         l = l % self.nlev

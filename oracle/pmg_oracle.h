@@ -72,21 +72,44 @@ int or_dense_solve(int n, double* A, double* g);
 void or_cr_coarse(int n, const double* l, const double* a, const double* u,
                   double* l0, double* a0, double* u0);
 
+/* Block-tridiagonal M (Def. block-tridiagonal matrix) of nb blocks of size
+ * m x m: Lb, Ab, Ub hold nb row-major m x m blocks each (Lb[0] and Ub[nb-1]
+ * are ignored).  Solves M y = g by the direct multigrid of Thm. "Two-level
+ * direct solver" with block operators (S^{-1} = blockdiag(A_F^{-1}), P with
+ * F rows -A_F^{-1}(L_F, U_F), R = P^T, M0 = D - C A^{-1} B as in the proof
+ * of Prop. "line coarse space"), applied recursively; one block is a dense
+ * solve.  g and y hold nb*m values.  Returns 0, or -1 on a singular block. */
+int or_bcr_solve(int nb, int m, const double* Lb, const double* Ab, const double* Ub,
+                 const double* g, double* y);
+
+/* One level of the block solver, exposed for pins: the coarse blocks of
+ * M0 = D - C A^{-1} B (nb/2 blocks, integer division). */
+int or_bcr_coarse(int nb, int m, const double* Lb, const double* Ab, const double* Ub,
+                  double* L0, double* A0, double* U0);
+
 /* ---- the hierarchy: discretisation, smoother, gamma-cycle ---- */
+
+/* Line systems of the smoother (Def. line preconditioners). */
+#define OR_SMOOTHER_GLL 0       /* [A_l]^(1) on the line: tridiagonal, scalar CR */
+#define OR_SMOOTHER_FEM 1       /* bilinear / trilinear FEM matrix on the GLL mesh */
+#define OR_SMOOTHER_GLL_BAND2 2 /* [A_l]^(2) on the line: 2x2-block tridiagonal, block CR */
+#define OR_SMOOTHER_GLL_FULL 3  /* the whole line block R A_l P (dense LU) */
+
+/* Restriction of Sec. 3.3. */
+#define OR_RESTRICT_TRANSPOSE 0 /* R_l = P_l^T */
+#define OR_RESTRICT_INTERP 1    /* R_l = interpolation of the fine polynomial at the coarse nodes */
 
 typedef struct or_hier or_hier;
 
 /* dim = 2 or 3; p[0..nlev-1] ascending degrees (p[0] is the coarsest level);
  * coords[l] holds dim*N_l doubles (all first coordinates, then all second,
- * ...), the physical positions of the level-l GLL nodes.  smoother = 0
- * selects the GLL line systems (Def. line preconditioners with A_p);
- * smoother = 1 the bilinear (2-D) / trilinear (3-D) finite-element line
- * systems (A~_p on the GLL node mesh).
+ * ...), the physical positions of the level-l GLL nodes.  smoother is one
+ * of OR_SMOOTHER_*, restriction one of OR_RESTRICT_*.
  * Returns NULL on bad arguments, non-positive Jacobian, or a failed coarse
  * factorisation. */
 or_hier* or_hier_create(int dim, int nlev, const int* p,
                         const double* const* coords,
-                        int gamma, int m, double alpha, int smoother);
+                        int gamma, int m, double alpha, int smoother, int restriction);
 void or_hier_destroy(or_hier* h);
 
 /* Number of nodes of level l. */
@@ -121,7 +144,9 @@ int or_dense_interior(const or_hier* h, int l, double* A);
  * boundary nodes and 0 inside. */
 void or_rhs(const or_hier* h, const double* f, const double* g, double* b);
 
-/* rc = R_l rf (level l -> l-1), R_l = P_l^T; coarse boundary set to 0. */
+/* rc = R_l rf (level l -> l-1), R_l = P_l^T or the interpolation of the
+ * fine polynomial at the coarse nodes (the hierarchy's restriction mode);
+ * coarse boundary set to 0. */
 void or_restrict(const or_hier* h, int l, const double* rf, double* rc);
 /* xf += P_l ec (level l-1 -> l). */
 void or_prolong_add(const or_hier* h, int l, const double* ec, double* xf);
@@ -133,8 +158,15 @@ void or_prolong_add(const or_hier* h, int l, const double* ec, double* xf);
 void or_line_coefs(const or_hier* h, int l, int dir,
                    double* lo, double* di, double* up);
 
-/* z = B_{l,dir}^{-1} r (block-Jacobi over lines, each line by or_cr_solve);
- * boundary entries of z are 0. */
+/* Banded line systems of the OR_SMOOTHER_GLL_BAND2 smoother: for every line
+ * (ordered as in or_line_coefs) and position s = 0..n-1, the entries
+ * [A_l]_{s, s+k} for k = -2..2 (zero outside the line), 5 per position:
+ * band[(line*n + s)*5 + k + 2].  Returns -1 if the hierarchy has another
+ * smoother. */
+int or_line_band(const or_hier* h, int l, int dir, double* band);
+
+/* z = B_{l,dir}^{-1} r (block-Jacobi over lines, each line by or_cr_solve,
+ * or_bcr_solve or a dense solve, by smoother); boundary entries of z are 0. */
 int or_line_solve(const or_hier* h, int l, int dir, const double* r, double* z);
 
 /* One smoothing step x <- x + alpha B_{l,dir}^{-1} (r - A_l x). */

@@ -32,10 +32,11 @@ def gpu_batch(probs, p_fine, device="cuda", **desc_kw):
     return s, f, g
 
 
-def oracle_of(prob, p_fine, gamma=1, m=1, alpha=0.16, smoother=1):
+def oracle_of(prob, p_fine, gamma=1, m=1, alpha=0.16, smoother=1, restriction=0):
     ps = inputs.halving_degrees(p_fine, 2)
     coords = [prob.coords(orc.gll(p)[0]) for p in ps]
-    h = orc.Hier(prob.dim, ps, coords, gamma=gamma, m=m, alpha=alpha, smoother=smoother)
+    h = orc.Hier(prob.dim, ps, coords, gamma=gamma, m=m, alpha=alpha, smoother=smoother,
+                 restriction=restriction)
     X = coords[-1]
     return h, prob.f(X), prob.g(X)
 

@@ -5,10 +5,12 @@ from oracle import oracle as orc
 from paper_2504_10710_amd import inputs
 
 
-def oracle_hier(problem, p_fine, p_coarse=2, gamma=1, m=1, alpha=2.0 / 3.0, smoother=0):
+def oracle_hier(problem, p_fine, p_coarse=2, gamma=1, m=1, alpha=2.0 / 3.0, smoother=0,
+                restriction=orc.RESTRICT_TRANSPOSE):
     ps = inputs.halving_degrees(p_fine, p_coarse)
     coords = [problem.coords(orc.gll(p)[0]) for p in ps]
-    h = orc.Hier(problem.dim, ps, coords, gamma=gamma, m=m, alpha=alpha, smoother=smoother)
+    h = orc.Hier(problem.dim, ps, coords, gamma=gamma, m=m, alpha=alpha, smoother=smoother,
+                 restriction=restriction)
     return h, ps, coords
 
 

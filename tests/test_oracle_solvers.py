@@ -307,3 +307,143 @@ def test_fem_entries():
     np.testing.assert_allclose(di[k], A[node, node], rtol=1e-14)
     np.testing.assert_allclose(lo[k], A[node, node - 1], rtol=1e-14)
     np.testing.assert_allclose(up[k], A[node, node + 1], rtol=1e-14)
+
+
+# ---------------------------------------------------------------- block CR
+
+def _random_blocks(rng, nb, m, kind):
+    Lb = rng.standard_normal((nb, m, m))
+    Ub = rng.standard_normal((nb, m, m))
+    if kind == "spd":
+        # symmetric: L_{i+1} = U_i^T, diagonal blocks dominant
+        for i in range(nb - 1):
+            Lb[i + 1] = Ub[i].T
+    Ab = np.empty((nb, m, m))
+    for i in range(nb):
+        S = rng.standard_normal((m, m))
+        Ab[i] = S @ S.T + (2.5 * m + 1.0) * np.eye(m)
+    Lb[0] = 0.0
+    Ub[-1] = 0.0
+    return Lb, Ab, Ub
+
+
+def _dense_blocks(Lb, Ab, Ub):
+    nb, m, _ = Ab.shape
+    M = np.zeros((nb * m, nb * m))
+    for i in range(nb):
+        M[i * m:(i + 1) * m, i * m:(i + 1) * m] = Ab[i]
+        if i > 0:
+            M[i * m:(i + 1) * m, (i - 1) * m:i * m] = Lb[i]
+        if i + 1 < nb:
+            M[i * m:(i + 1) * m, (i + 1) * m:(i + 2) * m] = Ub[i]
+    return M
+
+
+@pytest.mark.parametrize("m", [1, 2, 3])
+@pytest.mark.parametrize("nb", [1, 2, 3, 4, 5, 7, 8, 16, 31, 32, 64])
+@pytest.mark.parametrize("kind", ["spd", "general"])
+def test_block_cr_equals_dense_lu(m, nb, kind):
+    """Thm. two-level direct solver with m x m blocks, applied recursively
+    (Cor. direct multigrid): one pass solves M y = g exactly (to rounding)."""
+    rng = np.random.default_rng(100 * nb + 10 * m + (kind == "spd"))
+    Lb, Ab, Ub = _random_blocks(rng, nb, m, kind)
+    M = _dense_blocks(Lb, Ab, Ub)
+    g = rng.standard_normal(nb * m)
+    ref = np.linalg.solve(M, g)
+    y = orc.bcr_solve(Lb, Ab, Ub, g)
+    y_lu = orc.dense_solve(M, g)
+    tol = 50 * nb * m * np.linalg.cond(M) * np.finfo(float).eps * np.abs(ref).max()
+    assert np.abs(y - ref).max() <= tol
+    assert np.abs(y_lu - ref).max() <= tol
+
+
+def test_block_cr_m1_is_scalar_cr():
+    rng = np.random.default_rng(9)
+    n = 37
+    l, a, u = _random_line(rng, n, "general")
+    g = rng.standard_normal(n)
+    y = orc.bcr_solve(l.reshape(n, 1, 1), a.reshape(n, 1, 1), u.reshape(n, 1, 1), g)
+    np.testing.assert_allclose(y, orc.cr_solve(l, a, u, g), rtol=0, atol=1e-14 * np.abs(y).max())
+
+
+@pytest.mark.parametrize("m", [2, 3])
+@pytest.mark.parametrize("nb", [2, 3, 6, 9])
+def test_block_cr_coarse_is_schur_complement(m, nb):
+    """Prop. line coarse space with blocks: after the odd-even block
+    reordering, D - C A^{-1} B is block-tridiagonal and equals the oracle's
+    coarse blocks (the proof's middle term)."""
+    rng = np.random.default_rng(nb * 7 + m)
+    Lb, Ab, Ub = _random_blocks(rng, nb, m, "general")
+    M = _dense_blocks(Lb, Ab, Ub)
+    F = np.concatenate([np.arange(i * m, (i + 1) * m) for i in range(0, nb, 2)])
+    C = np.concatenate([np.arange(i * m, (i + 1) * m) for i in range(1, nb, 2)])
+    S = M[np.ix_(C, C)] - M[np.ix_(C, F)] @ np.linalg.solve(M[np.ix_(F, F)], M[np.ix_(F, C)])
+    L0, A0, U0 = orc.bcr_coarse(Lb, Ab, Ub)
+    np.testing.assert_allclose(_dense_blocks(L0, A0, U0), S, atol=1e-12 * np.abs(S).max())
+
+
+@pytest.mark.parametrize("dim,p", [(2, 8), (2, 16), (3, 8)])
+def test_band2_line_systems_are_entries_of_A_and_are_inverted(dim, p):
+    """GLL half-bandwidth-2 line systems: every band entry is an entry of A,
+    and the line solve inverts the assembled banded line matrices
+    (B_dir^{-1} (T_dir e) = e)."""
+    prob = inputs.config2(5) if dim == 2 else inputs.config3(5)
+    h, ps, coords = oracle_hier(prob, p, p_coarse=p, smoother=orc.SMOOTHER_GLL_BAND2)
+    n, n1 = p - 1, p + 1
+    mask = interior_mask(dim, p)
+    rng = np.random.default_rng(1)
+    e = np.where(mask, rng.standard_normal(n1 ** dim), 0.0)
+    for d in range(dim):
+        band = h.line_band(d)
+        st = n1 ** d
+        Te = np.zeros_like(e)
+        for line in range(n ** (dim - 1)):
+            c = [0] * dim
+            t = line
+            for a in range(dim):
+                if a == d:
+                    continue
+                c[a] = 1 + t % n
+                t //= n
+            base = sum(ci * n1 ** a for a, ci in enumerate(c) if a != d)
+            nodes = base + st * np.arange(1, p)
+            for s in range(n):
+                for k in range(-2, 3):
+                    if 0 <= s + k < n:
+                        v = band[line, s, k + 2]
+                        if line < 3 and s < 4:
+                            np.testing.assert_allclose(v, h.entry(nodes[s], nodes[s + k]), rtol=1e-14)
+                        Te[nodes[s]] += v * e[nodes[s + k]]
+                    else:
+                        assert band[line, s, k + 2] == 0.0
+        np.testing.assert_allclose(h.line_solve(Te, d), e, atol=1e-10)
+
+
+@pytest.mark.parametrize("dim,pc,pf", [(2, 4, 8), (2, 16, 32), (3, 4, 8)])
+def test_interpolation_restriction_evaluates_fine_polynomial(dim, pc, pf):
+    """Sec. 3.3, restriction as interpolation: the fine nodal values of a
+    polynomial of degree <= p_f per variable restrict to its values at the
+    coarse interior nodes (exactly, up to rounding), and restricting a
+    prolongated coarse vector returns it (R P = I on the interior)."""
+    prob = inputs.config2(1) if dim == 2 else inputs.config3(1)
+    h, ps, coords = oracle_hier(prob, pf, p_coarse=pc, restriction=orc.RESTRICT_INTERP)
+    xf = orc.gll(pf)[0]
+    xc = orc.gll(pc)[0]
+    rng = np.random.default_rng(3)
+    cf = [rng.standard_normal(pf + 1) for _ in range(dim)]
+
+    def poly(nodes):
+        vals = [np.polynomial.polynomial.polyval(nodes, c) for c in cf]
+        out = vals[0]
+        for v in vals[1:]:
+            out = np.multiply.outer(v, out)   # first axis fastest in the flattening
+        return out.reshape(-1)
+
+    mc = interior_mask(dim, pc)
+    rc = h.restrict(poly(xf))
+    ref = poly(xc)
+    np.testing.assert_allclose(rc[mc], ref[mc], rtol=0, atol=1e-11 * np.abs(ref).max())
+    assert np.all(rc[~mc] == 0.0)
+    ec = np.where(mc, rng.standard_normal((pc + 1) ** dim), 0.0)
+    back = h.restrict(h.prolong_add(ec, np.zeros((pf + 1) ** dim)))
+    np.testing.assert_allclose(back, ec, atol=1e-12)
