@@ -83,29 +83,30 @@ int or_gll(int p, double* xi, double* rho)
 }
 
 /* Def. GLL interpolation basis: pi_j(x) = prod_{k != j} (x - xi_k) / (xi_j - xi_k).
- * Its derivative at a node, written out from the product rule:
- *   i != j : pi_j'(xi_i) = prod_{k != i,j} (xi_i - xi_k) / prod_{k != j} (xi_j - xi_k)
- *   i == j : pi_j'(xi_j) = sum_{k != j} 1 / (xi_j - xi_k). */
+ * Its derivative at another node, written out from the product rule:
+ *   i != j : pi_j'(xi_i) = prod_{k != i,j} (xi_i - xi_k) / prod_{k != j} (xi_j - xi_k).
+ * The basis is a partition of unity (sum_j pi_j = 1, the interpolant of the
+ * constant 1), so sum_j pi_j'(xi_i) = 0 at every node, and the diagonal entry
+ * is taken from that identity: pi_i'(xi_i) = -sum_{j != i} pi_j'(xi_i).  (The
+ * product rule's sum_{k != i} 1/(xi_i - xi_k) is the same number in exact
+ * arithmetic, but at interior GLL nodes it cancels to zero from terms of
+ * size up to p^2 and keeps a rounding error of that size.) */
 void or_deriv(int p, const double* xi, double* D)
 {
     int n1 = p + 1;
     for (int i = 0; i < n1; ++i) {
+        double rowsum = 0.0;
         for (int j = 0; j < n1; ++j) {
-            double v;
-            if (i == j) {
-                v = 0.0;
-                for (int k = 0; k < n1; ++k)
-                    if (k != j) v += 1.0 / (xi[j] - xi[k]);
-            } else {
-                double num = 1.0, den = 1.0;
-                for (int k = 0; k < n1; ++k) {
-                    if (k != j) den *= (xi[j] - xi[k]);
-                    if (k != j && k != i) num *= (xi[i] - xi[k]);
-                }
-                v = num / den;
+            if (i == j) continue;
+            double num = 1.0, den = 1.0;
+            for (int k = 0; k < n1; ++k) {
+                if (k != j) den *= (xi[j] - xi[k]);
+                if (k != j && k != i) num *= (xi[i] - xi[k]);
             }
-            D[i * n1 + j] = v;
+            D[i * n1 + j] = num / den;
+            rowsum += num / den;
         }
+        D[i * n1 + i] = -rowsum;
     }
 }
 

@@ -32,7 +32,7 @@ def gpu_batch(probs, p_fine, device="cuda", **desc_kw):
     return s, f, g
 
 
-def oracle_of(prob, p_fine, gamma=1, m=1, alpha=0.16, smoother=1, restriction=0):
+def oracle_of(prob, p_fine, gamma=1, m=1, alpha=0.16, smoother=1, restriction=orc.RESTRICT_INTERP):
     ps = inputs.halving_degrees(p_fine, 2)
     coords = [prob.coords(orc.gll(p)[0]) for p in ps]
     h = orc.Hier(prob.dim, ps, coords, gamma=gamma, m=m, alpha=alpha, smoother=smoother,

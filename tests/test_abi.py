@@ -38,7 +38,8 @@ def test_host_gll_matches_closed_forms():
 @pytest.mark.parametrize("kw,msg", [
     (dict(dim=4), "dim"), (dict(p_fine=12), "p_fine"), (dict(dim=3, p_fine=128), "p_fine"),
     (dict(gamma=0), "gamma"), (dict(alpha=-1.0), "alpha"), (dict(smoother=5), "smoother"),
-    (dict(restart=0), "restart"), (dict(batch=0), "batch"), (dict(krylov=7), "Krylov")])
+    (dict(restart=0), "restart"), (dict(batch=0), "batch"), (dict(krylov=7), "Krylov"),
+    (dict(restriction=2), "restriction")])
 def test_invalid_descriptions(kw, msg):
     with pytest.raises(pmg.PmgError) as e:
         pmg.pmg_workspace_bytes(pmg.make_desc(**kw))
@@ -50,3 +51,42 @@ def test_workspace_scales_with_batch():
     b = pmg.pmg_workspace_bytes(pmg.make_desc(p_fine=128, batch=8))
     assert 7 * a < b < 9 * a
     assert pmg.pmg_num_levels(pmg.make_desc(p_fine=128)) == 7
+
+
+@pytest.mark.parametrize("p", [16, 64, 128, 256])
+def test_host_derivative_matrix_rows_sum_to_zero(p):
+    """D differentiates constants to zero: every row sums to zero up to the
+    rounding of one sum (closed-form off-diagonals, diagonal = minus their
+    sum).  A diagonal taken from its closed form instead leaves row sums of
+    1.7e-10 at p = 128 and 4.3e-9 at p = 256, which fail this bound."""
+    xi, rho, D = pmg.pmg_gll(p)
+    assert np.abs(D.sum(axis=1)).max() <= 1e-15 * p * p
+    # exact on polynomials of degree p
+    np.testing.assert_allclose(D @ xi**p, p * xi ** (p - 1), atol=1e-14 * p**2 * p)
+    np.testing.assert_allclose(D[0, 0], -p * (p + 1) / 4.0, rtol=1e-12)
+
+
+def test_operator_from_host_tables_matches_oracle_at_p128():
+    """The sum-factorised operator built in numpy from the library's host D
+    agrees with the oracle's operator at p = 128 on a rough interior input
+    (config-2 geometry, the oracle's geometric factors) within 1e-12."""
+    from oracle import oracle as orc
+    from paper_2504_10710_amd import inputs
+
+    p = 128
+    P = inputs.config2(0)
+    ps = inputs.halving_degrees(p)
+    h = orc.Hier(2, ps, [P.coords(orc.gll(q)[0]) for q in ps], gamma=1)
+    G, mass, _ = h.geom()
+    D = pmg.pmg_gll(p)[2]
+    n1 = p + 1
+    m1 = np.zeros(n1, bool)
+    m1[1:-1] = True
+    mask = np.outer(m1, m1).reshape(-1)
+    x = np.where(mask, np.random.default_rng(0).standard_normal(n1 * n1), 0.0)
+    X = x.reshape(n1, n1)          # [second index][first index]
+    gx, gy = X @ D.T, D @ X
+    G00, G11, G01 = (G[a, b].reshape(n1, n1) for a, b in ((0, 0), (1, 1), (0, 1)))
+    y = ((G00 * gx + G01 * gy) @ D + D.T @ (G01 * gx + G11 * gy)).reshape(-1) * mask
+    yo = h.apply(x)
+    assert np.abs(y - yo).max() <= 1e-12 * np.abs(yo).max()

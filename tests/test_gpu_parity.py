@@ -1,17 +1,30 @@
 """GPU parity: every C-ABI entry point against the CPU oracle on the same
 seeded inputs (each side with its own GLL nodes).
 
-Tolerances (FP64): geometry and transfers 1e-12 relative to the output's
-max-norm; operator and right-hand side eval_tol(p) = max(1e-12, 2e-12 (p/16)^3)
-(two FP64 evaluations of the degree-p operator differ by O(eps p^3)); line tridiagonals 1e-12; line solves and
-max(1e-12, 20 n eps kappa), kappa the largest condition number of the
-level's line tridiagonals (two cyclic reductions that round differently
-differ by O(n eps kappa)); a smoothing step that plus kappa eval_tol(p) (its
-residual evaluation amplified by the line solve); one gamma-cycle
-max(1e-9, 100 x the largest smoothing tolerance of its levels); full solves reach 1e-10 true relative residual (recomputed
-by the oracle's operator on the GPU's solution) with the solution within
-1e-7 relative of the oracle's (two independently converged iterates differ
-by up to cond(A) * 1e-10) and iteration counts within +-1.
+Tolerances (FP64, relative to the max-norm of the oracle's output):
+  * geometry, transfers and line tridiagonals: 1e-12;
+  * operator and right-hand side: op_tol(p) = max(1e-12, 4 eps p^2).  The
+    geometric factors are derivatives of the node coordinates (D x, whose
+    rows sum entries of size up to p^2/4), so two correct FP64 evaluations
+    of them differ by O(eps p^2) relative: on the CPU, the config-2 factors
+    computed with the library's D and with the oracle's D differ by 1.3e-13
+    (p = 64), 5.0e-13 (128) and 2.3e-12 (256); the operator inherits that
+    and its own summation order (the operator from the library's D on the
+    oracle's factors: 1.1e-13 at p = 128).  A derivative matrix whose rows
+    do not sum to zero (1.7e-10 at p = 128) fails this bound;
+  * line solves: max(1e-12, 20 n eps kappa), kappa the largest condition
+    number of the level's line tridiagonals (two cyclic reductions that
+    round differently differ by O(n eps kappa)); a smoothing step that plus
+    kappa * op_tol(p) (its residual, amplified by the line solve);
+  * one gamma-cycle: 1e-10 where every level's smoothing tolerance is at
+    most 1e-12 (every FEM case); otherwise 100 x the largest smoothing
+    tolerance of its levels, printed with the achieved error;
+  * full solves: the GPU's true relative residual <= 1e-10 and the same
+    residual recomputed with the oracle's operator on the GPU's solution
+    <= 1.0001e-10; the solution within 1e-7 relative of the oracle's (two
+    independently converged iterates differ by up to cond(A) * 1e-10);
+    iteration counts within +-1.
+Every test prints the errors it achieved.
 """
 import numpy as np
 import pytest
@@ -23,32 +36,41 @@ from tests.gpu_helpers import gpu_batch, interior_mask, oracle_of, problems, rel
 
 pytestmark = pytest.mark.gpu
 
-# (kind, p_fine, smoother, alpha, gamma)
+INTERP, TRANSPOSE = pmg.PMG_RESTRICT_INTERP, pmg.PMG_RESTRICT_TRANSPOSE
+OP_TOL = 1e-12
+
+
+def op_tol(p):
+    return max(OP_TOL, 4 * np.finfo(float).eps * p * p)
+
+# (kind, p_fine, smoother, alpha, gamma, restriction)
 CASES = [
-    ("cfg2", 16, pmg.PMG_SMOOTHER_FEM, 0.16, 1),
-    ("cfg2", 32, pmg.PMG_SMOOTHER_GLL, 0.3, 2),
-    ("cfg2", 64, pmg.PMG_SMOOTHER_FEM, 0.16, 2),
-    ("cfg1", 8, pmg.PMG_SMOOTHER_GLL, 2.0 / 3.0, 3),
-    ("cfg3", 8, pmg.PMG_SMOOTHER_GLL, 0.3, 1),
-    ("cfg3", 16, pmg.PMG_SMOOTHER_FEM, 0.16, 2),
+    ("cfg2", 16, pmg.PMG_SMOOTHER_FEM, 0.16, 1, INTERP),
+    ("cfg2", 32, pmg.PMG_SMOOTHER_FEM, 0.16, 3, TRANSPOSE),
+    ("cfg2", 64, pmg.PMG_SMOOTHER_FEM, 0.16, 2, INTERP),
+    ("cfg1", 8, pmg.PMG_SMOOTHER_GLL, 2.0 / 3.0, 3, INTERP),
+    ("cfg1", 16, pmg.PMG_SMOOTHER_GLL, 2.0 / 3.0, 2, TRANSPOSE),
+    ("cfg3", 8, pmg.PMG_SMOOTHER_GLL, 0.3, 1, TRANSPOSE),
+    ("cfg3", 16, pmg.PMG_SMOOTHER_FEM, 0.16, 2, INTERP),
 ]
 SEEDS = [0, 1, 2]
 
 
 def _ids(c):
-    return f"{c[0]}-p{c[1]}-{'fem' if c[2] else 'gll'}-g{c[4]}"
+    return f"{c[0]}-p{c[1]}-{'fem' if c[2] else 'gll'}-g{c[4]}-{'interp' if c[5] else 'PT'}"
 
 
 @pytest.fixture(scope="module", params=CASES, ids=_ids)
 def case(request):
-    kind, p, sm, alpha, gamma = request.param
-    print(f"[gpu case] {kind} p={p} smoother={sm} alpha={alpha} gamma={gamma}", flush=True)
+    kind, p, sm, alpha, gamma, rst = request.param
+    print(f"[gpu case] {kind} p={p} smoother={sm} alpha={alpha} gamma={gamma} restriction={rst}",
+          flush=True)
     probs = problems(kind, SEEDS)
-    s, f, g = gpu_batch(probs, p, gamma=gamma, alpha=alpha, smoother=sm)
+    s, f, g = gpu_batch(probs, p, gamma=gamma, alpha=alpha, smoother=sm, restriction=rst)
     torch.cuda.synchronize()
-    ors = [oracle_of(pr, p, gamma=gamma, alpha=alpha, smoother=sm) for pr in probs]
+    ors = [oracle_of(pr, p, gamma=gamma, alpha=alpha, smoother=sm, restriction=rst) for pr in probs]
     return dict(kind=kind, p=p, dim=probs[0].dim, s=s, f=f, g=g, ors=ors, probs=probs,
-                alpha=alpha, gamma=gamma, sm=sm)
+                alpha=alpha, gamma=gamma, sm=sm, rst=rst)
 
 
 def _rand_interior(dim, p, B, seed):
@@ -81,7 +103,7 @@ def _line_tol(h, l, d, dim, p):
 def _smooth_tol(h, l, d, dim, p):
     # a smoothing step also evaluates r - A x (operator tolerance), which the
     # line solve amplifies by at most kappa
-    return _line_tol(h, l, d, dim, p) + _line_kappa(h, l, d, dim, p) * eval_tol(p)
+    return _line_tol(h, l, d, dim, p) + _line_kappa(h, l, d, dim, p) * op_tol(p)
 
 
 def test_setup_status(case):
@@ -106,7 +128,11 @@ def test_geometry(case):
         for b, (h, _, _) in enumerate(case["ors"]):
             Go, mo, _ = h.geom(l)
             for k, (a, c) in enumerate(pairs):
-                assert rel_err(Gh[b, k], Go[a, c]) < 1e-12 * max(1.0, np.abs(Go[a, a]).max() / max(np.abs(Go[a, c]).max(), 1e-300)), (l, b, a, c)
+                eg = rel_err(Gh[b, k], Go[a, c])
+                tg = 1e-12 * max(1.0, np.abs(Go[a, a]).max() / max(np.abs(Go[a, c]).max(), 1e-300))
+                if l == s.nlev - 1:
+                    print(f"[geom] p={p} b={b} G{a}{c} rel err {eg:.2e} tol {tg:.1e}")
+                assert eg < tg, (l, b, a, c, eg)
             if mass is not None:
                 assert rel_err(mass.cpu().numpy()[b], mo) < 1e-12
 
@@ -138,7 +164,9 @@ def test_apply(case):
         pmg.pmg_apply(s.h, l, pmg.PMG_F64, xt, y)
         torch.cuda.synchronize()
         for b, (h, _, _) in enumerate(case["ors"]):
-            assert rel_err(y.cpu().numpy()[b], h.apply(x[b], l)) < eval_tol(p), (l, b)
+            err = rel_err(y.cpu().numpy()[b], h.apply(x[b], l))
+            print(f"[apply] p={p} b={b} rel err {err:.2e} tol {op_tol(p):.1e}")
+            assert err < op_tol(p), (l, b, err)
 
 
 def test_transfers(case):
@@ -156,8 +184,10 @@ def test_transfers(case):
         pmg.pmg_prolong_add(s.h, l, pmg.PMG_F64, torch.from_numpy(ec).cuda(), xf)
         torch.cuda.synchronize()
         for b, (h, _, _) in enumerate(case["ors"]):
-            assert rel_err(rc.cpu().numpy()[b], h.restrict(rf[b], l)) < 1e-12, (l, b)
-            assert rel_err(xf.cpu().numpy()[b], h.prolong_add(ec[b], xf0[b], l)) < 1e-12, (l, b)
+            er = rel_err(rc.cpu().numpy()[b], h.restrict(rf[b], l))
+            ep = rel_err(xf.cpu().numpy()[b], h.prolong_add(ec[b], xf0[b], l))
+            print(f"[transfers] p={pf} b={b} restrict {er:.2e} prolong {ep:.2e}")
+            assert er < 1e-12 and ep < 1e-12, (l, b, er, ep)
 
 
 def test_line_solve_and_smooth(case):
@@ -175,9 +205,20 @@ def test_line_solve_and_smooth(case):
             torch.cuda.synchronize()
             for b, (h, _, _) in enumerate(case["ors"]):
                 tol = _line_tol(h, l, d, dim, p)
-                assert rel_err(z.cpu().numpy()[b], h.line_solve(r[b], d, l)) < tol, (l, d, b, tol)
-                tol = _smooth_tol(h, l, d, dim, p)
-                assert rel_err(xs.cpu().numpy()[b], h.smooth(r[b], x0[b], d, l)) < tol, (l, d, b, tol)
+                err = rel_err(z.cpu().numpy()[b], h.line_solve(r[b], d, l))
+                assert err < tol, (l, d, b, err, tol)
+                tol2 = _smooth_tol(h, l, d, dim, p)
+                err2 = rel_err(xs.cpu().numpy()[b], h.smooth(r[b], x0[b], d, l))
+                print(f"[line] p={p} dir={d} b={b} solve {err:.2e} (tol {tol:.1e}) "
+                      f"smooth {err2:.2e} (tol {tol2:.1e})")
+                assert err2 < tol2, (l, d, b, err2, tol2)
+
+
+def _cycle_tol(h, dim):
+    """1e-10 when every level's smoothing tolerance is at most 1e-12, else
+    100 x the largest one (ill-conditioned GLL line tridiagonals)."""
+    st = max(_smooth_tol(h, l, d, dim, 2 << l) for l in range(1, h.nlev) for d in range(dim))
+    return 1e-10 if st <= 1e-12 else 100 * st
 
 
 def test_gamma_cycle(case):
@@ -187,9 +228,10 @@ def test_gamma_cycle(case):
     pmg.pmg_gamma_cycle(s.h, pmg.PMG_F64, torch.from_numpy(r).cuda(), y)
     torch.cuda.synchronize()
     for b, (h, _, _) in enumerate(case["ors"]):
-        tol = max(1e-9, 100 * max(_smooth_tol(h, l, d, dim, 2 << l)
-                                  for l in range(1, h.nlev) for d in range(dim)))
-        assert rel_err(y.cpu().numpy()[b], h.cycle(r[b])) < tol, (b, tol)
+        tol = _cycle_tol(h, dim)
+        err = rel_err(y.cpu().numpy()[b], h.cycle(r[b]))
+        print(f"[cycle] p={p} gamma={case['gamma']} b={b} rel err {err:.2e} tol {tol:.1e}")
+        assert err < tol, (b, err, tol)
 
 
 def test_rhs(case):
@@ -198,7 +240,9 @@ def test_rhs(case):
     pmg.pmg_rhs(s.h, case["f"], case["g"], b_t)
     torch.cuda.synchronize()
     for b, (h, f, g) in enumerate(case["ors"]):
-        assert rel_err(b_t.cpu().numpy()[b], h.rhs(f, g)) < eval_tol(case["p"]), b
+        err = rel_err(b_t.cpu().numpy()[b], h.rhs(f, g))
+        print(f"[rhs] p={case['p']} b={b} rel err {err:.2e} tol {op_tol(case['p']):.1e}")
+        assert err < op_tol(case["p"]), (b, err)
 
 
 def test_solve_fgmres(case):
@@ -215,13 +259,15 @@ def test_solve_fgmres(case):
         assert info["status"][b] == 0, info[b]
         # true residual of the GPU solution with the oracle's operator
         rr = np.linalg.norm(bh[b] - h.apply(xh[b])) / np.linalg.norm(bh[b])
-        assert info["relres"][b] <= 1e-10
-        assert rr <= 1e-10 + eval_tol(case["p"]), rr
-        assert abs(info["relres"][b] - rr) <= 1e-12 + eval_tol(case["p"]), (info["relres"][b], rr)
         xo, st, it, _ = h.fgmres(h.rhs(f, g), rtol=1e-10, maxit=200, restart=30)
+        ex = rel_err(xh[b], xo)
+        print(f"[solve] p={case['p']} b={b} its gpu {info['iterations'][b]} oracle {it}, "
+              f"relres gpu {info['relres'][b]:.3e} oracle-operator {rr:.3e}, err vs oracle {ex:.2e}")
+        assert info["relres"][b] <= 1e-10
+        assert rr <= 1.0001e-10, rr
         assert st == 0
         assert abs(int(info["iterations"][b]) - it) <= 1, (info["iterations"][b], it)
-        assert rel_err(xh[b], xo) < 1e-7
+        assert ex < x_tol, (ex, x_tol)
 
 
 def test_solve_mixed_precision():
@@ -240,6 +286,7 @@ def test_solve_mixed_precision():
         h, fo, go = oracle_of(pr, p, gamma=1, alpha=0.16, smoother=1)
         bo = h.rhs(fo, go)
         rr = np.linalg.norm(bo - h.apply(x.cpu().numpy()[b])) / np.linalg.norm(bo)
+        print(f"[mixed] p={p} seed={b} oracle-operator relres {rr:.3e}")
         assert info["status"][b] == 0 and rr <= 1.0001e-10, (info[b], rr)
         xo, st, it, _ = h.fgmres(bo, rtol=1e-10, maxit=200)
         print(f"[mixed] p={p} seed={b} its gpu={info['iterations'][b]} oracle={it} "
@@ -291,85 +338,83 @@ def test_alone_equals_in_the_mix():
     assert outs[0][1]["iterations"][2] == outs[1][1]["iterations"][0]
 
 
-def eval_tol(p):
-    """Relative disagreement allowed between two FP64 evaluations of the
-    operator (or right-hand side) at degree p: the GLL derivative matrix has
-    entries O(p^2) known to O(eps) relative accuracy and every output sums
-    O(p) products, so independent implementations differ by O(eps p^3);
-    2e-12 (p/16)^3 covers 1e-12 at p <= 16 and the measured 4e-10 at p = 128.
-    This is the precision limit the paper points to for degrees above 64."""
-    return max(1e-12, 2e-12 * (p / 16.0) ** 3)
-
-
-def test_full_size_config2():
-    """Config 2 at its full size (p = 128, 7 levels): solve to 1e-10 and check
-    the residual with the oracle's operator; compare with the oracle's solve."""
-    p = 128
-    probs = problems("cfg2", [0, 5])
-    s, f, g = gpu_batch(probs, p, gamma=1, alpha=0.16, smoother=pmg.PMG_SMOOTHER_FEM)
+def _full_solve(kind, p, seeds, gamma, inner_prec=pmg.PMG_F64, restart=30, rst=INTERP):
+    probs = problems(kind, seeds)
+    s, f, g = gpu_batch(probs, p, gamma=gamma, alpha=0.16, smoother=pmg.PMG_SMOOTHER_FEM,
+                        inner_prec=inner_prec, restart=restart, restriction=rst, max_iter=400)
     bt = torch.empty_like(f)
     pmg.pmg_rhs(s.h, f, g, bt)
     x = torch.empty_like(bt)
     pmg.pmg_solve(s.h, bt, x, s.info)
     torch.cuda.synchronize()
-    info = s.info_host()
+    return probs, s, bt.cpu().numpy(), x.cpu().numpy(), s.info_host()
+
+
+def _check_full(tag, probs, p, gamma, bh, xh, info, restart=30, rst=INTERP, its_tol=1,
+                same_method=True, x_tol=1e-7):
+    """Residual with the oracle's operator, solution against an oracle solve
+    to 1e-10.  The discrete solution does not depend on the preconditioner,
+    so where the oracle's run of the same method would take minutes
+    (same_method=False) the reference solve uses R = P^T and gamma = 1, and
+    the iteration counts are not compared."""
+    dim = probs[0].dim
     for b, pr in enumerate(probs):
-        h, fo, go = oracle_of(pr, p, gamma=1, alpha=0.16, smoother=1)
+        h, fo, go = oracle_of(pr, p, gamma=gamma, alpha=0.16, smoother=1, restriction=rst)
         bo = h.rhs(fo, go)
-        eb = rel_err(bt.cpu().numpy()[b], bo)
-        rr = np.linalg.norm(bo - h.apply(x.cpu().numpy()[b])) / np.linalg.norm(bo)
-        print(f"[p=128] problem {b}: rhs rel diff {eb:.2e}, gpu relres {info['relres'][b]:.2e}, "
-              f"oracle-operator relres {rr:.2e}, its {info['iterations'][b]}", flush=True)
-        assert eb < eval_tol(p)
-        assert info["status"][b] == 0 and info["relres"][b] <= 1e-10
-        assert rr <= 1e-10 + eval_tol(p), (info[b], rr)
-        xo, st, it, _ = h.fgmres(bo, rtol=1e-10, maxit=200)
-        assert abs(int(info["iterations"][b]) - it) <= 1
-        assert rel_err(x.cpu().numpy()[b], xo) < 1e-7
+        eb = rel_err(bh[b], bo)
+        rr = np.linalg.norm(bo - h.apply(xh[b])) / np.linalg.norm(bo)
+        href = h if same_method else oracle_of(pr, p, gamma=1, alpha=0.16, smoother=1,
+                                               restriction=TRANSPOSE)[0]
+        xo, st, it, _ = href.fgmres(bo, rtol=1e-10, maxit=400, restart=restart)
+        ex = rel_err(xh[b], xo)
+        print(f"[{tag}] problem {b}: rhs rel diff {eb:.2e} (tol {op_tol(p):.1e}), gpu relres {info['relres'][b]:.3e}, "
+              f"oracle-operator relres {rr:.3e}, its gpu {info['iterations'][b]} oracle {it}"
+              f"{'' if same_method else ' (reference solve: P^T, gamma 1)'}, "
+              f"solution err vs FP64 oracle {ex:.2e}", flush=True)
+        assert eb < op_tol(p)
+        assert info["status"][b] == 0 and info["relres"][b] <= 1e-10, info[b]
+        assert rr <= 1.0001e-10, (info[b], rr)
+        assert st == 0
+        if same_method:
+            assert abs(int(info["iterations"][b]) - it) <= its_tol, (info["iterations"][b], it)
+        assert ex < 1e-7
+
+
+def test_full_size_config2():
+    """Config 2 at its full size (p = 128, 7 levels, gamma = 3, restriction by
+    interpolation): solve to 1e-10, check the residual with the oracle's
+    operator, compare solution and iteration count with the oracle's solve."""
+    p = 128
+    probs, s, bh, xh, info = _full_solve("cfg2", p, [0, 5], gamma=3)
+    _check_full("cfg2 p=128 gamma=3", probs, p, 3, bh, xh, info)
+
+
+def test_full_size_config2_transpose_restriction():
+    """The same at gamma = 1 with R = P^T (the stronger labelled variant)."""
+    p = 128
+    probs, s, bh, xh, info = _full_solve("cfg2", p, [1], gamma=1, rst=TRANSPOSE)
+    _check_full("cfg2 p=128 gamma=1 P^T", probs, p, 1, bh, xh, info, rst=TRANSPOSE)
 
 
 def test_full_size_config3():
     """Config 3 at its full size (3-D p = 64, 6 levels, trilinear FEM line
-    smoother): solve to 1e-10; residual checked with the oracle's operator."""
+    smoother, gamma = 2): solve to 1e-10; residual with the oracle's
+    operator; solution and iterations against the oracle's solve."""
     p = 64
-    probs = problems("cfg3", [0])
-    s, f, g = gpu_batch(probs, p, gamma=1, alpha=0.16, smoother=pmg.PMG_SMOOTHER_FEM, restart=20)
-    bt = torch.empty_like(f)
-    pmg.pmg_rhs(s.h, f, g, bt)
-    x = torch.empty_like(bt)
-    pmg.pmg_solve(s.h, bt, x, s.info)
-    torch.cuda.synchronize()
-    info = s.info_host()
-    h, fo, go = oracle_of(probs[0], p, gamma=1, alpha=0.16, smoother=1)
-    bo = h.rhs(fo, go)
-    eb = rel_err(bt.cpu().numpy()[0], bo)
-    rr = np.linalg.norm(bo - h.apply(x.cpu().numpy()[0])) / np.linalg.norm(bo)
-    print(f"[3-D p=64] rhs rel diff {eb:.2e}, gpu relres {info['relres'][0]:.2e}, "
-          f"oracle-operator relres {rr:.2e}, its {info['iterations'][0]}", flush=True)
-    assert eb < eval_tol(p)
-    assert info["status"][0] == 0 and info["relres"][0] <= 1e-10
-    assert rr <= 1e-10 + eval_tol(p)
+    probs, s, bh, xh, info = _full_solve("cfg3", p, [0], gamma=2, restart=20)
+    _check_full("cfg3 p=64 gamma=2", probs, p, 2, bh, xh, info, restart=20, same_method=False)
 
 
 def test_p256_mixed_precision():
-    """Largest 2-D shape (p = 256, 8 levels) with the FP32 inner cycle."""
+    """Largest 2-D shape (p = 256, 8 levels) with the FP32 inner cycle
+    (gamma = 3): FP64 residual with the oracle's operator and the solution
+    against the FP64 oracle's solve.  The two solves take different paths
+    (FP32 cycle; reference with R = P^T), so their solutions differ by up to
+    cond(A) times their 1e-10 residuals, not by rounding: 1e-6 relative
+    (cond(A) of the degree-256 operator is about 1e7)."""
     p = 256
-    probs = problems("cfg2", [11])
-    s, f, g = gpu_batch(probs, p, gamma=1, alpha=0.16, smoother=pmg.PMG_SMOOTHER_FEM,
-                        inner_prec=pmg.PMG_F32)
-    bt = torch.empty_like(f)
-    pmg.pmg_rhs(s.h, f, g, bt)
-    x = torch.empty_like(bt)
-    pmg.pmg_solve(s.h, bt, x, s.info)
-    torch.cuda.synchronize()
-    info = s.info_host()
-    h, fo, go = oracle_of(probs[0], p, gamma=1, alpha=0.16, smoother=1)
-    bo = h.rhs(fo, go)
-    rr = np.linalg.norm(bo - h.apply(x.cpu().numpy()[0])) / np.linalg.norm(bo)
-    print(f"[p=256 f32 inner] gpu relres {info['relres'][0]:.2e}, oracle-operator relres {rr:.2e}, "
-          f"its {info['iterations'][0]}", flush=True)
-    assert info["status"][0] == 0 and info["relres"][0] <= 1e-10, info[0]
-    assert rr <= 1e-10 + eval_tol(p), (info[0], rr)
+    probs, s, bh, xh, info = _full_solve("cfg2", p, [11], gamma=3, inner_prec=pmg.PMG_F32)
+    _check_full("cfg2 p=256 FP32 cycle", probs, p, 3, bh, xh, info, same_method=False, x_tol=1e-6)
 
 
 def test_error_statuses():
@@ -467,7 +512,7 @@ def test_apply_transfers_mfma(dim, p):
     rf = rng.standard_normal((B, (p + 1) ** dim))
     ec = _rand_interior(dim, pc, B, 93)
     xf0 = rng.standard_normal((B, (p + 1) ** dim))
-    for prec, dt, tol_a, tol_t in ((pmg.PMG_F64, torch.float64, eval_tol(p), 1e-12),
+    for prec, dt, tol_a, tol_t in ((pmg.PMG_F64, torch.float64, op_tol(p), 1e-12),
                                    (pmg.PMG_F32, torch.float32, 1e-5, 1e-5)):
         h = s.h if prec == pmg.PMG_F64 else s32.h
         xt = torch.from_numpy(x).to(dt).cuda()
@@ -507,3 +552,56 @@ def test_gamma_cycle_smoothing_counts(dim, p, m, gamma):
         print(f"[cycle m={m} gamma={gamma}] dim={dim} p={p} b={b}: rel err {err:.2e} tol {tol:.1e}",
               flush=True)
         assert err < tol, (b, err, tol)
+
+
+@pytest.mark.parametrize("gamma,rst", [(1, INTERP), (7, INTERP), (1, TRANSPOSE)])
+def test_gamma_cycle_full_hierarchy_p128(gamma, rst):
+    """One FP64 gamma-cycle on the full 2-D p = 128 hierarchy (7 levels,
+    config-2 geometry, FEM line systems) against the oracle's cycle, on a
+    random interior vector and on a right-hand side, within 1e-10."""
+    p = 128
+    probs = problems("cfg2", [2, 3])
+    s, f, g = gpu_batch(probs, p, gamma=gamma, alpha=0.16, smoother=pmg.PMG_SMOOTHER_FEM,
+                        restriction=rst)
+    B = len(probs)
+    r = _rand_interior(2, p, B, 61)
+    bt = torch.empty_like(f)
+    pmg.pmg_rhs(s.h, f, g, bt)
+    for name, rin in (("random", torch.from_numpy(r).cuda()), ("rhs", bt)):
+        y = torch.empty_like(rin)
+        pmg.pmg_gamma_cycle(s.h, pmg.PMG_F64, rin, y)
+        torch.cuda.synchronize()
+        rh = rin.cpu().numpy()
+        for b, pr in enumerate(probs):
+            h = oracle_of(pr, p, gamma=gamma, alpha=0.16, smoother=1, restriction=rst)[0]
+            err = rel_err(y.cpu().numpy()[b], h.cycle(rh[b]))
+            print(f"[cycle p=128 gamma={gamma} rst={rst}] {name} b={b}: rel err {err:.2e}", flush=True)
+            assert err < 1e-10, (name, b, err)
+
+
+def test_line_solve_stored_factors_p256():
+    """2-D p = 256 (lines of 255 unknowns): the stored-factor thread-per-line
+    cyclic reduction, both axes, FP64 and FP32, element by element against
+    the oracle's literal cyclic reduction."""
+    p = 256
+    probs = problems("cfg2", [12, 13])
+    B = len(probs)
+    ors = [oracle_of(pr, p, gamma=1, alpha=0.16, smoother=1)[0] for pr in probs]
+    r = _rand_interior(2, p, B, 71)
+    for prec, dt in ((pmg.PMG_F64, torch.float64), (pmg.PMG_F32, torch.float32)):
+        s, _, _ = gpu_batch(probs, p, gamma=1, alpha=0.16, smoother=pmg.PMG_SMOOTHER_FEM,
+                            inner_prec=prec)
+        L = s.nlev - 1
+        for d in range(2):
+            z = torch.empty((B, (p + 1) ** 2), dtype=dt, device="cuda")
+            pmg.pmg_line_solve(s.h, L, d, prec, torch.from_numpy(r).to(dt).cuda(), z)
+            torch.cuda.synchronize()
+            for b, h in enumerate(ors):
+                zo = h.line_solve(r[b], d, L)
+                kap = _line_kappa(h, L, d, 2, p)
+                eps = np.finfo(np.float64 if prec == pmg.PMG_F64 else np.float32).eps
+                tol = max(1e-12 if prec == pmg.PMG_F64 else 1e-5, 20 * (p - 1) * eps * kap)
+                err = rel_err(z.cpu().double().numpy()[b], zo)
+                print(f"[line p=256 prec={prec}] dir={d} b={b} rel err {err:.2e} tol {tol:.1e}",
+                      flush=True)
+                assert err < tol, (prec, d, b, err, tol)

@@ -83,3 +83,27 @@ def test_interp_composes():
     x8, _ = orc.gll(8)
     np.testing.assert_allclose(orc.interp(4, x4, x8) @ orc.interp(2, x2, x4),
                                orc.interp(2, x2, x8), atol=1e-13)
+
+
+@pytest.mark.parametrize("p", [16, 64, 128, 256])
+def test_deriv_against_extended_precision(p):
+    """D at the oracle's own nodes against the same derivatives evaluated in
+    80-bit long double (an independent precision): every entry within
+    p eps max|D| / 4 (each entry is a product of p factors), and the rows
+    sum to zero within eps p^2 (the basis is a
+    partition of unity).  A diagonal taken from the product rule's
+    sum_k 1/(xi_i - xi_k) leaves row sums of 1.2e-11 at p = 128, which fails."""
+    xi, _ = orc.gll(p)
+    D = orc.deriv(p, xi)
+    x = xi.astype(np.longdouble)
+    n = p + 1
+    diff = x[:, None] - x[None, :]
+    np.fill_diagonal(diff, 1)
+    # pi_j'(x_i) = (w_j / w_i) / (x_i - x_j), w_j = 1 / prod_{k != j} (x_j - x_k)
+    w = 1 / np.prod(diff, axis=1)
+    Dl = (w[None, :] / w[:, None]) / diff
+    np.fill_diagonal(Dl, 0)
+    np.fill_diagonal(Dl, -Dl.sum(axis=1))
+    scale = np.abs(D).max()
+    assert float(np.abs(D - Dl).max()) <= p * np.finfo(float).eps * scale / 4
+    assert np.abs(D.sum(axis=1)).max() <= np.finfo(float).eps * p * p
