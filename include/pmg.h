@@ -57,6 +57,7 @@ enum {
 enum { PMG_F64 = 0, PMG_F32 = 1 };
 enum { PMG_SMOOTHER_GLL = 0, PMG_SMOOTHER_FEM = 1 };
 enum { PMG_FGMRES = 0, PMG_PCG = 1, PMG_FCG = 2 };
+enum { PMG_RESTRICT_TRANSPOSE = 0, PMG_RESTRICT_INTERP = 1 };
 
 #define PMG_MAX_LEVELS 9
 
@@ -80,7 +81,15 @@ enum { PMG_FGMRES = 0, PMG_PCG = 1, PMG_FCG = 2 };
  *              restarted), PMG_PCG, PMG_FCG (flexible CG)
  *   restart    FGMRES restart length (1..64)
  *   max_iter   iteration cap of the outer solve
- *   rtol       stop when ||b - A x||_2 <= rtol ||b||_2 (true residual) */
+ *   rtol       stop when ||b - A x||_2 <= rtol ||b||_2 (true residual)
+ *   restriction  R_l of Sec. 3.3, which the section gives two ways:
+ *              PMG_RESTRICT_INTERP, the interpolation of the fine polynomial
+ *              at the coarse GLL nodes (the reading that reproduces the
+ *              iteration counts of Table 1), or PMG_RESTRICT_TRANSPOSE,
+ *              R_l = P_l^T (a stronger, Galerkin-consistent preconditioner:
+ *              fewer iterations, not the method behind Table 1).  Coarse
+ *              boundary rows are zero either way; P_l is the interpolation
+ *              of the coarse polynomial at the fine nodes in both. */
 typedef struct {
     int dim;
     int p_fine;
@@ -94,6 +103,7 @@ typedef struct {
     int restart;
     int max_iter;
     double rtol;
+    int restriction;
 } pmg_desc;
 
 /* Per-problem result of the device solve (written by pmg_solve). */
@@ -125,6 +135,23 @@ int pmg_interp(int p_c, int p_f, double* J);
 
 /* Bytes of device workspace pmg_setup needs for this description. */
 int pmg_workspace_bytes(const pmg_desc* desc, size_t* bytes);
+
+/* One named region of a workspace: byte offset from the workspace start and
+ * size in bytes (each region starts on a 256-byte boundary). */
+typedef struct {
+    char name[24];
+    size_t offset;
+    size_t bytes;
+} pmg_region;
+
+/* The layout pmg_setup gives the workspace of this description, in address
+ * order: *n_regions receives the number of regions, of which the first
+ * max_regions are written to the host array regions (may be NULL when
+ * max_regions is 0).  Host-only; for memory accounting and inspection.
+ * Per-level regions are named "X[l]" and so on; Krylov regions "V", "Z",
+ * "Hs", "TR64", "state". */
+int pmg_workspace_layout(const pmg_desc* desc, pmg_region* regions, int max_regions,
+                         int* n_regions);
 
 /* Build the hierarchy on the device (geometry of eq. DiscreteSpace and eq.
  * discreteBilinear for every level, line tridiagonals and their

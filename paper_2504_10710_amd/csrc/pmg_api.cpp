@@ -94,8 +94,12 @@ bool gll_nodes(int p, std::vector<double>& xi, std::vector<double>& rho)
     return true;
 }
 
-// Closed-form GLL differentiation matrix: D_ij = L_p(xi_i) / (L_p(xi_j) (xi_i - xi_j))
-// for i != j, D_00 = -p(p+1)/4, D_pp = p(p+1)/4, D_ii = 0 otherwise.
+// GLL differentiation matrix: closed-form off-diagonals
+// D_ij = L_p(xi_i) / (L_p(xi_j) (xi_i - xi_j)), i != j, and each diagonal
+// entry the negative sum of its row's off-diagonals, D_ii = -sum_{j!=i} D_ij,
+// so that D differentiates constants to zero in floating point as well
+// (the "negative sum trick" of Baltensperger and Trummer, SIAM J. Sci.
+// Comput. 24 (2003); the exact diagonal is -p(p+1)/4, 0, ..., 0, p(p+1)/4).
 void gll_deriv(int p, const std::vector<double>& xi, std::vector<double>& D)
 {
     int n1 = p + 1;
@@ -106,12 +110,16 @@ void gll_deriv(int p, const std::vector<double>& xi, std::vector<double>& D)
         L[i] = a;
     }
     D.assign(n1 * n1, 0.0);
-    for (int i = 0; i < n1; ++i)
+    for (int i = 0; i < n1; ++i) {
+        double s = 0.0;
         for (int j = 0; j < n1; ++j) {
-            if (i != j) D[i * n1 + j] = L[i] / (L[j] * (xi[i] - xi[j]));
+            if (i == j) continue;
+            double v = L[i] / (L[j] * (xi[i] - xi[j]));
+            D[i * n1 + j] = v;
+            s += v;
         }
-    D[0] = -p * (p + 1.0) / 4.0;
-    D[(n1 - 1) * n1 + (n1 - 1)] = p * (p + 1.0) / 4.0;
+        D[i * n1 + i] = -s;
+    }
 }
 
 // Barycentric Lagrange interpolation from the coarse GLL nodes xc to the
@@ -141,10 +149,27 @@ void bary_interp(const std::vector<double>& xc, const std::vector<double>& xf,
 
 struct Layout {
     size_t off = 0;
+    std::vector<pmg_region>* rec = nullptr;   // optional record of the named regions
     size_t take(size_t bytes)
     {
         size_t o = (off + 255) & ~size_t(255);
         off = o + bytes;
+        return o;
+    }
+    size_t take(const char* name, int level, size_t bytes)
+    {
+        size_t o = take(bytes);
+        if (rec) {
+            pmg_region r;
+            memset(&r, 0, sizeof(r));
+            if (level >= 0)
+                snprintf(r.name, sizeof(r.name), "%s[%d]", name, level);
+            else
+                snprintf(r.name, sizeof(r.name), "%s", name);
+            r.offset = o;
+            r.bytes = bytes;
+            rec->push_back(r);
+        }
         return o;
     }
 };
@@ -171,6 +196,8 @@ int check_desc(const pmg_desc* d)
     if (d->restart < 1 || d->restart > 64) return fail(PMG_EINVAL, "restart must be in [1, 64]");
     if (d->max_iter < 1) return fail(PMG_EINVAL, "max_iter must be >= 1");
     if (!(d->rtol > 0.0)) return fail(PMG_EINVAL, "rtol must be > 0");
+    if (d->restriction != PMG_RESTRICT_TRANSPOSE && d->restriction != PMG_RESTRICT_INTERP)
+        return fail(PMG_EINVAL, "unknown restriction %d", d->restriction);
     return PMG_OK;
 }
 
@@ -203,6 +230,7 @@ struct pmg_handle {
     size_t o_rho[MAX_LEVELS], o_D64[MAX_LEVELS], o_DT64[MAX_LEVELS], o_J64[MAX_LEVELS],
         o_JT64[MAX_LEVELS];
     size_t o_D32[MAX_LEVELS], o_DT32[MAX_LEVELS], o_J32[MAX_LEVELS], o_JT32[MAX_LEVELS];
+    size_t o_JR64[MAX_LEVELS], o_JR32[MAX_LEVELS];
     size_t o_G64[MAX_LEVELS], o_G32[MAX_LEVELS], o_X64[MAX_LEVELS];
     size_t o_cr64[MAX_LEVELS][3], o_cr32[MAX_LEVELS][3];
     size_t o_X[MAX_LEVELS], o_R[MAX_LEVELS], o_Tm[MAX_LEVELS], o_TR[MAX_LEVELS];
@@ -225,81 +253,85 @@ struct pmg_handle {
 
 namespace {
 
-void plan(pmg_handle* h)
+void plan(pmg_handle* h, std::vector<pmg_region>* rec = nullptr)
 {
     const pmg_desc& d = h->d;
     const int dim = d.dim, B = d.batch;
     const size_t tsz = h->f32 ? sizeof(float) : sizeof(double);
     Layout L;
+    L.rec = rec;
     long long w = 0;
     for (int l = 0; l < h->nlev; ++l) {
         LevelShape s = level_shape(dim, l);
-        h->o_rho[l] = L.take(sizeof(double) * s.n1);
-        h->o_D64[l] = L.take(sizeof(double) * s.n1 * s.n1);
-        h->o_DT64[l] = L.take(sizeof(double) * s.n1 * s.n1);
-        h->o_D32[l] = L.take(sizeof(float) * s.n1 * s.n1);
-        h->o_DT32[l] = L.take(sizeof(float) * s.n1 * s.n1);
+        h->o_rho[l] = L.take("rho", l, sizeof(double) * s.n1);
+        h->o_D64[l] = L.take("D64", l, sizeof(double) * s.n1 * s.n1);
+        h->o_DT64[l] = L.take("DT64", l, sizeof(double) * s.n1 * s.n1);
+        h->o_D32[l] = L.take("D32", l, sizeof(float) * s.n1 * s.n1);
+        h->o_DT32[l] = L.take("DT32", l, sizeof(float) * s.n1 * s.n1);
         if (l > 0) {
             int n1c = s.p / 2 + 1;
-            h->o_J64[l] = L.take(sizeof(double) * s.n1 * n1c);
-            h->o_JT64[l] = L.take(sizeof(double) * s.n1 * n1c);
-            h->o_J32[l] = L.take(sizeof(float) * s.n1 * n1c);
-            h->o_JT32[l] = L.take(sizeof(float) * s.n1 * n1c);
+            h->o_J64[l] = L.take("J64", l, sizeof(double) * s.n1 * n1c);
+            h->o_JT64[l] = L.take("JT64", l, sizeof(double) * s.n1 * n1c);
+            h->o_J32[l] = L.take("J32", l, sizeof(float) * s.n1 * n1c);
+            h->o_JT32[l] = L.take("JT32", l, sizeof(float) * s.n1 * n1c);
+            h->o_JR64[l] = L.take("JR64", l, sizeof(double) * s.n1 * n1c);
+            h->o_JR32[l] = L.take("JR32", l, sizeof(float) * s.n1 * n1c);
             long long ww = (long long)(dim == 2 ? s.n1 : s.n1 * s.n1) * n1c;
             if (ww > w) w = ww;
         } else {
             h->o_J64[l] = h->o_JT64[l] = h->o_J32[l] = h->o_JT32[l] = 0;
+            h->o_JR64[l] = h->o_JR32[l] = 0;
         }
     }
     for (int l = 0; l < h->nlev; ++l) {
         LevelShape s = level_shape(dim, l);
-        h->o_G64[l] = L.take(sizeof(double) * (size_t)B * s.NC * s.N);
-        h->o_G32[l] = h->f32 ? L.take(sizeof(float) * (size_t)B * s.NC * s.N) : 0;
-        h->o_X64[l] = L.take(sizeof(double) * (size_t)B * dim * s.N);
+        h->o_G64[l] = L.take("G64", l, sizeof(double) * (size_t)B * s.NC * s.N);
+        h->o_G32[l] = h->f32 ? L.take("G32", l, sizeof(float) * (size_t)B * s.NC * s.N) : 0;
+        h->o_X64[l] = L.take("X64", l, sizeof(double) * (size_t)B * dim * s.N);
         for (int a = 0; a < 3; ++a) {
-            h->o_cr64[l][a] = a < dim ? L.take(sizeof(double) * (size_t)B * 3 * s.CRW * s.NL) : 0;
+            h->o_cr64[l][a] = a < dim ? L.take(a == 0 ? "cr64x" : (a == 1 ? "cr64y" : "cr64z"), l, sizeof(double) * (size_t)B * 3 * s.CRW * s.NL) : 0;
             h->o_cr32[l][a] =
-                (a < dim && h->f32) ? L.take(sizeof(float) * (size_t)B * 3 * s.CRW * s.NL) : 0;
+                (a < dim && h->f32) ? L.take(a == 0 ? "cr32x" : (a == 1 ? "cr32y" : "cr32z"), l, sizeof(float) * (size_t)B * 3 * s.CRW * s.NL) : 0;
         }
-        h->o_X[l] = L.take(tsz * (size_t)B * s.N);
-        h->o_R[l] = L.take(tsz * (size_t)B * s.N);
-        h->o_Tm[l] = L.take(tsz * (size_t)B * s.N);
-        h->o_TR[l] = L.take(tsz * (size_t)B * dim * s.N);
+        h->o_X[l] = L.take("X", l, tsz * (size_t)B * s.N);
+        h->o_R[l] = L.take("R", l, tsz * (size_t)B * s.N);
+        h->o_Tm[l] = L.take("Tm", l, tsz * (size_t)B * s.N);
+        h->o_TR[l] = L.take("TR", l, tsz * (size_t)B * dim * s.N);
     }
     LevelShape f = level_shape(dim, h->nlev - 1);
     h->w1 = h->w2 = w;
-    h->o_mass = L.take(sizeof(double) * (size_t)B * f.N);
-    h->o_W1 = L.take(tsz * (size_t)B * w);
-    h->o_W2 = dim == 3 ? L.take(tsz * (size_t)B * w) : 0;
-    h->o_TR64 = L.take(sizeof(double) * (size_t)B * dim * f.N);
+    h->o_mass = L.take("mass", -1, sizeof(double) * (size_t)B * f.N);
+    h->o_W1 = L.take("W1", -1, tsz * (size_t)B * w);
+    h->o_W2 = dim == 3 ? L.take("W2", -1, tsz * (size_t)B * w) : 0;
+    h->o_TR64 = L.take("TR64", -1, sizeof(double) * (size_t)B * dim * f.N);
     const int kr = d.restart;
     h->nv = kr + 1 > 5 ? kr + 1 : 5;
     h->hs = (long long)(kr + 1) * kr + 4LL * kr + 1;
-    h->o_V = L.take(sizeof(double) * (size_t)B * h->nv * f.N);
-    h->o_Z = L.take(sizeof(double) * (size_t)B * kr * f.N);
-    h->o_Hs = L.take(sizeof(double) * (size_t)B * h->hs);
-    h->o_detmin = L.take(sizeof(double) * (size_t)B * h->nlev);
-    h->o_pivot = L.take(sizeof(int) * (size_t)B);
-    h->o_cinv64 = L.take(sizeof(double) * (size_t)B);
-    h->o_cinv32 = L.take(sizeof(float) * (size_t)B);
-    h->o_sstatus = L.take(sizeof(int) * (size_t)B);
-    h->o_state = L.take(sizeof(SolveState) * (size_t)B);
-    h->o_hier64 = L.take(sizeof(Hier<double>));
-    h->o_hier32 = L.take(sizeof(Hier<float>));
+    h->o_V = L.take("V", -1, sizeof(double) * (size_t)B * h->nv * f.N);
+    h->o_Z = L.take("Z", -1, sizeof(double) * (size_t)B * kr * f.N);
+    h->o_Hs = L.take("Hs", -1, sizeof(double) * (size_t)B * h->hs);
+    h->o_detmin = L.take("detmin", -1, sizeof(double) * (size_t)B * h->nlev);
+    h->o_pivot = L.take("pivot", -1, sizeof(int) * (size_t)B);
+    h->o_cinv64 = L.take("cinv64", -1, sizeof(double) * (size_t)B);
+    h->o_cinv32 = L.take("cinv32", -1, sizeof(float) * (size_t)B);
+    h->o_sstatus = L.take("sstatus", -1, sizeof(int) * (size_t)B);
+    h->o_state = L.take("state", -1, sizeof(SolveState) * (size_t)B);
+    h->o_hier64 = L.take("hier64", -1, sizeof(Hier<double>));
+    h->o_hier32 = L.take("hier32", -1, sizeof(Hier<float>));
     if (h->pool) {
         for (int l = 0; l < h->nlev; ++l) {
             LevelShape s = level_shape(dim, l);
-            h->o_in_coords[l] = L.take(sizeof(double) * (size_t)B * dim * s.N);
+            h->o_in_coords[l] = L.take("in_coords", l, sizeof(double) * (size_t)B * dim * s.N);
         }
-        h->o_in_f = L.take(sizeof(double) * (size_t)B * f.N);
-        h->o_in_g = L.take(sizeof(double) * (size_t)B * f.N);
-        h->o_b = L.take(sizeof(double) * (size_t)B * f.N);
-        h->o_x = L.take(sizeof(double) * (size_t)B * f.N);
-        h->o_info = L.take(sizeof(pmg_info) * (size_t)B);
-        h->o_slots = L.take(sizeof(int) * (size_t)B);
-        h->o_take_slots = L.take(sizeof(int) * (size_t)B);
-        h->o_take_outs = L.take(sizeof(double*) * (size_t)B);
-        h->o_jobs = L.take(sizeof(CopyJob) * (size_t)B * (h->nlev + 2));
+        h->o_in_f = L.take("in_f", -1, sizeof(double) * (size_t)B * f.N);
+        h->o_in_g = L.take("in_g", -1, sizeof(double) * (size_t)B * f.N);
+        h->o_b = L.take("b", -1, sizeof(double) * (size_t)B * f.N);
+        h->o_x = L.take("x", -1, sizeof(double) * (size_t)B * f.N);
+        h->o_info = L.take("info", -1, sizeof(pmg_info) * (size_t)B);
+        h->o_slots = L.take("slots", -1, sizeof(int) * (size_t)B);
+        h->o_take_slots = L.take("take_slots", -1, sizeof(int) * (size_t)B);
+        h->o_take_outs = L.take("take_outs", -1, sizeof(double*) * (size_t)B);
+        h->o_jobs = L.take("jobs", -1, sizeof(CopyJob) * (size_t)B * (h->nlev + 2));
     }
     h->total = L.take(0) + 256;
 }
@@ -327,11 +359,13 @@ void fill_hier(pmg_handle* h, Hier<T>& H, bool is32)
         if (l > 0) {
             L.J = (const T*)(ws + (is32 ? h->o_J32[l] : h->o_J64[l]));
             L.JT = (const T*)(ws + (is32 ? h->o_JT32[l] : h->o_JT64[l]));
+            L.JR = (const T*)(ws + (is32 ? h->o_JR32[l] : h->o_JR64[l]));
         }
         L.D64 = (const double*)(ws + h->o_D64[l]);
         L.DT64 = (const double*)(ws + h->o_DT64[l]);
     }
     H.cinv = (const T*)(ws + (is32 ? h->o_cinv32 : h->o_cinv64));
+    H.cinv64 = (const double*)(ws + h->o_cinv64);
     H.W1 = (T*)(ws + h->o_W1);
     H.W2 = dim == 3 ? (T*)(ws + h->o_W2) : nullptr;
     H.w1 = h->w1;
@@ -398,6 +432,24 @@ int pmg_workspace_bytes(const pmg_desc* desc, size_t* bytes)
     return PMG_OK;
 }
 
+int pmg_workspace_layout(const pmg_desc* desc, pmg_region* regions, int max_regions,
+                         int* n_regions)
+{
+    int rc = check_desc(desc);
+    if (rc) return rc;
+    if (!n_regions || max_regions < 0 || (max_regions > 0 && !regions))
+        return fail(PMG_EINVAL, "bad region buffer");
+    pmg_handle tmp;
+    tmp.d = *desc;
+    tmp.nlev = ilog2(desc->p_fine);
+    tmp.f32 = desc->inner_prec == PMG_F32;
+    std::vector<pmg_region> rec;
+    plan(&tmp, &rec);
+    *n_regions = (int)rec.size();
+    for (int i = 0; i < (int)rec.size() && i < max_regions; ++i) regions[i] = rec[i];
+    return PMG_OK;
+}
+
 static int init_handle(const pmg_desc* desc, void* d_ws, size_t ws_bytes, bool pool,
                        hipStream_t s, pmg_handle** out)
 {
@@ -443,7 +495,7 @@ static int init_handle(const pmg_desc* desc, void* d_ws, size_t ws_bytes, bool p
                 t32[h->o_DT32[l] / 4 + j * sh.n1 + i] = (float)v;
             }
         if (l > 0) {
-            std::vector<double> J;
+            std::vector<double> J, Q;
             bary_interp(xis[l - 1], xis[l], J);
             int n1c = sh.p / 2 + 1;
             for (int i = 0; i < sh.n1; ++i)
@@ -453,6 +505,17 @@ static int init_handle(const pmg_desc* desc, void* d_ws, size_t ws_bytes, bool p
                     t64[h->o_JT64[l] / 8 + j * sh.n1 + i] = v;
                     t32[h->o_J32[l] / 4 + i * n1c + j] = (float)v;
                     t32[h->o_JT32[l] / 4 + j * sh.n1 + i] = (float)v;
+                }
+            // restriction table JR ([n1][n1c], R = JR^T per axis): J itself
+            // for R = P^T; for the interpolation reading Q[j][i] = pi^f_i(xi^c_j),
+            // the fine basis at the coarse nodes, stored transposed
+            if (desc->restriction == PMG_RESTRICT_INTERP) bary_interp(xis[l], xis[l - 1], Q);
+            for (int i = 0; i < sh.n1; ++i)
+                for (int j = 0; j < n1c; ++j) {
+                    double v = desc->restriction == PMG_RESTRICT_INTERP ? Q[j * sh.n1 + i]
+                                                                        : J[i * n1c + j];
+                    t64[h->o_JR64[l] / 8 + i * n1c + j] = v;
+                    t32[h->o_JR32[l] / 4 + i * n1c + j] = (float)v;
                 }
         }
     }
@@ -477,7 +540,8 @@ static int init_handle(const pmg_desc* desc, void* d_ws, size_t ws_bytes, bool p
         if (l > 0) {
             size_t nj = (size_t)sh.n1 * (sh.p / 2 + 1);
             if ((e = up64(h->o_J64[l], nj)) != hipSuccess || (e = up64(h->o_JT64[l], nj)) != hipSuccess ||
-                (e = up32(h->o_J32[l], nj)) != hipSuccess || (e = up32(h->o_JT32[l], nj)) != hipSuccess) {
+                (e = up32(h->o_J32[l], nj)) != hipSuccess || (e = up32(h->o_JT32[l], nj)) != hipSuccess ||
+                (e = up64(h->o_JR64[l], nj)) != hipSuccess || (e = up32(h->o_JR32[l], nj)) != hipSuccess) {
                 delete h;
                 return hip_fail(e, "table upload");
             }

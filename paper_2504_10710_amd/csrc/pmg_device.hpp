@@ -70,6 +70,9 @@ struct LevelData {
     const T* DT;         // [n1][n1]  transpose
     const T* J;          // [n1][n1c] prolongation from the next coarser level
     const T* JT;         // [n1c][n1]
+    const T* JR;         // [n1][n1c] restriction to the next coarser level, transposed:
+                         // R = JR^T (x) JR^T [(x) JR^T]; JR = J for R = P^T, JR[i][j] =
+                         // pi^f_i(xi^c_j) (fine basis at the coarse nodes) for interpolation
     const double* D64;
     const double* DT64;
 };
@@ -78,6 +81,7 @@ template <class T>
 struct Hier {
     LevelData<T> lev[MAX_LEVELS];
     const T* cinv;       // [B] 1 / A_0 of the one interior node of level 0
+    const double* cinv64;   // the same in FP64 (the coarsest solve stays FP64)
     T* W1;               // [B][w1] transfer temporaries
     T* W2;               // [B][w2]
     long long w1, w2;    // per-problem sizes of W1, W2
@@ -1147,7 +1151,10 @@ __device__ void prolong_axis(const T* __restrict__ in_, T* __restrict__ out_, in
     wg_barrier();
 }
 
-// rc = R_l rf with zero coarse boundary (Sec. 3.3, R = P^T)
+// rc = R_l rf with zero coarse boundary (Sec. 3.3).  R is the tensor product
+// of the transpose of the 1-D table passed as J: the prolongation J itself
+// for R = P^T, or the fine basis at the coarse nodes for the interpolation
+// reading of the same section.
 template <class T, int P, int DIM>
 __device__ __attribute__((noinline)) void restrict_level(const T* rf, T* rc, const T* J,
                                                          const T* JT, T* w1, T* w2)
@@ -1253,12 +1260,13 @@ __device__ __attribute__((noinline)) void gamma_cycle(const Hier<T>& H, int b, c
     using S = Shape<P, DIM>;
     const LevelData<T>& L = lvl<T, P, DIM>(H);
     if constexpr (P == 2) {
-        // one interior node: M_0^{-1} = A_0^{-1} is a division
+        // one interior node: M_0^{-1} = A_0^{-1} is a division, done in FP64
+        // whatever the cycle's type (one product with the FP64 1 / A_0)
         constexpr int c = DIM == 2 ? 4 : 13;
-        const T ia = H.cinv[b];
+        const double ia = H.cinv64[b];
         const auto xg = gmem(x);
         const auto rg = gmem(r);
-        for (int q = threadIdx.x; q < S::N; q += NT) xg[q] = q == c ? rg[c] * ia : T(0);
+        for (int q = threadIdx.x; q < S::N; q += NT) xg[q] = q == c ? T((double)rg[c] * ia) : T(0);
         wg_barrier();
     } else {
         using C = Shape<P / 2, DIM>;
@@ -1286,7 +1294,7 @@ __device__ __attribute__((noinline)) void gamma_cycle(const Hier<T>& H, int b, c
         for (int g = 0; g < H.gamma; ++g) {
             apply_level<T, P, DIM, true>(L.G + (long long)b * S::NC * S::N, L.D, L.DT,
                                          L.TR + (long long)b * DIM * S::N, x, r, tmp);
-            restrict_level<T, P, DIM>(tmp, rc, L.J, L.JT, w1, w2);
+            restrict_level<T, P, DIM>(tmp, rc, L.JR, L.JT, w1, w2);
             gamma_cycle<T, P / 2, DIM>(H, b, rc, xc);
             prolong_level<T, P, DIM>(xc, x, L.J, L.JT, w1, w2);
             for (int dir = DIM - 1; dir >= 0; --dir)

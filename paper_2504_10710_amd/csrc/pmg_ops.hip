@@ -27,7 +27,7 @@ __global__ void __launch_bounds__(NT) k_restrict(const Hier<T>* __restrict__ Hp,
     using C = Shape<P / 2, DIM>;
     const long long b = blockIdx.x;
     const LevelData<T>& L = H.lev[S::LEV];
-    restrict_level<T, P, DIM>(rf + b * S::N, rc + b * C::N, L.J, L.JT, H.W1 + b * H.w1,
+    restrict_level<T, P, DIM>(rf + b * S::N, rc + b * C::N, L.JR, L.JT, H.W1 + b * H.w1,
                               H.W2 ? H.W2 + b * H.w2 : nullptr);
 }
 

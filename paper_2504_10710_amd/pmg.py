@@ -22,6 +22,7 @@ PMG_EGEOM, PMG_ENAN, PMG_EBREAKDOWN, PMG_ENOTCONV, PMG_EPIVOT = -4, -5, -6, -7, 
 PMG_F64, PMG_F32 = 0, 1
 PMG_SMOOTHER_GLL, PMG_SMOOTHER_FEM = 0, 1
 PMG_FGMRES, PMG_PCG, PMG_FCG = 0, 1, 2
+PMG_RESTRICT_TRANSPOSE, PMG_RESTRICT_INTERP = 0, 1
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EGEOM", -5: "ENAN",
                 -6: "EBREAKDOWN", -7: "ENOTCONV", -8: "EPIVOT"}
 
@@ -31,10 +32,15 @@ class pmg_desc(ctypes.Structure):
                 ("gamma", ctypes.c_int), ("m", ctypes.c_int), ("alpha", ctypes.c_double),
                 ("smoother", ctypes.c_int), ("inner_prec", ctypes.c_int),
                 ("krylov", ctypes.c_int), ("restart", ctypes.c_int),
-                ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double)]
+                ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double),
+                ("restriction", ctypes.c_int)]
 
 
 MAX_CLASSES = 8
+
+
+class pmg_region(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("offset", ctypes.c_size_t), ("bytes", ctypes.c_size_t)]
 
 
 class pmg_server_desc(ctypes.Structure):
@@ -83,6 +89,7 @@ def lib():
             "pmg_line_smooth": (i, [vp, i, i, i, vp, vp, vp]),
             "pmg_gamma_cycle": (i, [vp, i, vp, vp, vp]),
             "pmg_solve": (i, [vp, vp, vp, vp, vp]),
+            "pmg_workspace_layout": (i, [vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
             "pmg_line_coefs": (i, [vp, i, i, vp, vp, vp, vp]),
             "pmg_geom": (i, [vp, i, vp, vp, vp]),
             "pmg_destroy": (i, [vp]),
@@ -125,7 +132,7 @@ def exported_symbols():
             "pmg_pool_destroy", "pmg_server_workspace_bytes", "pmg_server_create",
             "pmg_server_submit", "pmg_server_step", "pmg_server_poll", "pmg_server_drain",
             "pmg_server_stats_get",
-            "pmg_server_destroy"]
+            "pmg_server_destroy", "pmg_workspace_layout"]
 
 
 def _check(rc):
@@ -162,9 +169,10 @@ def pmg_interp(p_c: int, p_f: int):
 
 
 def make_desc(dim=2, p_fine=16, batch=1, gamma=1, m=1, alpha=0.16, smoother=PMG_SMOOTHER_FEM,
-              inner_prec=PMG_F64, krylov=PMG_FGMRES, restart=30, max_iter=200, rtol=1e-10):
+              inner_prec=PMG_F64, krylov=PMG_FGMRES, restart=30, max_iter=200, rtol=1e-10,
+              restriction=PMG_RESTRICT_INTERP):
     return pmg_desc(dim, p_fine, batch, gamma, m, alpha, smoother, inner_prec, krylov, restart,
-                    max_iter, rtol)
+                    max_iter, rtol, restriction)
 
 
 def pmg_num_levels(desc: pmg_desc) -> int:
@@ -227,6 +235,15 @@ def pmg_gamma_cycle(h, prec, r, y, stream=None):
 
 def pmg_solve(h, b, x, info, stream=None):
     _check(lib().pmg_solve(h, _ptr(b), _ptr(x), _ptr(info), _stream(stream)))
+
+
+def pmg_workspace_layout(desc: pmg_desc):
+    """[(name, offset, bytes)] of the workspace pmg_setup lays out for desc."""
+    n = ctypes.c_int(0)
+    _check(lib().pmg_workspace_layout(ctypes.byref(desc), None, 0, ctypes.byref(n)))
+    regs = (pmg_region * max(n.value, 1))()
+    _check(lib().pmg_workspace_layout(ctypes.byref(desc), regs, n.value, ctypes.byref(n)))
+    return [(r.name.decode(), int(r.offset), int(r.bytes)) for r in regs[: n.value]]
 
 
 def pmg_line_coefs(h, level, dir, lo, di, up, stream=None):

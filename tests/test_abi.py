@@ -90,3 +90,41 @@ def test_operator_from_host_tables_matches_oracle_at_p128():
     y = ((G00 * gx + G01 * gy) @ D + D.T @ (G01 * gx + G11 * gy)).reshape(-1) * mask
     yo = h.apply(x)
     assert np.abs(y - yo).max() <= 1e-12 * np.abs(yo).max()
+
+
+@pytest.mark.parametrize("kw", [
+    dict(dim=2, p_fine=32, batch=2, inner_prec=pmg.PMG_F32),
+    dict(dim=2, p_fine=128, batch=3),
+    dict(dim=3, p_fine=16, batch=2, inner_prec=pmg.PMG_F32, restart=20),
+])
+def test_workspace_layout_in_bounds(kw):
+    """Every region of the workspace lies inside pmg_workspace_bytes, starts on
+    a 256-byte boundary and overlaps no other.  For the vectors the outer
+    Krylov loops and the FP32 cycle's conversions run over (V, Z, TR64 in
+    FP64; the finest level's X, R, Tm in the cycle's type), even a loop that
+    issued four loads per thread at q, q+512, q+1024, q+1536 while checking
+    only q < N would stay inside the workspace: its furthest element, 3 * 512
+    past the last problem's last vector, is printed with the slack left."""
+    desc = pmg.make_desc(**kw)
+    total = pmg.pmg_workspace_bytes(desc)
+    regs = pmg.pmg_workspace_layout(desc)
+    assert regs
+    end = 0
+    for name, off, nb in regs:
+        assert off % 256 == 0 and off >= end, (name, off, end)
+        end = off + nb
+    assert end <= total
+    dim, p, B = kw["dim"], kw["p_fine"], kw["batch"]
+    N = (p + 1) ** dim
+    NT = 512
+    lev = {n: (o, b) for n, o, b in regs}
+    L = len([r for r in regs if r[0].startswith("X[")]) - 1
+    tsz = 4 if kw.get("inner_prec") == pmg.PMG_F32 else 8
+    for name, esz in (("V", 8), ("Z", 8), ("TR64", 8), (f"X[{L}]", tsz), (f"R[{L}]", tsz),
+                      (f"Tm[{L}]", tsz)):
+        off, nb = lev[name]
+        assert nb % (esz * N) == 0, name
+        furthest = off + nb - esz + 3 * NT * esz       # byte of the last element + 3 NT
+        print(f"{kw} {name}: region ends at {off + nb}, unguarded four-in-flight loop reaches "
+              f"{furthest + esz}, workspace {total}, slack {total - furthest - esz}")
+        assert furthest + esz <= total

@@ -267,7 +267,7 @@ def test_solve_fgmres(case):
         assert rr <= 1.0001e-10, rr
         assert st == 0
         assert abs(int(info["iterations"][b]) - it) <= 1, (info["iterations"][b], it)
-        assert ex < x_tol, (ex, x_tol)
+        assert ex < 1e-7
 
 
 def test_solve_mixed_precision():
@@ -377,7 +377,7 @@ def _check_full(tag, probs, p, gamma, bh, xh, info, restart=30, rst=INTERP, its_
         assert st == 0
         if same_method:
             assert abs(int(info["iterations"][b]) - it) <= its_tol, (info["iterations"][b], it)
-        assert ex < 1e-7
+        assert ex < x_tol, (ex, x_tol)
 
 
 def test_full_size_config2():
@@ -405,13 +405,25 @@ def test_full_size_config3():
     _check_full("cfg3 p=64 gamma=2", probs, p, 2, bh, xh, info, restart=20, same_method=False)
 
 
+def test_full_size_config3_mixed_precision():
+    """Config 4's 3-D shape: config 3 (3-D p = 64) with the FP32 inner cycle
+    and the FP64 outer FGMRES to 1e-10; residual with the oracle's operator
+    and the solution against the FP64 oracle's reference solve (different
+    paths: solutions agree to cond(A) times the residuals, 1e-6 asserted)."""
+    p = 64
+    probs, s, bh, xh, info = _full_solve("cfg3", p, [1], gamma=2, inner_prec=pmg.PMG_F32, restart=20)
+    _check_full("cfg3 p=64 FP32 cycle", probs, p, 2, bh, xh, info, restart=20, same_method=False,
+                x_tol=1e-6)
+
+
 def test_p256_mixed_precision():
     """Largest 2-D shape (p = 256, 8 levels) with the FP32 inner cycle
     (gamma = 3): FP64 residual with the oracle's operator and the solution
     against the FP64 oracle's solve.  The two solves take different paths
     (FP32 cycle; reference with R = P^T), so their solutions differ by up to
-    cond(A) times their 1e-10 residuals, not by rounding: 1e-6 relative
-    (cond(A) of the degree-256 operator is about 1e7)."""
+    cond(A) times their 1e-10 residuals, not by rounding.  cond(A) grows like
+    p^3 on this geometry (dense eigenvalues: 1.6e2, 1.1e3, 8.8e3 at p = 16,
+    32, 64), about 5e5 at p = 256, so the bound is 5e-5; 1e-6 is asserted."""
     p = 256
     probs, s, bh, xh, info = _full_solve("cfg2", p, [11], gamma=3, inner_prec=pmg.PMG_F32)
     _check_full("cfg2 p=256 FP32 cycle", probs, p, 3, bh, xh, info, same_method=False, x_tol=1e-6)
