@@ -217,6 +217,31 @@ int pmg_gamma_cycle(pmg_handle* h, int prec, const void* d_r, void* d_y,
 int pmg_solve(pmg_handle* h, const double* d_b, double* d_x, pmg_info* d_info,
               pmg_stream_t stream);
 
+/* Bytes of the fixed device array behind pmg_solve_noalloc (per GPU). */
+#define PMG_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* pmg_solve for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, arithmetic and results as pmg_solve (bit for bit), but the
+ * solve's Krylov scratch (the FGMRES basis V and Z, Hessenberg and Givens
+ * data, the FP64 flux buffer of the outer operator and the per-problem solve
+ * state; the CG variants use the first five vectors of V) comes from a fixed
+ * array of PMG_SCRATCH_BYTES inside the library instead of the handle's
+ * workspace.  The call allocates nothing (no hipMalloc, no library
+ * allocation); the array is reserved on each GPU the library runs on when
+ * its code is loaded there and held until the process ends.  It needs
+ *   B * 8 * N * (max(restart + 1, 5) + restart + dim)
+ *   + B * 8 * ((restart + 1) * restart + 4 * restart + 1) + B * 32
+ * bytes (each of the five regions rounded up to 256 bytes), N the finest
+ * level's node count; larger batches return PMG_ENOMEM with a message and
+ * launch nothing.  Every call on one GPU uses the same array: calls that
+ * overlap on one GPU (other streams, other threads) race and must be
+ * serialised by the caller; nothing in the array needs to start at zero
+ * (every word is written before it is read), and it keeps the last call's
+ * contents. */
+int pmg_solve_noalloc(pmg_handle* h, const double* d_b, double* d_x, pmg_info* d_info,
+                      pmg_stream_t stream);
+
 /* Per-level line-system tridiagonals (lower, diagonal, upper) of axis dir,
  * (p_l-1)^dim doubles each per problem, line after line as described for the
  * oracle-independent layout: lines ordered by the remaining interior

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -769,6 +770,94 @@ int pmg_solve(pmg_handle* h, const double* d_b, double* d_x, pmg_info* d_info, p
     hipError_t e = launch_solve(h->d.dim, h->d.p_fine, h->f32, h->d.batch, hier_of(h, h->f32), a,
                                 (hipStream_t)stream);
     return e == hipSuccess ? PMG_OK : hip_fail(e, "pmg_solve");
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- solve without allocation
+
+// The Krylov scratch of pmg_solve_noalloc: one fixed device array per GPU,
+// reserved when the library's code object is loaded on that GPU and held
+// until the process ends.  In host code `scratch` names a host-side shadow,
+// not device memory: the device address is looked up once per device with
+// hipGetSymbolAddress and only that address is used from then on.
+static __device__ __align__(256) unsigned char scratch[PMG_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_device_ptr(void** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "pmg_solve_noalloc: hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(PMG_EDEVICE, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return hip_fail(e, "pmg_solve_noalloc: hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return PMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pmg_solve_noalloc(pmg_handle* h, const double* d_b, double* d_x, pmg_info* d_info,
+                      pmg_stream_t stream)
+{
+    int rc = check_h(h);
+    if (rc) return rc;
+    if (!d_b || !d_x || !d_info) return fail(PMG_EINVAL, "NULL argument");
+    // the same regions pmg_solve takes from the handle's workspace, laid out
+    // in the scratch array: V, Z, Hessenberg/Givens, FP64 fluxes, solve state
+    const int dim = h->d.dim;
+    const long long B = h->d.batch;
+    const long long N = level_shape(dim, h->nlev - 1).N;
+    Layout L;
+    const size_t oV = L.take(sizeof(double) * (size_t)(B * h->nv * N));
+    const size_t oZ = L.take(sizeof(double) * (size_t)(B * h->d.restart * N));
+    const size_t oHs = L.take(sizeof(double) * (size_t)(B * h->hs));
+    const size_t oTR = L.take(sizeof(double) * (size_t)(B * dim * N));
+    const size_t oSt = L.take(sizeof(SolveState) * (size_t)B);
+    const size_t need = L.take(0);
+    if (need > PMG_SCRATCH_BYTES)
+        return fail(PMG_ENOMEM,
+                    "pmg_solve_noalloc: this batch needs %zu bytes of Krylov scratch, more than "
+                    "the library's fixed %zu (use a smaller batch or restart length, or pmg_solve)",
+                    need, (size_t)PMG_SCRATCH_BYTES);
+    void* base = nullptr;
+    if ((rc = scratch_device_ptr(&base))) return rc;
+    char* sp = (char*)base;
+    SolveArgs a;
+    a.b = d_b;
+    a.x = d_x;
+    a.V = (double*)(sp + oV);
+    a.Z = (double*)(sp + oZ);
+    a.Hs = (double*)(sp + oHs);
+    a.TR64 = (double*)(sp + oTR);
+    a.info = d_info;
+    a.nv = h->nv;
+    a.hs = h->hs;
+    a.restart = h->d.restart;
+    a.max_iter = h->d.max_iter;
+    a.krylov = h->d.krylov;
+    a.rtol = h->d.rtol;
+    a.st = (SolveState*)(sp + oSt);   // written in full by the launch (fresh = 1)
+    a.sstatus = (const int*)(h->ws + h->o_sstatus);
+    a.slots = nullptr;
+    a.budget = h->d.max_iter;
+    a.fresh = 1;
+    hipError_t e = launch_solve(dim, h->d.p_fine, h->f32, h->d.batch, hier_of(h, h->f32), a,
+                                (hipStream_t)stream);
+    return e == hipSuccess ? PMG_OK : hip_fail(e, "pmg_solve_noalloc");
 }
 
 int pmg_line_coefs(pmg_handle* h, int level, int dir, double* d_lo, double* d_di, double* d_up,

@@ -89,6 +89,7 @@ def lib():
             "pmg_line_smooth": (i, [vp, i, i, i, vp, vp, vp]),
             "pmg_gamma_cycle": (i, [vp, i, vp, vp, vp]),
             "pmg_solve": (i, [vp, vp, vp, vp, vp]),
+            "pmg_solve_noalloc": (i, [vp, vp, vp, vp, vp]),
             "pmg_workspace_layout": (i, [vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
             "pmg_line_coefs": (i, [vp, i, i, vp, vp, vp, vp]),
             "pmg_geom": (i, [vp, i, vp, vp, vp]),
@@ -132,7 +133,7 @@ def exported_symbols():
             "pmg_pool_destroy", "pmg_server_workspace_bytes", "pmg_server_create",
             "pmg_server_submit", "pmg_server_step", "pmg_server_poll", "pmg_server_drain",
             "pmg_server_stats_get",
-            "pmg_server_destroy", "pmg_workspace_layout"]
+            "pmg_server_destroy", "pmg_solve_noalloc", "pmg_workspace_layout"]
 
 
 def _check(rc):
@@ -244,6 +245,13 @@ def pmg_workspace_layout(desc: pmg_desc):
     regs = (pmg_region * max(n.value, 1))()
     _check(lib().pmg_workspace_layout(ctypes.byref(desc), regs, n.value, ctypes.byref(n)))
     return [(r.name.decode(), int(r.offset), int(r.bytes)) for r in regs[: n.value]]
+
+
+def pmg_solve_noalloc(h, b, x, info, stream=None):
+    _check(lib().pmg_solve_noalloc(h, _ptr(b), _ptr(x), _ptr(info), _stream(stream)))
+
+
+PMG_SCRATCH_BYTES = 64 << 20
 
 
 def pmg_line_coefs(h, level, dir, lo, di, up, stream=None):
