@@ -33,7 +33,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=2048)
     ap.add_argument("--p", type=int, default=128)
-    ap.add_argument("--gamma", type=int, default=1)
+    ap.add_argument("--gamma", type=int, default=2)
+    ap.add_argument("--gamma3", type=int, default=2, help="gamma of the 3-D leg")
+    ap.add_argument("--restriction", choices=["interp", "transpose"], default="interp",
+                    help="R of Sec. 3.3: interpolation (reproduces Table 1) or P^T")
     ap.add_argument("--alpha", type=float, default=0.16)
     ap.add_argument("--smoother", choices=["fem", "gll"], default="fem")
     ap.add_argument("--prec", choices=["f64", "f32"], default="f64")
@@ -49,6 +52,11 @@ def parse():
     ap.add_argument("--mixed", type=int, default=1, help="also time the FP32-inner solve")
     ap.add_argument("--components", type=int, default=1,
                     help="also time the operator and line-solve kernels alone")
+    ap.add_argument("--sweep", type=int, default=1,
+                    help="also time gamma = 1, 2, 3, 7 and the R = P^T variant")
+    ap.add_argument("--legs", type=int, default=1,
+                    help="also time 3-D p = 64 and 2-D p = 256, FP64 and FP32 cycle")
+    ap.add_argument("--legs-batch3", type=int, default=256)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     return ap.parse_args()
@@ -118,26 +126,41 @@ def flops_per_solve(dim, p, gamma, m, iters, krylov, restart):
     return total
 
 
-def run_batch(args, prec_name):
-    """Time `steps` whole-path steps of one batch; returns the measurements."""
+def make_problems(dim, B, seed0=0):
+    from paper_2504_10710_amd import inputs
+    make = inputs.config2 if dim == 2 else inputs.config3
+    return [make(seed0 + s) for s in range(B)]
+
+
+def run_batch(args, prec_name, dim=2, p=None, B=None, gamma=None, restriction=None,
+              steps=None, warmup=None, keep=0, restart=None, tag=""):
+    """Time `steps` whole-path steps of one batch; returns the measurements.
+    keep > 0 also returns the solutions of the first `keep` problems."""
     import numpy as np
     import torch
 
     from paper_2504_10710_amd import inputs, pmg
 
     dev = torch.device("cuda:0")
-    B, p = args.batch, args.p
-    dim = 2
+    B = args.batch if B is None else B
+    p = args.p if p is None else p
+    gamma = args.gamma if gamma is None else gamma
+    restriction = args.restriction if restriction is None else restriction
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
+    restart = (args.restart if dim == 2 else 20) if restart is None else restart
     smoother = pmg.PMG_SMOOTHER_FEM if args.smoother == "fem" else pmg.PMG_SMOOTHER_GLL
     prec = pmg.PMG_F32 if prec_name == "f32" else pmg.PMG_F64
     krylov = {"fgmres": pmg.PMG_FGMRES, "pcg": pmg.PMG_PCG, "fcg": pmg.PMG_FCG}[args.krylov]
-    desc = pmg.make_desc(dim=dim, p_fine=p, batch=B, gamma=args.gamma, m=1, alpha=args.alpha,
+    rst = pmg.PMG_RESTRICT_INTERP if restriction == "interp" else pmg.PMG_RESTRICT_TRANSPOSE
+    desc = pmg.make_desc(dim=dim, p_fine=p, batch=B, gamma=gamma, m=1, alpha=args.alpha,
                          smoother=smoother, inner_prec=prec, krylov=krylov,
-                         restart=args.restart, max_iter=500, rtol=args.rtol)
+                         restart=restart, max_iter=600, rtol=args.rtol, restriction=rst)
+    label = f"{tag or prec_name} {dim}-D p={p} gamma={gamma} R={restriction}"
 
     # ---- synthetic inputs (seeded), resident in HBM before timing
     t0 = time.time()
-    probs = [inputs.config2(s) for s in range(B)]
+    probs = make_problems(dim, B)
     ps = inputs.halving_degrees(p, 2)
     coords = []
     for q in ps:
@@ -153,9 +176,10 @@ def run_batch(args, prec_name):
     x = torch.empty_like(f)
     u = torch.empty_like(f)
     torch.cuda.synchronize()
-    print(f"[bench] {prec_name}: inputs ready: B={B} p={p} ws={ws.numel() / 2**30:.2f} GiB "
+    print(f"[bench] {label}: inputs ready: B={B} ws={ws.numel() / 2**30:.2f} GiB "
           f"({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
 
+    # the library enqueues on torch's current stream: the events are recorded there
     stream = torch.cuda.current_stream()
     ev = []
 
@@ -172,13 +196,13 @@ def run_batch(args, prec_name):
         pmg.pmg_lift(h, x, g, u)
         pmg.pmg_destroy(h)
 
-    for i in range(args.warmup):
+    for i in range(warmup):
         step(False)
         torch.cuda.synchronize()
-        print(f"[bench] {prec_name}: warmup step {i} done", file=sys.stderr, flush=True)
+        print(f"[bench] {label}: warmup step {i} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         step(True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t1
@@ -187,17 +211,43 @@ def run_batch(args, prec_name):
     its = nfo["iterations"]
     solve_ms = [a.elapsed_time(bb) for a, bb in ev]
     solve_s = sum(solve_ms) / len(solve_ms) / 1e3
-    ms_per_step = elapsed / args.steps * 1e3
-    value = B * args.steps / elapsed
-    print(f"[bench] {prec_name}: timed {args.steps} steps: {ms_per_step:.1f} ms/step, solve kernel "
-          f"{solve_s * 1e3:.1f} ms, ok {ok}/{B}, its min/med/max {its.min()}/"
+    ms_per_step = elapsed / steps * 1e3
+    value = B * steps / elapsed
+    print(f"[bench] {label}: timed {steps} steps: {ms_per_step:.1f} ms/step ({value:.1f} solves/s), "
+          f"solve kernel {solve_s * 1e3:.1f} ms, ok {ok}/{B}, its min/med/max {its.min()}/"
           f"{int(np.median(its))}/{its.max()}, max relres {nfo['relres'].max():.2e}",
           file=sys.stderr, flush=True)
-    flops = sum(flops_per_solve(dim, p, args.gamma, 1, int(k), args.krylov, args.restart)
-                for k in its)
+    flops = sum(flops_per_solve(dim, p, gamma, 1, int(k), args.krylov, restart) for k in its)
+    xk = x[:keep].cpu().numpy() if keep else None
     return {"value": value, "ms_per_step": ms_per_step, "solve_s": solve_s, "its": its,
             "ok": ok, "flops": flops, "max_relres": float(nfo["relres"].max()),
-            "probs": probs, "ps": ps}
+            "probs": probs, "ps": ps, "x_keep": xk, "dim": dim, "p": p, "B": B,
+            "gamma": gamma, "restriction": restriction, "prec": prec_name}
+
+
+def roofline_of(r, prec_name):
+    """Roofline of the dominant kernel (k_solve) from a run_batch result:
+    algorithmic flops per launch / average launch duration (HIP events)."""
+    achieved = r["flops"] / r["solve_s"] / 1e12
+    peak = PEAK_FP32_TFLOPS if prec_name == "f32" else PEAK_FP64_TFLOPS
+    tname = "float" if prec_name == "f32" else "double"
+    kname = f"k_solve<{tname}, {r['p']}, {r['dim']}>"
+    traffic, src = measured_traffic(kname, r["B"])
+    # the solve's flops are mostly matrix-core contractions (operator and
+    # transfers); MI355X's dense FP64 MFMA peak equals its FP64 vector peak
+    return {"bound": "mfma", "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 5), "traffic": traffic,
+            "traffic_source": src if traffic is not None else None,
+            "kernel": kname, "flops_per_launch": r["flops"],
+            "avg_launch_ms": round(r["solve_s"] * 1e3, 3)}
+
+
+def summary_of(r):
+    import numpy as np
+    return {"value": round(r["value"], 3), "unit": "solves/s", "ms_per_step": round(r["ms_per_step"], 3),
+            "batch": r["B"], "gamma": r["gamma"], "restriction": r["restriction"],
+            "iterations_median": int(np.median(r["its"])), "converged": r["ok"],
+            "max_relres": r["max_relres"]}
 
 
 def cr_words(n):
@@ -324,33 +374,62 @@ def main():
         sys.exit(2)
 
     import numpy as np
+
+    # the oracle baseline runs first, on the host only, before the GPU is touched
+    cpu, oracle_x = (cpu_baseline(args) if args.cpu_seconds > 0 else (None, []))
+
     import torch
 
     torch.cuda.set_device(0)
     B, p, dim = args.batch, args.p, 2
-    r64 = run_batch(args, args.prec)
-    achieved = r64["flops"] / r64["solve_s"] / 1e12
-    peak = PEAK_FP32_TFLOPS if args.prec == "f32" else PEAK_FP64_TFLOPS
-    kname = f"k_solve<{'float' if args.prec == 'f32' else 'double'}, {p}, 2>"
-    traffic, src = measured_traffic(kname, B)
-    # the solve's flops are mostly matrix-core contractions (operator and
-    # transfers); MI355X's dense FP64 MFMA peak equals its FP64 vector peak
-    roofline = {"bound": "mfma", "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 5), "traffic": traffic,
-                "traffic_source": src if traffic is not None else None,
-                "kernel": kname, "flops_per_launch": r64["flops"]}
+    keep = max(len(oracle_x), 1)
+    r64 = run_batch(args, args.prec, keep=keep, tag="headline")
+    roofline = roofline_of(r64, args.prec)
+
+    def oracle_err(r):
+        if not oracle_x:
+            return None
+        errs = [float(np.abs(r["x_keep"][i] - xo).max() / np.abs(xo).max())
+                for i, xo in enumerate(oracle_x)]
+        return {"max_rel_err_vs_fp64_oracle": max(errs), "problems": len(errs)}
+
     mixed = None
     if args.mixed and args.prec == "f64":
-        r32 = run_batch(args, "f32")
-        mixed = {"value": round(r32["value"], 3), "unit": "solves/s", "dtype": "f32 cycle + f64 Krylov",
-                 "ms_per_step": round(r32["ms_per_step"], 3),
-                 "iterations_median": int(np.median(r32["its"])), "converged": r32["ok"],
-                 "max_relres": r32["max_relres"],
-                 "achieved_tflops": round(r32["flops"] / r32["solve_s"] / 1e12, 4),
-                 "speedup_vs_f64": round(r32["value"] / r64["value"], 3)}
+        r32 = run_batch(args, "f32", keep=keep, tag="mixed")
+        mixed = summary_of(r32)
+        mixed.update({"dtype": "f32 cycle + f64 Krylov",
+                      "speedup_vs_f64": round(r32["value"] / r64["value"], 3),
+                      "roofline": roofline_of(r32, "f32"),
+                      "error_vs_fp64_oracle": oracle_err(r32)})
+    sweep = variants = None
+    if args.sweep:
+        sweep = {}
+        for gam in (1, 2, 3, 7):
+            r = r64 if gam == args.gamma else run_batch(args, "f64", gamma=gam, steps=2, warmup=0,
+                                                        tag="sweep")
+            sweep[f"gamma={gam}"] = summary_of(r)
+        variants = {}
+        for prec_name in ("f64", "f32"):
+            r = run_batch(args, prec_name, gamma=1, restriction="transpose", steps=2, warmup=0,
+                          tag="variant")
+            v = summary_of(r)
+            v["roofline"] = roofline_of(r, prec_name)
+            variants[f"R=P^T gamma=1 {prec_name}"] = v
+    legs = None
+    if args.legs:
+        legs = {}
+        for (ldim, lp, lB, lgam) in ((3, 64, args.legs_batch3, args.gamma3), (2, 256, 512, args.gamma)):
+            for prec_name in ("f64", "f32"):
+                r = run_batch(args, prec_name, dim=ldim, p=lp, B=lB, gamma=lgam, steps=2, warmup=1,
+                              tag="leg")
+                v = summary_of(r)
+                v["interior_dofs"] = (lp - 1) ** ldim
+                v["dof_per_s"] = round(r["value"] * (lp - 1) ** ldim, 1)
+                v["roofline"] = roofline_of(r, prec_name)
+                legs[f"{ldim}-D p={lp} {prec_name}"] = v
+                torch.cuda.empty_cache()
     comps = components(args, r64["probs"], r64["ps"]) if args.components else None
     served = serve(args) if args.serve > 0 else None
-    cpu = cpu_baseline(args, r64["probs"], r64["ps"]) if args.cpu_seconds > 0 else None
 
     ndof = (p - 1) ** 2
     value = r64["value"]
@@ -369,15 +448,20 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"2-D deformed square GLL Poisson, p={p}, gamma-cycle {p}->2",
                    "batch": B, "gamma": args.gamma, "m": 1, "alpha": args.alpha,
-                   "smoother": args.smoother, "krylov": args.krylov, "rtol": args.rtol,
+                   "smoother": args.smoother, "restriction": args.restriction,
+                   "krylov": args.krylov, "rtol": args.rtol,
                    "inner_precision": args.prec, "interior_dofs": ndof,
                    "dof_per_s": round(value * ndof, 1),
                    "iterations_median": int(np.median(r64["its"])), "converged": r64["ok"],
-                   "max_relres": r64["max_relres"]},
+                   "max_relres": r64["max_relres"],
+                   "error_vs_fp64_oracle": oracle_err(r64)},
         "roofline": roofline,
         "kernels": comps,
         "cpu_baseline": cpu,
         "mixed_precision": mixed,
+        "gamma_sweep": sweep,
+        "variants": variants,
+        "legs": legs,
         "serving": served,
     }
     print(json.dumps(line), flush=True)
@@ -560,26 +644,71 @@ def serve(args):
             "budget_bytes": budget, "steps": int(steps), "iters_per_step": SERVE_ITERS_PER_STEP}
 
 
-def cpu_baseline(args, probs, ps):
-    """The oracle (plain FP64 C, one thread) on a bounded sample of the same
-    workload: whole solves (setup + lifting + Krylov) of the first problems."""
+def _oracle_solve(args, prob, ps):
     from oracle import oracle as orc
+    oc = [prob.coords(orc.gll(q)[0]) for q in ps]
+    h = orc.Hier(2, ps, oc, gamma=args.gamma, m=1, alpha=args.alpha,
+                 smoother=1 if args.smoother == "fem" else 0,
+                 restriction=orc.RESTRICT_INTERP if args.restriction == "interp" else orc.RESTRICT_TRANSPOSE)
+    bo = h.rhs(prob.f(oc[-1]), prob.g(oc[-1]))
+    x, st, it, _ = getattr(h, args.krylov)(bo, rtol=args.rtol, maxit=600)
+    return x
 
-    smoother = 1 if args.smoother == "fem" else 0
-    solver = args.krylov
+
+def cpu_baseline(args):
+    """The oracle (plain FP64 C) on a bounded sample of the headline workload:
+    whole solves (setup + lifting + Krylov) of problems 0, 1, ... on one host
+    core for about cpu_seconds, then distinct problems on every available core
+    (a thread pool: the oracle's C calls release the interpreter lock) for
+    about cpu_seconds.  Returns the record and the one-core solutions, which
+    the GPU results are compared with."""
+    import concurrent.futures as cf
+    import threading
+
+    from paper_2504_10710_amd import inputs
+
+    ps = inputs.halving_degrees(args.p, 2)
+    probs = make_problems(2, 64)
     t0 = time.perf_counter()
-    n = 0
-    while n < 2 or (time.perf_counter() - t0 < args.cpu_seconds and n < len(probs)):
-        pr = probs[n]
-        oc = [pr.coords(orc.gll(q)[0]) for q in ps]
-        h = orc.Hier(2, ps, oc, gamma=args.gamma, m=1, alpha=args.alpha, smoother=smoother)
-        bo = h.rhs(pr.f(oc[-1]), pr.g(oc[-1]))
-        getattr(h, solver)(bo, rtol=args.rtol, maxit=500)
-        n += 1
-    dt = time.perf_counter() - t0
-    return {"value": round(n / dt, 4), "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} whole solves of the same workload (problems 0..{n - 1}), "
-                      f"{dt:.1f} s on one host core"}
+    xs = []
+    while len(xs) < 1 or (time.perf_counter() - t0 < args.cpu_seconds and len(xs) < 8):
+        xs.append(_oracle_solve(args, probs[len(xs)], ps))
+    dt1 = time.perf_counter() - t0
+    n1 = len(xs)
+    print(f"[bench] oracle on one core: {n1} solves in {dt1:.1f} s", file=sys.stderr, flush=True)
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    lock = threading.Lock()
+    nxt = [n1]
+    done = [0]
+    t_end = time.perf_counter() + args.cpu_seconds
+
+    def worker():
+        while time.perf_counter() < t_end:
+            with lock:
+                i = nxt[0]
+                nxt[0] += 1
+            _oracle_solve(args, make_problems(2, 1, seed0=i)[0], ps)
+            with lock:
+                done[0] += 1
+
+    t1 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=cores) as ex:
+        for fut in [ex.submit(worker) for _ in range(cores)]:
+            fut.result()
+    dtn = time.perf_counter() - t1
+    print(f"[bench] oracle on {cores} cores: {done[0]} solves in {dtn:.1f} s", file=sys.stderr,
+          flush=True)
+    rec = {"value": round(n1 / dt1, 4), "unit": "solves/s", "cores": 1, "kind": "oracle",
+           "sample": f"{n1} whole solves of the headline workload (problems 0..{n1 - 1}), "
+                     f"{dt1:.1f} s on one host core",
+           "all_cores": {"value": round(done[0] / dtn, 4), "unit": "solves/s", "cores": cores,
+                         "sample": f"{done[0]} whole solves of distinct problems, {dtn:.1f} s "
+                                   f"on {cores} threads"}}
+    return rec, xs
 
 
 if __name__ == "__main__":
