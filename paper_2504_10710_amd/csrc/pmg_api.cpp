@@ -237,6 +237,7 @@ struct pmg_handle {
     size_t o_X[MAX_LEVELS], o_R[MAX_LEVELS], o_Tm[MAX_LEVELS], o_TR[MAX_LEVELS];
     size_t o_mass, o_W1, o_W2, o_TR64, o_V, o_Z, o_Hs, o_detmin, o_pivot, o_cinv64, o_cinv32;
     size_t o_sstatus, o_state, o_hier64, o_hier32;
+    size_t o_Cc;   // collapsed coarse cycle, B x ni x ni doubles (0: none)
     // serving pools only: per-slot input staging, right-hand side, solution,
     // info, and the slot list of an admission
     bool pool = false;
@@ -317,6 +318,11 @@ void plan(pmg_handle* h, std::vector<pmg_region>* rec = nullptr)
     h->o_cinv32 = L.take("cinv32", -1, sizeof(float) * (size_t)B);
     h->o_sstatus = L.take("sstatus", -1, sizeof(int) * (size_t)B);
     h->o_state = L.take("state", -1, sizeof(SolveState) * (size_t)B);
+    {
+        const int pc = collapse_p(dim);
+        const long long ni = dim == 2 ? (pc - 1) * (pc - 1) : (pc - 1) * (pc - 1) * (pc - 1);
+        h->o_Cc = d.p_fine > pc ? L.take("Cc", -1, sizeof(double) * (size_t)B * ni * ni) : 0;
+    }
     h->o_hier64 = L.take("hier64", -1, sizeof(Hier<double>));
     h->o_hier32 = L.take("hier32", -1, sizeof(Hier<float>));
     if (h->pool) {
@@ -367,6 +373,7 @@ void fill_hier(pmg_handle* h, Hier<T>& H, bool is32)
     }
     H.cinv = (const T*)(ws + (is32 ? h->o_cinv32 : h->o_cinv64));
     H.cinv64 = (const double*)(ws + h->o_cinv64);
+    H.Cc = h->o_Cc ? (const double*)(ws + h->o_Cc) : nullptr;
     H.W1 = (T*)(ws + h->o_W1);
     H.W2 = dim == 3 ? (T*)(ws + h->o_W2) : nullptr;
     H.w1 = h->w1;
@@ -450,6 +457,8 @@ int pmg_workspace_layout(const pmg_desc* desc, pmg_region* regions, int max_regi
     for (int i = 0; i < (int)rec.size() && i < max_regions; ++i) regions[i] = rec[i];
     return PMG_OK;
 }
+
+static const void* hier_of(pmg_handle* h, bool f32);
 
 static int init_handle(const pmg_desc* desc, void* d_ws, size_t ws_bytes, bool pool,
                        hipStream_t s, pmg_handle** out)
@@ -606,6 +615,9 @@ int pmg_setup(const pmg_desc* desc, const double* const* d_coords, void* d_ws, s
     setup_args(h, a);
     for (int l = 0; l < h->nlev; ++l) a.coords[l] = d_coords[l];
     hipError_t e = launch_setup(h->d.dim, h->d.p_fine, h->nlev, h->d.batch, a, d_info, s);
+    if (e == hipSuccess && h->o_Cc)
+        e = launch_collapse(h->d.dim, h->f32, h->d.batch, hier_of(h, h->f32),
+                            (double*)(h->ws + h->o_Cc), nullptr, s);
     if (e != hipSuccess) {
         delete h;
         return hip_fail(e, "setup kernels");
@@ -1027,6 +1039,8 @@ int pmg_pool_admit(pmg_pool* P, int n, const int* slots, const double* const* d_
     a.nslots = n;
     pmg_info* info = (pmg_info*)(h->ws + h->o_info);
     e = launch_setup(dim, h->d.p_fine, h->nlev, B, a, info, s);
+    if (e == hipSuccess && h->o_Cc)
+        e = launch_collapse(dim, h->f32, n, hier_of(h, h->f32), (double*)(h->ws + h->o_Cc), dslots, s);
     if (e == hipSuccess)
         e = launch_rhs(dim, h->d.p_fine, B, hier64_dev(h), (const double*)(h->ws + h->o_in_f),
                        (const double*)(h->ws + h->o_in_g), (double*)(h->ws + h->o_b),

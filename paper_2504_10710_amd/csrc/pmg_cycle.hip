@@ -23,4 +23,48 @@ hipError_t launch_cycle(int dim, int p, bool f32, int B, const void* H, const vo
     return last();
 }
 
+// Build the dense matrix of the gamma-cycle of level PC (with every level
+// below it) for each problem: column i = M^{-1} e_i for the i-th interior
+// node, the cycle applied by its recursive form to unit vectors in the
+// level's own right-hand side and iterate buffers.  One workgroup per
+// problem (or per listed slot).
+template <class T, int PC, int DIM>
+__global__ void __launch_bounds__(NT, 4) k_collapse(const Hier<T>* __restrict__ Hp,
+                                                    double* __restrict__ Cc,
+                                                    const int* __restrict__ slots)
+{
+    const Hier<T>& H = *Hp;
+    using S = Shape<PC, DIM>;
+    constexpr int ni = ipow(PC - 1, DIM);
+    const int b = slots ? slots[blockIdx.x] : (int)blockIdx.x;
+    const LevelData<T>& L = H.lev[S::LEV];
+    T* r = L.R + (long long)b * S::N;
+    T* x = L.X + (long long)b * S::N;
+    const auto rg = gmem(r);
+    const auto xg = gmem((const T*)x);
+    const auto C = gmem(Cc + (long long)b * ni * ni);
+    for (int i = 0; i < ni; ++i) {
+        const int qi = interior_node<PC, DIM>(i);
+        for (int q = threadIdx.x; q < S::N; q += NT) rg[q] = q == qi ? T(1) : T(0);
+        wg_barrier();
+        gamma_cycle<T, PC, DIM, false>(H, b, r, x);
+        for (int j = threadIdx.x; j < ni; j += NT) C[(long long)i * ni + j] = (double)xg[interior_node<PC, DIM>(j)];
+        wg_barrier();
+    }
+}
+
+hipError_t launch_collapse(int dim, bool f32, int nb, const void* H, double* Cc, const int* slots,
+                           hipStream_t s)
+{
+    if (nb <= 0) return hipSuccess;
+    if (dim == 2) {
+        PMG_TYPED(f32, hipLaunchKernelGGL((k_collapse<T_, collapse_p(2), 2>), dim3(nb), dim3(NT), 0, s,
+                                          (const Hier<T_>*)H, Cc, slots));
+    } else {
+        PMG_TYPED(f32, hipLaunchKernelGGL((k_collapse<T_, collapse_p(3), 3>), dim3(nb), dim3(NT), 0, s,
+                                          (const Hier<T_>*)H, Cc, slots));
+    }
+    return last();
+}
+
 }  // namespace pmg
