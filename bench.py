@@ -33,7 +33,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=2048)
     ap.add_argument("--p", type=int, default=128)
-    ap.add_argument("--gamma", type=int, default=2)
+    ap.add_argument("--gamma", type=int, default=3)
     ap.add_argument("--gamma3", type=int, default=2, help="gamma of the 3-D leg")
     ap.add_argument("--restriction", choices=["interp", "transpose"], default="interp",
                     help="R of Sec. 3.3: interpolation (reproduces Table 1) or P^T")

@@ -237,7 +237,7 @@ struct pmg_handle {
     size_t o_X[MAX_LEVELS], o_R[MAX_LEVELS], o_Tm[MAX_LEVELS], o_TR[MAX_LEVELS];
     size_t o_mass, o_W1, o_W2, o_TR64, o_V, o_Z, o_Hs, o_detmin, o_pivot, o_cinv64, o_cinv32;
     size_t o_sstatus, o_state, o_hier64, o_hier32;
-    size_t o_Cc;   // collapsed coarse cycle, B x ni x ni doubles (0: none)
+    size_t o_Cc[MAX_LEVELS];   // collapsed coarse cycles, B x ni x ni doubles (0: none)
     // serving pools only: per-slot input staging, right-hand side, solution,
     // info, and the slot list of an admission
     bool pool = false;
@@ -318,10 +318,19 @@ void plan(pmg_handle* h, std::vector<pmg_region>* rec = nullptr)
     h->o_cinv32 = L.take("cinv32", -1, sizeof(float) * (size_t)B);
     h->o_sstatus = L.take("sstatus", -1, sizeof(int) * (size_t)B);
     h->o_state = L.take("state", -1, sizeof(SolveState) * (size_t)B);
-    {
-        const int pc = collapse_p(dim);
-        const long long ni = dim == 2 ? (pc - 1) * (pc - 1) : (pc - 1) * (pc - 1) * (pc - 1);
-        h->o_Cc = d.p_fine > pc ? L.take("Cc", -1, sizeof(double) * (size_t)B * ni * ni) : 0;
+    // A coarse level is collapsed when its matrix pays for itself: building
+    // it costs about ni cycles of that level, and every visit afterwards
+    // saves about one; a level is entered gamma^depth times per cycle, so
+    // with solves of about 16 iterations or more the build is repaid when
+    // gamma^depth >= ni / 16.
+    for (int l = 0; l < h->nlev; ++l) {
+        const int pl = 2 << l;
+        const long long ni = dim == 2 ? (pl - 1) * (pl - 1) : (pl - 1) * (pl - 1) * (pl - 1);
+        double visits = 1.0;
+        for (int k = l; k < h->nlev - 1; ++k) visits *= d.gamma;
+        const bool coll = (pl == collapse_lo(dim) || pl == collapse_p(dim)) && d.p_fine > pl &&
+                          16.0 * visits >= (double)ni;
+        h->o_Cc[l] = coll ? L.take("Cc", l, sizeof(double) * (size_t)B * ni * ni) : 0;
     }
     h->o_hier64 = L.take("hier64", -1, sizeof(Hier<double>));
     h->o_hier32 = L.take("hier32", -1, sizeof(Hier<float>));
@@ -373,7 +382,7 @@ void fill_hier(pmg_handle* h, Hier<T>& H, bool is32)
     }
     H.cinv = (const T*)(ws + (is32 ? h->o_cinv32 : h->o_cinv64));
     H.cinv64 = (const double*)(ws + h->o_cinv64);
-    H.Cc = h->o_Cc ? (const double*)(ws + h->o_Cc) : nullptr;
+    for (int l = 0; l < h->nlev; ++l) H.Cc[l] = h->o_Cc[l] ? (const double*)(ws + h->o_Cc[l]) : nullptr;
     H.W1 = (T*)(ws + h->o_W1);
     H.W2 = dim == 3 ? (T*)(ws + h->o_W2) : nullptr;
     H.w1 = h->w1;
@@ -615,9 +624,10 @@ int pmg_setup(const pmg_desc* desc, const double* const* d_coords, void* d_ws, s
     setup_args(h, a);
     for (int l = 0; l < h->nlev; ++l) a.coords[l] = d_coords[l];
     hipError_t e = launch_setup(h->d.dim, h->d.p_fine, h->nlev, h->d.batch, a, d_info, s);
-    if (e == hipSuccess && h->o_Cc)
-        e = launch_collapse(h->d.dim, h->f32, h->d.batch, hier_of(h, h->f32),
-                            (double*)(h->ws + h->o_Cc), nullptr, s);
+    for (int l = 0; l < h->nlev && e == hipSuccess; ++l)   // lower level first
+        if (h->o_Cc[l])
+            e = launch_collapse(h->d.dim, 2 << l, h->f32, h->d.batch, hier_of(h, h->f32),
+                                (double*)(h->ws + h->o_Cc[l]), nullptr, s);
     if (e != hipSuccess) {
         delete h;
         return hip_fail(e, "setup kernels");
@@ -1039,8 +1049,10 @@ int pmg_pool_admit(pmg_pool* P, int n, const int* slots, const double* const* d_
     a.nslots = n;
     pmg_info* info = (pmg_info*)(h->ws + h->o_info);
     e = launch_setup(dim, h->d.p_fine, h->nlev, B, a, info, s);
-    if (e == hipSuccess && h->o_Cc)
-        e = launch_collapse(dim, h->f32, n, hier_of(h, h->f32), (double*)(h->ws + h->o_Cc), dslots, s);
+    for (int l = 0; l < h->nlev && e == hipSuccess; ++l)   // lower level first
+        if (h->o_Cc[l])
+            e = launch_collapse(dim, 2 << l, h->f32, n, hier_of(h, h->f32),
+                                (double*)(h->ws + h->o_Cc[l]), dslots, s);
     if (e == hipSuccess)
         e = launch_rhs(dim, h->d.p_fine, B, hier64_dev(h), (const double*)(h->ws + h->o_in_f),
                        (const double*)(h->ws + h->o_in_g), (double*)(h->ws + h->o_b),

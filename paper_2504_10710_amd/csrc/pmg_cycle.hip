@@ -25,9 +25,10 @@ hipError_t launch_cycle(int dim, int p, bool f32, int B, const void* H, const vo
 
 // Build the dense matrix of the gamma-cycle of level PC (with every level
 // below it) for each problem: column i = M^{-1} e_i for the i-th interior
-// node, the cycle applied by its recursive form to unit vectors in the
-// level's own right-hand side and iterate buffers.  One workgroup per
-// problem (or per listed slot).
+// node, the cycle applied to unit vectors in the level's own right-hand side
+// and iterate buffers, with the levels below PC applied by their matrices
+// where those are already built.  One workgroup per problem (or per listed
+// slot).
 template <class T, int PC, int DIM>
 __global__ void __launch_bounds__(NT, 4) k_collapse(const Hier<T>* __restrict__ Hp,
                                                     double* __restrict__ Cc,
@@ -47,22 +48,30 @@ __global__ void __launch_bounds__(NT, 4) k_collapse(const Hier<T>* __restrict__ 
         const int qi = interior_node<PC, DIM>(i);
         for (int q = threadIdx.x; q < S::N; q += NT) rg[q] = q == qi ? T(1) : T(0);
         wg_barrier();
-        gamma_cycle<T, PC, DIM, false>(H, b, r, x);
+        gamma_cycle<T, PC, DIM, PC / 2>(H, b, r, x);
         for (int j = threadIdx.x; j < ni; j += NT) C[(long long)i * ni + j] = (double)xg[interior_node<PC, DIM>(j)];
         wg_barrier();
     }
 }
 
-hipError_t launch_collapse(int dim, bool f32, int nb, const void* H, double* Cc, const int* slots,
-                           hipStream_t s)
+hipError_t launch_collapse(int dim, int pc, bool f32, int nb, const void* H, double* Cc,
+                           const int* slots, hipStream_t s)
 {
     if (nb <= 0) return hipSuccess;
-    if (dim == 2) {
-        PMG_TYPED(f32, hipLaunchKernelGGL((k_collapse<T_, collapse_p(2), 2>), dim3(nb), dim3(NT), 0, s,
-                                          (const Hier<T_>*)H, Cc, slots));
+    if (dim == 2 && pc == collapse_lo(2)) {
+        PMG_TYPED(f32, hipLaunchKernelGGL((k_collapse<T_, collapse_lo(2), 2>), dim3(nb), dim3(NT), 0,
+                                          s, (const Hier<T_>*)H, Cc, slots));
+    } else if (dim == 2 && pc == collapse_p(2)) {
+        PMG_TYPED(f32, hipLaunchKernelGGL((k_collapse<T_, collapse_p(2), 2>), dim3(nb), dim3(NT), 0,
+                                          s, (const Hier<T_>*)H, Cc, slots));
+    } else if (dim == 3 && pc == collapse_lo(3)) {
+        PMG_TYPED(f32, hipLaunchKernelGGL((k_collapse<T_, collapse_lo(3), 3>), dim3(nb), dim3(NT), 0,
+                                          s, (const Hier<T_>*)H, Cc, slots));
+    } else if (dim == 3 && pc == collapse_p(3)) {
+        PMG_TYPED(f32, hipLaunchKernelGGL((k_collapse<T_, collapse_p(3), 3>), dim3(nb), dim3(NT), 0,
+                                          s, (const Hier<T_>*)H, Cc, slots));
     } else {
-        PMG_TYPED(f32, hipLaunchKernelGGL((k_collapse<T_, collapse_p(3), 3>), dim3(nb), dim3(NT), 0, s,
-                                          (const Hier<T_>*)H, Cc, slots));
+        return hipErrorInvalidValue;
     }
     return last();
 }

@@ -82,9 +82,9 @@ struct Hier {
     LevelData<T> lev[MAX_LEVELS];
     const T* cinv;       // [B] 1 / A_0 of the one interior node of level 0
     const double* cinv64;   // the same in FP64 (the coarsest solve stays FP64)
-    const double* Cc;    // [B][ni][ni] the gamma-cycle of level collapse_p(DIM) as a dense
-                         // matrix over its ni interior nodes, column after column; null
-                         // while it is being built or when the finest level is that coarse
+    const double* Cc[MAX_LEVELS];   // [B][ni][ni] the gamma-cycle of that level (with the
+                         // levels below it) as a dense matrix over its ni interior
+                         // nodes, column after column; null where not collapsed
     T* W1;               // [B][w1] transfer temporaries
     T* W2;               // [B][w2]
     long long w1, w2;    // per-problem sizes of W1, W2
@@ -1253,12 +1253,15 @@ __device__ void smooth_step(const Hier<T>& H, int b, int dir, const T* r, T* x, 
     line_cr<T, P, DIM, true>(L.cr[dir] + (long long)b * 3 * S::CRW * S::NL, dir, tmp, x, H.alpha);
 }
 
-// Level whose gamma-cycle (with everything below it) is applied as one dense
-// matrix: the cycle is linear in its right-hand side (Alg. 2 is a fixed
-// sequence of linear steps), so M_c^{-1} r = C r with C = M_c^{-1} built once
-// per problem at setup from the cycle itself (k_collapse).  49 interior
-// nodes in 2-D (p = 8), 27 in 3-D (p = 4).
-__host__ __device__ constexpr int collapse_p(int dim) { return dim == 2 ? 8 : 4; }
+// Levels whose gamma-cycle (with everything below it) is applied as one
+// dense matrix: the cycle is linear in its right-hand side (Alg. 2 is a
+// fixed sequence of linear steps), so M_c^{-1} r = C r with C = M_c^{-1}
+// built once per problem at setup from the cycle itself (k_collapse): first
+// the lower level from the recursive cycle, then the upper one from the
+// cycle that uses the lower matrix.  2-D: p = 8 and 16 (49 and 225 interior
+// nodes); 3-D: p = 4 and 8 (27 and 343).
+__host__ __device__ constexpr int collapse_p(int dim) { return dim == 2 ? 16 : 8; }
+__host__ __device__ constexpr int collapse_lo(int dim) { return collapse_p(dim) / 2; }
 
 // node index of interior node number i (interior nodes in lexicographic order)
 template <int P, int DIM>
@@ -1292,17 +1295,17 @@ __device__ void collapsed_solve(const double* C_, const T* r_, T* x_)
 // x = M_l^{-1} r (Alg. 2).  Readings: pre-smoothing m steps per axis in axis
 // order, then gamma passes of {coarse correction of the current iterate,
 // m post-smoothing steps per axis in reverse axis order}; level 0 (p = 2,
-// one interior node) is solved exactly.  With COLLAPSED the level
-// collapse_p(DIM) is applied as its dense matrix when the hierarchy has one.
-template <class T, int P, int DIM, bool COLLAPSED = true>
+// one interior node) is solved exactly.  Levels of degree <= CMAX that the
+// hierarchy holds a dense matrix for are applied as that matrix.
+template <class T, int P, int DIM, int CMAX = collapse_p(DIM)>
 __device__ __attribute__((noinline)) void gamma_cycle(const Hier<T>& H, int b, const T* r, T* x)
 {
     using S = Shape<P, DIM>;
     const LevelData<T>& L = lvl<T, P, DIM>(H);
-    if constexpr (COLLAPSED && P == collapse_p(DIM)) {
-        if (H.Cc) {
+    if constexpr (P <= CMAX && P >= collapse_lo(DIM)) {
+        if (H.Cc[S::LEV]) {
             constexpr int ni = ipow(P - 1, DIM);
-            collapsed_solve<T, P, DIM>(H.Cc + (long long)b * ni * ni, r, x);
+            collapsed_solve<T, P, DIM>(H.Cc[S::LEV] + (long long)b * ni * ni, r, x);
             return;
         }
     }
@@ -1342,7 +1345,7 @@ __device__ __attribute__((noinline)) void gamma_cycle(const Hier<T>& H, int b, c
             apply_level<T, P, DIM, true>(L.G + (long long)b * S::NC * S::N, L.D, L.DT,
                                          L.TR + (long long)b * DIM * S::N, x, r, tmp);
             restrict_level<T, P, DIM>(tmp, rc, L.JR, L.JT, w1, w2);
-            gamma_cycle<T, P / 2, DIM, COLLAPSED>(H, b, rc, xc);
+            gamma_cycle<T, P / 2, DIM, CMAX>(H, b, rc, xc);
             prolong_level<T, P, DIM>(xc, x, L.J, L.JT, w1, w2);
             for (int dir = DIM - 1; dir >= 0; --dir)
                 for (int s = 0; s < H.m; ++s) smooth_step<T, P, DIM>(H, b, dir, r, x, false);

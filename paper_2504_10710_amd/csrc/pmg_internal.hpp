@@ -82,10 +82,11 @@ hipError_t launch_line_smooth(int dim, int p, bool f32, int B, const void* H, in
                               const void* r, void* x, hipStream_t s);
 hipError_t launch_cycle(int dim, int p, bool f32, int B, const void* H, const void* r,
                         void* y, hipStream_t s);
-// dense matrices of the collapsed coarse cycle (level collapse_p(dim)) for
-// nb problems (all, or the listed slots); H's Cc must still be null
-hipError_t launch_collapse(int dim, bool f32, int nb, const void* H, double* Cc, const int* slots,
-                           hipStream_t s);
+// dense matrices of the collapsed coarse cycle of level pc (collapse_lo(dim)
+// or collapse_p(dim); the lower one first) for nb problems (all, or the
+// listed slots)
+hipError_t launch_collapse(int dim, int pc, bool f32, int nb, const void* H, double* Cc,
+                           const int* slots, hipStream_t s);
 // grid = B workgroups (problem b = workgroup, or a.slots[workgroup])
 hipError_t launch_solve_f64(int dim, int p, bool f32, int B, const void* H, const SolveArgs& a,
                             hipStream_t s);
