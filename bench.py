@@ -34,7 +34,9 @@ def parse():
     ap.add_argument("--batch", type=int, default=2048)
     ap.add_argument("--p", type=int, default=128)
     ap.add_argument("--gamma", type=int, default=3)
-    ap.add_argument("--gamma3", type=int, default=2, help="gamma of the 3-D leg")
+    ap.add_argument("--gamma3", type=int, default=1, help="gamma of the 3-D leg")
+    ap.add_argument("--restriction3", choices=["interp", "transpose"], default="transpose",
+                    help="R of the 3-D leg (the paper has no 3-D experiment)")
     ap.add_argument("--restriction", choices=["interp", "transpose"], default="interp",
                     help="R of Sec. 3.3: interpolation (reproduces Table 1) or P^T")
     ap.add_argument("--alpha", type=float, default=0.16)
@@ -56,7 +58,7 @@ def parse():
                     help="also time gamma = 1, 2, 3, 7 and the R = P^T variant")
     ap.add_argument("--legs", type=int, default=1,
                     help="also time 3-D p = 64 and 2-D p = 256, FP64 and FP32 cycle")
-    ap.add_argument("--legs-batch3", type=int, default=256)
+    ap.add_argument("--legs-batch3", type=int, default=128)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     return ap.parse_args()
@@ -418,10 +420,11 @@ def main():
     legs = None
     if args.legs:
         legs = {}
-        for (ldim, lp, lB, lgam) in ((3, 64, args.legs_batch3, args.gamma3), (2, 256, 512, args.gamma)):
+        for (ldim, lp, lB, lgam, lrst) in ((3, 64, args.legs_batch3, args.gamma3, args.restriction3),
+                                           (2, 256, 512, args.gamma, args.restriction)):
             for prec_name in ("f64", "f32"):
-                r = run_batch(args, prec_name, dim=ldim, p=lp, B=lB, gamma=lgam, steps=2, warmup=1,
-                              tag="leg")
+                r = run_batch(args, prec_name, dim=ldim, p=lp, B=lB, gamma=lgam, restriction=lrst,
+                              steps=2, warmup=1, tag="leg")
                 v = summary_of(r)
                 v["interior_dofs"] = (lp - 1) ** ldim
                 v["dof_per_s"] = round(r["value"] * (lp - 1) ** ldim, 1)
@@ -467,24 +470,52 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-# (dim, p, slots, inner precision).  A class with 1024 slots can fill the chip
-# by itself (256 CUs x 2 resident one-problem workgroups, twice over); 3-D
-# p = 64 slots cost 178 MB each (FP64 cycle: the FP32 one leaves one problem
-# in eight needing half again as many iterations), so that class holds 768.
+# (dim, p, slots, inner precision, gamma, restriction).  A class with 1024
+# slots can fill the chip by itself (256 CUs x 2 resident one-problem
+# workgroups, twice over); 3-D p = 64 slots cost about 180 MB each, so that
+# class holds 768.  2-D: the restriction by interpolation that reproduces
+# Table 1, gamma per class the fastest on that shape.  3-D (the paper has no
+# 3-D experiment to decide the restriction): R = P^T, gamma 1 (11 iterations
+# at p = 64, where interpolation needs 69 at gamma 2 and 26 at gamma 4).
+# 3-D p = 64 keeps the FP64 cycle: with the FP32 cycle and R = P^T about one
+# problem in five of the served mix stagnates between 1e-8 and 1e-6.
 SERVE_CLASSES = [
-    (2, 16, 1024, "f32"), (2, 32, 1024, "f32"), (2, 64, 1024, "f32"), (2, 128, 1024, "f32"),
-    (3, 16, 1024, "f32"), (3, 32, 1024, "f32"), (3, 64, 768, "f64"),
+    (2, 16, 1024, "f32", 2, "interp"), (2, 32, 1024, "f32", 3, "interp"),
+    (2, 64, 1024, "f32", 3, "interp"), (2, 128, 1024, "f32", 3, "interp"),
+    (3, 16, 1024, "f32", 1, "transpose"), (3, 32, 1024, "f32", 1, "transpose"),
+    (3, 64, 768, "f64", 1, "transpose"),
 ]
+
+
+def _rst(name):
+    from paper_2504_10710_amd import pmg
+    return pmg.PMG_RESTRICT_INTERP if name == "interp" else pmg.PMG_RESTRICT_TRANSPOSE
 SERVE_BUDGET_FRAC = 0.8     # admission budget: this share of the slot pools' bytes
 SERVE_ITERS_PER_STEP = 16   # outer iterations of every running solve per server step
+SERVE_ORACLE_SAMPLE = 4     # served results re-checked with the oracle's operator
+
+
+def _request_arrays(item):
+    """Host arrays of one request: per-level coordinates, f and g."""
+    from paper_2504_10710_amd import inputs, pmg
+    dim, p, prob = item
+    ps = inputs.halving_degrees(p, 2)
+    coords = [prob.coords(pmg.pmg_gll(q)[0]) for q in ps]
+    X = coords[-1]
+    return coords, prob.f(X), prob.g(X)
 
 
 def serve(args):
     """Served stream: continuous batching of mixed 2-D/3-D requests through the
-    library's server (mixed precision, graph-replayed steps, byte-budget
-    admission).  Pass 1 submits every request at once (saturated throughput);
-    pass 2 paces Poisson arrivals at serve_load x that throughput and reports
-    per-request latency (arrival to retirement)."""
+    library's server (FP32 cycle, FP64 Krylov, graph-replayed steps,
+    byte-budget admission), every request its own seeded problem.  Pass 1
+    submits every request at once (saturated throughput); pass 2 paces
+    Poisson arrivals at serve_load x that throughput and reports per-request
+    latency (arrival to retirement).  Baselines: the same requests solved
+    the plain way, one batched pmg_solve per class, with the FP64 and with
+    the FP32 cycle."""
+    import concurrent.futures as cf
+
     import numpy as np
     import torch
 
@@ -492,39 +523,37 @@ def serve(args):
 
     dev = torch.device("cuda:0")
     torch.cuda.empty_cache()         # the batch runs' workspaces go back first
-    classes, bank = [], []
-    for dim, p, slots, prec in SERVE_CLASSES:
-        classes.append(pmg.make_desc(dim=dim, p_fine=p, batch=slots, gamma=1, alpha=0.16,
+    classes = []
+    for dim, p, slots, prec, gam, rst in SERVE_CLASSES:
+        classes.append(pmg.make_desc(dim=dim, p_fine=p, batch=slots, gamma=gam, alpha=0.16,
                                      smoother=pmg.PMG_SMOOTHER_FEM,
                                      inner_prec=pmg.PMG_F32 if prec == "f32" else pmg.PMG_F64,
-                                     restart=30 if dim == 2 else 20, max_iter=300, rtol=1e-10))
+                                     restart=30 if dim == 2 else 20, max_iter=400, rtol=1e-10,
+                                     restriction=_rst(rst)))
     footprint = [pmg.pmg_pool_workspace_bytes(c) // c.batch for c in classes]
     budget = int(sum(f * c.batch for f, c in zip(footprint, classes)) * SERVE_BUDGET_FRAC)
     sdesc = pmg.make_server_desc(classes, iters_per_step=SERVE_ITERS_PER_STEP, budget_bytes=budget)
-    # a bank of distinct seeded problems per class; request i of class c uses
-    # bank entry i mod K (every request still runs its own setup and solve)
-    K = 8
-    for ci, (dim, p, _, _) in enumerate(SERVE_CLASSES):
-        ps = inputs.halving_degrees(p, 2)
-        entries = []
-        for k in range(K):
-            prob = inputs.config2(1000 + 31 * ci + k) if dim == 2 else inputs.config3(1000 + 31 * ci + k)
-            coords = [torch.from_numpy(prob.coords(pmg.pmg_gll(q)[0])).to(dev).contiguous() for q in ps]
-            X = prob.coords(pmg.pmg_gll(p)[0])
-            entries.append((coords, torch.from_numpy(prob.f(X)).to(dev), torch.from_numpy(prob.g(X)).to(dev)))
-        bank.append(entries)
-    stream = inputs.served_stream(args.serve, seed=7)
-    cls_of = {(d, p): i for i, (d, p, _, _) in enumerate(SERVE_CLASSES)}
+    stream = inputs.served_stream(args.serve, seed=7, amp_max=0.15)
+    cls_of = {(d, p): i for i, (d, p, _, _, _, _) in enumerate(SERVE_CLASSES)}
     reqs = [cls_of[(d, p)] for d, p, _ in stream]
+    n = len(reqs)
+    t0 = time.time()
+    with cf.ThreadPoolExecutor(max_workers=16) as ex:
+        host = list(ex.map(_request_arrays, stream))
+    data = []
+    for coords, f, g in host:
+        data.append(([torch.from_numpy(c).to(dev).contiguous() for c in coords],
+                      torch.from_numpy(f).to(dev), torch.from_numpy(g).to(dev)))
+    del host
     torch.cuda.synchronize()
+    print(f"[bench] serving: {n} requests, each its own problem, inputs ready "
+          f"({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
 
     def run(arrivals):
         srv = pmg.pmg_server_create(sdesc, ws)
-        n = len(reqs)
         outs, tickets, t_arr, t_done = [None] * n, [None] * n, np.zeros(n), np.zeros(n)
         nxt, done, its, worst = 0, 0, [], 0.0
         open_, req_of = set(), {}
-        seen = [0] * len(SERVE_CLASSES)
         t0 = time.perf_counter()
         last_print = t0
         while done < n:
@@ -534,11 +563,9 @@ def serve(args):
                       f"{pmg.pmg_server_stats_get(srv)}", file=sys.stderr, flush=True)
             now = time.perf_counter() - t0
             while nxt < n and arrivals[nxt] <= now:
-                c = reqs[nxt]
-                coords, f, g = bank[c][seen[c] % K]
-                seen[c] += 1
+                coords, f, g = data[nxt]
                 outs[nxt] = torch.empty_like(f)
-                tickets[nxt] = pmg.pmg_server_submit(srv, c, coords, f, g, outs[nxt])
+                tickets[nxt] = pmg.pmg_server_submit(srv, reqs[nxt], coords, f, g, outs[nxt])
                 req_of[tickets[nxt]] = nxt
                 t_arr[nxt] = max(arrivals[nxt], 0.0)
                 open_.add(nxt)
@@ -558,41 +585,36 @@ def serve(args):
                 t_done[i] = now
                 done += 1
                 its.append(int(info["iterations"]))
-                if info["status"] != 0:
-                    worst = float("inf")
-                else:
-                    worst = max(worst, float(info["relres"]))
-                outs[i] = None
+                worst = float("inf") if info["status"] != 0 else max(worst, float(info["relres"]))
         makespan = time.perf_counter() - t0
         steps = pmg.pmg_server_stats_get(srv)["steps"]
         pmg.pmg_server_destroy(srv)
         lat = (t_done - t_arr) * 1e3
         last = {f"{d}d_p{p}": round(float(max((t_done[i] for i in range(n) if reqs[i] == c),
                                               default=0.0)), 4)
-                for c, (d, p, _, _) in enumerate(SERVE_CLASSES)}
-        return makespan, lat, steps, worst, its, last
+                for c, (d, p, _, _, _, _) in enumerate(SERVE_CLASSES)}
+        return makespan, lat, steps, worst, its, last, outs
 
-    def plain_fp64():
-        """The same request mix solved the plain way: FP64 inner cycle, one
-        one-shot batched pmg_solve per class over all of that class's
-        requests (setup, lifting, solve, lift), classes back to back."""
+    def plain(prec):
+        """The same requests solved the plain way: one one-shot batched
+        pmg_solve per class over all of that class's requests (setup,
+        lifting, solve, lift), classes back to back."""
         t0 = time.perf_counter()
         per_class = {}
-        for ci, (dim, p, _, _) in enumerate(SERVE_CLASSES):
-            cnt = sum(1 for c in reqs if c == ci)
-            if cnt == 0:
+        for ci, (dim, p, _, _, gam, rst) in enumerate(SERVE_CLASSES):
+            idx = [i for i in range(n) if reqs[i] == ci]
+            if not idx:
                 continue
             tc = time.perf_counter()
             d = classes[ci]
-            desc = pmg.make_desc(dim=dim, p_fine=p, batch=cnt, gamma=d.gamma, alpha=d.alpha,
-                                 smoother=d.smoother, inner_prec=pmg.PMG_F64, restart=d.restart,
-                                 max_iter=d.max_iter, rtol=d.rtol)
-            ent = [bank[ci][k % K] for k in range(cnt)]
-            cs = [torch.stack([e[0][l] for e in ent]) for l in range(len(ent[0][0]))]
-            f = torch.stack([e[1] for e in ent])
-            g = torch.stack([e[2] for e in ent])
+            desc = pmg.make_desc(dim=dim, p_fine=p, batch=len(idx), gamma=gam, alpha=d.alpha,
+                                 smoother=d.smoother, inner_prec=prec, restart=d.restart,
+                                 max_iter=d.max_iter, rtol=d.rtol, restriction=_rst(rst))
+            cs = [torch.stack([data[i][0][l] for i in idx]) for l in range(len(data[idx[0]][0]))]
+            f = torch.stack([data[i][1] for i in idx])
+            g = torch.stack([data[i][2] for i in idx])
             wsp = torch.empty(pmg.pmg_workspace_bytes(desc), dtype=torch.uint8, device=dev)
-            info = torch.empty(cnt * pmg.INFO_BYTES, dtype=torch.uint8, device=dev)
+            info = torch.empty(len(idx) * pmg.INFO_BYTES, dtype=torch.uint8, device=dev)
             b = torch.empty_like(f)
             x = torch.empty_like(f)
             h = pmg.pmg_setup(desc, cs, wsp, info)
@@ -601,39 +623,57 @@ def serve(args):
             pmg.pmg_lift(h, x, g, b)
             torch.cuda.synchronize()
             nfo = pmg.info_to_numpy(info)
-            assert np.all(nfo["status"] == 0), (dim, p)
+            bad = np.flatnonzero(nfo["status"] != 0)
+            if len(bad):
+                print(f"[bench] plain {dim}-D p={p} prec={prec}: {len(bad)} of {len(idx)} not "
+                      f"converged: " + ", ".join(
+                          f"req {idx[k]} status {nfo['status'][k]} its {nfo['iterations'][k]} "
+                          f"relres {nfo['relres'][k]:.2e}" for k in bad[:8]),
+                      file=sys.stderr, flush=True)
+            failed[prec] = failed.get(prec, 0) + len(bad)
             pmg.pmg_destroy(h)
-            del wsp
+            del wsp, cs, f, g, b, x
             per_class[f"{dim}d_p{p}"] = round(time.perf_counter() - tc, 4)
-        return len(reqs) / (time.perf_counter() - t0), per_class
+        torch.cuda.empty_cache()
+        return n / (time.perf_counter() - t0), per_class
 
-    n = len(reqs)
-    plain_fp64()                     # warm-up (module load, graph-free path)
-    plain_thr, plain_cls = plain_fp64()
-    print(f"[bench] served mix, plain FP64 batched per class: {plain_thr:.1f} solves/s "
-          f"(seconds per class: {plain_cls})", file=sys.stderr, flush=True)
-    torch.cuda.empty_cache()         # the plain batches' workspaces go back before the pools
+    failed = {}
+    plain(pmg.PMG_F32)               # warm-up (module load, graph-free path)
+    failed.clear()
+    plain64, plain64_cls = plain(pmg.PMG_F64)
+    plain32, plain32_cls = plain(pmg.PMG_F32)
+    print(f"[bench] served mix, plain batched per class: FP64 cycle {plain64:.1f}, FP32 cycle "
+          f"{plain32:.1f} solves/s (seconds per class FP32: {plain32_cls})", file=sys.stderr,
+          flush=True)
     ws = torch.empty(pmg.pmg_server_workspace_bytes(sdesc), dtype=torch.uint8, device=dev)
-    mk, lat_sat, steps_sat, worst_sat, its, last_sat = run(np.zeros(n))
+    mk, lat_sat, steps_sat, worst_sat, its, last_sat, outs_sat = run(np.zeros(n))
     print(f"[bench] served saturated: last completion per class (s): {last_sat}",
           file=sys.stderr, flush=True)
+    # a sample of served results re-checked with the oracle's FP64 operator:
+    # relative residual of w = u - v (interior) against the oracle's b
+    check = oracle_check_served(stream, reqs, outs_sat) if args.cpu_seconds > 0 else None
+    del outs_sat
     thr = n / mk
     rate = args.serve_load * thr
     rng = np.random.default_rng(11)
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n))
-    mk2, lat, steps, worst, _, _ = run(arrivals)
+    mk2, lat, steps, worst, _, _, _ = run(arrivals)
     mix = {f"{d}d_p{p}": int(sum(1 for c in reqs if SERVE_CLASSES[c][:2] == (d, p)))
-           for d, p, _, _ in SERVE_CLASSES}
+           for d, p, _, _, _, _ in SERVE_CLASSES}
     print(f"[bench] served: saturated {thr:.1f} req/s, paced at {rate:.1f} req/s: "
           f"p50 {np.percentile(lat, 50):.1f} ms p99 {np.percentile(lat, 99):.1f} ms",
           file=sys.stderr, flush=True)
-    return {"requests": n, "mix": mix,
-            "inner_precision": {f"{d}d_p{p}": pr for d, p, _, pr in SERVE_CLASSES},
+    return {"requests": n, "mix": mix, "distinct_problems": n,
+            "inner_precision": {f"{d}d_p{p}": pr for d, p, _, pr, _, _ in SERVE_CLASSES},
+            "gamma": {f"{d}d_p{p}": g for d, p, _, _, g, _ in SERVE_CLASSES},
+            "restriction": {f"{d}d_p{p}": r for d, p, _, _, _, r in SERVE_CLASSES},
             "saturated_solves_per_s": round(thr, 2),
-            "plain_fp64_batched_solves_per_s": round(plain_thr, 2),
-            "plain_seconds_per_class": plain_cls,
+            "plain_fp64_batched_solves_per_s": round(plain64, 2),
+            "plain_mixed_batched_solves_per_s": round(plain32, 2),
+            "plain_mixed_seconds_per_class": plain32_cls,
             "saturated_last_done_s": last_sat,
-            "speedup_vs_plain_fp64": round(thr / plain_thr, 3),
+            "speedup_vs_plain_fp64": round(thr / plain64, 3),
+            "speedup_vs_plain_mixed": round(thr / plain32, 3),
             "saturated_latency_ms": {"p50": round(float(np.percentile(lat_sat, 50)), 2),
                                      "p99": round(float(np.percentile(lat_sat, 99)), 2)},
             "paced_rate_per_s": round(rate, 2),
@@ -641,7 +681,43 @@ def serve(args):
             "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2),
                            "p99": round(float(np.percentile(lat, 99)), 2)},
             "max_relres": worst, "iterations_median": int(np.median(its)),
+            "plain_not_converged": {"fp64": failed.get(pmg.PMG_F64, 0),
+                                    "mixed": failed.get(pmg.PMG_F32, 0)},
+            "oracle_check": check,
             "budget_bytes": budget, "steps": int(steps), "iters_per_step": SERVE_ITERS_PER_STEP}
+
+
+def oracle_check_served(stream, reqs, outs):
+    """Relative FP64 residual, with the oracle's operator, of a sample of
+    served solutions (the first requests of the small classes: 2-D p <= 64,
+    3-D p = 16): w = u - v on the interior against the oracle's b = M f - A v."""
+    import numpy as np
+
+    from oracle import oracle as orc
+    from paper_2504_10710_amd import inputs
+
+    worst, picked = 0.0, []
+    for i, (dim, p, prob) in enumerate(stream):
+        if len(picked) >= SERVE_ORACLE_SAMPLE:
+            break
+        if (dim == 2 and p > 64) or (dim == 3 and p > 16):
+            continue
+        ps = inputs.halving_degrees(p, 2)
+        oc = [prob.coords(orc.gll(q)[0]) for q in ps]
+        h = orc.Hier(dim, ps, oc, gamma=1, smoother=1, alpha=0.16)
+        X = oc[-1]
+        f, g = prob.f(X), prob.g(X)
+        bo = h.rhs(f, g)
+        u = outs[i].cpu().numpy()
+        m1 = np.zeros(p + 1, dtype=bool)
+        m1[1:-1] = True
+        grids = np.meshgrid(*([m1] * dim), indexing="ij")
+        interior = np.logical_and.reduce([gr.reshape(-1, order="F") for gr in grids])
+        w = np.where(interior, u, 0.0)
+        rr = float(np.linalg.norm(bo - h.apply(w)) / np.linalg.norm(bo))
+        worst = max(worst, rr)
+        picked.append({"request": i, "dim": dim, "p": p, "relres_oracle_operator": rr})
+    return {"max_relres_oracle_operator": worst, "sample": picked}
 
 
 def _oracle_solve(args, prob, ps):

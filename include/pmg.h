@@ -55,7 +55,7 @@ enum {
 };
 
 enum { PMG_F64 = 0, PMG_F32 = 1 };
-enum { PMG_SMOOTHER_GLL = 0, PMG_SMOOTHER_FEM = 1 };
+enum { PMG_SMOOTHER_GLL = 0, PMG_SMOOTHER_FEM = 1, PMG_SMOOTHER_GLL_BAND2 = 2 };
 enum { PMG_FGMRES = 0, PMG_PCG = 1, PMG_FCG = 2 };
 enum { PMG_RESTRICT_TRANSPOSE = 0, PMG_RESTRICT_INTERP = 1 };
 
@@ -74,7 +74,12 @@ enum { PMG_RESTRICT_TRANSPOSE = 0, PMG_RESTRICT_INTERP = 1 };
  *              (Def. line preconditioners with half-bandwidth 1);
  *              PMG_SMOOTHER_FEM: tridiagonal line systems of the bilinear
  *              (2-D) / trilinear (3-D) finite-element matrix on the GLL
- *              node mesh
+ *              node mesh;
+ *              PMG_SMOOTHER_GLL_BAND2: the part of A_p within half-bandwidth 2
+ *              along each line (Def. Axelsson incomplete bandwidth
+ *              preconditioner with bandwidth 2), a block-tridiagonal matrix
+ *              of 2x2 blocks solved by block cyclic reduction (Thm. two-level
+ *              direct solver with m = 2); p_fine <= 128
  *   inner_prec PMG_F64, or PMG_F32 for an FP32 gamma-cycle inside FP64
  *              Krylov (geometric factors and the outer solve stay FP64)
  *   krylov     PMG_FGMRES (right-preconditioned, modified Gram-Schmidt,
@@ -250,6 +255,13 @@ int pmg_solve_noalloc(pmg_handle* h, const double* d_b, double* d_x, pmg_info* d
 int pmg_line_coefs(pmg_handle* h, int level, int dir, double* d_lo, double* d_di,
                    double* d_up, pmg_stream_t stream);
 
+/* Half-bandwidth-2 line rows of a PMG_SMOOTHER_GLL_BAND2 handle, level l,
+ * axis dir: d_band holds B x (p_l-1)^(dim-1) x (p_l-1) x 5 doubles, for each
+ * line (ordered as in pmg_line_coefs) and position s the entries (s, s+k),
+ * k = -2..2, of A_l along the line (zero outside it).  FP64; for inspection
+ * and tests.  PMG_EINVAL for handles with other smoothers. */
+int pmg_line_band(pmg_handle* h, int level, int dir, double* d_band, pmg_stream_t stream);
+
 /* Geometric factors of level l: d_G B x ncomp x N_l doubles (ncomp = 3 in
  * 2-D: G_00, G_11, G_01; 6 in 3-D: G_00, G_11, G_22, G_01, G_02, G_12) and
  * d_mass B x N_l doubles (may be NULL). */
@@ -308,7 +320,7 @@ int pmg_pool_destroy(pmg_pool* pool);
 /* A server owns one pool per shape class and admits queued requests in
  * arrival order whenever a slot of their class is free and the summed
  * footprint (per-slot workspace bytes) of the admitted, unfinished requests
- * stays within budget_bytes.  Each class runs on its own stream and
+ * stays within budget_bytes.  Each class runs on its own (caller's) stream and
  * advances independently: pmg_server_step retires the finished requests of
  * every class whose previous step has completed (waiting up to about 2 ms for
  * one if none has), admits queued requests into idle classes, and launches
@@ -339,8 +351,11 @@ typedef struct {
 typedef struct pmg_server pmg_server;
 
 int pmg_server_workspace_bytes(const pmg_server_desc* desc, size_t* bytes);
+/* streams: n_classes caller-owned streams, class c runs on streams[c] (the
+ * same stream may serve several classes, which then do not overlap); they
+ * must outlive the server, which neither creates nor destroys streams. */
 int pmg_server_create(const pmg_server_desc* desc, void* d_ws, size_t ws_bytes,
-                      pmg_server** out);
+                      const pmg_stream_t* streams, pmg_server** out);
 /* Queue a request of class cls.  d_coords holds n_levels pointers (level
  * order, coarsest first); the device inputs must stay valid until the request
  * is admitted (its step).  The solution is written to d_u (N doubles). */

@@ -188,8 +188,12 @@ int check_desc(const pmg_desc* d)
     if (d->gamma < 1 || d->gamma > 16) return fail(PMG_EINVAL, "gamma must be in [1, 16]");
     if (d->m < 0 || d->m > 8) return fail(PMG_EINVAL, "m must be in [0, 8]");
     if (!(d->alpha > 0.0) || !std::isfinite(d->alpha)) return fail(PMG_EINVAL, "alpha must be > 0");
-    if (d->smoother != PMG_SMOOTHER_GLL && d->smoother != PMG_SMOOTHER_FEM)
+    if (d->smoother != PMG_SMOOTHER_GLL && d->smoother != PMG_SMOOTHER_FEM &&
+        d->smoother != PMG_SMOOTHER_GLL_BAND2)
         return fail(PMG_EINVAL, "unknown smoother %d", d->smoother);
+    if (d->smoother == PMG_SMOOTHER_GLL_BAND2 && d->p_fine > 128)
+        return fail(PMG_EINVAL, "half-bandwidth-2 line systems are supported up to p = 128 (got %d)",
+                    d->p_fine);
     if (d->inner_prec != PMG_F64 && d->inner_prec != PMG_F32)
         return fail(PMG_EINVAL, "unknown inner precision %d", d->inner_prec);
     if (d->krylov != PMG_FGMRES && d->krylov != PMG_PCG && d->krylov != PMG_FCG)
@@ -234,6 +238,7 @@ struct pmg_handle {
     size_t o_JR64[MAX_LEVELS], o_JR32[MAX_LEVELS];
     size_t o_G64[MAX_LEVELS], o_G32[MAX_LEVELS], o_X64[MAX_LEVELS];
     size_t o_cr64[MAX_LEVELS][3], o_cr32[MAX_LEVELS][3];
+    size_t o_bd64[MAX_LEVELS][3], o_bd32[MAX_LEVELS][3];   // band-2 line rows (0: none)
     size_t o_X[MAX_LEVELS], o_R[MAX_LEVELS], o_Tm[MAX_LEVELS], o_TR[MAX_LEVELS];
     size_t o_mass, o_W1, o_W2, o_TR64, o_V, o_Z, o_Hs, o_detmin, o_pivot, o_cinv64, o_cinv32;
     size_t o_sstatus, o_state, o_hier64, o_hier32;
@@ -294,6 +299,15 @@ void plan(pmg_handle* h, std::vector<pmg_region>* rec = nullptr)
             h->o_cr64[l][a] = a < dim ? L.take(a == 0 ? "cr64x" : (a == 1 ? "cr64y" : "cr64z"), l, sizeof(double) * (size_t)B * 3 * s.CRW * s.NL) : 0;
             h->o_cr32[l][a] =
                 (a < dim && h->f32) ? L.take(a == 0 ? "cr32x" : (a == 1 ? "cr32y" : "cr32z"), l, sizeof(float) * (size_t)B * 3 * s.CRW * s.NL) : 0;
+        }
+        const bool band = d.smoother == PMG_SMOOTHER_GLL_BAND2;
+        for (int a = 0; a < 3; ++a) {
+            h->o_bd64[l][a] = (band && a < dim)
+                ? L.take(a == 0 ? "bd64x" : (a == 1 ? "bd64y" : "bd64z"), l,
+                         sizeof(double) * (size_t)B * 5 * s.n * s.NL) : 0;
+            h->o_bd32[l][a] = (band && a < dim && h->f32)
+                ? L.take(a == 0 ? "bd32x" : (a == 1 ? "bd32y" : "bd32z"), l,
+                         sizeof(float) * (size_t)B * 5 * s.n * s.NL) : 0;
         }
         h->o_X[l] = L.take("X", l, tsz * (size_t)B * s.N);
         h->o_R[l] = L.take("R", l, tsz * (size_t)B * s.N);
@@ -364,8 +378,11 @@ void fill_hier(pmg_handle* h, Hier<T>& H, bool is32)
         L.G = is32 ? (const T*)(ws + h->o_G32[l]) : (const T*)(ws + h->o_G64[l]);
         L.mass = (l == h->nlev - 1) ? (const double*)(ws + h->o_mass) : nullptr;
         L.X64 = (const double*)(ws + h->o_X64[l]);
-        for (int a = 0; a < dim; ++a)
+        for (int a = 0; a < dim; ++a) {
             L.cr[a] = is32 ? (const T*)(ws + h->o_cr32[l][a]) : (const T*)(ws + h->o_cr64[l][a]);
+            const size_t ob = is32 ? h->o_bd32[l][a] : h->o_bd64[l][a];
+            L.bd[a] = ob ? (const T*)(ws + ob) : nullptr;
+        }
         L.X = (T*)(ws + h->o_X[l]);
         L.R = (T*)(ws + h->o_R[l]);
         L.Tm = (T*)(ws + h->o_Tm[l]);
@@ -590,6 +607,8 @@ static void setup_args(pmg_handle* h, SetupArgs& a)
         for (int k = 0; k < 3; ++k) {
             a.cr64[l][k] = k < dim ? (double*)(h->ws + h->o_cr64[l][k]) : nullptr;
             a.cr32[l][k] = (k < dim && h->f32) ? (float*)(h->ws + h->o_cr32[l][k]) : nullptr;
+            a.bd64[l][k] = (k < dim && h->o_bd64[l][k]) ? (double*)(h->ws + h->o_bd64[l][k]) : nullptr;
+            a.bd32[l][k] = (k < dim && h->o_bd32[l][k]) ? (float*)(h->ws + h->o_bd32[l][k]) : nullptr;
         }
         a.G64[l] = (double*)(h->ws + h->o_G64[l]);
         a.G32[l] = h->f32 ? (float*)(h->ws + h->o_G32[l]) : nullptr;
@@ -889,9 +908,26 @@ int pmg_line_coefs(pmg_handle* h, int level, int dir, double* d_lo, double* d_di
     if ((rc = check_h(h)) || (rc = check_level(h, level, 0))) return rc;
     if (dir < 0 || dir >= h->d.dim) return fail(PMG_EINVAL, "dir %d out of range", dir);
     if (!d_lo || !d_di || !d_up) return fail(PMG_EINVAL, "NULL argument");
+    if (h->d.smoother == PMG_SMOOTHER_GLL_BAND2)
+        return fail(PMG_EINVAL, "the handle's line systems are banded: use pmg_line_band");
     hipError_t e = launch_line_coefs(h->d.dim, 2 << level, h->d.batch, hier64_dev(h), h->d.smoother, dir,
                                      d_lo, d_di, d_up, (hipStream_t)stream);
     return e == hipSuccess ? PMG_OK : hip_fail(e, "pmg_line_coefs");
+}
+
+int pmg_line_band(pmg_handle* h, int level, int dir, double* d_band, pmg_stream_t stream)
+{
+    int rc;
+    if ((rc = check_h(h)) || (rc = check_level(h, level, 0))) return rc;
+    if (dir < 0 || dir >= h->d.dim) return fail(PMG_EINVAL, "dir %d out of range", dir);
+    if (!d_band) return fail(PMG_EINVAL, "NULL argument");
+    if (!h->o_bd64[level][dir])
+        return fail(PMG_EINVAL, "the handle's smoother has no half-bandwidth-2 line systems");
+    LevelShape sh = level_shape(h->d.dim, level);
+    hipError_t e = hipMemcpyAsync(d_band, h->ws + h->o_bd64[level][dir],
+                                  sizeof(double) * (size_t)h->d.batch * 5 * sh.n * sh.NL,
+                                  hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    return e == hipSuccess ? PMG_OK : hip_fail(e, "pmg_line_band");
 }
 
 int pmg_geom(pmg_handle* h, int level, double* d_G, double* d_mass, pmg_stream_t stream)
@@ -1243,11 +1279,12 @@ int pmg_server_workspace_bytes(const pmg_server_desc* d, size_t* bytes)
     return PMG_OK;
 }
 
-int pmg_server_create(const pmg_server_desc* d, void* d_ws, size_t ws_bytes, pmg_server** out)
+int pmg_server_create(const pmg_server_desc* d, void* d_ws, size_t ws_bytes,
+                      const pmg_stream_t* streams, pmg_server** out)
 {
     int rc = check_server_desc(d);
     if (rc) return rc;
-    if (!d_ws || !out) return fail(PMG_EINVAL, "NULL argument");
+    if (!d_ws || !out || !streams) return fail(PMG_EINVAL, "NULL argument");
     size_t need = 0;
     pmg_server_workspace_bytes(d, &need);
     if (ws_bytes < need) return fail(PMG_ENOMEM, "server workspace too small: %zu < %zu", ws_bytes, need);
@@ -1258,11 +1295,8 @@ int pmg_server_create(const pmg_server_desc* d, void* d_ws, size_t ws_bytes, pmg
         size_t b = 0;
         pmg_pool_workspace_bytes(&d->classes[c], &b);
         pmg_server::Class& C = S->cls[c];
-        hipError_t e = hipStreamCreateWithFlags(&C.stream, hipStreamNonBlocking);
-        if (e != hipSuccess) {
-            pmg_server_destroy(S);
-            return hip_fail(e, "server stream");
-        }
+        C.stream = (hipStream_t)streams[c];   // the caller's stream for this class
+        hipError_t e;
         if ((rc = pmg_pool_create(&d->classes[c], d->iters_per_step, base, b, (pmg_stream_t)C.stream,
                                   &C.pool))) {
             pmg_server_destroy(S);
@@ -1499,7 +1533,7 @@ int pmg_server_destroy(pmg_server* S)
         if (C.hinfo) hipHostFree(C.hinfo);
         if (C.htake) hipHostFree(C.htake);
         if (C.hout) hipHostFree(C.hout);
-        if (C.stream) hipStreamDestroy(C.stream);
+        // the class streams belong to the caller
     }
     delete S;
     return PMG_OK;

@@ -62,6 +62,8 @@ struct LevelData {
     const double* mass;  // [B][N] finest level only
     const double* X64;   // [B][DIM][N] physical node coordinates
     const T* cr[3];      // [B][3][CRW][NL] cyclic-reduction factors per axis
+    const T* bd[3];      // [B][NL][n][5] half-bandwidth-2 line rows per axis (entries at
+                         // offsets -2..2 along the line, zero outside it), or null
     T* X;                // [B][N] level iterate
     T* R;                // [B][N] level right-hand side
     T* Tm;               // [B][N] residual / line-solve buffer
@@ -880,7 +882,130 @@ __device__ inline void cr_wave_solve(PC c, int u, bool has1, T& e0, T& e1)
     }
 }
 
-template <class T, int P, int DIM, bool FUSED>
+// Block cyclic reduction of one line whose matrix has half-bandwidth 2, as a
+// block-tridiagonal matrix of 2x2 blocks (Def. block-tridiagonal matrix;
+// unknowns 2u and 2u+1 form block u, an odd line length is padded with one
+// decoupled unknown), solved by the direct multigrid of Thm. "Two-level
+// direct solver" with block operators, level after level (Cor. "Direct
+// multigrid solver").  Lane u of a group of W = (n+1)/2 lanes holds block u
+// (positions 2u, 2u+1: the same data placement as cr_wave_solve).  At level
+// k the blocks still present sit in lanes (t+1) 2^k - 1, t = 0, 1, ...; the F
+// blocks (t even) form A^{-1} L, A^{-1} U and A^{-1} g and keep them for the
+// way up; each C block forms its row of D - C A^{-1} B and its right-hand
+// side from its F neighbours' (stencil of the proof of Prop. "line coarse
+// space"), received by cross-lane shuffles.  c[s*5 + k + 2] = entry (s, s+k).
+template <class T, int n, int W, class PC>
+__device__ inline void bcr_wave_solve(PC c, int u, bool has1, T& e0, T& e1)
+{
+    constexpr int NB = (n + 1) / 2;
+    constexpr int NK = ilog2(NB);
+    static_assert((1 << NK) == NB, "a power-of-two number of blocks");
+    const int s0 = 2 * u, s1 = 2 * u + 1;
+    auto E = [&](int s, int k) -> T { return c[s * 5 + k + 2]; };
+    // A, L (block u-1), U (block u+1) of this lane's block row; out-of-line
+    // entries are stored as zero, the padding row is an identity row
+    T a00 = E(s0, 0), a01 = E(s0, 1), a10 = has1 ? E(s1, -1) : T(0), a11 = has1 ? E(s1, 0) : T(1);
+    T l00 = E(s0, -2), l01 = E(s0, -1), l10 = T(0), l11 = has1 ? E(s1, -2) : T(0);
+    T u00 = E(s0, 2), u01 = T(0), u10 = has1 ? E(s1, 1) : T(0), u11 = has1 ? E(s1, 2) : T(0);
+    T g0 = e0, g1 = has1 ? e1 : T(0);
+    T p00 = 0, p01 = 0, p10 = 0, p11 = 0;   // A^{-1} L of the level where this block is F
+    T q00 = 0, q01 = 0, q10 = 0, q11 = 0;   // A^{-1} U
+    T y0 = 0, y1 = 0;                       // A^{-1} g
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+        const int hs = 1 << k, nbk = NB >> k;
+        const bool on = (u + 1) % hs == 0;
+        const int t = (u + 1) / hs - 1;
+        if (on && (t & 1) == 0) {
+            const T id = T(1) / (a00 * a11 - a01 * a10);
+            const T i00 = a11 * id, i01 = -a01 * id, i10 = -a10 * id, i11 = a00 * id;
+            p00 = i00 * l00 + i01 * l10; p01 = i00 * l01 + i01 * l11;
+            p10 = i10 * l00 + i11 * l10; p11 = i10 * l01 + i11 * l11;
+            q00 = i00 * u00 + i01 * u10; q01 = i00 * u01 + i01 * u11;
+            q10 = i10 * u00 + i11 * u10; q11 = i10 * u01 + i11 * u11;
+            y0 = i00 * g0 + i01 * g1;
+            y1 = i10 * g0 + i11 * g1;
+        }
+        // from the F block on the left (u - hs) and on the right (u + hs)
+        const int ul = u - hs, ur = u + hs;
+        const T Lp00 = __shfl(p00, ul, W), Lp01 = __shfl(p01, ul, W), Lp10 = __shfl(p10, ul, W),
+                Lp11 = __shfl(p11, ul, W);
+        const T Lq00 = __shfl(q00, ul, W), Lq01 = __shfl(q01, ul, W), Lq10 = __shfl(q10, ul, W),
+                Lq11 = __shfl(q11, ul, W);
+        const T Ly0 = __shfl(y0, ul, W), Ly1 = __shfl(y1, ul, W);
+        const T Rp00 = __shfl(p00, ur, W), Rp01 = __shfl(p01, ur, W), Rp10 = __shfl(p10, ur, W),
+                Rp11 = __shfl(p11, ur, W);
+        const T Rq00 = __shfl(q00, ur, W), Rq01 = __shfl(q01, ur, W), Rq10 = __shfl(q10, ur, W),
+                Rq11 = __shfl(q11, ur, W);
+        const T Ry0 = __shfl(y0, ur, W), Ry1 = __shfl(y1, ur, W);
+        if (on && (t & 1) == 1) {
+            const bool hasR = t + 1 < nbk;
+            // right-hand side and diagonal block of D - C A^{-1} B
+            g0 -= l00 * Ly0 + l01 * Ly1;
+            g1 -= l10 * Ly0 + l11 * Ly1;
+            a00 -= l00 * Lq00 + l01 * Lq10; a01 -= l00 * Lq01 + l01 * Lq11;
+            a10 -= l10 * Lq00 + l11 * Lq10; a11 -= l10 * Lq01 + l11 * Lq11;
+            T n00 = -(l00 * Lp00 + l01 * Lp10), n01 = -(l00 * Lp01 + l01 * Lp11);
+            T n10 = -(l10 * Lp00 + l11 * Lp10), n11 = -(l10 * Lp01 + l11 * Lp11);
+            T m00 = 0, m01 = 0, m10 = 0, m11 = 0;
+            if (hasR) {
+                g0 -= u00 * Ry0 + u01 * Ry1;
+                g1 -= u10 * Ry0 + u11 * Ry1;
+                a00 -= u00 * Rp00 + u01 * Rp10; a01 -= u00 * Rp01 + u01 * Rp11;
+                a10 -= u10 * Rp00 + u11 * Rp10; a11 -= u10 * Rp01 + u11 * Rp11;
+                m00 = -(u00 * Rq00 + u01 * Rq10); m01 = -(u00 * Rq01 + u01 * Rq11);
+                m10 = -(u10 * Rq00 + u11 * Rq10); m11 = -(u10 * Rq01 + u11 * Rq11);
+            }
+            l00 = n00; l01 = n01; l10 = n10; l11 = n11;
+            u00 = m00; u01 = m01; u10 = m10; u11 = m11;
+        }
+    }
+    // the one block left (lane NB - 1) is solved directly
+    T x0 = T(0), x1 = T(0);
+    if (u == NB - 1) {
+        const T id = T(1) / (a00 * a11 - a01 * a10);
+        x0 = (a11 * g0 - a01 * g1) * id;
+        x1 = (a00 * g1 - a10 * g0) * id;
+    }
+#pragma unroll
+    for (int k = NK - 1; k >= 0; --k) {
+        const int hs = 1 << k, nbk = NB >> k;
+        const bool on = (u + 1) % hs == 0;
+        const int t = (u + 1) / hs - 1;
+        const T xl0 = __shfl(x0, u - hs, W), xl1 = __shfl(x1, u - hs, W);
+        const T xr0 = __shfl(x0, u + hs, W), xr1 = __shfl(x1, u + hs, W);
+        if (on && (t & 1) == 0) {
+            // y = A^{-1} g - A^{-1} L x_left - A^{-1} U x_right  (x + P e)
+            T v0 = y0, v1 = y1;
+            if (t >= 1) {
+                v0 -= p00 * xl0 + p01 * xl1;
+                v1 -= p10 * xl0 + p11 * xl1;
+            }
+            if (t + 1 < nbk) {
+                v0 -= q00 * xr0 + q01 * xr1;
+                v1 -= q10 * xr0 + q11 * xr1;
+            }
+            x0 = v0;
+            x1 = v1;
+        }
+    }
+    e0 = x0;
+    e1 = has1 ? x1 : T(0);
+}
+
+// One lane-group solve of line lc: scalar cyclic reduction on the
+// tridiagonal rows (3 CRW words per line), or block cyclic reduction on the
+// half-bandwidth-2 rows (5 n words per line).
+template <class T, int n, int W, int CRW, bool BAND, class PC>
+__device__ inline void wave_line_solve(PC cr, int lc, int u, bool has1, T& e0, T& e1)
+{
+    if constexpr (BAND)
+        bcr_wave_solve<T, n, W>(cr + (long long)lc * 5 * n, u, has1, e0, e1);
+    else
+        cr_wave_solve<T, n, W>(cr + (long long)lc * 3 * CRW, u, has1, e0, e1);
+}
+
+template <class T, int P, int DIM, bool FUSED, bool BAND = false>
 __device__ void line_cr_wave(const T* __restrict__ cr_, T* __restrict__ g_, T* __restrict__ x_,
                              T alpha, bool assign)
 {
@@ -902,7 +1027,7 @@ __device__ void line_cr_wave(const T* __restrict__ cr_, T* __restrict__ g_, T* _
         line_base<P, DIM>(0, lc, base, st);
         T e0 = g[base + 2 * u + 1];
         T e1 = has1 ? g[base + 2 * u + 2] : T(0);
-        cr_wave_solve<T, n, W>(cr + (long long)lc * 3 * CRW, u, has1, e0, e1);
+        wave_line_solve<T, n, W, CRW, BAND>(cr, lc, u, has1, e0, e1);
         if (act) {
             if (FUSED) {
                 const int q0 = base + 2 * u + 1;
@@ -935,7 +1060,7 @@ __device__ inline void* line_strip_lds()
 // and the solutions go back row by row.  Line index = (i-1) + n (o-1) for
 // first-axis position i and outer coordinate o, as everywhere else; the
 // lines' tridiagonals are stored line-major like the first axis'.
-template <class T, int P, int DIM, bool FUSED>
+template <class T, int P, int DIM, bool FUSED, bool BAND = false>
 __device__ void line_cr_wave_strided(const T* __restrict__ cr_, int dir, T* __restrict__ g_,
                                      T* __restrict__ x_, T alpha, bool assign)
 {
@@ -969,7 +1094,7 @@ __device__ void line_cr_wave_strided(const T* __restrict__ cr_, int dir, T* __re
                 const int lc = min(l0 + sc, n - 1) + n * o;   // compute on a copy, store nothing
                 T e0 = strip[(2 * u) * LD + sc];
                 T e1 = has1 ? strip[(2 * u + 1) * LD + sc] : T(0);
-                cr_wave_solve<T, n, W>(cr + (long long)lc * 3 * CRW, u, has1, e0, e1);
+                wave_line_solve<T, n, W, CRW, BAND>(cr, lc, u, has1, e0, e1);
                 if (sl < SW) {
                     strip[(2 * u) * LD + sl] = e0;
                     if (has1) strip[(2 * u + 1) * LD + sl] = e1;
@@ -1005,19 +1130,20 @@ __device__ void line_cr_wave_strided(const T* __restrict__ cr_, int dir, T* __re
 // groups only: x is then not read).  Not fused, lines solved by
 // lane groups (wave_lines) store z into x when x is given (g is then only
 // read), else in place; the thread-per-line form is in place only.
-template <class T, int P, int DIM, bool FUSED>
+template <class T, int P, int DIM, bool FUSED, bool BAND = false>
 __device__ __attribute__((noinline)) void line_cr(const T* __restrict__ cr_, int dir,
                                                   T* __restrict__ g_, T* __restrict__ x_, T alpha,
                                                   bool assign = false)
 {
     if constexpr (wave_lines<P>()) {
         if (dir == 0) {
-            line_cr_wave<T, P, DIM, FUSED>(cr_, g_, x_, alpha, assign);
+            line_cr_wave<T, P, DIM, FUSED, BAND>(cr_, g_, x_, alpha, assign);
             return;
         }
-        line_cr_wave_strided<T, P, DIM, FUSED>(cr_, dir, g_, x_, alpha, assign);
+        line_cr_wave_strided<T, P, DIM, FUSED, BAND>(cr_, dir, g_, x_, alpha, assign);
         return;
     }
+    if constexpr (BAND) return;   // half-bandwidth-2 lines only up to p = 128 (host-checked)
     const auto cr = gmem(cr_);
     const auto g = gmem(g_);
     const auto x = gmem(x_);
@@ -1228,6 +1354,25 @@ __device__ inline const LevelData<T>& lvl(const Hier<T>& H)
     return H.lev[Shape<P, DIM>::LEV];
 }
 
+// The line solve of level P along axis dir on the level's line systems:
+// half-bandwidth-2 rows by block cyclic reduction when the hierarchy has
+// them, else the tridiagonal rows by scalar cyclic reduction.
+template <class T, int P, int DIM, bool FUSED>
+__device__ inline void level_lines(const LevelData<T>& L, int b, int dir, T* g, T* x, T alpha,
+                                   bool assign = false)
+{
+    using S = Shape<P, DIM>;
+    if constexpr (wave_lines<P>()) {
+        if (L.bd[dir]) {
+            line_cr<T, P, DIM, FUSED, true>(L.bd[dir] + (long long)b * 5 * S::n * S::NL, dir, g, x,
+                                            alpha, assign);
+            return;
+        }
+    }
+    line_cr<T, P, DIM, FUSED>(L.cr[dir] + (long long)b * 3 * S::CRW * S::NL, dir, g, x, alpha,
+                              assign);
+}
+
 // x += alpha B_dir^{-1} (r - A x)   (Alg. 2 smoothing step)
 template <class T, int P, int DIM>
 __device__ void smooth_step(const Hier<T>& H, int b, int dir, const T* r, T* x, bool x_is_zero)
@@ -1239,8 +1384,7 @@ __device__ void smooth_step(const Hier<T>& H, int b, int dir, const T* r, T* x, 
         // the residual is r itself; lane-group lines only read their
         // right-hand side, so they take it from r without a copy, and they
         // assign x = alpha z on the interior (x's boundary is already zero)
-        line_cr<T, P, DIM, true>(L.cr[dir] + (long long)b * 3 * S::CRW * S::NL, dir,
-                                 const_cast<T*>(r), x, H.alpha, true);
+        level_lines<T, P, DIM, true>(L, b, dir, const_cast<T*>(r), x, H.alpha, true);
         return;
     }
     if (x_is_zero) {
@@ -1250,7 +1394,7 @@ __device__ void smooth_step(const Hier<T>& H, int b, int dir, const T* r, T* x, 
         apply_level<T, P, DIM, true>(L.G + (long long)b * S::NC * S::N, L.D, L.DT,
                                      L.TR + (long long)b * DIM * S::N, x, r, tmp);
     }
-    line_cr<T, P, DIM, true>(L.cr[dir] + (long long)b * 3 * S::CRW * S::NL, dir, tmp, x, H.alpha);
+    level_lines<T, P, DIM, true>(L, b, dir, tmp, x, H.alpha);
 }
 
 // Levels whose gamma-cycle (with everything below it) is applied as one

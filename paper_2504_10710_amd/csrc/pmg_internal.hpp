@@ -18,6 +18,8 @@ struct SetupArgs {
     int nslots;                         // workgroups to launch (B without slots)
     double* cr64[MAX_LEVELS][3];        // FP64 line factors per level and axis
     float* cr32[MAX_LEVELS][3];         // FP32 copies (nullptr if unused)
+    double* bd64[MAX_LEVELS][3];        // half-bandwidth-2 line rows (GLL band-2 smoother)
+    float* bd32[MAX_LEVELS][3];         // FP32 copies (nullptr if unused)
     double* G64[MAX_LEVELS];
     float* G32[MAX_LEVELS];             // nullptr if unused
     double* mass;                       // finest level

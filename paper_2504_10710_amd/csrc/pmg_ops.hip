@@ -58,8 +58,7 @@ __global__ void __launch_bounds__(NT, 8) k_line_solve(const Hier<T>* __restrict_
         // boundary of z set to zero (the lines cover every interior node)
         for (int q = threadIdx.x; q < S::N; q += NT)
             if (is_boundary<P, DIM>(q)) zb[q] = T(0);
-        line_cr<T, P, DIM, false>(L.cr[dir] + b * 3 * S::CRW * S::NL, dir, const_cast<T*>(rb), zb,
-                                  T(0));
+        level_lines<T, P, DIM, false>(L, (int)b, dir, const_cast<T*>(rb), zb, T(0));
     } else {
         for (int q = threadIdx.x; q < S::N; q += NT) zb[q] = is_boundary<P, DIM>(q) ? T(0) : rb[q];
         wg_barrier();

@@ -414,7 +414,9 @@ __global__ void __launch_bounds__(NT) k_lines(const double* __restrict__ G,
                                               const double* __restrict__ D, int smoother,
                                               double* cr0, double* cr1, double* cr2, float* f0,
                                               float* f1, float* f2, int* pivot,
-                                              double* cinv64, float* cinv32, const int* slots)
+                                              double* cinv64, float* cinv32, const int* slots,
+                                              double* bd0, double* bd1, double* bd2, float* bf0,
+                                              float* bf1, float* bf2)
 {
     using S = Shape<P, DIM>;
     constexpr int n = S::n, NL = S::NL, CRW = S::CRW, N = S::N, NC = S::NC;
@@ -427,6 +429,46 @@ __global__ void __launch_bounds__(NT) k_lines(const double* __restrict__ G,
         const bool lm = wave_lines<P>();   // line-major, raw level 0
         return lm ? ((long long)line * CRW + slot) * 3 + w : (long long)(slot * 3 + w) * NL + line;
     };
+    if (bd0) {
+        // half-bandwidth-2 line rows of the GLL operator: entries (s, s+k),
+        // k = -2..2, of every line of every axis (zero outside the line),
+        // then every block-CR level's 2x2 pivots checked by a solve with a
+        // right-hand side of ones
+        if constexpr (wave_lines<P>()) {
+            auto bdp = [&](int dir) { return (dir == 0 ? bd0 : (dir == 1 ? bd1 : bd2)) + b * 5 * n * NL; };
+            for (int e = threadIdx.x; e < DIM * NL * n * 5; e += NT) {
+                const int dir = e / (NL * n * 5), line = (e / (n * 5)) % NL, sq = (e / 5) % n;
+                const int k = e % 5 - 2;
+                int base, st;
+                line_base<P, DIM>(dir, line, base, st);
+                const int q = base + (sq + 1) * st;
+                const int c[3] = {q % (P + 1), (q / (P + 1)) % (P + 1), DIM == 3 ? q / ((P + 1) * (P + 1)) : 0};
+                const double v = (sq + k >= 0 && sq + k < n) ? gll_entry<P, DIM>(Gb, D, q, c, dir, k) : 0.0;
+                bdp(dir)[((long long)line * n + sq) * 5 + k + 2] = v;
+            }
+            wg_barrier();
+            constexpr int W = (n + 1) / 2 > 0 ? (n + 1) / 2 : 1;
+            constexpr int LPW = 64 / W;
+            const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+            const int u = lane % W, sub = lane / W;
+            const bool has1 = 2 * u + 1 < n;
+            for (int dir = 0; dir < DIM; ++dir) {
+                const auto bd = gmem((const double*)bdp(dir));
+                for (int line0 = wave * LPW; line0 < NL; line0 += (NT / 64) * LPW) {
+                    const int line = line0 + sub;
+                    const int lc = line < NL ? line : NL - 1;
+                    double e0 = 1.0, e1 = has1 ? 1.0 : 0.0;
+                    bcr_wave_solve<double, n, W>(bd + (long long)lc * 5 * n, u, has1, e0, e1);
+                    if (line < NL && !(isfinite(e0) && isfinite(e1))) bad = 1;
+                }
+                float* bf = dir == 0 ? bf0 : (dir == 1 ? bf1 : bf2);
+                if (bf) {
+                    const auto bfb = gmem(bf + b * 5 * n * NL);
+                    for (int e = threadIdx.x; e < NL * 5 * n; e += NT) bfb[e] = (float)bd[e];
+                }
+            }
+        }
+    } else {
     // 1. the raw tridiagonals of every line of every axis, one entry per work
     //    item (3-D FEM: one interior node per work item, all axes at once)
     if constexpr (DIM == 3) {
@@ -538,6 +580,7 @@ __global__ void __launch_bounds__(NT) k_lines(const double* __restrict__ G,
         }
     }
     }
+    }   // tridiagonal line systems
     if (P == 2 && threadIdx.x == 0) {
         // level 0: the exact coarse solve uses A_0 itself (eq. discreteBilinear),
         // whatever line systems the smoother uses
@@ -702,7 +745,9 @@ hipError_t launch_setup(int dim, int p_fine, int nlev, int B, const SetupArgs& a
                                                    a.G64[l], a.X64[l], a.D64[l], a.smoother,
                                                    a.cr64[l][0], a.cr64[l][1], a.cr64[l][2],
                                                    a.cr32[l][0], a.cr32[l][1], a.cr32[l][2],
-                                                   a.pivot, a.cinv64, a.cinv32, a.slots));
+                                                   a.pivot, a.cinv64, a.cinv32, a.slots,
+                                                   a.bd64[l][0], a.bd64[l][1], a.bd64[l][2],
+                                                   a.bd32[l][0], a.bd32[l][1], a.bd32[l][2]));
         if ((e = last()) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_setup_finish, dim3((nb + 255) / 256), dim3(256), 0, s, a.detmin, a.pivot,

@@ -90,14 +90,13 @@ class Problem:
                     v = v + c[k1 - 1, k2 - 1] / (k1 * k1 + k2 * k2) * np.sin(k1 * PI * x) * np.sin(k2 * PI * y)
             return v
         if self.kind == "deformed3d":
+            # sum_{k in {1,2,3}^3} c_k / |k|^2 prod_i sin(k_i pi x_i), the three
+            # sine factors of each axis evaluated once
             c = P["c"]
-            v = np.zeros_like(X[0])
-            for k1 in range(1, 4):
-                for k2 in range(1, 4):
-                    for k3 in range(1, 4):
-                        v = v + c[k1 - 1, k2 - 1, k3 - 1] / (k1 * k1 + k2 * k2 + k3 * k3) * (
-                            np.sin(k1 * PI * X[0]) * np.sin(k2 * PI * X[1]) * np.sin(k3 * PI * X[2]))
-            return v
+            k = np.arange(1, 4)
+            w = c / (k[:, None, None] ** 2 + k[None, :, None] ** 2 + k[None, None, :] ** 2)
+            S = [np.sin(np.multiply.outer(k * PI, X[a])) for a in range(3)]
+            return np.einsum("abc,an,bn,cn->n", w, S[0], S[1], S[2], optimize=True)
         if self.kind == "table1":
             x, y = X
             which = P["problem"]
@@ -164,10 +163,31 @@ def config2(seed: int, amp_max: float = 0.15) -> Problem:
     return Problem(2, "deformed2d", {"a": float(a), "b": float(b), "c": c, "d": d, "e": e})
 
 
+def _mapping3_min_det(beta, amp, m: int = 13) -> float:
+    """Smallest Jacobian determinant of the config-3 mapping
+    x_c = s_c + beta_c s t u + amp_c sin(pi s) sin(pi t) sin(pi u) on an m^3
+    grid of the unit cube (analytic derivatives of the mapping; a check that
+    a drawn problem is a valid domain, not part of the method)."""
+    g = np.linspace(0.0, 1.0, m)
+    s = np.stack(np.meshgrid(g, g, g, indexing="ij")).reshape(3, -1)
+    sn, cs = np.sin(PI * s), np.cos(PI * s)
+    J = np.zeros((s.shape[1], 3, 3))
+    for c in range(3):
+        for d in range(3):
+            e1, e2 = [e for e in range(3) if e != d]
+            J[:, c, d] = (c == d) + beta[c] * s[e1] * s[e2] + amp[c] * PI * cs[d] * sn[e1] * sn[e2]
+    return float(np.linalg.det(J).min())
+
+
 def config3(seed: int, amp_max: float = 0.1) -> Problem:
+    """Config-3 problem; amplitudes ~ U[0, amp_max], redrawn (same stream)
+    while the mapping folds (det J <= 0 somewhere)."""
     rng = np.random.default_rng(seed)
-    beta = rng.uniform(0.0, amp_max, size=3)
-    amp = rng.uniform(0.0, amp_max, size=3)
+    while True:
+        beta = rng.uniform(0.0, amp_max, size=3)
+        amp = rng.uniform(0.0, amp_max, size=3)
+        if amp_max <= 0.1 or _mapping3_min_det(beta, amp) > 0.0:
+            break
     c = rng.standard_normal((3, 3, 3))
     return Problem(3, "deformed3d", {"beta": beta, "amp": amp, "c": c})
 
@@ -198,7 +218,8 @@ def halving_degrees(p_fine: int, p_coarse: int = 2):
 def served_stream(n_requests: int, seed: int, amp_max: float = 0.15):
     """Request mix of the served workload: dim in {2, 3} with probability 1/2,
     2-D p ~ U{16,32,64,128}, 3-D p ~ U{16,32,64}; each request carries its own
-    problem seed.  Returns a list of (dim, p, Problem)."""
+    problem seed; deformation amplitudes ~ U[0, amp_max] in 2-D and 3-D (3-D
+    redrawn while the mapping folds).  Returns a list of (dim, p, Problem)."""
     rng = np.random.default_rng(seed)
     out = []
     for i in range(n_requests):
@@ -208,6 +229,6 @@ def served_stream(n_requests: int, seed: int, amp_max: float = 0.15):
             prob = config2(seed * 1_000_003 + i, amp_max)
         else:
             p = int(rng.choice([16, 32, 64]))
-            prob = config3(seed * 1_000_003 + i, min(amp_max, 0.1))
+            prob = config3(seed * 1_000_003 + i, amp_max)
         out.append((dim, p, prob))
     return out

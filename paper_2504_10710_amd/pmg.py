@@ -20,7 +20,7 @@ _lib = None
 PMG_OK, PMG_EINVAL, PMG_ENOMEM, PMG_EDEVICE = 0, -1, -2, -3
 PMG_EGEOM, PMG_ENAN, PMG_EBREAKDOWN, PMG_ENOTCONV, PMG_EPIVOT = -4, -5, -6, -7, -8
 PMG_F64, PMG_F32 = 0, 1
-PMG_SMOOTHER_GLL, PMG_SMOOTHER_FEM = 0, 1
+PMG_SMOOTHER_GLL, PMG_SMOOTHER_FEM, PMG_SMOOTHER_GLL_BAND2 = 0, 1, 2
 PMG_FGMRES, PMG_PCG, PMG_FCG = 0, 1, 2
 PMG_RESTRICT_TRANSPOSE, PMG_RESTRICT_INTERP = 0, 1
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EGEOM", -5: "ENAN",
@@ -91,6 +91,7 @@ def lib():
             "pmg_solve": (i, [vp, vp, vp, vp, vp]),
             "pmg_solve_noalloc": (i, [vp, vp, vp, vp, vp]),
             "pmg_workspace_layout": (i, [vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+            "pmg_line_band": (i, [vp, i, i, vp, vp]),
             "pmg_line_coefs": (i, [vp, i, i, vp, vp, vp, vp]),
             "pmg_geom": (i, [vp, i, vp, vp, vp]),
             "pmg_destroy": (i, [vp]),
@@ -106,7 +107,7 @@ def lib():
             "pmg_server_workspace_bytes": (i, [ctypes.POINTER(pmg_server_desc),
                                                ctypes.POINTER(ctypes.c_size_t)]),
             "pmg_server_create": (i, [ctypes.POINTER(pmg_server_desc), vp, ctypes.c_size_t,
-                                      ctypes.POINTER(vp)]),
+                                      ctypes.POINTER(vp), ctypes.POINTER(vp)]),
             "pmg_server_submit": (i, [vp, i, ctypes.POINTER(vp), vp, vp, vp,
                                       ctypes.POINTER(ctypes.c_longlong)]),
             "pmg_server_step": (i, [vp, ctypes.POINTER(i)]),
@@ -133,7 +134,7 @@ def exported_symbols():
             "pmg_pool_destroy", "pmg_server_workspace_bytes", "pmg_server_create",
             "pmg_server_submit", "pmg_server_step", "pmg_server_poll", "pmg_server_drain",
             "pmg_server_stats_get",
-            "pmg_server_destroy", "pmg_solve_noalloc", "pmg_workspace_layout"]
+            "pmg_server_destroy", "pmg_solve_noalloc", "pmg_workspace_layout", "pmg_line_band"]
 
 
 def _check(rc):
@@ -258,6 +259,10 @@ def pmg_line_coefs(h, level, dir, lo, di, up, stream=None):
     _check(lib().pmg_line_coefs(h, level, dir, _ptr(lo), _ptr(di), _ptr(up), _stream(stream)))
 
 
+def pmg_line_band(h, level, dir, band, stream=None):
+    _check(lib().pmg_line_band(h, level, dir, _ptr(band), _stream(stream)))
+
+
 def pmg_geom(h, level, G, mass=None, stream=None):
     _check(lib().pmg_geom(h, level, _ptr(G), _ptr(mass), _stream(stream)))
 
@@ -329,10 +334,20 @@ def pmg_server_workspace_bytes(desc) -> int:
     return n.value
 
 
-def pmg_server_create(desc, ws):
+_server_streams = {}
+
+
+def pmg_server_create(desc, ws, streams=None):
+    """streams: one torch stream per class (default: a new default-priority
+    stream each); the binding keeps them alive until pmg_server_destroy."""
+    import torch
+    if streams is None:
+        streams = [torch.cuda.Stream() for _ in range(desc.n_classes)]
+    arr = (ctypes.c_void_p * desc.n_classes)(*[s.cuda_stream for s in streams])
     h = ctypes.c_void_p()
     _check(lib().pmg_server_create(ctypes.byref(desc), _ptr(ws), ws.numel() * ws.element_size(),
-                                   ctypes.byref(h)))
+                                   arr, ctypes.byref(h)))
+    _server_streams[h.value] = list(streams)
     return h
 
 
@@ -375,6 +390,7 @@ def pmg_server_stats_get(srv):
 def pmg_server_destroy(srv):
     if srv:
         _check(lib().pmg_server_destroy(srv))
+        _server_streams.pop(srv.value, None)
 
 
 def info_to_numpy(info_tensor) -> np.ndarray:

@@ -143,3 +143,55 @@ def test_server_mixed_classes_budget_and_bitwise_results():
             ref_u, ref_info = _one_shot([prob], p, **kw)
             assert np.array_equal(res[k][0], ref_u[0]), k
             assert res[k][1]["iterations"] == ref_info["iterations"][0]
+
+
+def test_server_large_classes_bitwise():
+    """The served benchmark's largest classes, 2-D p = 128 (gamma 3) and 3-D
+    p = 64 (gamma 4), FP32 cycle, with a budget that forces queueing: every
+    served result equals the same problem solved alone in a one-shot batch,
+    bit for bit (solution, iterations, relres)."""
+    classes = [
+        pmg.make_desc(dim=2, p_fine=128, batch=2, gamma=3, alpha=0.16,
+                      smoother=pmg.PMG_SMOOTHER_FEM, inner_prec=pmg.PMG_F32, max_iter=400),
+        pmg.make_desc(dim=3, p_fine=64, batch=1, gamma=4, alpha=0.16,
+                      smoother=pmg.PMG_SMOOTHER_FEM, inner_prec=pmg.PMG_F32, restart=20,
+                      max_iter=400),
+    ]
+    fp = [pmg.pmg_pool_workspace_bytes(c) // c.batch for c in classes]
+    budget = fp[0] + fp[1]                  # one 2-D and one 3-D request at a time
+    sdesc = pmg.make_server_desc(classes, iters_per_step=8, budget_bytes=budget)
+    ws = torch.empty(pmg.pmg_server_workspace_bytes(sdesc), dtype=torch.uint8, device="cuda")
+    srv = pmg.pmg_server_create(sdesc, ws)
+    reqs = [(0, inputs.config2(60 + i), 128) for i in range(3)] + \
+           [(1, inputs.config3(70 + i, 0.15), 64) for i in range(2)]
+    outs, tickets = [], []
+    for k, (c, prob, p) in enumerate(reqs):
+        print(f"[serve large] submit request {k}: class {c} p={p}", flush=True)
+        d = _request_data(prob, p)
+        u = torch.empty_like(d[1])
+        outs.append((d, u))
+        tickets.append(pmg.pmg_server_submit(srv, c, d[0], d[1], d[2], u))
+    for step in range(5000):
+        pmg.pmg_server_step(srv)
+        st = pmg.pmg_server_stats_get(srv)
+        assert st["bytes_in_use"] <= budget
+        if st["finished"] == len(reqs):
+            break
+    torch.cuda.synchronize()
+    assert pmg.pmg_server_stats_get(srv)["finished"] == len(reqs)
+    res = []
+    for t, (_, u) in zip(tickets, outs):
+        ok, info = pmg.pmg_server_poll(srv, t)
+        assert ok and info["status"] == 0 and info["relres"] <= 1e-10, info
+        res.append((u.cpu().numpy(), info))
+    pmg.pmg_server_destroy(srv)
+    for k, (c, prob, p) in enumerate(reqs):
+        desc = classes[c]
+        kw = dict(gamma=desc.gamma, alpha=desc.alpha, smoother=desc.smoother,
+                  inner_prec=desc.inner_prec, restart=desc.restart, max_iter=desc.max_iter)
+        ref_u, ref_info = _one_shot([prob], p, **kw)
+        print(f"[serve large] request {k}: served its {res[k][1]['iterations']} alone "
+              f"{ref_info['iterations'][0]}", flush=True)
+        assert np.array_equal(res[k][0], ref_u[0]), k
+        assert res[k][1]["iterations"] == ref_info["iterations"][0]
+        assert res[k][1]["relres"] == ref_info["relres"][0]
