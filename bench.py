@@ -78,11 +78,13 @@ def copy_calibration(mib):
                       "launches": 3}), flush=True)
 
 
-def flops_per_solve(dim, p, gamma, m, iters, krylov, restart):
+def flops_per_solve(dim, p, gamma, m, iters, krylov, restart, collapsed=()):
     """Algorithmic flop count of one solve: per level visit the operator's
     contractions and flux products, the line sweeps' cyclic reduction, the
     transfers and the vector updates; per outer iteration the FP64 operator
-    and the Krylov vector work."""
+    and the Krylov vector work.  A level in `collapsed` (degrees) is applied
+    as its dense matrix: 2 ni^2 flops per visit, and the levels below it are
+    not visited."""
     def level_costs(pl):
         n1 = pl + 1
         N = n1 ** dim
@@ -104,6 +106,9 @@ def flops_per_solve(dim, p, gamma, m, iters, krylov, restart):
     cycle = 0.0
     for depth, pl in enumerate(levels):
         visits = gamma ** depth
+        if pl in collapsed:
+            cycle += visits * 2 * (pl - 1) ** (2 * dim)
+            break
         if pl == 2:
             cycle += visits * 1
             continue
@@ -219,7 +224,10 @@ def run_batch(args, prec_name, dim=2, p=None, B=None, gamma=None, restriction=No
           f"solve kernel {solve_s * 1e3:.1f} ms, ok {ok}/{B}, its min/med/max {its.min()}/"
           f"{int(np.median(its))}/{its.max()}, max relres {nfo['relres'].max():.2e}",
           file=sys.stderr, flush=True)
-    flops = sum(flops_per_solve(dim, p, gamma, 1, int(k), args.krylov, restart) for k in its)
+    # levels the library applies as dense matrices (named "Cc[l]" in the layout)
+    coll = tuple(2 << int(name[3:-1]) for name, _, _ in pmg.pmg_workspace_layout(desc)
+                 if name.startswith("Cc["))
+    flops = sum(flops_per_solve(dim, p, gamma, 1, int(k), args.krylov, restart, coll) for k in its)
     xk = x[:keep].cpu().numpy() if keep else None
     return {"value": value, "ms_per_step": ms_per_step, "solve_s": solve_s, "its": its,
             "ok": ok, "flops": flops, "max_relres": float(nfo["relres"].max()),

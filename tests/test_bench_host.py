@@ -43,3 +43,14 @@ def test_flop_model_monotone():
     n1 = 129
     apply_ = (4 * 2 * n1 + 7 + 1) * n1 ** 2
     assert b - a > apply_
+
+
+def test_flop_model_collapsed_levels():
+    """A collapsed level costs its matrix-vector product per visit and hides
+    the levels below it: cheaper than the recursive count at gamma = 7."""
+    full = bench.flops_per_solve(2, 128, 7, 1, 8, "fgmres", 30)
+    coll = bench.flops_per_solve(2, 128, 7, 1, 8, "fgmres", 30, collapsed=(8, 16))
+    assert 0 < coll < full
+    one = bench.flops_per_solve(2, 128, 3, 1, 1, "fgmres", 30, collapsed=(16,))
+    two = bench.flops_per_solve(2, 128, 3, 1, 1, "fgmres", 30, collapsed=(8, 16))
+    assert one == two        # the p = 16 matrix hides p = 8
