@@ -56,6 +56,11 @@ def lib():
             "or_hier_create": (vp, [ctypes.c_int, ctypes.c_int, _I, ctypes.POINTER(_D),
                                     ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                     ctypes.c_int]),
+            "or_hier_create_elements": (vp, [ctypes.c_int, ctypes.c_int, ctypes.c_int, _I,
+                                             ctypes.POINTER(_D), ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_double, ctypes.c_int, ctypes.c_int]),
+            "or_elements": (ctypes.c_int, [vp]),
+            "or_geom_elements": (ctypes.c_int, [vp, ctypes.c_int, _D]),
             "or_line_band": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, _D]),
             "or_hier_destroy": (None, [vp]),
             "or_nodes": (ctypes.c_int, [vp, ctypes.c_int]),
@@ -198,19 +203,23 @@ class Hier:
     """A multigrid hierarchy of the oracle.
 
     ``plist`` ascending degrees (coarsest first); ``coords[l]`` is a
-    (dim, N_l) array of physical node positions of level l.
+    (dim, N_l) array of physical node positions of level l.  ``elements`` =
+    K > 1: K^dim spectral elements per level, ``plist`` the degrees of the
+    composite grids (K times the element degrees).
     """
 
     def __init__(self, dim, plist, coords, gamma=7, m=1, alpha=2.0 / 3.0, smoother=0,
-                 restriction=RESTRICT_TRANSPOSE):
+                 restriction=RESTRICT_TRANSPOSE, elements=1):
         self.dim = int(dim)
         self.plist = [int(p) for p in plist]
         self.nlev = len(self.plist)
         self._coords = [_f64(np.asarray(c).reshape(-1)) for c in coords]
         cp = (_D * self.nlev)(*[_p(c) for c in self._coords])
         pl = (ctypes.c_int * self.nlev)(*self.plist)
-        self.h = lib().or_hier_create(self.dim, self.nlev, pl, cp, int(gamma), int(m),
-                                      float(alpha), int(smoother), int(restriction))
+        self.elements = int(elements)
+        self.h = lib().or_hier_create_elements(self.dim, self.elements, self.nlev, pl, cp,
+                                               int(gamma), int(m), float(alpha), int(smoother),
+                                               int(restriction))
         if not self.h:
             raise ValueError("or_hier_create failed (bad arguments or det J <= 0)")
         self.gamma, self.m, self.alpha = gamma, m, alpha
@@ -232,6 +241,16 @@ class Hier:
         mass = np.zeros(N)
         mindet = lib().or_geom(self.h, l, _p(G), _p(mass))
         return G.reshape(self.dim, self.dim, N), mass, mindet
+
+    def geom_elements(self, l=-1):
+        """Element geometric factors (K^dim, dim, dim, NE) of an element hierarchy."""
+        l = l % self.nlev
+        n = lib().or_geom_elements(self.h, l, None)
+        if n < 0:
+            raise ValueError("not an element hierarchy")
+        G = np.zeros(n)
+        lib().or_geom_elements(self.h, l, _p(G))
+        return G.reshape(self.elements ** self.dim, self.dim, self.dim, -1)
 
     def apply(self, x, l=-1, all_rows=False):
         l = l % self.nlev

@@ -503,6 +503,15 @@ typedef struct {
     double* band[3];  /* OR_SMOOTHER_GLL_BAND2: 5 entries per line position */
     double* full[3];  /* OR_SMOOTHER_GLL_FULL: dense n x n block per line */
     double* A0inv; /* dense inverse of the interior matrix (level 0 only) */
+    /* several elements (K > 1): K^dim elements of degree pe = p / K on the
+     * tensor grid of K x K (x K) equal squares of the reference square; the
+     * level's node grid is the composite one (element nodes, shared
+     * interface nodes once), so vectors keep the one-element layout */
+    int K, pe, ne1, NE;
+    double* exi;   /* element GLL nodes (pe+1) */
+    double* erho;  /* element GLL weights */
+    double* eD;    /* element derivative matrix ne1 x ne1 */
+    double* eG;    /* per element e: dim*dim arrays of NE, at eG + e*dim*dim*NE */
 } or_level;
 
 struct or_hier {
@@ -601,8 +610,10 @@ static int level_geometry(int dim, or_level* L, const double* X)
  * of sum_ab G_ab(q) d_a v_row(q) d_b v_col(q), where for the tensor basis
  * d_a v_n(q) = D[q_a][n_a] if q agrees with n on every axis but a, else 0.
  * The loops visit only the nodes q where d_a v_row(q) can be nonzero. */
+static double elements_entry(int dim, const or_level* L, int row, int col);
 static double level_entry(int dim, const or_level* L, int row, int col)
 {
+    if (L->K > 1) return elements_entry(dim, L, row, col);
     int n1 = L->n1, N = L->N;
     int rn[3], cn[3];
     unrank(dim, n1, row, rn);
@@ -631,8 +642,13 @@ static double level_entry(int dim, const or_level* L, int row, int col)
  * For each q: reference gradient g_b(q) = sum_k D[q_b][k] x(q with axis b <- k),
  * flux f_a(q) = sum_b G_ab(q) g_b(q); then
  * (A x)(n) = sum_a sum_k D[k][n_a] f_a(n with axis a <- k). */
+static void elements_apply_all(int dim, const or_level* L, const double* x, double* y);
 static void level_apply_all(int dim, const or_level* L, const double* x, double* y)
 {
+    if (L->K > 1) {
+        elements_apply_all(dim, L, x, y);
+        return;
+    }
     int n1 = L->n1, N = L->N;
     int stride[3] = {1, n1, n1 * n1};
     double* flux = (double*)malloc(sizeof(double) * (size_t)N * dim);
@@ -672,6 +688,216 @@ static void level_apply(int dim, const or_level* L, const double* x, double* y)
     level_apply_all(dim, L, x, y);
     for (int q = 0; q < L->N; ++q)
         if (!is_interior(dim, L->n1, q)) y[q] = 0.0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Several elements (the paper's closing outlook: multi-element           */
+/* hp-multigrid).  The paper defines one element; the coupling used here   */
+/* is the standard conforming one of spectral elements: the global basis  */
+/* function of an interface node is the union of the element basis         */
+/* functions that share it, so A = sum_e Q_e^T A_e Q_e and the mass is the */
+/* sum of the element masses (direct stiffness summation).                */
+/* ------------------------------------------------------------------ */
+
+/* global node of local node lq of element e */
+static int elem_node(int dim, const or_level* L, int e, int lq)
+{
+    int ec[3], lc[3], c[3];
+    unrank(dim, L->K, e, ec);
+    unrank(dim, L->ne1, lq, lc);
+    for (int a = 0; a < dim; ++a) c[a] = ec[a] * L->pe + lc[a];
+    return rank_(dim, L->n1, c);
+}
+
+/* Geometry of every element from the level's composite coordinates, with
+ * the element's own GLL rule and derivative matrix (the one-element
+ * formulas of level_geometry per element); the mass is assembled. */
+static int elements_geometry(int dim, or_level* L, const double* X)
+{
+    int ne1 = L->ne1, NE = L->NE, N = L->N, d2 = dim * dim;
+    int nel = ipow(L->K, dim);
+    L->mindet = INFINITY;
+    for (int q = 0; q < N; ++q) L->mass[q] = 0.0;
+    for (int e = 0; e < nel; ++e) {
+        double* G = L->eG + (size_t)e * d2 * NE;
+        for (int lq = 0; lq < NE; ++lq) {
+            int c[3];
+            unrank(dim, ne1, lq, c);
+            double Jm[3][3];
+            for (int comp = 0; comp < dim; ++comp)
+                for (int a = 0; a < dim; ++a) {
+                    double sum = 0.0;
+                    int cc[3] = {c[0], c[1], c[2]};
+                    for (int k = 0; k < ne1; ++k) {
+                        cc[a] = k;
+                        sum += L->eD[c[a] * ne1 + k] * X[comp * N + elem_node(dim, L, e, rank_(dim, ne1, cc))];
+                    }
+                    Jm[comp][a] = sum;
+                }
+            double det, inv[3][3];
+            if (dim == 2) {
+                det = Jm[0][0] * Jm[1][1] - Jm[0][1] * Jm[1][0];
+                inv[0][0] = Jm[1][1] / det;  inv[0][1] = -Jm[0][1] / det;
+                inv[1][0] = -Jm[1][0] / det; inv[1][1] = Jm[0][0] / det;
+            } else {
+                det = Jm[0][0] * (Jm[1][1] * Jm[2][2] - Jm[1][2] * Jm[2][1])
+                    - Jm[0][1] * (Jm[1][0] * Jm[2][2] - Jm[1][2] * Jm[2][0])
+                    + Jm[0][2] * (Jm[1][0] * Jm[2][1] - Jm[1][1] * Jm[2][0]);
+                inv[0][0] = (Jm[1][1] * Jm[2][2] - Jm[1][2] * Jm[2][1]) / det;
+                inv[0][1] = (Jm[0][2] * Jm[2][1] - Jm[0][1] * Jm[2][2]) / det;
+                inv[0][2] = (Jm[0][1] * Jm[1][2] - Jm[0][2] * Jm[1][1]) / det;
+                inv[1][0] = (Jm[1][2] * Jm[2][0] - Jm[1][0] * Jm[2][2]) / det;
+                inv[1][1] = (Jm[0][0] * Jm[2][2] - Jm[0][2] * Jm[2][0]) / det;
+                inv[1][2] = (Jm[0][2] * Jm[1][0] - Jm[0][0] * Jm[1][2]) / det;
+                inv[2][0] = (Jm[1][0] * Jm[2][1] - Jm[1][1] * Jm[2][0]) / det;
+                inv[2][1] = (Jm[0][1] * Jm[2][0] - Jm[0][0] * Jm[2][1]) / det;
+                inv[2][2] = (Jm[0][0] * Jm[1][1] - Jm[0][1] * Jm[1][0]) / det;
+            }
+            if (det < L->mindet) L->mindet = det;
+            double w = 1.0;
+            for (int a = 0; a < dim; ++a) w *= L->erho[c[a]];
+            double phi = w * det;
+            L->mass[elem_node(dim, L, e, lq)] += phi;
+            for (int a = 0; a < dim; ++a)
+                for (int b = 0; b < dim; ++b) {
+                    double sum = 0.0;
+                    for (int comp = 0; comp < dim; ++comp) sum += inv[a][comp] * inv[b][comp];
+                    G[(a * dim + b) * NE + lq] = phi * sum;
+                }
+        }
+    }
+    return L->mindet > 0.0 ? 0 : -1;
+}
+
+/* A x on every row: per element, the one-element quadrature sum on the
+ * element's nodes (gradients, fluxes, D^T of the fluxes), added into the
+ * rows of the element's global nodes. */
+static void elements_apply_all(int dim, const or_level* L, const double* x, double* y)
+{
+    int ne1 = L->ne1, NE = L->NE, d2 = dim * dim;
+    int nel = ipow(L->K, dim);
+    int stride[3] = {1, ne1, ne1 * ne1};
+    double* xe = (double*)malloc(sizeof(double) * (size_t)NE);
+    double* flux = (double*)malloc(sizeof(double) * (size_t)NE * dim);
+    for (int q = 0; q < L->N; ++q) y[q] = 0.0;
+    for (int e = 0; e < nel; ++e) {
+        const double* G = L->eG + (size_t)e * d2 * NE;
+        for (int lq = 0; lq < NE; ++lq) xe[lq] = x[elem_node(dim, L, e, lq)];
+        for (int lq = 0; lq < NE; ++lq) {
+            int c[3];
+            unrank(dim, ne1, lq, c);
+            double g[3];
+            for (int b = 0; b < dim; ++b) {
+                int q0 = lq - c[b] * stride[b];
+                double sum = 0.0;
+                for (int k = 0; k < ne1; ++k) sum += L->eD[c[b] * ne1 + k] * xe[q0 + k * stride[b]];
+                g[b] = sum;
+            }
+            for (int a = 0; a < dim; ++a) {
+                double sum = 0.0;
+                for (int b = 0; b < dim; ++b) sum += G[(a * dim + b) * NE + lq] * g[b];
+                flux[a * NE + lq] = sum;
+            }
+        }
+        for (int ln = 0; ln < NE; ++ln) {
+            int c[3];
+            unrank(dim, ne1, ln, c);
+            double sum = 0.0;
+            for (int a = 0; a < dim; ++a) {
+                int n0 = ln - c[a] * stride[a];
+                for (int k = 0; k < ne1; ++k)
+                    sum += L->eD[k * ne1 + c[a]] * flux[a * NE + n0 + k * stride[a]];
+            }
+            y[elem_node(dim, L, e, ln)] += sum;
+        }
+    }
+    free(xe); free(flux);
+}
+
+/* elements containing the global node with coordinates c: on each axis the
+ * element whose closed interval holds c[a] (two at an interface) */
+static int node_elements(int dim, const or_level* L, const int* c, int* out)
+{
+    int cand[3][2], nc[3];
+    for (int a = 0; a < dim; ++a) {
+        nc[a] = 0;
+        int e0 = c[a] / L->pe;
+        if (e0 < L->K) cand[a][nc[a]++] = e0;
+        if (c[a] % L->pe == 0 && e0 - 1 >= 0) cand[a][nc[a]++] = e0 - 1;
+    }
+    int n = 0;
+    for (int i0 = 0; i0 < nc[0]; ++i0)
+        for (int i1 = 0; i1 < nc[1]; ++i1)
+            for (int i2 = 0; i2 < (dim > 2 ? nc[2] : 1); ++i2) {
+                int ec[3] = {cand[0][i0], cand[1][i1], dim > 2 ? cand[2][i2] : 0};
+                out[n++] = rank_(dim, L->K, ec);
+            }
+    return n;
+}
+
+/* Entry A[row, col] of the assembled operator: the one-element quadrature
+ * formula of level_entry summed over the elements holding both nodes. */
+static double elements_entry(int dim, const or_level* L, int row, int col)
+{
+    int ne1 = L->ne1, NE = L->NE, d2 = dim * dim;
+    int rn[3], cn[3], er[8], ec_[8];
+    unrank(dim, L->n1, row, rn);
+    unrank(dim, L->n1, col, cn);
+    int nr = node_elements(dim, L, rn, er), ncl = node_elements(dim, L, cn, ec_);
+    double s = 0.0;
+    for (int i = 0; i < nr; ++i) {
+        int e = er[i], both = 0;
+        for (int j = 0; j < ncl; ++j) both |= ec_[j] == e;
+        if (!both) continue;
+        int ecoord[3], lr[3], lc[3];
+        unrank(dim, L->K, e, ecoord);
+        for (int a = 0; a < dim; ++a) {
+            lr[a] = rn[a] - ecoord[a] * L->pe;
+            lc[a] = cn[a] - ecoord[a] * L->pe;
+        }
+        const double* G = L->eG + (size_t)e * d2 * NE;
+        for (int a = 0; a < dim; ++a)
+            for (int k = 0; k < ne1; ++k) {
+                int qc[3] = {lr[0], lr[1], lr[2]};
+                qc[a] = k;
+                double da = L->eD[k * ne1 + lr[a]];
+                if (da == 0.0) continue;
+                int q = rank_(dim, ne1, qc);
+                for (int b = 0; b < dim; ++b) {
+                    int match = 1;
+                    for (int f = 0; f < dim; ++f)
+                        if (f != b && qc[f] != lc[f]) { match = 0; break; }
+                    if (!match) continue;
+                    s += G[(a * dim + b) * NE + q] * da * L->eD[qc[b] * ne1 + lc[b]];
+                }
+            }
+    }
+    return s;
+}
+
+/* The 1-D transfers between two composite grids with the same K elements:
+ * J[(e pf + i)][(e pc + j)] = pi^c_j(xi^f_i) (coarse element basis at the
+ * fine element nodes) and Q[(e pc + j)][(e pf + i)] = pi^f_i(xi^c_j) (fine
+ * element basis at the coarse element nodes), zero between different
+ * elements.  At an interface node both elements give the same value (the
+ * bases interpolate), so the composite functions are continuous. */
+static void elements_interp(int K, int pc, const double* xic, int pf, const double* xif,
+                            double* J, double* Q)
+{
+    int nf = K * pf + 1, nc = K * pc + 1;
+    double* Jl = (double*)malloc(sizeof(double) * (size_t)(pf + 1) * (pc + 1));
+    double* Ql = (double*)malloc(sizeof(double) * (size_t)(pf + 1) * (pc + 1));
+    or_interp(pc, xic, pf + 1, xif, Jl);   /* (pf+1) x (pc+1) */
+    or_interp(pf, xif, pc + 1, xic, Ql);   /* (pc+1) x (pf+1) */
+    memset(J, 0, sizeof(double) * (size_t)nf * nc);
+    memset(Q, 0, sizeof(double) * (size_t)nf * nc);
+    for (int e = 0; e < K; ++e)
+        for (int i = 0; i <= pf; ++i)
+            for (int j = 0; j <= pc; ++j) {
+                J[(size_t)(e * pf + i) * nc + e * pc + j] = Jl[i * (pc + 1) + j];
+                Q[(size_t)(e * pc + j) * nf + e * pf + i] = Ql[j * (pf + 1) + i];
+            }
+    free(Jl); free(Ql);
 }
 
 /* Entry of the bilinear finite-element stiffness matrix A~_p of Sec. 3.1
@@ -946,6 +1172,7 @@ static void level_free(or_level* L)
     for (int a = 0; a < 3; ++a) { free(L->lo[a]); free(L->di[a]); free(L->up[a]); }
     for (int a = 0; a < 3; ++a) { free(L->band[a]); free(L->full[a]); }
     free(L->J); free(L->Q); free(L->A0inv); free(L->X);
+    free(L->exi); free(L->erho); free(L->eD); free(L->eG);
     memset(L, 0, sizeof(*L));
 }
 
@@ -959,12 +1186,22 @@ void or_hier_destroy(or_hier* h)
 or_hier* or_hier_create(int dim, int nlev, const int* p, const double* const* coords,
                         int gamma, int m, double alpha, int smoother, int restriction)
 {
+    return or_hier_create_elements(dim, 1, nlev, p, coords, gamma, m, alpha, smoother,
+                                   restriction);
+}
+
+or_hier* or_hier_create_elements(int dim, int K, int nlev, const int* p,
+                                 const double* const* coords, int gamma, int m, double alpha,
+                                 int smoother, int restriction)
+{
     if ((dim != 2 && dim != 3) || nlev < 1 || nlev > OR_MAXLEV || gamma < 1 || m < 0
         || smoother < OR_SMOOTHER_GLL || smoother > OR_SMOOTHER_GLL_FULL
-        || (restriction != OR_RESTRICT_TRANSPOSE && restriction != OR_RESTRICT_INTERP))
+        || (restriction != OR_RESTRICT_TRANSPOSE && restriction != OR_RESTRICT_INTERP)
+        || K < 1)
         return NULL;
     for (int l = 0; l < nlev; ++l)
-        if (p[l] < 2 || (l > 0 && p[l] <= p[l - 1])) return NULL;
+        if (p[l] < 2 || (l > 0 && p[l] <= p[l - 1]) || p[l] % K != 0 || p[l] / K < 2)
+            return NULL;
     or_hier* h = (or_hier*)calloc(1, sizeof(or_hier));
     h->dim = dim; h->nlev = nlev; h->gamma = gamma; h->m = m; h->alpha = alpha;
     h->smoother = smoother;
@@ -973,16 +1210,35 @@ or_hier* or_hier_create(int dim, int nlev, const int* p, const double* const* co
         or_level* L = &h->lev[l];
         L->p = p[l]; L->n1 = p[l] + 1; L->N = ipow(L->n1, dim);
         L->nint = ipow(p[l] - 1, dim);
+        L->K = K;
         L->xi = (double*)malloc(sizeof(double) * L->n1);
         L->rho = (double*)malloc(sizeof(double) * L->n1);
         L->D = (double*)malloc(sizeof(double) * L->n1 * L->n1);
         L->G = (double*)malloc(sizeof(double) * (size_t)L->N * dim * dim);
         L->mass = (double*)malloc(sizeof(double) * (size_t)L->N);
-        if (or_gll(L->p, L->xi, L->rho)) goto fail;
-        or_deriv(L->p, L->xi, L->D);
         L->X = (double*)malloc(sizeof(double) * (size_t)L->N * dim);
         memcpy(L->X, coords[l], sizeof(double) * (size_t)L->N * dim);
-        if (level_geometry(dim, L, coords[l])) goto fail;
+        if (K == 1) {
+            if (or_gll(L->p, L->xi, L->rho)) goto fail;
+            or_deriv(L->p, L->xi, L->D);
+            if (level_geometry(dim, L, coords[l])) goto fail;
+        } else {
+            L->pe = p[l] / K; L->ne1 = L->pe + 1; L->NE = ipow(L->ne1, dim);
+            L->exi = (double*)malloc(sizeof(double) * L->ne1);
+            L->erho = (double*)malloc(sizeof(double) * L->ne1);
+            L->eD = (double*)malloc(sizeof(double) * L->ne1 * L->ne1);
+            L->eG = (double*)malloc(sizeof(double) * (size_t)ipow(K, dim) * dim * dim * L->NE);
+            if (or_gll(L->pe, L->exi, L->erho)) goto fail;
+            or_deriv(L->pe, L->exi, L->eD);
+            /* composite reference nodes (element e covers [-1 + 2e/K, -1 + 2(e+1)/K]) */
+            for (int e = 0; e < K; ++e)
+                for (int i = 0; i <= L->pe; ++i)
+                    L->xi[e * L->pe + i] = -1.0 + (2.0 * e + 1.0 + L->exi[i]) / K;
+            memset(L->rho, 0, sizeof(double) * L->n1);
+            memset(L->D, 0, sizeof(double) * L->n1 * L->n1);
+            memset(L->G, 0, sizeof(double) * (size_t)L->N * dim * dim);
+            if (elements_geometry(dim, L, coords[l])) goto fail;
+        }
         for (int a = 0; a < dim; ++a) {
             L->lo[a] = (double*)malloc(sizeof(double) * (size_t)L->nint);
             L->di[a] = (double*)malloc(sizeof(double) * (size_t)L->nint);
@@ -999,10 +1255,14 @@ or_hier* or_hier_create(int dim, int nlev, const int* p, const double* const* co
         if (l > 0) {
             or_level* C = &h->lev[l - 1];
             L->J = (double*)malloc(sizeof(double) * L->n1 * C->n1);
-            or_interp(C->p, C->xi, L->n1, L->xi, L->J);
-            /* Q[i][j] = pi^f_j(xc_i): the fine basis at the coarse nodes */
             L->Q = (double*)malloc(sizeof(double) * L->n1 * C->n1);
-            or_interp(L->p, L->xi, C->n1, C->xi, L->Q);
+            if (K == 1) {
+                or_interp(C->p, C->xi, L->n1, L->xi, L->J);
+                /* Q[i][j] = pi^f_j(xc_i): the fine basis at the coarse nodes */
+                or_interp(L->p, L->xi, C->n1, C->xi, L->Q);
+            } else {
+                elements_interp(K, C->pe, C->exi, L->pe, L->exi, L->J, L->Q);
+            }
         }
     }
     {
@@ -1047,6 +1307,17 @@ or_hier* or_hier_create(int dim, int nlev, const int* p, const double* const* co
 fail:
     or_hier_destroy(h);
     return NULL;
+}
+
+int or_elements(const or_hier* h) { return h->lev[0].K; }
+
+int or_geom_elements(const or_hier* h, int l, double* G)
+{
+    const or_level* L = &h->lev[l];
+    if (L->K < 2) return -1;
+    size_t n = (size_t)ipow(L->K, h->dim) * h->dim * h->dim * L->NE;
+    if (G) memcpy(G, L->eG, sizeof(double) * n);
+    return (int)n;
 }
 
 double or_geom(const or_hier* h, int l, double* G, double* mass)

@@ -112,11 +112,33 @@ or_hier* or_hier_create(int dim, int nlev, const int* p,
                         int gamma, int m, double alpha, int smoother, int restriction);
 void or_hier_destroy(or_hier* h);
 
+/* The same hierarchy on K^dim spectral elements (K per axis; the paper's
+ * closing outlook, multi-element hp-multigrid): the reference square (cube)
+ * is split into K equal parts per axis, each an element of degree p[l] / K
+ * (>= 2) with its own GLL rule; interface nodes are shared (continuous
+ * basis), the operator and the mass are assembled from the element ones,
+ * and the transfers interpolate element by element.  p[l] is the degree of
+ * the level's composite grid (K * element degree; p[l] + 1 nodes per axis)
+ * and coords[l] its node positions, so every vector keeps the one-element
+ * layout.  K = 1 is or_hier_create. */
+or_hier* or_hier_create_elements(int dim, int K, int nlev, const int* p,
+                                 const double* const* coords, int gamma, int m, double alpha,
+                                 int smoother, int restriction);
+/* K of the hierarchy */
+int or_elements(const or_hier* h);
+/* Element geometric factors of level l of an element hierarchy (K > 1):
+ * element e (lexicographic, first axis fastest) at G + e*dim*dim*NE, NE =
+ * (p/K + 1)^dim, arrays ordered as in or_geom.  Returns the number of
+ * doubles, or -1 for K = 1. */
+int or_geom_elements(const or_hier* h, int l, double* G);
+
 /* Number of nodes of level l. */
 int or_nodes(const or_hier* h, int l);
 
 /* Geometric factors of level l: G has dim*dim arrays of N doubles
- * (G[(a*dim+b)*N + q]), mass has N doubles.  Returns minimum det J. */
+ * (G[(a*dim+b)*N + q]; all zero for an element hierarchy, see
+ * or_geom_elements), mass has N doubles (assembled over elements).
+ * Returns minimum det J. */
 double or_geom(const or_hier* h, int l, double* G, double* mass);
 
 /* y = A_l x restricted to interior rows (boundary rows set to 0).  x is a

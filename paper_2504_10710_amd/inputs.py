@@ -44,6 +44,18 @@ def unit_coords(nodes_1d, dim: int):
     return np.stack([g.reshape(-1, order="F") for g in grids])
 
 
+def composite_nodes(nodes_1d, K: int) -> np.ndarray:
+    """Reference positions in [-1, 1] of the composite node grid of K equal
+    elements along an axis, each carrying the 1-D nodes ``nodes_1d`` (given
+    on [-1, 1]); interface nodes appear once (K p + 1 nodes)."""
+    xi = np.asarray(nodes_1d, dtype=np.float64)
+    pe = len(xi) - 1
+    out = np.empty(K * pe + 1)
+    for e in range(K):
+        out[e * pe:(e + 1) * pe + 1] = -1.0 + (2.0 * e + 1.0 + xi) / K
+    return out
+
+
 @dataclass
 class Problem:
     """A seeded problem instance: mapping parameters and data coefficients."""
