@@ -94,7 +94,24 @@ enum { PMG_RESTRICT_TRANSPOSE = 0, PMG_RESTRICT_INTERP = 1 };
  *              R_l = P_l^T (a stronger, Galerkin-consistent preconditioner:
  *              fewer iterations, not the method behind Table 1).  Coarse
  *              boundary rows are zero either way; P_l is the interpolation
- *              of the coarse polynomial at the fine nodes in both. */
+ *              of the coarse polynomial at the fine nodes in both.
+ *   elements   K spectral elements per axis (0 or 1: the one element of the
+ *              paper; 2, 4 or 8: the multi-element hp-multigrid of the
+ *              paper's closing outlook, 2-D, FEM line smoother).  The square
+ *              is split into K x K equal parts of the reference square,
+ *              each an element of degree p_l / K with its own GLL rule; an
+ *              interface node is shared by the elements that meet there
+ *              (continuous basis), the operator and the mass are the sums
+ *              of the element ones, and the transfers interpolate element
+ *              by element.  p_fine is the degree of the composite node grid
+ *              (K times the finest element degree, which must be >= 4):
+ *              vectors keep the one-element layout of p_fine + 1 nodes per
+ *              axis.  The levels halve the element degree down to 2, so the
+ *              coarsest level has degree 2K (level index log2(2K) - 1; the
+ *              levels below it are absent) and is solved exactly with the
+ *              inverse of its (2K-1)^2 x (2K-1)^2 interior matrix, built at
+ *              setup in FP64.  Line systems run along the composite grid
+ *              lines across element interfaces. */
 typedef struct {
     int dim;
     int p_fine;
@@ -109,6 +126,7 @@ typedef struct {
     int max_iter;
     double rtol;
     int restriction;
+    int elements;
 } pmg_desc;
 
 /* Per-problem result of the device solve (written by pmg_solve). */
@@ -125,8 +143,11 @@ typedef struct pmg_handle pmg_handle;
 /* Thread-local text of the last error. */
 const char* pmg_last_error(void);
 
-/* Number of levels of a description (p_fine = 2^L * 2 gives L + 1). */
+/* Number of levels of a description (p_fine = 2^L * 2 gives L + 1), and
+ * the index of its coarsest present level (0, or log2(2K) - 1 for K
+ * elements per axis; first_level may be NULL). */
 int pmg_num_levels(const pmg_desc* desc, int* n_levels);
+int pmg_first_level(const pmg_desc* desc, int* first_level);
 
 /* GLL nodes xi[0..p] and weights rho[0..p] of order p (Def. GLL quadrature
  * rule), and D[i*(p+1)+j] = pi_j'(xi_i) (derivative of the Lagrange basis of
@@ -163,7 +184,10 @@ int pmg_workspace_layout(const pmg_desc* desc, pmg_region* regions, int max_regi
  * cyclic-reduction factors, Sec. 3.2).
  *   d_coords[l]  level-l physical node positions: B x dim x N_l doubles
  *                (all first coordinates of a problem, then all second, ...)
- *                at the level's GLL nodes; read during the call's stream work
+ *                at the level's GLL nodes (the composite grid's nodes for
+ *                K elements per axis); read during the call's stream work.
+ *                Entries of absent levels (below the first level) are
+ *                ignored and may be NULL.
  *   d_ws         caller-owned device workspace of ws_bytes >= the size from
  *                pmg_workspace_bytes; must stay valid until pmg_destroy
  *   d_info       B pmg_info records (device), min_detj and status filled
@@ -264,7 +288,10 @@ int pmg_line_band(pmg_handle* h, int level, int dir, double* d_band, pmg_stream_
 
 /* Geometric factors of level l: d_G B x ncomp x N_l doubles (ncomp = 3 in
  * 2-D: G_00, G_11, G_01; 6 in 3-D: G_00, G_11, G_22, G_01, G_02, G_12) and
- * d_mass B x N_l doubles (may be NULL). */
+ * d_mass B x N_l doubles (may be NULL).  K elements per axis: d_G holds per
+ * problem the K^2 elements in lexicographic order (first axis fastest),
+ * each ncomp x (p_l/K + 1)^2 doubles at its element nodes, and the mass is
+ * the assembled one at the composite nodes. */
 int pmg_geom(pmg_handle* h, int level, double* d_G, double* d_mass, pmg_stream_t stream);
 
 /* Release the host handle (the workspace stays the caller's). */

@@ -203,8 +203,22 @@ int check_desc(const pmg_desc* d)
     if (!(d->rtol > 0.0)) return fail(PMG_EINVAL, "rtol must be > 0");
     if (d->restriction != PMG_RESTRICT_TRANSPOSE && d->restriction != PMG_RESTRICT_INTERP)
         return fail(PMG_EINVAL, "unknown restriction %d", d->restriction);
+    if (d->elements < 0 || d->elements > 8 || (d->elements > 1 && !is_pow2(d->elements)))
+        return fail(PMG_EINVAL, "elements must be 0, 1, 2, 4 or 8 (got %d)", d->elements);
+    if (d->elements > 1) {
+        if (d->dim != 2) return fail(PMG_EINVAL, "several elements per axis are supported in 2-D");
+        if (d->p_fine / d->elements < 4)
+            return fail(PMG_EINVAL, "the finest element degree p_fine / elements must be >= 4 "
+                                    "(got %d / %d)", d->p_fine, d->elements);
+        if (d->smoother != PMG_SMOOTHER_FEM)
+            return fail(PMG_EINVAL, "several elements per axis use the FEM line smoother");
+    }
     return PMG_OK;
 }
+
+// elements per axis and the index of the coarsest present level (degree 2K)
+int elems_of(const pmg_desc& d) { return d.elements > 1 ? d.elements : 1; }
+int first_level_of(const pmg_desc& d) { return ilog2(2 * elems_of(d)) - 1; }
 
 struct LevelShape {
     int p, n1, N, n, NL, NC, CRW;
@@ -228,6 +242,8 @@ LevelShape level_shape(int dim, int l)
 struct pmg_handle {
     pmg_desc d;
     int nlev;
+    int K = 1;    // elements per axis
+    int l0 = 0;   // coarsest present level (degree 2K)
     bool f32;
     size_t ws_bytes;
     char* ws;
@@ -260,6 +276,25 @@ struct pmg_handle {
 
 namespace {
 
+void describe(pmg_handle* h, const pmg_desc* desc)
+{
+    h->d = *desc;
+    h->nlev = ilog2(desc->p_fine);
+    h->K = elems_of(*desc);
+    h->l0 = first_level_of(*desc);
+    h->f32 = desc->inner_prec == PMG_F32;
+}
+
+// element nodes of level l of a K-element handle (per problem: K^dim
+// elements of (p_l/K + 1)^dim nodes); N_l for one element
+long long elem_nodes(const pmg_handle* h, int l)
+{
+    const LevelShape s = level_shape(h->d.dim, l);
+    if (h->K == 1) return s.N;
+    const long long ne1 = s.p / h->K + 1;
+    return (long long)h->K * h->K * ne1 * ne1;
+}
+
 void plan(pmg_handle* h, std::vector<pmg_region>* rec = nullptr)
 {
     const pmg_desc& d = h->d;
@@ -268,14 +303,22 @@ void plan(pmg_handle* h, std::vector<pmg_region>* rec = nullptr)
     Layout L;
     L.rec = rec;
     long long w = 0;
-    for (int l = 0; l < h->nlev; ++l) {
+    for (int l = 0; l < MAX_LEVELS; ++l) {
+        h->o_rho[l] = h->o_D64[l] = h->o_DT64[l] = h->o_D32[l] = h->o_DT32[l] = 0;
+        h->o_J64[l] = h->o_JT64[l] = h->o_J32[l] = h->o_JT32[l] = h->o_JR64[l] = h->o_JR32[l] = 0;
+        h->o_G64[l] = h->o_G32[l] = h->o_X64[l] = h->o_X[l] = h->o_R[l] = h->o_Tm[l] = h->o_TR[l] = 0;
+        h->o_Cc[l] = 0;
+        for (int a = 0; a < 3; ++a)
+            h->o_cr64[l][a] = h->o_cr32[l][a] = h->o_bd64[l][a] = h->o_bd32[l][a] = 0;
+    }
+    for (int l = h->l0; l < h->nlev; ++l) {
         LevelShape s = level_shape(dim, l);
         h->o_rho[l] = L.take("rho", l, sizeof(double) * s.n1);
         h->o_D64[l] = L.take("D64", l, sizeof(double) * s.n1 * s.n1);
         h->o_DT64[l] = L.take("DT64", l, sizeof(double) * s.n1 * s.n1);
         h->o_D32[l] = L.take("D32", l, sizeof(float) * s.n1 * s.n1);
         h->o_DT32[l] = L.take("DT32", l, sizeof(float) * s.n1 * s.n1);
-        if (l > 0) {
+        if (l > h->l0) {
             int n1c = s.p / 2 + 1;
             h->o_J64[l] = L.take("J64", l, sizeof(double) * s.n1 * n1c);
             h->o_JT64[l] = L.take("JT64", l, sizeof(double) * s.n1 * n1c);
@@ -290,10 +333,11 @@ void plan(pmg_handle* h, std::vector<pmg_region>* rec = nullptr)
             h->o_JR64[l] = h->o_JR32[l] = 0;
         }
     }
-    for (int l = 0; l < h->nlev; ++l) {
+    for (int l = h->l0; l < h->nlev; ++l) {
         LevelShape s = level_shape(dim, l);
-        h->o_G64[l] = L.take("G64", l, sizeof(double) * (size_t)B * s.NC * s.N);
-        h->o_G32[l] = h->f32 ? L.take("G32", l, sizeof(float) * (size_t)B * s.NC * s.N) : 0;
+        const long long NE = elem_nodes(h, l);   // geometric factors and fluxes per element node
+        h->o_G64[l] = L.take("G64", l, sizeof(double) * (size_t)B * s.NC * NE);
+        h->o_G32[l] = h->f32 ? L.take("G32", l, sizeof(float) * (size_t)B * s.NC * NE) : 0;
         h->o_X64[l] = L.take("X64", l, sizeof(double) * (size_t)B * dim * s.N);
         for (int a = 0; a < 3; ++a) {
             h->o_cr64[l][a] = a < dim ? L.take(a == 0 ? "cr64x" : (a == 1 ? "cr64y" : "cr64z"), l, sizeof(double) * (size_t)B * 3 * s.CRW * s.NL) : 0;
@@ -312,14 +356,14 @@ void plan(pmg_handle* h, std::vector<pmg_region>* rec = nullptr)
         h->o_X[l] = L.take("X", l, tsz * (size_t)B * s.N);
         h->o_R[l] = L.take("R", l, tsz * (size_t)B * s.N);
         h->o_Tm[l] = L.take("Tm", l, tsz * (size_t)B * s.N);
-        h->o_TR[l] = L.take("TR", l, tsz * (size_t)B * dim * s.N);
+        h->o_TR[l] = L.take("TR", l, tsz * (size_t)B * dim * NE);
     }
     LevelShape f = level_shape(dim, h->nlev - 1);
     h->w1 = h->w2 = w;
     h->o_mass = L.take("mass", -1, sizeof(double) * (size_t)B * f.N);
     h->o_W1 = L.take("W1", -1, tsz * (size_t)B * w);
     h->o_W2 = dim == 3 ? L.take("W2", -1, tsz * (size_t)B * w) : 0;
-    h->o_TR64 = L.take("TR64", -1, sizeof(double) * (size_t)B * dim * f.N);
+    h->o_TR64 = L.take("TR64", -1, sizeof(double) * (size_t)B * dim * elem_nodes(h, h->nlev - 1));
     const int kr = d.restart;
     h->nv = kr + 1 > 5 ? kr + 1 : 5;
     h->hs = (long long)(kr + 1) * kr + 4LL * kr + 1;
@@ -337,19 +381,23 @@ void plan(pmg_handle* h, std::vector<pmg_region>* rec = nullptr)
     // saves about one; a level is entered gamma^depth times per cycle, so
     // with solves of about 16 iterations or more the build is repaid when
     // gamma^depth >= ni / 16.
-    for (int l = 0; l < h->nlev; ++l) {
+    for (int l = h->l0; l < h->nlev; ++l) {
         const int pl = 2 << l;
         const long long ni = dim == 2 ? (pl - 1) * (pl - 1) : (pl - 1) * (pl - 1) * (pl - 1);
         double visits = 1.0;
         for (int k = l; k < h->nlev - 1; ++k) visits *= d.gamma;
-        const bool coll = (pl == collapse_lo(dim) || pl == collapse_p(dim)) && d.p_fine > pl &&
-                          16.0 * visits >= (double)ni;
+        const bool coll = h->K > 1
+            // several elements: the coarsest level's exact inverse only
+            ? l == h->l0
+            : (pl == collapse_lo(dim) || pl == collapse_p(dim)) && d.p_fine > pl &&
+                  16.0 * visits >= (double)ni;
         h->o_Cc[l] = coll ? L.take("Cc", l, sizeof(double) * (size_t)B * ni * ni) : 0;
     }
     h->o_hier64 = L.take("hier64", -1, sizeof(Hier<double>));
     h->o_hier32 = L.take("hier32", -1, sizeof(Hier<float>));
     if (h->pool) {
-        for (int l = 0; l < h->nlev; ++l) {
+        for (int l = 0; l < MAX_LEVELS; ++l) h->o_in_coords[l] = 0;
+        for (int l = h->l0; l < h->nlev; ++l) {
             LevelShape s = level_shape(dim, l);
             h->o_in_coords[l] = L.take("in_coords", l, sizeof(double) * (size_t)B * dim * s.N);
         }
@@ -372,7 +420,7 @@ void fill_hier(pmg_handle* h, Hier<T>& H, bool is32)
     memset(&H, 0, sizeof(H));
     char* ws = h->ws;
     const int dim = h->d.dim;
-    for (int l = 0; l < h->nlev; ++l) {
+    for (int l = h->l0; l < h->nlev; ++l) {
         LevelData<T>& L = H.lev[l];
         L.G64 = (const double*)(ws + h->o_G64[l]);
         L.G = is32 ? (const T*)(ws + h->o_G32[l]) : (const T*)(ws + h->o_G64[l]);
@@ -389,13 +437,14 @@ void fill_hier(pmg_handle* h, Hier<T>& H, bool is32)
         L.TR = (T*)(ws + h->o_TR[l]);
         L.D = (const T*)(ws + (is32 ? h->o_D32[l] : h->o_D64[l]));
         L.DT = (const T*)(ws + (is32 ? h->o_DT32[l] : h->o_DT64[l]));
-        if (l > 0) {
+        if (l > h->l0) {
             L.J = (const T*)(ws + (is32 ? h->o_J32[l] : h->o_J64[l]));
             L.JT = (const T*)(ws + (is32 ? h->o_JT32[l] : h->o_JT64[l]));
             L.JR = (const T*)(ws + (is32 ? h->o_JR32[l] : h->o_JR64[l]));
         }
         L.D64 = (const double*)(ws + h->o_D64[l]);
         L.DT64 = (const double*)(ws + h->o_DT64[l]);
+        L.ng = elem_nodes(h, l);
     }
     H.cinv = (const T*)(ws + (is32 ? h->o_cinv32 : h->o_cinv64));
     H.cinv64 = (const double*)(ws + h->o_cinv64);
@@ -405,6 +454,7 @@ void fill_hier(pmg_handle* h, Hier<T>& H, bool is32)
     H.w1 = h->w1;
     H.w2 = h->w2;
     H.nlev = h->nlev;
+    H.K = h->K;
     H.gamma = h->d.gamma;
     H.m = h->d.m;
     H.alpha = (T)h->d.alpha;
@@ -422,6 +472,15 @@ int pmg_num_levels(const pmg_desc* desc, int* n_levels)
     if (rc) return rc;
     if (!n_levels) return fail(PMG_EINVAL, "n_levels is NULL");
     *n_levels = ilog2(desc->p_fine);
+    return PMG_OK;
+}
+
+int pmg_first_level(const pmg_desc* desc, int* first_level)
+{
+    int rc = check_desc(desc);
+    if (rc) return rc;
+    if (!first_level) return fail(PMG_EINVAL, "first_level is NULL");
+    *first_level = first_level_of(*desc);
     return PMG_OK;
 }
 
@@ -458,9 +517,7 @@ int pmg_workspace_bytes(const pmg_desc* desc, size_t* bytes)
     if (rc) return rc;
     if (!bytes) return fail(PMG_EINVAL, "bytes is NULL");
     pmg_handle tmp;
-    tmp.d = *desc;
-    tmp.nlev = ilog2(desc->p_fine);
-    tmp.f32 = desc->inner_prec == PMG_F32;
+    describe(&tmp, desc);
     plan(&tmp);
     *bytes = tmp.total;
     return PMG_OK;
@@ -474,9 +531,7 @@ int pmg_workspace_layout(const pmg_desc* desc, pmg_region* regions, int max_regi
     if (!n_regions || max_regions < 0 || (max_regions > 0 && !regions))
         return fail(PMG_EINVAL, "bad region buffer");
     pmg_handle tmp;
-    tmp.d = *desc;
-    tmp.nlev = ilog2(desc->p_fine);
-    tmp.f32 = desc->inner_prec == PMG_F32;
+    describe(&tmp, desc);
     std::vector<pmg_region> rec;
     plan(&tmp, &rec);
     *n_regions = (int)rec.size();
@@ -493,9 +548,7 @@ static int init_handle(const pmg_desc* desc, void* d_ws, size_t ws_bytes, bool p
     if (rc) return rc;
     if (!d_ws || !out) return fail(PMG_EINVAL, "NULL argument");
     pmg_handle* h = new pmg_handle();
-    h->d = *desc;
-    h->nlev = ilog2(desc->p_fine);
-    h->f32 = desc->inner_prec == PMG_F32;
+    describe(h, desc);
     h->pool = pool;
     plan(h);
     if (ws_bytes < h->total) {
@@ -507,55 +560,62 @@ static int init_handle(const pmg_desc* desc, void* d_ws, size_t ws_bytes, bool p
     h->ws_bytes = ws_bytes;
     const int dim = desc->dim;
 
-    // host tables -> one staging buffer per precision, uploaded in one copy each
-    h->h64.assign(h->o_G64[0] / sizeof(double) + 1, 0.0);
-    h->h32.assign(h->o_G64[0] / sizeof(float) + 1, 0.0f);
+    // host tables -> one staging buffer per precision, uploaded in one copy each.
+    // Per level: the GLL rule and derivative matrix of the level's element
+    // (the whole level for one element), and the 1-D transfers of the level's
+    // composite grid, element block by element block.
+    const size_t tab_end = h->o_G64[h->l0];
+    h->h64.assign(tab_end / sizeof(double) + 1, 0.0);
+    h->h32.assign(tab_end / sizeof(float) + 1, 0.0f);
     std::vector<std::vector<double>> xis(h->nlev);
-    for (int l = 0; l < h->nlev; ++l) {
+    const int K = h->K;
+    for (int l = h->l0; l < h->nlev; ++l) {
         LevelShape sh = level_shape(dim, l);
+        const int pe = sh.p / K, ne1 = pe + 1;
         std::vector<double> rho, D;
-        if (!gll_nodes(sh.p, xis[l], rho)) {
+        if (!gll_nodes(pe, xis[l], rho)) {
             delete h;
-            return fail(PMG_EINVAL, "GLL Newton iteration failed for p = %d", sh.p);
+            return fail(PMG_EINVAL, "GLL Newton iteration failed for p = %d", pe);
         }
-        gll_deriv(sh.p, xis[l], D);
+        gll_deriv(pe, xis[l], D);
         double* t64 = h->h64.data();
         float* t32 = h->h32.data();
-        for (int i = 0; i < sh.n1; ++i) t64[h->o_rho[l] / 8 + i] = rho[i];
-        for (int i = 0; i < sh.n1; ++i)
-            for (int j = 0; j < sh.n1; ++j) {
-                double v = D[i * sh.n1 + j];
-                t64[h->o_D64[l] / 8 + i * sh.n1 + j] = v;
-                t64[h->o_DT64[l] / 8 + j * sh.n1 + i] = v;
-                t32[h->o_D32[l] / 4 + i * sh.n1 + j] = (float)v;
-                t32[h->o_DT32[l] / 4 + j * sh.n1 + i] = (float)v;
+        for (int i = 0; i < ne1; ++i) t64[h->o_rho[l] / 8 + i] = rho[i];
+        for (int i = 0; i < ne1; ++i)
+            for (int j = 0; j < ne1; ++j) {
+                double v = D[i * ne1 + j];
+                t64[h->o_D64[l] / 8 + i * ne1 + j] = v;
+                t64[h->o_DT64[l] / 8 + j * ne1 + i] = v;
+                t32[h->o_D32[l] / 4 + i * ne1 + j] = (float)v;
+                t32[h->o_DT32[l] / 4 + j * ne1 + i] = (float)v;
             }
-        if (l > 0) {
-            std::vector<double> J, Q;
-            bary_interp(xis[l - 1], xis[l], J);
-            int n1c = sh.p / 2 + 1;
-            for (int i = 0; i < sh.n1; ++i)
-                for (int j = 0; j < n1c; ++j) {
-                    double v = J[i * n1c + j];
-                    t64[h->o_J64[l] / 8 + i * n1c + j] = v;
-                    t64[h->o_JT64[l] / 8 + j * sh.n1 + i] = v;
-                    t32[h->o_J32[l] / 4 + i * n1c + j] = (float)v;
-                    t32[h->o_JT32[l] / 4 + j * sh.n1 + i] = (float)v;
-                }
-            // restriction table JR ([n1][n1c], R = JR^T per axis): J itself
-            // for R = P^T; for the interpolation reading Q[j][i] = pi^f_i(xi^c_j),
-            // the fine basis at the coarse nodes, stored transposed
-            if (desc->restriction == PMG_RESTRICT_INTERP) bary_interp(xis[l], xis[l - 1], Q);
-            for (int i = 0; i < sh.n1; ++i)
-                for (int j = 0; j < n1c; ++j) {
-                    double v = desc->restriction == PMG_RESTRICT_INTERP ? Q[j * sh.n1 + i]
-                                                                        : J[i * n1c + j];
-                    t64[h->o_JR64[l] / 8 + i * n1c + j] = v;
-                    t32[h->o_JR32[l] / 4 + i * n1c + j] = (float)v;
-                }
+        if (l > h->l0) {
+            // element blocks: Jl[i][j] = pi^c_j(xi^f_i); for the interpolation
+            // reading Ql[j][i] = pi^f_i(xi^c_j), the fine basis at the coarse
+            // nodes.  The composite tables put element e's block at rows
+            // e pe .., columns e pc ..; an interface row is written by both
+            // elements with the same values (the bases interpolate).
+            const int pc = pe / 2, n1c = sh.p / 2 + 1;
+            std::vector<double> Jl, Ql;
+            bary_interp(xis[l - 1], xis[l], Jl);
+            if (desc->restriction == PMG_RESTRICT_INTERP) bary_interp(xis[l], xis[l - 1], Ql);
+            for (int e = 0; e < K; ++e)
+                for (int i = 0; i < ne1; ++i)
+                    for (int j = 0; j <= pc; ++j) {
+                        const int I = e * pe + i, Jc = e * pc + j;
+                        const double v = Jl[i * (pc + 1) + j];
+                        // restriction table JR ([n1][n1c], R = JR^T per axis)
+                        const double vr = desc->restriction == PMG_RESTRICT_INTERP ? Ql[j * ne1 + i] : v;
+                        t64[h->o_J64[l] / 8 + I * n1c + Jc] = v;
+                        t64[h->o_JT64[l] / 8 + Jc * sh.n1 + I] = v;
+                        t32[h->o_J32[l] / 4 + I * n1c + Jc] = (float)v;
+                        t32[h->o_JT32[l] / 4 + Jc * sh.n1 + I] = (float)v;
+                        t64[h->o_JR64[l] / 8 + I * n1c + Jc] = vr;
+                        t32[h->o_JR32[l] / 4 + I * n1c + Jc] = (float)vr;
+                    }
         }
     }
-    // The FP64 and FP32 tables interleave in [0, o_G64[0]); upload the FP64
+    // The FP64 and FP32 tables interleave in [0, o_G64[l0]); upload the FP64
     // table regions from h64 and the FP32 regions from h32.
     hipError_t e;
     auto up64 = [&](size_t off, size_t n) {
@@ -564,16 +624,16 @@ static int init_handle(const pmg_desc* desc, void* d_ws, size_t ws_bytes, bool p
     auto up32 = [&](size_t off, size_t n) {
         return hipMemcpyAsync(h->ws + off, h->h32.data() + off / 4, n * 4, hipMemcpyHostToDevice, s);
     };
-    for (int l = 0; l < h->nlev; ++l) {
+    for (int l = h->l0; l < h->nlev; ++l) {
         LevelShape sh = level_shape(dim, l);
-        size_t nn = (size_t)sh.n1 * sh.n1;
-        if ((e = up64(h->o_rho[l], sh.n1)) != hipSuccess ||
+        const size_t ne1 = sh.p / K + 1, nn = ne1 * ne1;
+        if ((e = up64(h->o_rho[l], ne1)) != hipSuccess ||
             (e = up64(h->o_D64[l], nn)) != hipSuccess || (e = up64(h->o_DT64[l], nn)) != hipSuccess ||
             (e = up32(h->o_D32[l], nn)) != hipSuccess || (e = up32(h->o_DT32[l], nn)) != hipSuccess) {
             delete h;
             return hip_fail(e, "table upload");
         }
-        if (l > 0) {
+        if (l > h->l0) {
             size_t nj = (size_t)sh.n1 * (sh.p / 2 + 1);
             if ((e = up64(h->o_J64[l], nj)) != hipSuccess || (e = up64(h->o_JT64[l], nj)) != hipSuccess ||
                 (e = up32(h->o_J32[l], nj)) != hipSuccess || (e = up32(h->o_JT32[l], nj)) != hipSuccess ||
@@ -603,7 +663,10 @@ static void setup_args(pmg_handle* h, SetupArgs& a)
 {
     const int dim = h->d.dim;
     memset(&a, 0, sizeof(a));
-    for (int l = 0; l < h->nlev; ++l) {
+    a.K = h->K;
+    a.l0 = h->l0;
+    a.Cc0 = h->K > 1 ? (double*)(h->ws + h->o_Cc[h->l0]) : nullptr;
+    for (int l = h->l0; l < h->nlev; ++l) {
         for (int k = 0; k < 3; ++k) {
             a.cr64[l][k] = k < dim ? (double*)(h->ws + h->o_cr64[l][k]) : nullptr;
             a.cr32[l][k] = (k < dim && h->f32) ? (float*)(h->ws + h->o_cr32[l][k]) : nullptr;
@@ -634,16 +697,16 @@ int pmg_setup(const pmg_desc* desc, const double* const* d_coords, void* d_ws, s
     pmg_handle* h = nullptr;
     int rc = init_handle(desc, d_ws, ws_bytes, false, s, &h);
     if (rc) return rc;
-    for (int l = 0; l < h->nlev; ++l)
+    for (int l = h->l0; l < h->nlev; ++l)
         if (!d_coords[l]) {
             delete h;
             return fail(PMG_EINVAL, "coordinates of level %d are NULL", l);
         }
     SetupArgs a;
     setup_args(h, a);
-    for (int l = 0; l < h->nlev; ++l) a.coords[l] = d_coords[l];
+    for (int l = h->l0; l < h->nlev; ++l) a.coords[l] = d_coords[l];
     hipError_t e = launch_setup(h->d.dim, h->d.p_fine, h->nlev, h->d.batch, a, d_info, s);
-    for (int l = 0; l < h->nlev && e == hipSuccess; ++l)   // lower level first
+    for (int l = 0; l < h->nlev && e == hipSuccess && h->K == 1; ++l)   // lower level first
         if (h->o_Cc[l])
             e = launch_collapse(h->d.dim, 2 << l, h->f32, h->d.batch, hier_of(h, h->f32),
                                 (double*)(h->ws + h->o_Cc[l]), nullptr, s);
@@ -703,6 +766,7 @@ int pmg_lift(pmg_handle* h, const double* d_w, const double* d_g, double* d_u, p
 
 static int check_level(pmg_handle* h, int level, int lo)
 {
+    lo += h->l0;   // levels below the first present one do not exist
     if (level < lo || level >= h->nlev)
         return fail(PMG_EINVAL, "level %d out of range [%d, %d]", level, lo, h->nlev - 1);
     return PMG_OK;
@@ -937,7 +1001,7 @@ int pmg_geom(pmg_handle* h, int level, double* d_G, double* d_mass, pmg_stream_t
     if (!d_G) return fail(PMG_EINVAL, "d_G is NULL");
     LevelShape sh = level_shape(h->d.dim, level);
     hipStream_t s = (hipStream_t)stream;
-    size_t nG = sizeof(double) * (size_t)h->d.batch * sh.NC * sh.N;
+    size_t nG = sizeof(double) * (size_t)h->d.batch * sh.NC * elem_nodes(h, level);
     hipError_t e = hipMemcpyAsync(d_G, h->ws + h->o_G64[level], nG, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess && d_mass) {
         if (level != h->nlev - 1) return fail(PMG_EINVAL, "mass is stored for the finest level only");
@@ -997,9 +1061,7 @@ int pmg_pool_workspace_bytes(const pmg_desc* desc, size_t* bytes)
     if (rc) return rc;
     if (!bytes) return fail(PMG_EINVAL, "bytes is NULL");
     pmg_handle tmp;
-    tmp.d = *desc;
-    tmp.nlev = ilog2(desc->p_fine);
-    tmp.f32 = desc->inner_prec == PMG_F32;
+    describe(&tmp, desc);
     tmp.pool = true;
     plan(&tmp);
     *bytes = tmp.total;
@@ -1059,7 +1121,7 @@ int pmg_pool_admit(pmg_pool* P, int n, const int* slots, const double* const* d_
     for (int i = 0; i < n; ++i) {
         const int b = slots[i];
         if (b < 0 || b >= B) return fail(PMG_EINVAL, "slot %d out of range", b);
-        for (int l = 0; l < h->nlev; ++l) {
+        for (int l = h->l0; l < h->nlev; ++l) {
             const long long cnt = (long long)dim * level_shape(dim, l).N;
             const double* src = d_coords[(size_t)i * h->nlev + l];
             if (!src) return fail(PMG_EINVAL, "NULL coordinates");
@@ -1080,12 +1142,12 @@ int pmg_pool_admit(pmg_pool* P, int n, const int* slots, const double* const* d_
     if (e != hipSuccess) return hip_fail(e, "slot list upload");
     SetupArgs a;
     setup_args(h, a);
-    for (int l = 0; l < h->nlev; ++l) a.coords[l] = (const double*)(h->ws + h->o_in_coords[l]);
+    for (int l = h->l0; l < h->nlev; ++l) a.coords[l] = (const double*)(h->ws + h->o_in_coords[l]);
     a.slots = dslots;
     a.nslots = n;
     pmg_info* info = (pmg_info*)(h->ws + h->o_info);
     e = launch_setup(dim, h->d.p_fine, h->nlev, B, a, info, s);
-    for (int l = 0; l < h->nlev && e == hipSuccess; ++l)   // lower level first
+    for (int l = 0; l < h->nlev && e == hipSuccess && h->K == 1; ++l)   // lower level first
         if (h->o_Cc[l])
             e = launch_collapse(dim, 2 << l, h->f32, n, hier_of(h, h->f32),
                                 (double*)(h->ws + h->o_Cc[l]), dslots, s);

@@ -77,6 +77,8 @@ struct LevelData {
                          // pi^f_i(xi^c_j) (fine basis at the coarse nodes) for interpolation
     const double* D64;
     const double* DT64;
+    long long ng;        // per-problem nodes of G and TR: N, or for K elements per
+                         // axis the K^dim (p/K + 1)^dim element nodes
 };
 
 template <class T>
@@ -91,6 +93,7 @@ struct Hier {
     T* W2;               // [B][w2]
     long long w1, w2;    // per-problem sizes of W1, W2
     int nlev, gamma, m;
+    int K;               // spectral elements per axis (1: one element)
     T alpha;
 };
 
@@ -688,6 +691,68 @@ __device__ void apply3d_mfma(const T* __restrict__ G_, const T* __restrict__ D_,
     wg_barrier();
 }
 
+// ------------------------------------------------------------------ several elements
+
+// Levels made of K x K spectral elements of degree pe = P / K on the
+// composite node grid of degree P (interface nodes shared, the one-element
+// vector layout): the operator is the sum of the element operators
+// (direct stiffness summation), each the one-element sum factorisation of
+// eq. discreteBilinear with the element's own GLL rule, derivative matrix D
+// (ne1 x ne1, ne1 = pe + 1) and geometric factors G (per element e: G00,
+// G11, G01 arrays of NE = ne1^2 element nodes at G + 3 NE e, elements in
+// lexicographic order).  Pass 1: per element node, the two reference
+// gradients and the fluxes into TR (per element: 2 NE).  Pass 2: per global
+// node, the sum over the elements holding it (one inside an element, two
+// on an edge, four at a corner, in element order) of D^T of their fluxes.
+template <class T, int P, bool RESID>
+__device__ void apply2d_elements(int K, const T* __restrict__ G_, const T* __restrict__ D_,
+                                 T* __restrict__ TR_, const T* __restrict__ x_,
+                                 const T* __restrict__ r_, T* __restrict__ out_)
+{
+    const auto G = gmem(G_);
+    const auto D = gmem(D_);
+    const auto TR = gmem(TR_);
+    const auto x = gmem(x_);
+    const auto r = gmem(r_);
+    const auto out = gmem(out_);
+    constexpr int n1 = P + 1, N = n1 * n1;
+    const int pe = P / K, ne1 = pe + 1, NE = ne1 * ne1;
+    for (int t = threadIdx.x; t < K * K * NE; t += NT) {
+        const int e = t / NE, lq = t - e * NE;
+        const int i = lq % ne1, j = lq / ne1;
+        const int gx = (e % K) * pe, gy = (e / K) * pe;
+        T g0 = 0, g1 = 0;
+        for (int k = 0; k < ne1; ++k) {
+            g0 += D[i * ne1 + k] * x[(gx + k) + (gy + j) * n1];
+            g1 += D[j * ne1 + k] * x[(gx + i) + (gy + k) * n1];
+        }
+        const auto Ge = G + (long long)3 * NE * e;
+        const T g00 = Ge[lq], g11 = Ge[NE + lq], g01 = Ge[2 * NE + lq];
+        TR[(long long)2 * NE * e + lq] = g00 * g0 + g01 * g1;
+        TR[(long long)2 * NE * e + NE + lq] = g01 * g0 + g11 * g1;
+    }
+    wg_barrier();
+    for (int q = threadIdx.x; q < N; q += NT) {
+        const int I = q % n1, J = q / n1;
+        if (I == 0 || I == P || J == 0 || J == P) {
+            out[q] = T(0);
+            continue;
+        }
+        const int ex1 = I / pe, ey1 = J / pe;
+        const int ex0 = I % pe == 0 ? ex1 - 1 : ex1, ey0 = J % pe == 0 ? ey1 - 1 : ey1;
+        T y = 0;
+        for (int ey = ey0; ey <= ey1 && ey < K; ++ey)
+            for (int ex = ex0; ex <= ex1 && ex < K; ++ex) {
+                const int e = ex + K * ey, i = I - ex * pe, j = J - ey * pe;
+                const auto f = TR + (long long)2 * NE * e;
+                for (int k = 0; k < ne1; ++k)
+                    y += D[k * ne1 + i] * f[k + j * ne1] + D[k * ne1 + j] * f[NE + i + k * ne1];
+            }
+        out[q] = RESID ? r[q] - y : y;
+    }
+    wg_barrier();
+}
+
 // Matrix-free A x of eq. discreteBilinear by sum factorisation: reference
 // gradients g_b = D along axis b, fluxes f_a = sum_b G_ab g_b at every node,
 // then (A x)(n) = sum_a sum_k D[k][n_a] f_a(n with axis a <- k) on interior
@@ -697,8 +762,15 @@ __device__ __attribute__((noinline)) void apply_level(const T* __restrict__ G_,
                                                       const T* __restrict__ D_,
                                                       const T* __restrict__ DT_, T* __restrict__ TR_,
                                                       const T* __restrict__ x_,
-                                                      const T* __restrict__ r_, T* __restrict__ out_)
+                                                      const T* __restrict__ r_, T* __restrict__ out_,
+                                                      int K = 1)
 {
+    if constexpr (DIM == 2 && P >= 4) {
+        if (K > 1) {
+            apply2d_elements<T, P, RESID>(K, G_, D_, TR_, x_, r_, out_);
+            return;
+        }
+    }
     if constexpr (DIM == 2 && P >= MFMA_MIN_P) {
         apply2d_mfma<T, P, RESID>(G_, D_, DT_, TR_, x_, r_, out_);
         return;
@@ -1391,8 +1463,8 @@ __device__ void smooth_step(const Hier<T>& H, int b, int dir, const T* r, T* x, 
         wg_copy(tmp, r, S::N);   // the thread-per-line form works in place
         wg_barrier();
     } else {
-        apply_level<T, P, DIM, true>(L.G + (long long)b * S::NC * S::N, L.D, L.DT,
-                                     L.TR + (long long)b * DIM * S::N, x, r, tmp);
+        apply_level<T, P, DIM, true>(L.G + (long long)b * S::NC * L.ng, L.D, L.DT,
+                                     L.TR + (long long)b * DIM * L.ng, x, r, tmp, H.K);
     }
     level_lines<T, P, DIM, true>(L, b, dir, tmp, x, H.alpha);
 }
@@ -1446,7 +1518,8 @@ __device__ __attribute__((noinline)) void gamma_cycle(const Hier<T>& H, int b, c
 {
     using S = Shape<P, DIM>;
     const LevelData<T>& L = lvl<T, P, DIM>(H);
-    if constexpr (P <= CMAX && P >= collapse_lo(DIM)) {
+    // (also the coarsest level of K x K elements, degree 2K: its exact inverse)
+    if constexpr (P <= CMAX && P >= 4) {
         if (H.Cc[S::LEV]) {
             constexpr int ni = ipow(P - 1, DIM);
             collapsed_solve<T, P, DIM>(H.Cc[S::LEV] + (long long)b * ni * ni, r, x);
@@ -1486,8 +1559,8 @@ __device__ __attribute__((noinline)) void gamma_cycle(const Hier<T>& H, int b, c
                 zero = false;
             }
         for (int g = 0; g < H.gamma; ++g) {
-            apply_level<T, P, DIM, true>(L.G + (long long)b * S::NC * S::N, L.D, L.DT,
-                                         L.TR + (long long)b * DIM * S::N, x, r, tmp);
+            apply_level<T, P, DIM, true>(L.G + (long long)b * S::NC * L.ng, L.D, L.DT,
+                                         L.TR + (long long)b * DIM * L.ng, x, r, tmp, H.K);
             restrict_level<T, P, DIM>(tmp, rc, L.JR, L.JT, w1, w2);
             gamma_cycle<T, P / 2, DIM, CMAX>(H, b, rc, xc);
             prolong_level<T, P, DIM>(xc, x, L.J, L.JT, w1, w2);

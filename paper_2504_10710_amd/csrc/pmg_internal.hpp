@@ -30,6 +30,9 @@ struct SetupArgs {
     const double* D64[MAX_LEVELS];
     const double* DT64[MAX_LEVELS];
     int smoother;
+    int K;                              // spectral elements per axis (1: one element)
+    int l0;                             // coarsest present level
+    double* Cc0;                        // K > 1: [B][ni][ni] exact inverse of level l0
 };
 
 // Resumable state of one problem's outer solve (kept in the workspace, so a

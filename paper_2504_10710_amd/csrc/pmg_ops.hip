@@ -15,8 +15,8 @@ __global__ void __launch_bounds__(NT) k_apply(const Hier<T>* __restrict__ Hp, co
     using S = Shape<P, DIM>;
     const long long b = blockIdx.x;
     const LevelData<T>& L = H.lev[S::LEV];
-    apply_level<T, P, DIM, false>(L.G + b * S::NC * S::N, L.D, L.DT, L.TR + b * DIM * S::N,
-                                  x + b * S::N, nullptr, y + b * S::N);
+    apply_level<T, P, DIM, false>(L.G + b * S::NC * L.ng, L.D, L.DT, L.TR + b * DIM * L.ng,
+                                  x + b * S::N, nullptr, y + b * S::N, H.K);
 }
 
 template <class T, int P, int DIM>

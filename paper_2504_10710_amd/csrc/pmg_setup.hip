@@ -594,15 +594,176 @@ __global__ void __launch_bounds__(NT) k_lines(const double* __restrict__ G,
     if (bad) atomicOr(pivot + b, 1);
 }
 
+// Geometry of a level of K x K elements (2-D): per element node, the
+// Jacobian of the mapping by the element's derivative matrix on the element
+// block of the composite coordinates, then G = rho_i rho_j det J J^{-1}
+// J^{-T} (element layout, as in the one-element kernel); per global node,
+// the assembled mass (the element weights rho_i rho_j det J of every
+// element holding the node, in element order).
+template <int P>
+__global__ void __launch_bounds__(NT) k_geom_elements(int K, const double* __restrict__ coords,
+                                                      const double* __restrict__ rho_,
+                                                      const double* __restrict__ D_,
+                                                      double* __restrict__ G, float* __restrict__ G32,
+                                                      double* __restrict__ mass,
+                                                      double* __restrict__ X64,
+                                                      double* __restrict__ detmin,
+                                                      const int* slots, int* pivot)
+{
+    constexpr int n1 = P + 1, N = n1 * n1;
+    const int pe = P / K, ne1 = pe + 1, NE = ne1 * ne1, NEt = K * K * NE;
+    __shared__ double red[NT];
+    const long long b = slots ? slots[blockIdx.x] : blockIdx.x;
+    if (pivot && threadIdx.x == 0) pivot[b] = 0;
+    const auto X = gmem(coords + b * 2 * N);
+    const auto D = gmem(D_);
+    const auto rho = gmem(rho_);
+    const auto Gb = gmem(G + b * 3 * NEt);
+    const auto G32b = G32 ? gmem(G32 + b * 3 * NEt) : nullptr;
+    const auto Xo = gmem(X64 + b * 2 * N);
+    for (int q = threadIdx.x; q < 2 * N; q += NT) Xo[q] = X[q];
+    // det J and J at element node (i, j) of element (ex, ey)
+    auto jac = [&](int ex, int ey, int i, int j, double (&Jm)[2][2]) {
+        const int gx = ex * pe, gy = ey * pe;
+        for (int comp = 0; comp < 2; ++comp) {
+            const auto Xc = X + comp * N;
+            double s0 = 0.0, s1 = 0.0;
+            for (int k = 0; k < ne1; ++k) {
+                s0 += D[i * ne1 + k] * Xc[(gx + k) + (gy + j) * n1];
+                s1 += D[j * ne1 + k] * Xc[(gx + i) + (gy + k) * n1];
+            }
+            Jm[comp][0] = s0;
+            Jm[comp][1] = s1;
+        }
+        return Jm[0][0] * Jm[1][1] - Jm[0][1] * Jm[1][0];
+    };
+    double dmin = INFINITY;
+    for (int t = threadIdx.x; t < NEt; t += NT) {
+        const int e = t / NE, lq = t - e * NE, i = lq % ne1, j = lq / ne1;
+        double Jm[2][2];
+        const double det = jac(e % K, e / K, i, j, Jm);
+        dmin = fmin(dmin, det);
+        const double id = 1.0 / det;
+        const double inv[2][2] = {{Jm[1][1] * id, -Jm[0][1] * id}, {-Jm[1][0] * id, Jm[0][0] * id}};
+        const double phi = rho[i] * rho[j] * det;
+        for (int a = 0; a < 2; ++a)
+            for (int c = a; c < 2; ++c) {
+                const double v = phi * (inv[a][0] * inv[c][0] + inv[a][1] * inv[c][1]);
+                const int gi = gidx(2, a, c);
+                Gb[(long long)3 * NE * e + gi * NE + lq] = v;
+                if (G32b) G32b[(long long)3 * NE * e + gi * NE + lq] = (float)v;
+            }
+    }
+    if (mass) {
+        const auto massb = gmem(mass + b * N);
+        for (int q = threadIdx.x; q < N; q += NT) {
+            const int I = q % n1, J = q / n1;
+            const int ex1 = min(I / pe, K - 1), ey1 = min(J / pe, K - 1);
+            const int ex0 = (I % pe == 0 && I > 0) ? I / pe - 1 : ex1;
+            const int ey0 = (J % pe == 0 && J > 0) ? J / pe - 1 : ey1;
+            double m = 0.0;
+            for (int ey = ey0; ey <= ey1; ++ey)
+                for (int ex = ex0; ex <= ex1; ++ex) {
+                    double Jm[2][2];
+                    const int i = I - ex * pe, j = J - ey * pe;
+                    m += rho[i] * rho[j] * jac(ex, ey, i, j, Jm);
+                }
+            massb[q] = m;
+        }
+    }
+    const double mn = wg_min(dmin, red);
+    if (threadIdx.x == 0) detmin[b] = mn;
+}
+
+// Exact solve on the coarsest level of K x K elements (degree P = 2K, ni =
+// (P-1)^2 interior nodes): the interior matrix of the assembled operator,
+// entry by entry (the element quadrature sums of eq. discreteBilinear over
+// the elements holding both nodes), then its inverse by Gauss-Jordan
+// elimination in place (symmetric positive definite: no pivoting; a pivot
+// that is not positive flags the problem), stored for collapsed_solve as
+// C[i ni + j] = (A^{-1})[j][i].
+template <int P>
+__global__ void __launch_bounds__(NT) k_elements_coarse(int K, const double* __restrict__ G,
+                                                        const double* __restrict__ D_,
+                                                        double* __restrict__ Cc, const int* slots,
+                                                        int* pivot)
+{
+    constexpr int n = P - 1, ni = n * n;
+    const int pe = P / K, ne1 = pe + 1, NE = ne1 * ne1;
+    const long long b = slots ? slots[blockIdx.x] : blockIdx.x;
+    const auto A = gmem(Cc + b * (long long)ni * ni);
+    const auto Gb = gmem(G + b * 3LL * K * K * NE);
+    const auto D = gmem(D_);
+    // elements holding coordinate I along an axis: [lo, hi]
+    auto lo_of = [&](int I) { return (I % pe == 0 && I > 0) ? I / pe - 1 : min(I / pe, K - 1); };
+    auto hi_of = [&](int I) { return min(I / pe, K - 1); };
+    for (int t = threadIdx.x; t < ni * ni; t += NT) {
+        const int row = t / ni, col = t - row * ni;
+        const int r[2] = {row % n + 1, row / n + 1}, c[2] = {col % n + 1, col / n + 1};
+        double v = 0.0;
+        const int ex0 = max(lo_of(r[0]), lo_of(c[0])), ex1 = min(hi_of(r[0]), hi_of(c[0]));
+        const int ey0 = max(lo_of(r[1]), lo_of(c[1])), ey1 = min(hi_of(r[1]), hi_of(c[1]));
+        for (int ey = ey0; ey <= ey1; ++ey)
+            for (int ex = ex0; ex <= ex1; ++ex) {
+                const int e = ex + K * ey;
+                const int lr[2] = {r[0] - ex * pe, r[1] - ey * pe};
+                const int lc[2] = {c[0] - ex * pe, c[1] - ey * pe};
+                const auto Ge = Gb + 3LL * NE * e;
+                for (int a = 0; a < 2; ++a)
+                    for (int k = 0; k < ne1; ++k) {
+                        int qc[2] = {lr[0], lr[1]};
+                        qc[a] = k;
+                        const double da = D[k * ne1 + lr[a]];
+                        const int q = qc[0] + ne1 * qc[1];
+                        for (int bb = 0; bb < 2; ++bb)
+                            if (qc[1 - bb] == lc[1 - bb])
+                                v += Ge[gidx(2, a, bb) * NE + q] * da * D[qc[bb] * ne1 + lc[bb]];
+                    }
+            }
+        A[t] = v;
+    }
+    wg_barrier();
+    bool bad = false;
+    for (int k = 0; k < ni; ++k) {
+        const double akk = A[(long long)k * ni + k];
+        bad = bad || !(akk > 0.0);
+        const double pk = 1.0 / akk;
+        for (int t = threadIdx.x; t < ni * ni; t += NT) {
+            const int i = t / ni, j = t - i * ni;
+            if (i != k && j != k) A[t] -= A[(long long)i * ni + k] * A[(long long)k * ni + j] * pk;
+        }
+        wg_barrier();
+        for (int t = threadIdx.x; t < ni; t += NT) {
+            if (t != k) {
+                A[(long long)k * ni + t] *= pk;
+                A[(long long)t * ni + k] *= -pk;
+            }
+        }
+        if (threadIdx.x == 0) A[(long long)k * ni + k] = pk;
+        wg_barrier();
+    }
+    // transpose in place: C[i ni + j] = (A^{-1})[j][i]
+    for (int t = threadIdx.x; t < ni * ni; t += NT) {
+        const int i = t / ni, j = t - i * ni;
+        if (i < j) {
+            const double u = A[t], w = A[(long long)j * ni + i];
+            A[t] = w;
+            A[(long long)j * ni + i] = u;
+        }
+    }
+    if (bad && threadIdx.x == 0) pivot[b] = 1;
+    wg_barrier();
+}
+
 __global__ void k_setup_finish(const double* __restrict__ detmin, const int* __restrict__ pivot,
-                               int nlev, int B, int n, const int* slots, pmg_info* __restrict__ info,
-                               int* sstatus)
+                               int l0, int nlev, int B, int n, const int* slots,
+                               pmg_info* __restrict__ info, int* sstatus)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int b = slots ? slots[i] : i;
     double m = INFINITY;
-    for (int l = 0; l < nlev; ++l) m = fmin(m, detmin[(long long)l * B + b]);
+    for (int l = l0; l < nlev; ++l) m = fmin(m, detmin[(long long)l * B + b]);
     pmg_info r;
     r.min_detj = m;
     r.iterations = 0;
@@ -630,8 +791,8 @@ __global__ void __launch_bounds__(NT) k_rhs(const Hier<double>* __restrict__ Hp,
     for (int q = threadIdx.x; q < N; q += NT) v[q] = is_boundary<P, DIM>(q) ? g[b * N + q] : 0.0;
     wg_barrier();
     double* out = bo + b * N;
-    apply_level<double, P, DIM, false>(L.G64 + b * S::NC * N, L.D64, L.DT64,
-                                       L.TR + b * DIM * N, v, nullptr, out);
+    apply_level<double, P, DIM, false>(L.G64 + b * S::NC * L.ng, L.D64, L.DT64,
+                                       L.TR + b * DIM * L.ng, v, nullptr, out, H.K);
     for (int q = threadIdx.x; q < N; q += NT)
         out[q] = is_boundary<P, DIM>(q) ? 0.0 : L.mass[b * N + q] * f[b * N + q] - out[q];
 }
@@ -655,7 +816,7 @@ __global__ void __launch_bounds__(NT) k_line_coefs(const Hier<double>* __restric
     constexpr int n = S::n, NL = S::NL;
     const long long b = blockIdx.x;
     const LevelData<double>& L = H.lev[S::LEV];
-    const double* Gb = L.G64 + b * S::NC * S::N;
+    const double* Gb = L.G64 + b * S::NC * L.ng;
     const double* Xb = L.X64 + b * DIM * S::N;
     const long long o = b * (long long)NL * n;
     for (int k = threadIdx.x; k < NL * n; k += NT) {
@@ -732,14 +893,23 @@ hipError_t launch_setup(int dim, int p_fine, int nlev, int B, const SetupArgs& a
     hipError_t e;
     const int nb = a.slots ? a.nslots : B;
     if (nb <= 0) return hipSuccess;
-    for (int l = 0; l < nlev; ++l) {
+    for (int l = a.l0; l < nlev; ++l) {
         const int p = 2 << l;
         double* mass = (p == p_fine) ? a.mass : nullptr;
-        PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_geom<P_, D_>), dim3(nb), dim3(NT), 0, s,
-                                                   a.coords[l], a.rho[l], a.D64[l], a.DT64[l],
-                                                   a.G64[l], a.G32[l], mass, a.X64[l],
+        if (a.K > 1) {
+            if (dim != 2) return hipErrorInvalidValue;
+            PMG_DISPATCH_P2D(p, hipLaunchKernelGGL((k_geom_elements<P_>), dim3(nb), dim3(NT), 0, s,
+                                                   a.K, a.coords[l], a.rho[l], a.D64[l], a.G64[l],
+                                                   a.G32[l], mass, a.X64[l],
                                                    a.detmin + (long long)l * B, a.slots,
-                                                   l == 0 ? a.pivot : nullptr));
+                                                   l == a.l0 ? a.pivot : nullptr));
+        } else {
+            PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_geom<P_, D_>), dim3(nb), dim3(NT), 0, s,
+                                                       a.coords[l], a.rho[l], a.D64[l], a.DT64[l],
+                                                       a.G64[l], a.G32[l], mass, a.X64[l],
+                                                       a.detmin + (long long)l * B, a.slots,
+                                                       l == 0 ? a.pivot : nullptr));
+        }
         if ((e = last()) != hipSuccess) return e;
         PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_lines<P_, D_>), dim3(nb), dim3(NT), 0, s,
                                                    a.G64[l], a.X64[l], a.D64[l], a.smoother,
@@ -750,8 +920,25 @@ hipError_t launch_setup(int dim, int p_fine, int nlev, int B, const SetupArgs& a
                                                    a.bd32[l][0], a.bd32[l][1], a.bd32[l][2]));
         if ((e = last()) != hipSuccess) return e;
     }
+    if (a.K > 1) {
+        // the coarsest level's exact inverse (degree 2K), after its geometry
+        const int p0 = 2 << a.l0;
+        switch (p0) {
+#define PMG_COARSE(PC)                                                                          \
+    case PC:                                                                                    \
+        hipLaunchKernelGGL((k_elements_coarse<PC>), dim3(nb), dim3(NT), 0, s, a.K, a.G64[a.l0], \
+                           a.D64[a.l0], a.Cc0, a.slots, a.pivot);                               \
+        break;
+            PMG_COARSE(4)
+            PMG_COARSE(8)
+            PMG_COARSE(16)
+#undef PMG_COARSE
+        default: return hipErrorInvalidValue;
+        }
+        if ((e = last()) != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_setup_finish, dim3((nb + 255) / 256), dim3(256), 0, s, a.detmin, a.pivot,
-                       nlev, B, nb, a.slots, info, a.sstatus);
+                       a.l0, nlev, B, nb, a.slots, info, a.sstatus);
     return last();
 }
 

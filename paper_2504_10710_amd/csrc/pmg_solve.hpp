@@ -62,11 +62,12 @@ __device__ void apply64(const Hier<T>& H, const SolveArgs& A, int b, const doubl
     using S = Shape<P, DIM>;
     const LevelData<T>& L = H.lev[S::LEV];
     if (r)
-        apply_level<double, P, DIM, true>(L.G64 + (long long)b * S::NC * S::N, L.D64, L.DT64,
-                                          A.TR64 + (long long)b * DIM * S::N, x, r, out);
+        apply_level<double, P, DIM, true>(L.G64 + (long long)b * S::NC * L.ng, L.D64, L.DT64,
+                                          A.TR64 + (long long)b * DIM * L.ng, x, r, out, H.K);
     else
-        apply_level<double, P, DIM, false>(L.G64 + (long long)b * S::NC * S::N, L.D64, L.DT64,
-                                           A.TR64 + (long long)b * DIM * S::N, x, nullptr, out);
+        apply_level<double, P, DIM, false>(L.G64 + (long long)b * S::NC * L.ng, L.D64, L.DT64,
+                                           A.TR64 + (long long)b * DIM * L.ng, x, nullptr, out,
+                                           H.K);
 }
 
 // Modified Gram-Schmidt for column j of the Arnoldi process: for i = 0..j,

@@ -33,7 +33,7 @@ class pmg_desc(ctypes.Structure):
                 ("smoother", ctypes.c_int), ("inner_prec", ctypes.c_int),
                 ("krylov", ctypes.c_int), ("restart", ctypes.c_int),
                 ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double),
-                ("restriction", ctypes.c_int)]
+                ("restriction", ctypes.c_int), ("elements", ctypes.c_int)]
 
 
 MAX_CLASSES = 8
@@ -75,6 +75,7 @@ def lib():
         sig = {
             "pmg_last_error": (ctypes.c_char_p, []),
             "pmg_num_levels": (i, [ctypes.POINTER(pmg_desc), ctypes.POINTER(i)]),
+            "pmg_first_level": (i, [ctypes.POINTER(pmg_desc), ctypes.POINTER(i)]),
             "pmg_gll": (i, [i, dp, dp, dp]),
             "pmg_interp": (i, [i, i, dp]),
             "pmg_workspace_bytes": (i, [ctypes.POINTER(pmg_desc), ctypes.POINTER(ctypes.c_size_t)]),
@@ -126,7 +127,7 @@ def lib():
 
 def exported_symbols():
     """Names the binding expects the library to export."""
-    return ["pmg_last_error", "pmg_num_levels", "pmg_gll", "pmg_interp", "pmg_workspace_bytes",
+    return ["pmg_last_error", "pmg_num_levels", "pmg_first_level", "pmg_gll", "pmg_interp", "pmg_workspace_bytes",
             "pmg_setup", "pmg_rhs", "pmg_lift", "pmg_apply", "pmg_restrict", "pmg_prolong_add",
             "pmg_line_solve", "pmg_line_smooth", "pmg_gamma_cycle", "pmg_solve",
             "pmg_line_coefs", "pmg_geom", "pmg_destroy", "pmg_pool_workspace_bytes",
@@ -172,14 +173,20 @@ def pmg_interp(p_c: int, p_f: int):
 
 def make_desc(dim=2, p_fine=16, batch=1, gamma=1, m=1, alpha=0.16, smoother=PMG_SMOOTHER_FEM,
               inner_prec=PMG_F64, krylov=PMG_FGMRES, restart=30, max_iter=200, rtol=1e-10,
-              restriction=PMG_RESTRICT_INTERP):
+              restriction=PMG_RESTRICT_INTERP, elements=1):
     return pmg_desc(dim, p_fine, batch, gamma, m, alpha, smoother, inner_prec, krylov, restart,
-                    max_iter, rtol, restriction)
+                    max_iter, rtol, restriction, elements)
 
 
 def pmg_num_levels(desc: pmg_desc) -> int:
     n = ctypes.c_int(0)
     _check(lib().pmg_num_levels(ctypes.byref(desc), ctypes.byref(n)))
+    return n.value
+
+
+def pmg_first_level(desc: pmg_desc) -> int:
+    n = ctypes.c_int(0)
+    _check(lib().pmg_first_level(ctypes.byref(desc), ctypes.byref(n)))
     return n.value
 
 
@@ -196,7 +203,7 @@ def pmg_setup(desc, coords, ws, info, stream=None):
     ws: uint8 device tensor of pmg_workspace_bytes(desc); info: uint8 device
     tensor of B * INFO_BYTES.  Returns the handle (c_void_p)."""
     n = len(coords)
-    arr = (ctypes.c_void_p * n)(*[c.data_ptr() for c in coords])
+    arr = (ctypes.c_void_p * n)(*[None if c is None else c.data_ptr() for c in coords])
     h = ctypes.c_void_p()
     _check(lib().pmg_setup(ctypes.byref(desc), arr, _ptr(ws), ws.numel() * ws.element_size(),
                            _ptr(info), _stream(stream), ctypes.byref(h)))
@@ -292,7 +299,8 @@ def pmg_pool_admit(pool, slots, coords, fs, gs, stream=None):
     (coarsest first); fs, gs: per request finest-level tensors."""
     n = len(slots)
     sl = (ctypes.c_int * n)(*slots)
-    cp = (ctypes.c_void_p * sum(len(c) for c in coords))(*[t.data_ptr() for c in coords for t in c])
+    cp = (ctypes.c_void_p * sum(len(c) for c in coords))(
+        *[None if t is None else t.data_ptr() for c in coords for t in c])
     fp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in fs])
     gp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in gs])
     _check(lib().pmg_pool_admit(pool, n, sl, cp, fp, gp, _stream(stream)))
@@ -352,7 +360,7 @@ def pmg_server_create(desc, ws, streams=None):
 
 
 def pmg_server_submit(srv, cls, coords, f, g, u) -> int:
-    cp = (ctypes.c_void_p * len(coords))(*[t.data_ptr() for t in coords])
+    cp = (ctypes.c_void_p * len(coords))(*[None if t is None else t.data_ptr() for t in coords])
     t = ctypes.c_longlong(-1)
     _check(lib().pmg_server_submit(srv, cls, cp, _ptr(f), _ptr(g), _ptr(u), ctypes.byref(t)))
     return t.value
@@ -410,7 +418,7 @@ class Solver:
         self.nlev = pmg_num_levels(desc)
         self.ws = torch.empty(pmg_workspace_bytes(desc), dtype=torch.uint8, device=device)
         self.info = torch.empty(desc.batch * INFO_BYTES, dtype=torch.uint8, device=device)
-        self.coords = [c.contiguous() for c in coords]
+        self.coords = [None if c is None else c.contiguous() for c in coords]
         self.h = pmg_setup(desc, self.coords, self.ws, self.info)
 
     def __del__(self):

@@ -128,3 +128,51 @@ def test_workspace_layout_in_bounds(kw):
         print(f"{kw} {name}: region ends at {off + nb}, unguarded four-in-flight loop reaches "
               f"{furthest + esz}, workspace {total}, slack {total - furthest - esz}")
         assert furthest + esz <= total
+
+
+@pytest.mark.parametrize("K,p,prec", [(2, 16, pmg.PMG_F64), (4, 128, pmg.PMG_F64),
+                                      (8, 64, pmg.PMG_F32), (4, 256, pmg.PMG_F32)])
+def test_element_workspace_layout(K, p, prec):
+    """Several elements per axis: levels below degree 2K are absent; the
+    geometric factors and fluxes of a level hold K^2 (p_l/K + 1)^2 element
+    nodes per problem; the coarsest level holds its (2K-1)^2 square exact
+    inverse; every region in bounds, aligned, without overlap."""
+    B = 3
+    desc = pmg.make_desc(dim=2, p_fine=p, batch=B, elements=K, smoother=pmg.PMG_SMOOTHER_FEM,
+                         inner_prec=prec)
+    l0 = pmg.pmg_first_level(desc)
+    assert l0 == int(np.log2(2 * K)) - 1
+    nlev = pmg.pmg_num_levels(desc)
+    total = pmg.pmg_workspace_bytes(desc)
+    regs = pmg.pmg_workspace_layout(desc)
+    end = 0
+    for name, off, nb in regs:
+        assert off % 256 == 0 and off >= end, (name, off, end)
+        end = off + nb
+    assert end <= total
+    lev = {n: nb for n, _, nb in regs}
+    tsz = 4 if prec == pmg.PMG_F32 else 8
+    for l in range(nlev):
+        present = l >= l0
+        assert (f"X[{l}]" in lev) == present and (f"G64[{l}]" in lev) == present, l
+        if not present:
+            continue
+        pl = 2 << l
+        ng = K * K * (pl // K + 1) ** 2
+        assert lev[f"G64[{l}]"] == 8 * B * 3 * ng
+        assert lev[f"TR[{l}]"] == tsz * B * 2 * ng
+        assert lev[f"X[{l}]"] == tsz * B * (pl + 1) ** 2
+    ni = (2 * K - 1) ** 2
+    cc = [n for n in lev if n.startswith("Cc")]
+    assert cc == [f"Cc[{l0}]"] and lev[cc[0]] == 8 * B * ni * ni
+
+
+@pytest.mark.parametrize("kw", [dict(elements=3, p_fine=48), dict(elements=2, dim=3, p_fine=16),
+                                dict(elements=4, p_fine=8),
+                                dict(elements=2, p_fine=16, smoother=pmg.PMG_SMOOTHER_GLL),
+                                dict(elements=16, p_fine=64), dict(elements=-1, p_fine=16)])
+def test_element_descriptions_rejected(kw):
+    args = dict(dim=2, batch=1, smoother=pmg.PMG_SMOOTHER_FEM)
+    args.update(kw)
+    with pytest.raises(pmg.PmgError):
+        pmg.pmg_workspace_bytes(pmg.make_desc(**args))
