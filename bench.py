@@ -78,17 +78,28 @@ def copy_calibration(mib):
                       "launches": 3}), flush=True)
 
 
-def flops_per_solve(dim, p, gamma, m, iters, krylov, restart, collapsed=()):
+def flops_per_solve(dim, p, gamma, m, iters, krylov, restart, collapsed=(), elements=1):
     """Algorithmic flop count of one solve: per level visit the operator's
     contractions and flux products, the line sweeps' cyclic reduction, the
     transfers and the vector updates; per outer iteration the FP64 operator
     and the Krylov vector work.  A level in `collapsed` (degrees) is applied
     as its dense matrix: 2 ni^2 flops per visit, and the levels below it are
-    not visited."""
+    not visited.  elements = K > 1 (2-D): every level is K x K elements of
+    degree p_l / K (the operator's contractions per element, the transfers'
+    element blocks), the hierarchy stops at degree 2K (dense exact solve)."""
+    K = elements
+
     def level_costs(pl):
         n1 = pl + 1
         N = n1 ** dim
         nint = (pl - 1) ** dim
+        if K > 1:
+            ne1 = pl // K + 1
+            apply_ = K ** dim * (4 * dim * ne1 + (2 * dim * dim - dim)) * ne1 ** dim + N
+            nb = K * ne1 * (pl // (2 * K) + 1)          # nonzeros of a 1-D composite transfer
+            n1c = pl // 2 + 1
+            transfer = 2 * nb * (n1 + n1c)
+            return apply_, 11 * nint, transfer
         apply_ = (4 * dim * n1 + (2 * dim * dim - dim) + 1) * N
         cr = 11 * nint
         n1c = pl // 2 + 1
@@ -100,9 +111,11 @@ def flops_per_solve(dim, p, gamma, m, iters, krylov, restart, collapsed=()):
 
     levels = []
     pl = p
-    while pl >= 2:
+    while pl >= 2 * K:
         levels.append(pl)
         pl //= 2
+    if K > 1:
+        collapsed = tuple(collapsed) + (2 * K,)
     cycle = 0.0
     for depth, pl in enumerate(levels):
         visits = gamma ** depth
@@ -140,7 +153,7 @@ def make_problems(dim, B, seed0=0):
 
 
 def run_batch(args, prec_name, dim=2, p=None, B=None, gamma=None, restriction=None,
-              steps=None, warmup=None, keep=0, restart=None, tag=""):
+              steps=None, warmup=None, keep=0, restart=None, tag="", elements=1):
     """Time `steps` whole-path steps of one batch; returns the measurements.
     keep > 0 also returns the solutions of the first `keep` problems."""
     import numpy as np
@@ -162,18 +175,27 @@ def run_batch(args, prec_name, dim=2, p=None, B=None, gamma=None, restriction=No
     rst = pmg.PMG_RESTRICT_INTERP if restriction == "interp" else pmg.PMG_RESTRICT_TRANSPOSE
     desc = pmg.make_desc(dim=dim, p_fine=p, batch=B, gamma=gamma, m=1, alpha=args.alpha,
                          smoother=smoother, inner_prec=prec, krylov=krylov,
-                         restart=restart, max_iter=600, rtol=args.rtol, restriction=rst)
+                         restart=restart, max_iter=600, rtol=args.rtol, restriction=rst,
+                         elements=elements)
     label = f"{tag or prec_name} {dim}-D p={p} gamma={gamma} R={restriction}"
+    if elements > 1:
+        label += f" {elements}x{elements} elements"
 
     # ---- synthetic inputs (seeded), resident in HBM before timing
     t0 = time.time()
     probs = make_problems(dim, B)
-    ps = inputs.halving_degrees(p, 2)
-    coords = []
+    K = elements
+    # levels below degree 2K are absent for K elements per axis (no coordinates)
+    l0 = pmg.pmg_first_level(desc)
+    ps = inputs.halving_degrees(p, 2 * K)
+    coords = [None] * l0
+
+    def nodes(q):   # composite node grid of level degree q (K elements of degree q / K)
+        return inputs.composite_nodes(pmg.pmg_gll(q // K)[0], K) if K > 1 else pmg.pmg_gll(q)[0]
     for q in ps:
-        xi = pmg.pmg_gll(q)[0]
+        xi = nodes(q)
         coords.append(torch.from_numpy(np.stack([pr.coords(xi) for pr in probs])).to(dev))
-    xi = pmg.pmg_gll(p)[0]
+    xi = nodes(p)
     Xf = [pr.coords(xi) for pr in probs]
     f = torch.from_numpy(np.stack([pr.f(x) for pr, x in zip(probs, Xf)])).to(dev)
     g = torch.from_numpy(np.stack([pr.g(x) for pr, x in zip(probs, Xf)])).to(dev)
@@ -226,13 +248,14 @@ def run_batch(args, prec_name, dim=2, p=None, B=None, gamma=None, restriction=No
           file=sys.stderr, flush=True)
     # levels the library applies as dense matrices (named "Cc[l]" in the layout)
     coll = tuple(2 << int(name[3:-1]) for name, _, _ in pmg.pmg_workspace_layout(desc)
-                 if name.startswith("Cc["))
-    flops = sum(flops_per_solve(dim, p, gamma, 1, int(k), args.krylov, restart, coll) for k in its)
+                 if name.startswith("Cc[")) if K == 1 else ()
+    flops = sum(flops_per_solve(dim, p, gamma, 1, int(k), args.krylov, restart, coll, K)
+                for k in its)
     xk = x[:keep].cpu().numpy() if keep else None
     return {"value": value, "ms_per_step": ms_per_step, "solve_s": solve_s, "its": its,
             "ok": ok, "flops": flops, "max_relres": float(nfo["relres"].max()),
             "probs": probs, "ps": ps, "x_keep": xk, "dim": dim, "p": p, "B": B,
-            "gamma": gamma, "restriction": restriction, "prec": prec_name}
+            "gamma": gamma, "restriction": restriction, "prec": prec_name, "elements": K}
 
 
 def roofline_of(r, prec_name):
@@ -244,8 +267,10 @@ def roofline_of(r, prec_name):
     kname = f"k_solve<{tname}, {r['p']}, {r['dim']}>"
     traffic, src = measured_traffic(kname, r["B"])
     # the solve's flops are mostly matrix-core contractions (operator and
-    # transfers); MI355X's dense FP64 MFMA peak equals its FP64 vector peak
-    return {"bound": "mfma", "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
+    # transfers); MI355X's dense FP64 MFMA peak equals its FP64 vector peak.
+    # Element hierarchies run their operator on the vector units.
+    bound = "alu" if r.get("elements", 1) > 1 else "mfma"
+    return {"bound": bound, "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 5), "traffic": traffic,
             "traffic_source": src if traffic is not None else None,
             "kernel": kname, "flops_per_launch": r["flops"],
@@ -439,6 +464,18 @@ def main():
                 v["roofline"] = roofline_of(r, prec_name)
                 legs[f"{ldim}-D p={lp} {prec_name}"] = v
                 torch.cuda.empty_cache()
+        # multi-element hp-multigrid: 4 x 4 elements of degree 32 (the composite
+        # grid of the p = 128 workload), FEM lines, exact solve at degree 8
+        for prec_name in ("f64", "f32"):
+            r = run_batch(args, prec_name, dim=2, p=128, B=args.batch, gamma=args.gamma,
+                          restriction=args.restriction, steps=2, warmup=1, tag="leg", elements=4)
+            v = summary_of(r)
+            v["elements"] = "4x4, degree 32"
+            v["interior_dofs"] = 127 ** 2
+            v["dof_per_s"] = round(r["value"] * 127 ** 2, 1)
+            v["roofline"] = roofline_of(r, prec_name)
+            legs[f"2-D 4x4 elements p=32 {prec_name}"] = v
+            torch.cuda.empty_cache()
     comps = components(args, r64["probs"], r64["ps"]) if args.components else None
     served = serve(args) if args.serve > 0 else None
 

@@ -54,3 +54,33 @@ def test_flop_model_collapsed_levels():
     one = bench.flops_per_solve(2, 128, 3, 1, 1, "fgmres", 30, collapsed=(16,))
     two = bench.flops_per_solve(2, 128, 3, 1, 1, "fgmres", 30, collapsed=(8, 16))
     assert one == two        # the p = 16 matrix hides p = 8
+
+
+def test_element_flop_model():
+    """Several elements: the per-visit operator count is the element
+    contractions summed over elements (plus the assembly), the hierarchy
+    stops at degree 2K with a dense exact solve, and K = 1 is unchanged."""
+    import bench
+    one = bench.flops_per_solve(2, 32, 2, 1, 10, "fgmres", 30)
+    assert one == bench.flops_per_solve(2, 32, 2, 1, 10, "fgmres", 30, (), 1)
+    K, p, gamma = 2, 16, 1
+    # hand count: levels 16 and 8 (element degrees 8, 4), dense solve at degree 4
+    def apply_(pl):
+        ne1 = pl // K + 1
+        return K * K * (8 * ne1 + 6) * ne1 ** 2 + (pl + 1) ** 2
+    def transfer(pl):
+        nb = K * (pl // K + 1) * (pl // (2 * K) + 1)
+        return 2 * nb * (pl + 1 + pl // 2 + 1)
+    sweeps = 2 * (1 + gamma)
+    cycle = 0.0
+    for depth, pl in enumerate((16, 8)):
+        cycle += gamma ** depth * ((sweeps - 1 + gamma) * apply_(pl) + sweeps * 11 * (pl - 1) ** 2
+                                   + 2 * gamma * transfer(pl))
+    cycle += gamma ** 2 * 2 * (4 - 1) ** 4
+    N = 17 ** 2
+    iters = 3
+    total = 0.0
+    for j in range(iters):
+        total += cycle + apply_(16) + 4 * (j + 1) * N + 3 * N
+    total += 1 * (apply_(16) + 4 * N) + iters * 2 * N
+    assert bench.flops_per_solve(2, p, gamma, 1, iters, "fgmres", 30, (), K) == total
