@@ -268,8 +268,10 @@ def roofline_of(r, prec_name):
     traffic, src = measured_traffic(kname, r["B"])
     # the solve's flops are mostly matrix-core contractions (operator and
     # transfers); MI355X's dense FP64 MFMA peak equals its FP64 vector peak.
-    # Element hierarchies run their operator on the vector units.
-    bound = "alu" if r.get("elements", 1) > 1 else "mfma"
+    # Element hierarchies run their operator on the matrix cores where the
+    # element degree is at least 16, else on the vector units.
+    K = r.get("elements", 1)
+    bound = "alu" if K > 1 and r["p"] // K < 16 else "mfma"
     return {"bound": bound, "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 5), "traffic": traffic,
             "traffic_source": src if traffic is not None else None,

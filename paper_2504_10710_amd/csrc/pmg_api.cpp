@@ -256,6 +256,8 @@ struct pmg_handle {
     size_t o_cr64[MAX_LEVELS][3], o_cr32[MAX_LEVELS][3];
     size_t o_bd64[MAX_LEVELS][3], o_bd32[MAX_LEVELS][3];   // band-2 line rows (0: none)
     size_t o_X[MAX_LEVELS], o_R[MAX_LEVELS], o_Tm[MAX_LEVELS], o_TR[MAX_LEVELS];
+    size_t o_EX[MAX_LEVELS];   // element-local operand / output (K > 1), 0: none
+    size_t o_EX64;             // its FP64 form on the finest level (K > 1), 0: none
     size_t o_mass, o_W1, o_W2, o_TR64, o_V, o_Z, o_Hs, o_detmin, o_pivot, o_cinv64, o_cinv32;
     size_t o_sstatus, o_state, o_hier64, o_hier32;
     size_t o_Cc[MAX_LEVELS];   // collapsed coarse cycles, B x ni x ni doubles (0: none)
@@ -307,6 +309,7 @@ void plan(pmg_handle* h, std::vector<pmg_region>* rec = nullptr)
         h->o_rho[l] = h->o_D64[l] = h->o_DT64[l] = h->o_D32[l] = h->o_DT32[l] = 0;
         h->o_J64[l] = h->o_JT64[l] = h->o_J32[l] = h->o_JT32[l] = h->o_JR64[l] = h->o_JR32[l] = 0;
         h->o_G64[l] = h->o_G32[l] = h->o_X64[l] = h->o_X[l] = h->o_R[l] = h->o_Tm[l] = h->o_TR[l] = 0;
+        h->o_EX[l] = 0;
         h->o_Cc[l] = 0;
         for (int a = 0; a < 3; ++a)
             h->o_cr64[l][a] = h->o_cr32[l][a] = h->o_bd64[l][a] = h->o_bd32[l][a] = 0;
@@ -357,6 +360,7 @@ void plan(pmg_handle* h, std::vector<pmg_region>* rec = nullptr)
         h->o_R[l] = L.take("R", l, tsz * (size_t)B * s.N);
         h->o_Tm[l] = L.take("Tm", l, tsz * (size_t)B * s.N);
         h->o_TR[l] = L.take("TR", l, tsz * (size_t)B * dim * NE);
+        h->o_EX[l] = h->K > 1 ? L.take("EX", l, tsz * (size_t)B * NE) : 0;
     }
     LevelShape f = level_shape(dim, h->nlev - 1);
     h->w1 = h->w2 = w;
@@ -364,6 +368,9 @@ void plan(pmg_handle* h, std::vector<pmg_region>* rec = nullptr)
     h->o_W1 = L.take("W1", -1, tsz * (size_t)B * w);
     h->o_W2 = dim == 3 ? L.take("W2", -1, tsz * (size_t)B * w) : 0;
     h->o_TR64 = L.take("TR64", -1, sizeof(double) * (size_t)B * dim * elem_nodes(h, h->nlev - 1));
+    h->o_EX64 = h->K == 1 ? 0
+        : (h->f32 ? L.take("EX64", -1, sizeof(double) * (size_t)B * elem_nodes(h, h->nlev - 1))
+                  : h->o_EX[h->nlev - 1]);
     const int kr = d.restart;
     h->nv = kr + 1 > 5 ? kr + 1 : 5;
     h->hs = (long long)(kr + 1) * kr + 4LL * kr + 1;
@@ -435,6 +442,7 @@ void fill_hier(pmg_handle* h, Hier<T>& H, bool is32)
         L.R = (T*)(ws + h->o_R[l]);
         L.Tm = (T*)(ws + h->o_Tm[l]);
         L.TR = (T*)(ws + h->o_TR[l]);
+        L.EX = h->o_EX[l] ? (T*)(ws + h->o_EX[l]) : nullptr;
         L.D = (const T*)(ws + (is32 ? h->o_D32[l] : h->o_D64[l]));
         L.DT = (const T*)(ws + (is32 ? h->o_DT32[l] : h->o_DT64[l]));
         if (l > h->l0) {
@@ -647,6 +655,7 @@ static int init_handle(const pmg_desc* desc, void* d_ws, size_t ws_bytes, bool p
     fill_hier<float>(h, h->H32, true);
     // FP64 views used by the FP64-only operations of an FP32 handle
     h->H64.lev[h->nlev - 1].TR = (double*)(h->ws + h->o_TR64);
+    h->H64.lev[h->nlev - 1].EX = h->o_EX64 ? (double*)(h->ws + h->o_EX64) : nullptr;
     // kernels read the hierarchy description from device memory
     if ((e = hipMemcpyAsync(h->ws + h->o_hier64, &h->H64, sizeof(Hier<double>), hipMemcpyHostToDevice,
                             s)) != hipSuccess ||
@@ -860,6 +869,7 @@ int pmg_solve(pmg_handle* h, const double* d_b, double* d_x, pmg_info* d_info, p
     a.Z = (double*)(h->ws + h->o_Z);
     a.Hs = (double*)(h->ws + h->o_Hs);
     a.TR64 = (double*)(h->ws + h->o_TR64);
+    a.EX64 = h->o_EX64 ? (double*)(h->ws + h->o_EX64) : nullptr;
     a.info = d_info;
     a.nv = h->nv;
     a.hs = h->hs;
@@ -930,7 +940,9 @@ int pmg_solve_noalloc(pmg_handle* h, const double* d_b, double* d_x, pmg_info* d
     const size_t oV = L.take(sizeof(double) * (size_t)(B * h->nv * N));
     const size_t oZ = L.take(sizeof(double) * (size_t)(B * h->d.restart * N));
     const size_t oHs = L.take(sizeof(double) * (size_t)(B * h->hs));
-    const size_t oTR = L.take(sizeof(double) * (size_t)(B * dim * N));
+    const long long NG = h->H64.lev[h->nlev - 1].ng;   // element nodes of the finest level
+    const size_t oTR = L.take(sizeof(double) * (size_t)(B * dim * NG));
+    const size_t oEX = h->K > 1 ? L.take(sizeof(double) * (size_t)(B * NG)) : 0;
     const size_t oSt = L.take(sizeof(SolveState) * (size_t)B);
     const size_t need = L.take(0);
     if (need > PMG_SCRATCH_BYTES)
@@ -948,6 +960,7 @@ int pmg_solve_noalloc(pmg_handle* h, const double* d_b, double* d_x, pmg_info* d
     a.Z = (double*)(sp + oZ);
     a.Hs = (double*)(sp + oHs);
     a.TR64 = (double*)(sp + oTR);
+    a.EX64 = h->K > 1 ? (double*)(sp + oEX) : nullptr;
     a.info = d_info;
     a.nv = h->nv;
     a.hs = h->hs;
@@ -1040,6 +1053,7 @@ static SolveArgs pool_solve_args(pmg_pool* P)
     a.Z = (double*)(h->ws + h->o_Z);
     a.Hs = (double*)(h->ws + h->o_Hs);
     a.TR64 = (double*)(h->ws + h->o_TR64);
+    a.EX64 = h->o_EX64 ? (double*)(h->ws + h->o_EX64) : nullptr;
     a.info = (pmg_info*)(h->ws + h->o_info);
     a.nv = h->nv;
     a.hs = h->hs;

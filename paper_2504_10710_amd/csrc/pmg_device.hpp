@@ -68,6 +68,8 @@ struct LevelData {
     T* R;                // [B][N] level right-hand side
     T* Tm;               // [B][N] residual / line-solve buffer
     T* TR;               // [B][DIM][N] apply fluxes
+    T* EX;               // [B][ng] K > 1: element-local operand and output of the element
+                         // operator on the matrix cores (element degree >= 16), or null
     const T* D;          // [n1][n1]  D[i][j] = pi_j'(xi_i)
     const T* DT;         // [n1][n1]  transpose
     const T* J;          // [n1][n1c] prolongation from the next coarser level
@@ -753,6 +755,143 @@ __device__ void apply2d_elements(int K, const T* __restrict__ G_, const T* __res
     wg_barrier();
 }
 
+// The element operator on the matrix cores (element degree PE = P / K, a
+// multiple of 16): the elements' nodal values are first copied into the
+// element-local array EX (interface nodes once per element); each element is
+// then the one-element sum factorisation of apply2d_mfma on its own tiles
+// (rows and columns 1..PE on 16x16 tiles, row and column 0 on the vector
+// units), with the full element output (no boundary rows dropped) written
+// back into EX; finally each global node sums the outputs of the elements
+// holding it, in element order.  Tiles of all elements are shared out over
+// the waves.
+template <class T, int P, int PE, bool RESID>
+__device__ void apply2d_elements_mfma(const T* __restrict__ G_, const T* __restrict__ D_,
+                                      const T* __restrict__ DT_, T* __restrict__ TR_,
+                                      T* __restrict__ EX_, const T* __restrict__ x_,
+                                      const T* __restrict__ r_, T* __restrict__ out_)
+{
+    static_assert(PE % 16 == 0 && P % PE == 0, "element tiles cover rows 1..PE");
+    const auto G = gmem(G_);
+    const auto D = gmem(D_);
+    const auto DT = gmem(DT_);
+    const auto TR = gmem(TR_);
+    const auto EX = gmem(EX_);
+    const auto x = gmem(x_);
+    const auto r = gmem(r_);
+    const auto out = gmem(out_);
+    constexpr int K = P / PE, n1 = P + 1, N = n1 * n1;
+    constexpr int ne1 = PE + 1, NE = ne1 * ne1, NEL = K * K;
+    constexpr int BLK = PE >= 64 ? 2 : 1, NB = PE / (16 * BLK), NT2 = NB * NB;
+    using V4 = typename Mfma<T>::v4;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, kq = lane >> 4;
+    for (int t = threadIdx.x; t < NEL * NE; t += NT) {
+        const int e = t / NE, lq = t - e * NE;
+        EX[t] = x[((e % K) * PE + lq % ne1) + ((e / K) * PE + lq / ne1) * n1];
+    }
+    wg_barrier();
+    // pass 1: reference gradients and fluxes of every element node
+    for (int t = wave; t < NEL * NT2; t += NT / 64) {
+        const int e = t / NT2, tb = t - e * NT2;
+        const int r0 = 1 + (tb / NB) * 16 * BLK, c0 = 1 + (tb % NB) * 16 * BLK;
+        const auto xe = EX + (long long)NE * e;
+        const auto Ge = G + 3LL * NE * e;
+        const auto Fe = TR + 2LL * NE * e;
+        V4 ur[BLK][BLK], us[BLK][BLK];
+#pragma unroll
+        for (int i = 0; i < BLK; ++i)
+#pragma unroll
+            for (int j = 0; j < BLK; ++j) {
+                ur[i][j] = V4{0, 0, 0, 0};
+                us[i][j] = V4{0, 0, 0, 0};
+            }
+        mfma_blocks<T, ne1, ne1, ne1, 1, ne1, BLK, BLK, 2, 1, ne1>(xe + (r0 + lr) * ne1 + kq,
+                                                                    DT + kq * ne1 + c0 + lr,
+                                                                    DT + kq * ne1 + r0 + lr,
+                                                                    xe + kq * ne1 + c0 + lr, ur, us);
+#pragma unroll
+        for (int i = 0; i < BLK; ++i)
+#pragma unroll
+            for (int j = 0; j < BLK; ++j) {
+                const int col = c0 + 16 * j + lr;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int q = (r0 + 16 * i + Mfma<T>::row(lane, v)) * ne1 + col;
+                    const T g00 = Ge[q], g11 = Ge[NE + q], g01 = Ge[2 * NE + q];
+                    Fe[q] = g00 * ur[i][j][v] + g01 * us[i][j][v];
+                    Fe[NE + q] = g01 * ur[i][j][v] + g11 * us[i][j][v];
+                }
+            }
+    }
+    for (int t = threadIdx.x; t < NEL * (2 * PE + 1); t += NT) {
+        const int e = t / (2 * PE + 1), k2 = t - e * (2 * PE + 1);
+        const int j = k2 <= PE ? 0 : k2 - PE, i = k2 <= PE ? k2 : 0;
+        const auto xe = EX + (long long)NE * e;
+        T ur = 0, us = 0;
+        for (int k = 0; k < ne1; ++k) {
+            ur += xe[j * ne1 + k] * DT[k * ne1 + i];
+            us += D[j * ne1 + k] * xe[k * ne1 + i];
+        }
+        const int q = j * ne1 + i;
+        const auto Ge = G + 3LL * NE * e;
+        const auto Fe = TR + 2LL * NE * e;
+        const T g00 = Ge[q], g11 = Ge[NE + q], g01 = Ge[2 * NE + q];
+        Fe[q] = g00 * ur + g01 * us;
+        Fe[NE + q] = g01 * ur + g11 * us;
+    }
+    wg_barrier();
+    // pass 2: every element's full output (its values are no longer needed)
+    for (int t = wave; t < NEL * NT2; t += NT / 64) {
+        const int e = t / NT2, tb = t - e * NT2;
+        const int r0 = 1 + (tb / NB) * 16 * BLK, c0 = 1 + (tb % NB) * 16 * BLK;
+        const auto Fe = TR + 2LL * NE * e;
+        const auto ye = EX + (long long)NE * e;
+        V4 y[BLK][BLK];
+#pragma unroll
+        for (int i = 0; i < BLK; ++i)
+#pragma unroll
+            for (int j = 0; j < BLK; ++j) y[i][j] = V4{0, 0, 0, 0};
+        mfma_blocks<T, ne1, ne1, ne1, 1, ne1, BLK, BLK, 2, 1, ne1>(Fe + (r0 + lr) * ne1 + kq,
+                                                                    D + kq * ne1 + c0 + lr,
+                                                                    D + kq * ne1 + r0 + lr,
+                                                                    Fe + NE + kq * ne1 + c0 + lr, y, y);
+#pragma unroll
+        for (int i = 0; i < BLK; ++i)
+#pragma unroll
+            for (int jj = 0; jj < BLK; ++jj) {
+                const int col = c0 + 16 * jj + lr;
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    ye[(r0 + 16 * i + Mfma<T>::row(lane, v)) * ne1 + col] = y[i][jj][v];
+            }
+    }
+    for (int t = threadIdx.x; t < NEL * (2 * PE + 1); t += NT) {
+        const int e = t / (2 * PE + 1), k2 = t - e * (2 * PE + 1);
+        const int j = k2 <= PE ? 0 : k2 - PE, i = k2 <= PE ? k2 : 0;
+        const auto Fe = TR + 2LL * NE * e;
+        T y = 0;
+        for (int k = 0; k < ne1; ++k) y += Fe[j * ne1 + k] * D[k * ne1 + i] + D[k * ne1 + j] * Fe[NE + k * ne1 + i];
+        EX[(long long)NE * e + j * ne1 + i] = y;
+    }
+    wg_barrier();
+    // assembly: each interior global node sums the elements holding it
+    for (int q = threadIdx.x; q < N; q += NT) {
+        const int I = q % n1, J = q / n1;
+        if (I == 0 || I == P || J == 0 || J == P) {
+            out[q] = T(0);
+            continue;
+        }
+        const int ex1 = I / PE, ey1 = J / PE;
+        const int ex0 = I % PE == 0 ? ex1 - 1 : ex1, ey0 = J % PE == 0 ? ey1 - 1 : ey1;
+        T y = 0;
+        for (int ey = ey0; ey <= ey1; ++ey)
+            for (int ex = ex0; ex <= ex1; ++ex)
+                y += EX[(long long)NE * (ex + K * ey) + (I - ex * PE) + (J - ey * PE) * ne1];
+        out[q] = RESID ? r[q] - y : y;
+    }
+    wg_barrier();
+}
+
 // Matrix-free A x of eq. discreteBilinear by sum factorisation: reference
 // gradients g_b = D along axis b, fluxes f_a = sum_b G_ab g_b at every node,
 // then (A x)(n) = sum_a sum_k D[k][n_a] f_a(n with axis a <- k) on interior
@@ -763,10 +902,29 @@ __device__ __attribute__((noinline)) void apply_level(const T* __restrict__ G_,
                                                       const T* __restrict__ DT_, T* __restrict__ TR_,
                                                       const T* __restrict__ x_,
                                                       const T* __restrict__ r_, T* __restrict__ out_,
-                                                      int K = 1)
+                                                      int K = 1, T* __restrict__ EX_ = nullptr)
 {
     if constexpr (DIM == 2 && P >= 4) {
         if (K > 1) {
+            // element degree P / K >= 16 on the matrix cores, else the vector units
+            if constexpr (P / 2 >= 16 && (P / 2) % 16 == 0) {
+                if (K == 2 && EX_) {
+                    apply2d_elements_mfma<T, P, P / 2, RESID>(G_, D_, DT_, TR_, EX_, x_, r_, out_);
+                    return;
+                }
+            }
+            if constexpr (P / 4 >= 16 && (P / 4) % 16 == 0) {
+                if (K == 4 && EX_) {
+                    apply2d_elements_mfma<T, P, P / 4, RESID>(G_, D_, DT_, TR_, EX_, x_, r_, out_);
+                    return;
+                }
+            }
+            if constexpr (P / 8 >= 16 && (P / 8) % 16 == 0) {
+                if (K == 8 && EX_) {
+                    apply2d_elements_mfma<T, P, P / 8, RESID>(G_, D_, DT_, TR_, EX_, x_, r_, out_);
+                    return;
+                }
+            }
             apply2d_elements<T, P, RESID>(K, G_, D_, TR_, x_, r_, out_);
             return;
         }
@@ -1464,7 +1622,8 @@ __device__ void smooth_step(const Hier<T>& H, int b, int dir, const T* r, T* x, 
         wg_barrier();
     } else {
         apply_level<T, P, DIM, true>(L.G + (long long)b * S::NC * L.ng, L.D, L.DT,
-                                     L.TR + (long long)b * DIM * L.ng, x, r, tmp, H.K);
+                                     L.TR + (long long)b * DIM * L.ng, x, r, tmp, H.K,
+                                     L.EX ? L.EX + (long long)b * L.ng : nullptr);
     }
     level_lines<T, P, DIM, true>(L, b, dir, tmp, x, H.alpha);
 }
@@ -1560,7 +1719,8 @@ __device__ __attribute__((noinline)) void gamma_cycle(const Hier<T>& H, int b, c
             }
         for (int g = 0; g < H.gamma; ++g) {
             apply_level<T, P, DIM, true>(L.G + (long long)b * S::NC * L.ng, L.D, L.DT,
-                                         L.TR + (long long)b * DIM * L.ng, x, r, tmp, H.K);
+                                         L.TR + (long long)b * DIM * L.ng, x, r, tmp, H.K,
+                                         L.EX ? L.EX + (long long)b * L.ng : nullptr);
             restrict_level<T, P, DIM>(tmp, rc, L.JR, L.JT, w1, w2);
             gamma_cycle<T, P / 2, DIM, CMAX>(H, b, rc, xc);
             prolong_level<T, P, DIM>(xc, x, L.J, L.JT, w1, w2);

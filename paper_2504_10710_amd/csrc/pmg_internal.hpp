@@ -60,6 +60,7 @@ struct SolveArgs {
     double* Z;          // [B][restart][N]
     double* Hs;         // [B][hs]
     double* TR64;       // [B][DIM][N]
+    double* EX64;       // [B][ng] FP64 element-local operand (element hierarchies), or null
     pmg_info* info;     // [B]
     long long nv, hs;
     int restart, max_iter, krylov;

@@ -16,7 +16,8 @@ __global__ void __launch_bounds__(NT) k_apply(const Hier<T>* __restrict__ Hp, co
     const long long b = blockIdx.x;
     const LevelData<T>& L = H.lev[S::LEV];
     apply_level<T, P, DIM, false>(L.G + b * S::NC * L.ng, L.D, L.DT, L.TR + b * DIM * L.ng,
-                                  x + b * S::N, nullptr, y + b * S::N, H.K);
+                                  x + b * S::N, nullptr, y + b * S::N, H.K,
+                                  L.EX ? L.EX + b * L.ng : nullptr);
 }
 
 template <class T, int P, int DIM>

@@ -61,13 +61,15 @@ __device__ void apply64(const Hier<T>& H, const SolveArgs& A, int b, const doubl
 {
     using S = Shape<P, DIM>;
     const LevelData<T>& L = H.lev[S::LEV];
+    // the FP64 element-local operand of an element hierarchy's finest level
+    double* ex = A.EX64 ? A.EX64 + (long long)b * L.ng : nullptr;
     if (r)
         apply_level<double, P, DIM, true>(L.G64 + (long long)b * S::NC * L.ng, L.D64, L.DT64,
-                                          A.TR64 + (long long)b * DIM * L.ng, x, r, out, H.K);
+                                          A.TR64 + (long long)b * DIM * L.ng, x, r, out, H.K, ex);
     else
         apply_level<double, P, DIM, false>(L.G64 + (long long)b * S::NC * L.ng, L.D64, L.DT64,
                                            A.TR64 + (long long)b * DIM * L.ng, x, nullptr, out,
-                                           H.K);
+                                           H.K, ex);
 }
 
 // Modified Gram-Schmidt for column j of the Arnoldi process: for i = 0..j,
