@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--legs", type=int, default=1,
                     help="also time 3-D p = 64 and 2-D p = 256, FP64 and FP32 cycle")
     ap.add_argument("--legs-batch3", type=int, default=128)
+    ap.add_argument("--elements", type=int, default=1,
+                    help="spectral elements per axis of the headline run (profiling of the "
+                         "element path; the default run and its metric use one element)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     return ap.parse_args()
@@ -265,7 +268,7 @@ def roofline_of(r, prec_name):
     peak = PEAK_FP32_TFLOPS if prec_name == "f32" else PEAK_FP64_TFLOPS
     tname = "float" if prec_name == "f32" else "double"
     kname = f"k_solve<{tname}, {r['p']}, {r['dim']}>"
-    traffic, src = measured_traffic(kname, r["B"])
+    traffic, src = measured_traffic(kname, r["B"], r.get("elements", 1))
     # the solve's flops are mostly matrix-core contractions (operator and
     # transfers); MI355X's dense FP64 MFMA peak equals its FP64 vector peak.
     # Element hierarchies run their operator on the matrix cores where the
@@ -378,9 +381,10 @@ def sources_digest(root=ROOT):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, batch, root=ROOT):
+def measured_traffic(kernel, batch, elements=1, root=ROOT):
     """HBM bytes per launch of `kernel` from the committed counter summary, if
-    it was taken on the current kernel sources at this batch size; else None."""
+    it was taken on the current kernel sources at this batch size and element
+    count (records without `elements` are one-element runs); else None."""
     import glob
 
     digest = sources_digest(root)
@@ -394,7 +398,7 @@ def measured_traffic(kernel, batch, root=ROOT):
                             k, v = kv.split("=", 1)
                             rec[k.strip()] = v.strip()
         if rec.get("kernel") == kernel and rec.get("batch") == str(batch) and \
-                rec.get("sources") == digest:
+                rec.get("sources") == digest and rec.get("elements", "1") == str(elements):
             return float(rec["bytes_per_launch"]), os.path.basename(f)
     return None, digest
 
@@ -420,11 +424,12 @@ def main():
     torch.cuda.set_device(0)
     B, p, dim = args.batch, args.p, 2
     keep = max(len(oracle_x), 1)
-    r64 = run_batch(args, args.prec, keep=keep, tag="headline")
+    r64 = run_batch(args, args.prec, keep=keep if args.elements == 1 else 0, tag="headline",
+                    elements=args.elements)
     roofline = roofline_of(r64, args.prec)
 
     def oracle_err(r):
-        if not oracle_x:
+        if not oracle_x or r["x_keep"] is None:
             return None
         errs = [float(np.abs(r["x_keep"][i] - xo).max() / np.abs(xo).max())
                 for i, xo in enumerate(oracle_x)]
@@ -432,7 +437,8 @@ def main():
 
     mixed = None
     if args.mixed and args.prec == "f64":
-        r32 = run_batch(args, "f32", keep=keep, tag="mixed")
+        r32 = run_batch(args, "f32", keep=keep if args.elements == 1 else 0, tag="mixed",
+                        elements=args.elements)
         mixed = summary_of(r32)
         mixed.update({"dtype": "f32 cycle + f64 Krylov",
                       "speedup_vs_f64": round(r32["value"] / r64["value"], 3),
@@ -496,7 +502,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if args.prec == "f32" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"2-D deformed square GLL Poisson, p={p}, gamma-cycle {p}->2",
+        "config": {"workload": (f"2-D deformed square GLL Poisson, p={p}, gamma-cycle {p}->2"
+                                if args.elements == 1 else
+                                f"2-D deformed square, {args.elements}x{args.elements} GLL "
+                                f"elements of degree {p // args.elements}, composite p={p}"),
+                   "elements": args.elements,
                    "batch": B, "gamma": args.gamma, "m": 1, "alpha": args.alpha,
                    "smoother": args.smoother, "restriction": args.restriction,
                    "krylov": args.krylov, "rtol": args.rtol,

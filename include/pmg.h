@@ -97,7 +97,7 @@ enum { PMG_RESTRICT_TRANSPOSE = 0, PMG_RESTRICT_INTERP = 1 };
  *              of the coarse polynomial at the fine nodes in both.
  *   elements   K spectral elements per axis (0 or 1: the one element of the
  *              paper; 2, 4 or 8: the multi-element hp-multigrid of the
- *              paper's closing outlook, 2-D, FEM line smoother).  The square
+ *              paper's closing outlook, 2-D, any line smoother).  The square
  *              is split into K x K equal parts of the reference square,
  *              each an element of degree p_l / K with its own GLL rule; an
  *              interface node is shared by the elements that meet there
@@ -111,7 +111,8 @@ enum { PMG_RESTRICT_TRANSPOSE = 0, PMG_RESTRICT_INTERP = 1 };
  *              levels below it are absent) and is solved exactly with the
  *              inverse of its (2K-1)^2 x (2K-1)^2 interior matrix, built at
  *              setup in FP64.  Line systems run along the composite grid
- *              lines across element interfaces. */
+ *              lines across element interfaces (GLL rows: entries of the
+ *              assembled operator; FEM rows: the composite node mesh). */
 typedef struct {
     int dim;
     int p_fine;

@@ -210,8 +210,6 @@ int check_desc(const pmg_desc* d)
         if (d->p_fine / d->elements < 4)
             return fail(PMG_EINVAL, "the finest element degree p_fine / elements must be >= 4 "
                                     "(got %d / %d)", d->p_fine, d->elements);
-        if (d->smoother != PMG_SMOOTHER_FEM)
-            return fail(PMG_EINVAL, "several elements per axis use the FEM line smoother");
     }
     return PMG_OK;
 }

@@ -372,15 +372,75 @@ __device__ double gll_entry(const double* __restrict__ Gb, const double* __restr
     return s;
 }
 
+// Entry A[r, c] (composite nodes r = (r0, r1), c = (c0, c1)) of the assembled
+// operator of K x K elements of degree P / K (2-D): the one-element
+// quadrature formula of eq. discreteBilinear on each element holding both
+// nodes (element factors Gb: per element G00, G11, G01 arrays of NE element
+// nodes; D the element's derivative matrix), summed in element order; zero
+// when no element holds both.
+template <int P>
+__device__ double elements_entry2d(int K, const double* __restrict__ Gb_, const double* __restrict__ D_,
+                                   const int* r, const int* c)
+{
+    const auto Gb = gmem(Gb_);
+    const auto D = gmem(D_);
+    const int pe = P / K, ne1 = pe + 1, NE = ne1 * ne1;
+    auto lo_of = [&](int I) { return (I % pe == 0 && I > 0) ? I / pe - 1 : min(I / pe, K - 1); };
+    auto hi_of = [&](int I) { return min(I / pe, K - 1); };
+    const int ex0 = max(lo_of(r[0]), lo_of(c[0])), ex1 = min(hi_of(r[0]), hi_of(c[0]));
+    const int ey0 = max(lo_of(r[1]), lo_of(c[1])), ey1 = min(hi_of(r[1]), hi_of(c[1]));
+    double v = 0.0;
+    for (int ey = ey0; ey <= ey1; ++ey)
+        for (int ex = ex0; ex <= ex1; ++ex) {
+            const int e = ex + K * ey;
+            const int lr[2] = {r[0] - ex * pe, r[1] - ey * pe};
+            const int lc[2] = {c[0] - ex * pe, c[1] - ey * pe};
+            const auto Ge = Gb + 3LL * NE * e;
+            for (int a = 0; a < 2; ++a)
+                for (int k = 0; k < ne1; ++k) {
+                    int qc[2] = {lr[0], lr[1]};
+                    qc[a] = k;
+                    const double da = D[k * ne1 + lr[a]];
+                    const int q = qc[0] + ne1 * qc[1];
+                    for (int bb = 0; bb < 2; ++bb)
+                        if (qc[1 - bb] == lc[1 - bb])
+                            v += Ge[gidx(2, a, bb) * NE + q] * da * D[qc[bb] * ne1 + lc[bb]];
+                }
+        }
+    return v;
+}
+
+// per-problem offset of a level's geometric factors: N nodes, or the
+// K^2 (P/K + 1)^2 element nodes of K x K elements
+template <int P, int DIM>
+__host__ __device__ inline long long geom_nodes(int K)
+{
+    if (K <= 1) return Shape<P, DIM>::N;
+    const long long ne1 = P / K + 1;
+    return (long long)K * K * ne1 * ne1;
+}
+
 template <int P, int DIM>
 __device__ void line_raw(const double* Gb, const double* Xb, const double* D, int smoother,
-                         int dir, int line, int s, double& l, double& a, double& u)
+                         int dir, int line, int s, double& l, double& a, double& u, int K = 1)
 {
     constexpr int n1 = P + 1, n = P - 1;
     int base, st;
     line_base<P, DIM>(dir, line, base, st);
     const int q = base + (s + 1) * st;
     int c[3] = {q % n1, (q / n1) % n1, DIM == 3 ? q / (n1 * n1) : 0};
+    if constexpr (DIM == 2) {
+        if (K > 1 && smoother != PMG_SMOOTHER_FEM) {
+            // GLL rows of the assembled operator of several elements
+            int cl[2] = {c[0], c[1]}, cu[2] = {c[0], c[1]};
+            cl[dir] -= 1;
+            cu[dir] += 1;
+            a = elements_entry2d<P>(K, Gb, D, c, c);
+            l = s > 0 ? elements_entry2d<P>(K, Gb, D, c, cl) : 0.0;
+            u = s < n - 1 ? elements_entry2d<P>(K, Gb, D, c, cu) : 0.0;
+            return;
+        }
+    }
     if (smoother == PMG_SMOOTHER_FEM && DIM == 2) {
         const int di = dir == 0 ? 1 : 0, dj = dir == 0 ? 0 : 1;
         a = fem_entry_2d<P>(Xb, c[0], c[1], c[0], c[1]);
@@ -416,12 +476,12 @@ __global__ void __launch_bounds__(NT) k_lines(const double* __restrict__ G,
                                               float* f1, float* f2, int* pivot,
                                               double* cinv64, float* cinv32, const int* slots,
                                               double* bd0, double* bd1, double* bd2, float* bf0,
-                                              float* bf1, float* bf2)
+                                              float* bf1, float* bf2, int K)
 {
     using S = Shape<P, DIM>;
     constexpr int n = S::n, NL = S::NL, CRW = S::CRW, N = S::N, NC = S::NC;
     const long long b = slots ? slots[blockIdx.x] : blockIdx.x;
-    const double* Gb = G + b * NC * N;
+    const double* Gb = G + b * NC * geom_nodes<P, DIM>(K);
     const double* Xb = X64 + b * DIM * N;
     int bad = 0;
     auto crp = [&](int dir) { return (dir == 0 ? cr0 : (dir == 1 ? cr1 : cr2)) + b * 3 * CRW * NL; };
@@ -443,7 +503,16 @@ __global__ void __launch_bounds__(NT) k_lines(const double* __restrict__ G,
                 line_base<P, DIM>(dir, line, base, st);
                 const int q = base + (sq + 1) * st;
                 const int c[3] = {q % (P + 1), (q / (P + 1)) % (P + 1), DIM == 3 ? q / ((P + 1) * (P + 1)) : 0};
-                const double v = (sq + k >= 0 && sq + k < n) ? gll_entry<P, DIM>(Gb, D, q, c, dir, k) : 0.0;
+                double v = 0.0;
+                if (sq + k >= 0 && sq + k < n) {
+                    if (DIM == 2 && K > 1) {
+                        int c2[2] = {c[0], c[1]};
+                        c2[dir] += k;
+                        v = elements_entry2d<P>(K, Gb, D, c, c2);
+                    } else {
+                        v = gll_entry<P, DIM>(Gb, D, q, c, dir, k);
+                    }
+                }
                 bdp(dir)[((long long)line * n + sq) * 5 + k + 2] = v;
             }
             wg_barrier();
@@ -492,7 +561,7 @@ __global__ void __launch_bounds__(NT) k_lines(const double* __restrict__ G,
         if (DIM == 3 && smoother == PMG_SMOOTHER_FEM) break;
         const int dir = e / (NL * n), line = (e / n) % NL, sq = e % n;
         double l, a, u;
-        line_raw<P, DIM>(Gb, Xb, D, smoother, dir, line, sq, l, a, u);
+        line_raw<P, DIM>(Gb, Xb, D, smoother, dir, line, sq, l, a, u, K);
         double* cr = crp(dir);
         cr[idx(dir, line, sq, 0)] = l;
         cr[idx(dir, line, sq, 1)] = a;
@@ -692,35 +761,11 @@ __global__ void __launch_bounds__(NT) k_elements_coarse(int K, const double* __r
     const int pe = P / K, ne1 = pe + 1, NE = ne1 * ne1;
     const long long b = slots ? slots[blockIdx.x] : blockIdx.x;
     const auto A = gmem(Cc + b * (long long)ni * ni);
-    const auto Gb = gmem(G + b * 3LL * K * K * NE);
-    const auto D = gmem(D_);
-    // elements holding coordinate I along an axis: [lo, hi]
-    auto lo_of = [&](int I) { return (I % pe == 0 && I > 0) ? I / pe - 1 : min(I / pe, K - 1); };
-    auto hi_of = [&](int I) { return min(I / pe, K - 1); };
+    const double* Gb = G + b * 3LL * K * K * NE;
     for (int t = threadIdx.x; t < ni * ni; t += NT) {
         const int row = t / ni, col = t - row * ni;
         const int r[2] = {row % n + 1, row / n + 1}, c[2] = {col % n + 1, col / n + 1};
-        double v = 0.0;
-        const int ex0 = max(lo_of(r[0]), lo_of(c[0])), ex1 = min(hi_of(r[0]), hi_of(c[0]));
-        const int ey0 = max(lo_of(r[1]), lo_of(c[1])), ey1 = min(hi_of(r[1]), hi_of(c[1]));
-        for (int ey = ey0; ey <= ey1; ++ey)
-            for (int ex = ex0; ex <= ex1; ++ex) {
-                const int e = ex + K * ey;
-                const int lr[2] = {r[0] - ex * pe, r[1] - ey * pe};
-                const int lc[2] = {c[0] - ex * pe, c[1] - ey * pe};
-                const auto Ge = Gb + 3LL * NE * e;
-                for (int a = 0; a < 2; ++a)
-                    for (int k = 0; k < ne1; ++k) {
-                        int qc[2] = {lr[0], lr[1]};
-                        qc[a] = k;
-                        const double da = D[k * ne1 + lr[a]];
-                        const int q = qc[0] + ne1 * qc[1];
-                        for (int bb = 0; bb < 2; ++bb)
-                            if (qc[1 - bb] == lc[1 - bb])
-                                v += Ge[gidx(2, a, bb) * NE + q] * da * D[qc[bb] * ne1 + lc[bb]];
-                    }
-            }
-        A[t] = v;
+        A[t] = elements_entry2d<P>(K, Gb, D_, r, c);
     }
     wg_barrier();
     bool bad = false;
@@ -823,7 +868,7 @@ __global__ void __launch_bounds__(NT) k_line_coefs(const Hier<double>* __restric
     for (int k = threadIdx.x; k < NL * n; k += NT) {
         int line = k / n, s = k % n;
         double l, a, u;
-        line_raw<P, DIM>(Gb, Xb, L.D64, smoother, dir, line, s, l, a, u);
+        line_raw<P, DIM>(Gb, Xb, L.D64, smoother, dir, line, s, l, a, u, H.K);
         lo[o + k] = l;
         di[o + k] = a;
         up[o + k] = u;
@@ -918,7 +963,7 @@ hipError_t launch_setup(int dim, int p_fine, int nlev, int B, const SetupArgs& a
                                                    a.cr32[l][0], a.cr32[l][1], a.cr32[l][2],
                                                    a.pivot, a.cinv64, a.cinv32, a.slots,
                                                    a.bd64[l][0], a.bd64[l][1], a.bd64[l][2],
-                                                   a.bd32[l][0], a.bd32[l][1], a.bd32[l][2]));
+                                                   a.bd32[l][0], a.bd32[l][1], a.bd32[l][2], a.K));
         if ((e = last()) != hipSuccess) return e;
     }
     if (a.K > 1) {

@@ -169,7 +169,6 @@ def test_element_workspace_layout(K, p, prec):
 
 @pytest.mark.parametrize("kw", [dict(elements=3, p_fine=48), dict(elements=2, dim=3, p_fine=16),
                                 dict(elements=4, p_fine=8),
-                                dict(elements=2, p_fine=16, smoother=pmg.PMG_SMOOTHER_GLL),
                                 dict(elements=16, p_fine=64), dict(elements=-1, p_fine=16)])
 def test_element_descriptions_rejected(kw):
     args = dict(dim=2, batch=1, smoother=pmg.PMG_SMOOTHER_FEM)

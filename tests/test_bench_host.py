@@ -26,12 +26,19 @@ def test_traffic_record_matches_sources_and_batch(tmp_path):
     with open(os.path.join(root, "profiles", "k.md"), "w") as f:
         f.write(f"traffic-record: kernel=k<double, 128, 2>; batch=2048; sources={dig}; "
                 f"bytes_per_launch=1234; fetch=1000; write=234\n")
-    assert bench.measured_traffic("k<double, 128, 2>", 2048, root)[0] == 1234.0
-    assert bench.measured_traffic("k<double, 128, 2>", 1024, root)[0] is None
-    assert bench.measured_traffic("k<float, 128, 2>", 2048, root)[0] is None
+    assert bench.measured_traffic("k<double, 128, 2>", 2048, root=root)[0] == 1234.0
+    assert bench.measured_traffic("k<double, 128, 2>", 1024, root=root)[0] is None
+    assert bench.measured_traffic("k<float, 128, 2>", 2048, root=root)[0] is None
+    # a one-element record does not serve an element run of the same kernel
+    assert bench.measured_traffic("k<double, 128, 2>", 2048, 4, root=root)[0] is None
+    with open(os.path.join(root, "profiles", "k4.md"), "w") as f:
+        f.write(f"traffic-record: kernel=k<double, 128, 2>; batch=2048; sources={dig}; "
+                f"elements=4; bytes_per_launch=99; fetch=90; write=9\n")
+    assert bench.measured_traffic("k<double, 128, 2>", 2048, 4, root=root)[0] == 99.0
+    assert bench.measured_traffic("k<double, 128, 2>", 2048, root=root)[0] == 1234.0
     with open(os.path.join(root, "paper_2504_10710_amd", "csrc", "k.hip"), "w") as f:
         f.write("kernel v2")          # sources changed since the counters
-    assert bench.measured_traffic("k<double, 128, 2>", 2048, root)[0] is None
+    assert bench.measured_traffic("k<double, 128, 2>", 2048, root=root)[0] is None
 
 
 def test_flop_model_monotone():

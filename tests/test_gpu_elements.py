@@ -50,32 +50,40 @@ def gpu_elements(probs, K, p_fine, device="cuda", **kw):
     return s, f, g, l0
 
 
-def oracle_elements(prob, K, p_fine, gamma=1, alpha=0.16, restriction=orc.RESTRICT_INTERP):
+def oracle_elements(prob, K, p_fine, gamma=1, alpha=0.16, restriction=orc.RESTRICT_INTERP,
+                    smoother=orc.SMOOTHER_FEM):
     pes = element_degrees(p_fine, K)
     coords = [prob.coords(inputs.composite_nodes(orc.gll(pe)[0], K)) for pe in pes]
     h = orc.Hier(2, [K * pe for pe in pes], coords, gamma=gamma, m=1, alpha=alpha,
-                 smoother=orc.SMOOTHER_FEM, restriction=restriction, elements=K)
+                 smoother=smoother, restriction=restriction, elements=K)
     X = coords[-1]
     return h, prob.f(X), prob.g(X)
 
 
-# (K, p_fine, gamma, restriction)
-CASES = [(2, 16, 1, pmg.PMG_RESTRICT_INTERP), (4, 32, 3, pmg.PMG_RESTRICT_INTERP),
-         (2, 32, 2, pmg.PMG_RESTRICT_TRANSPOSE), (8, 64, 2, pmg.PMG_RESTRICT_INTERP)]
+GLL, BAND2 = pmg.PMG_SMOOTHER_GLL, pmg.PMG_SMOOTHER_GLL_BAND2
+# (K, p_fine, gamma, restriction, smoother, alpha): FEM lines, and the GLL
+# line systems of the assembled operator across interfaces (tridiagonal and
+# half-bandwidth 2)
+CASES = [(2, 16, 1, pmg.PMG_RESTRICT_INTERP, FEM, 0.16), (4, 32, 3, pmg.PMG_RESTRICT_INTERP, FEM, 0.16),
+         (2, 32, 2, pmg.PMG_RESTRICT_TRANSPOSE, FEM, 0.16), (8, 64, 2, pmg.PMG_RESTRICT_INTERP, FEM, 0.16),
+         (2, 16, 3, pmg.PMG_RESTRICT_INTERP, GLL, 2.0 / 3.0),
+         (4, 64, 3, pmg.PMG_RESTRICT_INTERP, BAND2, 2.0 / 3.0)]
 SEEDS = [0, 1, 2]
+SM_NAME = {FEM: "fem", GLL: "gll", BAND2: "band2"}
 
 
 @pytest.fixture(scope="module", params=CASES,
-                ids=lambda c: f"K{c[0]}-p{c[1]}-g{c[2]}-{'interp' if c[3] else 'PT'}")
+                ids=lambda c: f"K{c[0]}-p{c[1]}-g{c[2]}-{'interp' if c[3] else 'PT'}-{SM_NAME[c[4]]}")
 def case(request):
-    K, p, gamma, rst = request.param
-    print(f"[gpu elements] K={K} p={p} gamma={gamma} restriction={rst}", flush=True)
+    K, p, gamma, rst, sm, alpha = request.param
+    print(f"[gpu elements] K={K} p={p} gamma={gamma} restriction={rst} smoother={sm}", flush=True)
     probs = [inputs.config2(s, 0.1) for s in SEEDS]
-    s, f, g, l0 = gpu_elements(probs, K, p, gamma=gamma, alpha=0.16, smoother=FEM,
+    s, f, g, l0 = gpu_elements(probs, K, p, gamma=gamma, alpha=alpha, smoother=sm,
                                restriction=rst)
     torch.cuda.synchronize()
-    ors = [oracle_elements(pr, K, p, gamma=gamma, restriction=rst) for pr in probs]
-    return dict(K=K, p=p, l0=l0, s=s, f=f, g=g, ors=ors, probs=probs, gamma=gamma)
+    ors = [oracle_elements(pr, K, p, gamma=gamma, alpha=alpha, restriction=rst, smoother=sm)
+           for pr in probs]
+    return dict(K=K, p=p, l0=l0, s=s, f=f, g=g, ors=ors, probs=probs, gamma=gamma, sm=sm)
 
 
 def _levels(case):
@@ -90,10 +98,22 @@ def _rand_interior(p, B, seed):
     return np.where(m[None, :], rng.standard_normal((B, (p + 1) ** 2)), 0.0)
 
 
-def _line_kappa(h, lo_, d, p):
+def _line_kappa(h, lo_, d, p, band=False):
+    """Largest condition number of the level's line matrices (tridiagonal,
+    or half-bandwidth 2)."""
     n = p - 1
-    lo, di, up = h.line_coefs(d, lo_)
     kmax = 1.0
+    if band:
+        bd = h.line_band(d, lo_)
+        for line in range(n):
+            M = np.zeros((n, n))
+            for s_ in range(n):
+                for k in range(-2, 3):
+                    if 0 <= s_ + k < n:
+                        M[s_, s_ + k] = bd[line, s_, k + 2]
+            kmax = max(kmax, np.linalg.cond(M))
+        return kmax
+    lo, di, up = h.line_coefs(d, lo_)
     for line in range(n):
         sl = slice(line * n, (line + 1) * n)
         M = np.diag(di[sl]) + np.diag(lo[sl][1:], -1) + np.diag(up[sl][:-1], 1)
@@ -141,6 +161,17 @@ def test_line_coefs(case):
     B = len(SEEDS)
     for l, lo_, p in _levels(case):
         n = (p - 1) ** 2
+        if case["sm"] == BAND2:
+            for d in range(2):
+                band = torch.empty((B, p - 1, p - 1, 5), dtype=torch.float64, device="cuda")
+                pmg.pmg_line_band(s.h, l, d, band)
+                torch.cuda.synchronize()
+                for b, (h, _, _) in enumerate(case["ors"]):
+                    ob = h.line_band(d, lo_)
+                    err = np.abs(band.cpu().numpy()[b] - ob).max() / np.abs(ob).max()
+                    print(f"[elements band] p={p} dir={d} b={b} rel err {err:.2e}")
+                    assert err <= 1e-12, (l, d, b, err)
+            continue
         for d in range(2):
             lo, di, up = (torch.empty((B, n), dtype=torch.float64, device="cuda") for _ in range(3))
             pmg.pmg_line_coefs(s.h, l, d, lo, di, up)
@@ -201,7 +232,7 @@ def test_line_solve_and_smooth(case):
             pmg.pmg_line_smooth(s.h, l, d, pmg.PMG_F64, torch.from_numpy(r).cuda(), xs)
             torch.cuda.synchronize()
             for b, (h, _, _) in enumerate(case["ors"]):
-                kap = _line_kappa(h, lo_, d, p)
+                kap = _line_kappa(h, lo_, d, p, case["sm"] == BAND2)
                 tol = max(1e-12, 20 * (p - 1) * np.finfo(float).eps * kap)
                 err = rel_err(z.cpu().numpy()[b], h.line_solve(r[b], d, lo_))
                 tol2 = tol + kap * op_tol(p)
@@ -221,6 +252,32 @@ def test_gamma_cycle(case):
         err = rel_err(y.cpu().numpy()[b], h.cycle(r[b]))
         print(f"[elements cycle] K={case['K']} p={p} gamma={case['gamma']} b={b} rel err {err:.2e}")
         assert err < 1e-10, (b, err)
+
+
+def test_band2_full_size():
+    """4 x 4 elements of degree 32 with the half-bandwidth-2 GLL line systems
+    of the assembled operator (alpha = 2/3), gamma = 3: iterations within +-1
+    of the oracle's, solution within 1e-7."""
+    K, p = 4, 128
+    probs = [inputs.config2(s, 0.1) for s in (31,)]
+    s, f, g, _ = gpu_elements(probs, K, p, gamma=3, alpha=2.0 / 3.0, smoother=BAND2)
+    bt = torch.empty_like(f)
+    pmg.pmg_rhs(s.h, f, g, bt)
+    x = torch.empty_like(bt)
+    pmg.pmg_solve(s.h, bt, x, s.info)
+    torch.cuda.synchronize()
+    info = s.info_host()
+    h, fo, go = oracle_elements(probs[0], K, p, gamma=3, alpha=2.0 / 3.0,
+                                smoother=orc.SMOOTHER_GLL_BAND2)
+    bo = h.rhs(fo, go)
+    xg = x.cpu().numpy()[0]
+    rr = np.linalg.norm(bo - h.apply(xg)) / np.linalg.norm(bo)
+    xo, st, it, _ = h.fgmres(bo, rtol=1e-10, maxit=200)
+    ex = rel_err(xg, xo)
+    print(f"[elements band2 full] its gpu {info['iterations'][0]} oracle {it} "
+          f"oracle-operator relres {rr:.3e} err vs oracle {ex:.2e}")
+    assert info["status"][0] == 0 and rr <= 1.0001e-10 and st == 0
+    assert abs(int(info["iterations"][0]) - it) <= 1 and ex < 1e-7
 
 
 def test_rhs_and_solve(case):
