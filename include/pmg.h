@@ -96,10 +96,11 @@ enum { PMG_RESTRICT_TRANSPOSE = 0, PMG_RESTRICT_INTERP = 1 };
  *              boundary rows are zero either way; P_l is the interpolation
  *              of the coarse polynomial at the fine nodes in both.
  *   elements   K spectral elements per axis (0 or 1: the one element of the
- *              paper; 2, 4 or 8: the multi-element hp-multigrid of the
- *              paper's closing outlook, 2-D, any line smoother).  The square
- *              is split into K x K equal parts of the reference square,
- *              each an element of degree p_l / K with its own GLL rule; an
+ *              paper; 2, 4 or 8 in 2-D, 2 or 4 in 3-D: the multi-element
+ *              hp-multigrid of the paper's closing outlook, any line
+ *              smoother).  The square (cube) is split into K^dim equal
+ *              parts of the reference square (cube), each an element of
+ *              degree p_l / K with its own GLL rule; an
  *              interface node is shared by the elements that meet there
  *              (continuous basis), the operator and the mass are the sums
  *              of the element ones, and the transfers interpolate element
@@ -109,7 +110,7 @@ enum { PMG_RESTRICT_TRANSPOSE = 0, PMG_RESTRICT_INTERP = 1 };
  *              axis.  The levels halve the element degree down to 2, so the
  *              coarsest level has degree 2K (level index log2(2K) - 1; the
  *              levels below it are absent) and is solved exactly with the
- *              inverse of its (2K-1)^2 x (2K-1)^2 interior matrix, built at
+ *              inverse of its (2K-1)^dim x (2K-1)^dim interior matrix, built at
  *              setup in FP64.  Line systems run along the composite grid
  *              lines across element interfaces (GLL rows: entries of the
  *              assembled operator; FEM rows: the composite node mesh). */
@@ -290,8 +291,8 @@ int pmg_line_band(pmg_handle* h, int level, int dir, double* d_band, pmg_stream_
 /* Geometric factors of level l: d_G B x ncomp x N_l doubles (ncomp = 3 in
  * 2-D: G_00, G_11, G_01; 6 in 3-D: G_00, G_11, G_22, G_01, G_02, G_12) and
  * d_mass B x N_l doubles (may be NULL).  K elements per axis: d_G holds per
- * problem the K^2 elements in lexicographic order (first axis fastest),
- * each ncomp x (p_l/K + 1)^2 doubles at its element nodes, and the mass is
+ * problem the K^dim elements in lexicographic order (first axis fastest),
+ * each ncomp x (p_l/K + 1)^dim doubles at its element nodes, and the mass is
  * the assembled one at the composite nodes. */
 int pmg_geom(pmg_handle* h, int level, double* d_G, double* d_mass, pmg_stream_t stream);
 

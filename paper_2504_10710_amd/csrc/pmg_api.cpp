@@ -206,7 +206,9 @@ int check_desc(const pmg_desc* d)
     if (d->elements < 0 || d->elements > 8 || (d->elements > 1 && !is_pow2(d->elements)))
         return fail(PMG_EINVAL, "elements must be 0, 1, 2, 4 or 8 (got %d)", d->elements);
     if (d->elements > 1) {
-        if (d->dim != 2) return fail(PMG_EINVAL, "several elements per axis are supported in 2-D");
+        if (d->dim == 3 && d->elements > 4)
+            return fail(PMG_EINVAL, "3-D supports up to 4 elements per axis (the coarsest level's "
+                                    "exact inverse grows as (2K-1)^6)");
         if (d->p_fine / d->elements < 4)
             return fail(PMG_EINVAL, "the finest element degree p_fine / elements must be >= 4 "
                                     "(got %d / %d)", d->p_fine, d->elements);
@@ -292,7 +294,8 @@ long long elem_nodes(const pmg_handle* h, int l)
     const LevelShape s = level_shape(h->d.dim, l);
     if (h->K == 1) return s.N;
     const long long ne1 = s.p / h->K + 1;
-    return (long long)h->K * h->K * ne1 * ne1;
+    return h->d.dim == 2 ? (long long)h->K * h->K * ne1 * ne1
+                         : (long long)h->K * h->K * h->K * ne1 * ne1 * ne1;
 }
 
 void plan(pmg_handle* h, std::vector<pmg_region>* rec = nullptr)

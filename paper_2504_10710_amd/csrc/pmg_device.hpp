@@ -755,6 +755,76 @@ __device__ void apply2d_elements(int K, const T* __restrict__ G_, const T* __res
     wg_barrier();
 }
 
+// The same in 3-D (K^3 elements of degree pe, per element G00, G11, G22,
+// G01, G02, G12 arrays of NE = ne1^3 element nodes, fluxes 3 NE): pass 1 the
+// three reference gradients and the fluxes per element node, pass 2 per
+// global node the sum over the (up to eight) elements holding it.
+template <class T, int P, bool RESID>
+__device__ void apply3d_elements(int K, const T* __restrict__ G_, const T* __restrict__ D_,
+                                 T* __restrict__ TR_, const T* __restrict__ x_,
+                                 const T* __restrict__ r_, T* __restrict__ out_)
+{
+    const auto G = gmem(G_);
+    const auto D = gmem(D_);
+    const auto TR = gmem(TR_);
+    const auto x = gmem(x_);
+    const auto r = gmem(r_);
+    const auto out = gmem(out_);
+    constexpr int n1 = P + 1, N = n1 * n1 * n1;
+    const int pe = P / K, ne1 = pe + 1, NE = ne1 * ne1 * ne1;
+    const int gst[3] = {1, n1, n1 * n1};
+    const int est[3] = {1, ne1, ne1 * ne1};
+    for (int t = threadIdx.x; t < K * K * K * NE; t += NT) {
+        const int e = t / NE, lq = t - e * NE;
+        const int c[3] = {lq % ne1, (lq / ne1) % ne1, lq / (ne1 * ne1)};
+        const int eo[3] = {(e % K) * pe, ((e / K) % K) * pe, (e / (K * K)) * pe};
+        const int g0 = (eo[0] + c[0]) + (eo[1] + c[1]) * n1 + (eo[2] + c[2]) * n1 * n1;
+        T g[3];
+        for (int a = 0; a < 3; ++a) {
+            const int gb = g0 - c[a] * gst[a];
+            T sum = 0;
+            for (int k = 0; k < ne1; ++k) sum += D[c[a] * ne1 + k] * x[gb + k * gst[a]];
+            g[a] = sum;
+        }
+        const auto Ge = G + 6LL * NE * e;
+        const T g00 = Ge[lq], g11 = Ge[NE + lq], g22 = Ge[2 * NE + lq];
+        const T g01 = Ge[3 * NE + lq], g02 = Ge[4 * NE + lq], g12 = Ge[5 * NE + lq];
+        const auto f = TR + 3LL * NE * e;
+        f[lq] = g00 * g[0] + g01 * g[1] + g02 * g[2];
+        f[NE + lq] = g01 * g[0] + g11 * g[1] + g12 * g[2];
+        f[2 * NE + lq] = g02 * g[0] + g12 * g[1] + g22 * g[2];
+    }
+    wg_barrier();
+    for (int q = threadIdx.x; q < N; q += NT) {
+        const int I[3] = {q % n1, (q / n1) % n1, q / (n1 * n1)};
+        if (I[0] == 0 || I[0] == P || I[1] == 0 || I[1] == P || I[2] == 0 || I[2] == P) {
+            out[q] = T(0);
+            continue;
+        }
+        int e0[3], e1[3];
+        for (int a = 0; a < 3; ++a) {
+            e1[a] = I[a] / pe;
+            e0[a] = I[a] % pe == 0 ? e1[a] - 1 : e1[a];
+        }
+        T y = 0;
+        for (int ez = e0[2]; ez <= e1[2]; ++ez)
+            for (int ey = e0[1]; ey <= e1[1]; ++ey)
+                for (int ex = e0[0]; ex <= e1[0]; ++ex) {
+                    const int e = ex + K * (ey + K * ez);
+                    const int c[3] = {I[0] - ex * pe, I[1] - ey * pe, I[2] - ez * pe};
+                    const int lq = c[0] + c[1] * ne1 + c[2] * ne1 * ne1;
+                    const auto f = TR + 3LL * NE * e;
+                    for (int a = 0; a < 3; ++a) {
+                        const int lb = lq - c[a] * est[a];
+                        for (int k = 0; k < ne1; ++k)
+                            y += D[k * ne1 + c[a]] * f[(long long)a * NE + lb + k * est[a]];
+                    }
+                }
+        out[q] = RESID ? r[q] - y : y;
+    }
+    wg_barrier();
+}
+
 // The element operator on the matrix cores (element degree PE = P / K, a
 // multiple of 16): the elements' nodal values are first copied into the
 // element-local array EX (interface nodes once per element); each element is
@@ -926,6 +996,12 @@ __device__ __attribute__((noinline)) void apply_level(const T* __restrict__ G_,
                 }
             }
             apply2d_elements<T, P, RESID>(K, G_, D_, TR_, x_, r_, out_);
+            return;
+        }
+    }
+    if constexpr (DIM == 3 && P >= 4) {
+        if (K > 1) {
+            apply3d_elements<T, P, RESID>(K, G_, D_, TR_, x_, r_, out_);
             return;
         }
     }

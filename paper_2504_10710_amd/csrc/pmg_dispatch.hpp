@@ -49,6 +49,19 @@
         }                                                              \
     } while (0)
 
+// 3-D degrees 4..64 only (levels of several elements per axis)
+#define PMG_DISPATCH_P3D(p, ...)                                      \
+    do {                                                               \
+        switch (p) {                                                   \
+        case 4: { constexpr int P_ = 4; __VA_ARGS__; } break;          \
+        case 8: { constexpr int P_ = 8; __VA_ARGS__; } break;          \
+        case 16: { constexpr int P_ = 16; __VA_ARGS__; } break;        \
+        case 32: { constexpr int P_ = 32; __VA_ARGS__; } break;        \
+        case 64: { constexpr int P_ = 64; __VA_ARGS__; } break;        \
+        default: return hipErrorInvalidValue;                          \
+        }                                                              \
+    } while (0)
+
 // same, p >= 4 only (operations that need a coarser level)
 #define PMG_DISPATCH_P4(dim, p, ...)                                  \
     do {                                                               \

@@ -410,6 +410,51 @@ __device__ double elements_entry2d(int K, const double* __restrict__ Gb_, const 
     return v;
 }
 
+// The same in 3-D: K^3 elements, per element the six arrays G00, G11, G22,
+// G01, G02, G12 of NE = ne1^3 element nodes.
+template <int P>
+__device__ double elements_entry3d(int K, const double* __restrict__ Gb_, const double* __restrict__ D_,
+                                   const int* r, const int* c)
+{
+    const auto Gb = gmem(Gb_);
+    const auto D = gmem(D_);
+    const int pe = P / K, ne1 = pe + 1, NE = ne1 * ne1 * ne1;
+    auto lo_of = [&](int I) { return (I % pe == 0 && I > 0) ? I / pe - 1 : min(I / pe, K - 1); };
+    auto hi_of = [&](int I) { return min(I / pe, K - 1); };
+    int e0[3], e1[3];
+    for (int a = 0; a < 3; ++a) {
+        e0[a] = max(lo_of(r[a]), lo_of(c[a]));
+        e1[a] = min(hi_of(r[a]), hi_of(c[a]));
+    }
+    double v = 0.0;
+    for (int ez = e0[2]; ez <= e1[2]; ++ez)
+        for (int ey = e0[1]; ey <= e1[1]; ++ey)
+            for (int ex = e0[0]; ex <= e1[0]; ++ex) {
+                const int e = ex + K * (ey + K * ez);
+                const int eo[3] = {ex * pe, ey * pe, ez * pe};
+                int lr[3], lc[3];
+                for (int a = 0; a < 3; ++a) {
+                    lr[a] = r[a] - eo[a];
+                    lc[a] = c[a] - eo[a];
+                }
+                const auto Ge = Gb + 6LL * NE * e;
+                for (int a = 0; a < 3; ++a)
+                    for (int k = 0; k < ne1; ++k) {
+                        int qc[3] = {lr[0], lr[1], lr[2]};
+                        qc[a] = k;
+                        const double da = D[k * ne1 + lr[a]];
+                        const int q = qc[0] + ne1 * (qc[1] + ne1 * qc[2]);
+                        for (int bb = 0; bb < 3; ++bb) {
+                            bool match = true;
+                            for (int f = 0; f < 3; ++f)
+                                if (f != bb && qc[f] != lc[f]) match = false;
+                            if (match) v += Ge[gidx(3, a, bb) * NE + q] * da * D[qc[bb] * ne1 + lc[bb]];
+                        }
+                    }
+            }
+    return v;
+}
+
 // per-problem offset of a level's geometric factors: N nodes, or the
 // K^2 (P/K + 1)^2 element nodes of K x K elements
 template <int P, int DIM>
@@ -417,7 +462,7 @@ __host__ __device__ inline long long geom_nodes(int K)
 {
     if (K <= 1) return Shape<P, DIM>::N;
     const long long ne1 = P / K + 1;
-    return (long long)K * K * ne1 * ne1;
+    return DIM == 2 ? (long long)K * K * ne1 * ne1 : (long long)K * K * K * ne1 * ne1 * ne1;
 }
 
 template <int P, int DIM>
@@ -438,6 +483,16 @@ __device__ void line_raw(const double* Gb, const double* Xb, const double* D, in
             a = elements_entry2d<P>(K, Gb, D, c, c);
             l = s > 0 ? elements_entry2d<P>(K, Gb, D, c, cl) : 0.0;
             u = s < n - 1 ? elements_entry2d<P>(K, Gb, D, c, cu) : 0.0;
+            return;
+        }
+    } else {
+        if (K > 1 && smoother != PMG_SMOOTHER_FEM) {
+            int cl[3] = {c[0], c[1], c[2]}, cu[3] = {c[0], c[1], c[2]};
+            cl[dir] -= 1;
+            cu[dir] += 1;
+            a = elements_entry3d<P>(K, Gb, D, c, c);
+            l = s > 0 ? elements_entry3d<P>(K, Gb, D, c, cl) : 0.0;
+            u = s < n - 1 ? elements_entry3d<P>(K, Gb, D, c, cu) : 0.0;
             return;
         }
     }
@@ -509,6 +564,10 @@ __global__ void __launch_bounds__(NT) k_lines(const double* __restrict__ G,
                         int c2[2] = {c[0], c[1]};
                         c2[dir] += k;
                         v = elements_entry2d<P>(K, Gb, D, c, c2);
+                    } else if (K > 1) {
+                        int c2[3] = {c[0], c[1], c[2]};
+                        c2[dir] += k;
+                        v = elements_entry3d<P>(K, Gb, D, c, c2);
                     } else {
                         v = gll_entry<P, DIM>(Gb, D, q, c, dir, k);
                     }
@@ -744,6 +803,105 @@ __global__ void __launch_bounds__(NT) k_geom_elements(int K, const double* __res
     if (threadIdx.x == 0) detmin[b] = mn;
 }
 
+// Geometry of a level of K^3 elements (3-D): the one-element formulas per
+// element node (Jacobian by the element's D on the element block of the
+// composite coordinates, adjugate inverse), G in the six-array element layout;
+// the assembled mass per global node (the weights of the elements holding it,
+// in element order).
+template <int P>
+__global__ void __launch_bounds__(NT) k_geom_elements3d(int K, const double* __restrict__ coords,
+                                                        const double* __restrict__ rho_,
+                                                        const double* __restrict__ D_,
+                                                        double* __restrict__ G, float* __restrict__ G32,
+                                                        double* __restrict__ mass,
+                                                        double* __restrict__ X64,
+                                                        double* __restrict__ detmin,
+                                                        const int* slots, int* pivot)
+{
+    constexpr int n1 = P + 1, N = n1 * n1 * n1;
+    const int pe = P / K, ne1 = pe + 1, NE = ne1 * ne1 * ne1, NEt = K * K * K * NE;
+    __shared__ double red[NT];
+    const long long b = slots ? slots[blockIdx.x] : blockIdx.x;
+    if (pivot && threadIdx.x == 0) pivot[b] = 0;
+    const auto X = gmem(coords + b * 3 * N);
+    const auto D = gmem(D_);
+    const auto rho = gmem(rho_);
+    const auto Gb = gmem(G + b * 6 * NEt);
+    const auto G32b = G32 ? gmem(G32 + b * 6 * NEt) : nullptr;
+    const auto Xo = gmem(X64 + b * 3 * N);
+    for (int q = threadIdx.x; q < 3 * N; q += NT) Xo[q] = X[q];
+    const int gst[3] = {1, n1, n1 * n1};
+    // Jacobian Jm[comp][a] at element node c of the element at offset eo
+    auto jac = [&](const int (&eo)[3], const int (&c)[3], double (&Jm)[3][3]) {
+        const int g0 = (eo[0] + c[0]) + (eo[1] + c[1]) * n1 + (eo[2] + c[2]) * n1 * n1;
+        for (int comp = 0; comp < 3; ++comp) {
+            const auto Xc = X + comp * N;
+            for (int a = 0; a < 3; ++a) {
+                const int gb = g0 - c[a] * gst[a];
+                double sum = 0.0;
+                for (int k = 0; k < ne1; ++k) sum += D[c[a] * ne1 + k] * Xc[gb + k * gst[a]];
+                Jm[comp][a] = sum;
+            }
+        }
+        const double c00 = Jm[1][1] * Jm[2][2] - Jm[1][2] * Jm[2][1];
+        const double c01 = Jm[1][2] * Jm[2][0] - Jm[1][0] * Jm[2][2];
+        const double c02 = Jm[1][0] * Jm[2][1] - Jm[1][1] * Jm[2][0];
+        return Jm[0][0] * c00 + Jm[0][1] * c01 + Jm[0][2] * c02;
+    };
+    double dmin = INFINITY;
+    for (int t = threadIdx.x; t < NEt; t += NT) {
+        const int e = t / NE, lq = t - e * NE;
+        const int c[3] = {lq % ne1, (lq / ne1) % ne1, lq / (ne1 * ne1)};
+        const int eo[3] = {(e % K) * pe, ((e / K) % K) * pe, (e / (K * K)) * pe};
+        double Jm[3][3];
+        const double det = jac(eo, c, Jm);
+        dmin = fmin(dmin, det);
+        const double id = 1.0 / det;
+        double inv[3][3];   // inv[a][comp] = d xi_a / d x_comp
+        inv[0][0] = (Jm[1][1] * Jm[2][2] - Jm[1][2] * Jm[2][1]) * id;
+        inv[1][0] = (Jm[1][2] * Jm[2][0] - Jm[1][0] * Jm[2][2]) * id;
+        inv[2][0] = (Jm[1][0] * Jm[2][1] - Jm[1][1] * Jm[2][0]) * id;
+        inv[0][1] = (Jm[0][2] * Jm[2][1] - Jm[0][1] * Jm[2][2]) * id;
+        inv[1][1] = (Jm[0][0] * Jm[2][2] - Jm[0][2] * Jm[2][0]) * id;
+        inv[2][1] = (Jm[0][1] * Jm[2][0] - Jm[0][0] * Jm[2][1]) * id;
+        inv[0][2] = (Jm[0][1] * Jm[1][2] - Jm[0][2] * Jm[1][1]) * id;
+        inv[1][2] = (Jm[0][2] * Jm[1][0] - Jm[0][0] * Jm[1][2]) * id;
+        inv[2][2] = (Jm[0][0] * Jm[1][1] - Jm[0][1] * Jm[1][0]) * id;
+        const double phi = rho[c[0]] * rho[c[1]] * rho[c[2]] * det;
+        for (int a = 0; a < 3; ++a)
+            for (int bb = a; bb < 3; ++bb) {
+                const double v = phi * (inv[a][0] * inv[bb][0] + inv[a][1] * inv[bb][1] +
+                                        inv[a][2] * inv[bb][2]);
+                const int gi = gidx(3, a, bb);
+                Gb[6LL * NE * e + gi * NE + lq] = v;
+                if (G32b) G32b[6LL * NE * e + gi * NE + lq] = (float)v;
+            }
+    }
+    if (mass) {
+        const auto massb = gmem(mass + b * N);
+        for (int q = threadIdx.x; q < N; q += NT) {
+            const int I[3] = {q % n1, (q / n1) % n1, q / (n1 * n1)};
+            int e0[3], e1[3];
+            for (int a = 0; a < 3; ++a) {
+                e1[a] = min(I[a] / pe, K - 1);
+                e0[a] = (I[a] % pe == 0 && I[a] > 0) ? I[a] / pe - 1 : e1[a];
+            }
+            double m = 0.0;
+            for (int ez = e0[2]; ez <= e1[2]; ++ez)
+                for (int ey = e0[1]; ey <= e1[1]; ++ey)
+                    for (int ex = e0[0]; ex <= e1[0]; ++ex) {
+                        const int eo[3] = {ex * pe, ey * pe, ez * pe};
+                        const int c[3] = {I[0] - eo[0], I[1] - eo[1], I[2] - eo[2]};
+                        double Jm[3][3];
+                        m += rho[c[0]] * rho[c[1]] * rho[c[2]] * jac(eo, c, Jm);
+                    }
+            massb[q] = m;
+        }
+    }
+    const double mn = wg_min(dmin, red);
+    if (threadIdx.x == 0) detmin[b] = mn;
+}
+
 // Exact solve on the coarsest level of K x K elements (degree P = 2K, ni =
 // (P-1)^2 interior nodes): the interior matrix of the assembled operator,
 // entry by entry (the element quadrature sums of eq. discreteBilinear over
@@ -751,21 +909,26 @@ __global__ void __launch_bounds__(NT) k_geom_elements(int K, const double* __res
 // elimination in place (symmetric positive definite: no pivoting; a pivot
 // that is not positive flags the problem), stored for collapsed_solve as
 // C[i ni + j] = (A^{-1})[j][i].
-template <int P>
+template <int P, int DIM>
 __global__ void __launch_bounds__(NT) k_elements_coarse(int K, const double* __restrict__ G,
                                                         const double* __restrict__ D_,
                                                         double* __restrict__ Cc, const int* slots,
                                                         int* pivot)
 {
-    constexpr int n = P - 1, ni = n * n;
-    const int pe = P / K, ne1 = pe + 1, NE = ne1 * ne1;
+    constexpr int n = P - 1, ni = DIM == 2 ? n * n : n * n * n;
     const long long b = slots ? slots[blockIdx.x] : blockIdx.x;
     const auto A = gmem(Cc + b * (long long)ni * ni);
-    const double* Gb = G + b * 3LL * K * K * NE;
+    const double* Gb = G + b * (DIM == 2 ? 3LL : 6LL) * geom_nodes<P, DIM>(K);
     for (int t = threadIdx.x; t < ni * ni; t += NT) {
         const int row = t / ni, col = t - row * ni;
-        const int r[2] = {row % n + 1, row / n + 1}, c[2] = {col % n + 1, col / n + 1};
-        A[t] = elements_entry2d<P>(K, Gb, D_, r, c);
+        if constexpr (DIM == 2) {
+            const int r[2] = {row % n + 1, row / n + 1}, c[2] = {col % n + 1, col / n + 1};
+            A[t] = elements_entry2d<P>(K, Gb, D_, r, c);
+        } else {
+            const int r[3] = {row % n + 1, (row / n) % n + 1, row / (n * n) + 1};
+            const int c[3] = {col % n + 1, (col / n) % n + 1, col / (n * n) + 1};
+            A[t] = elements_entry3d<P>(K, Gb, D_, r, c);
+        }
     }
     wg_barrier();
     bool bad = false;
@@ -942,9 +1105,14 @@ hipError_t launch_setup(int dim, int p_fine, int nlev, int B, const SetupArgs& a
     for (int l = a.l0; l < nlev; ++l) {
         const int p = 2 << l;
         double* mass = (p == p_fine) ? a.mass : nullptr;
-        if (a.K > 1) {
-            if (dim != 2) return hipErrorInvalidValue;
+        if (a.K > 1 && dim == 2) {
             PMG_DISPATCH_P2D(p, hipLaunchKernelGGL((k_geom_elements<P_>), dim3(nb), dim3(NT), 0, s,
+                                                   a.K, a.coords[l], a.rho[l], a.D64[l], a.G64[l],
+                                                   a.G32[l], mass, a.X64[l],
+                                                   a.detmin + (long long)l * B, a.slots,
+                                                   l == a.l0 ? a.pivot : nullptr));
+        } else if (a.K > 1) {
+            PMG_DISPATCH_P3D(p, hipLaunchKernelGGL((k_geom_elements3d<P_>), dim3(nb), dim3(NT), 0, s,
                                                    a.K, a.coords[l], a.rho[l], a.D64[l], a.G64[l],
                                                    a.G32[l], mass, a.X64[l],
                                                    a.detmin + (long long)l * B, a.slots,
@@ -969,15 +1137,17 @@ hipError_t launch_setup(int dim, int p_fine, int nlev, int B, const SetupArgs& a
     if (a.K > 1) {
         // the coarsest level's exact inverse (degree 2K), after its geometry
         const int p0 = 2 << a.l0;
-        switch (p0) {
-#define PMG_COARSE(PC)                                                                          \
-    case PC:                                                                                    \
-        hipLaunchKernelGGL((k_elements_coarse<PC>), dim3(nb), dim3(NT), 0, s, a.K, a.G64[a.l0], \
-                           a.D64[a.l0], a.Cc0, a.slots, a.pivot);                               \
+        switch (dim * 100 + p0) {
+#define PMG_COARSE(DM, PC)                                                                      \
+    case DM * 100 + PC:                                                                         \
+        hipLaunchKernelGGL((k_elements_coarse<PC, DM>), dim3(nb), dim3(NT), 0, s, a.K,          \
+                           a.G64[a.l0], a.D64[a.l0], a.Cc0, a.slots, a.pivot);                  \
         break;
-            PMG_COARSE(4)
-            PMG_COARSE(8)
-            PMG_COARSE(16)
+            PMG_COARSE(2, 4)
+            PMG_COARSE(2, 8)
+            PMG_COARSE(2, 16)
+            PMG_COARSE(3, 4)
+            PMG_COARSE(3, 8)
 #undef PMG_COARSE
         default: return hipErrorInvalidValue;
         }

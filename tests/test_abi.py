@@ -130,15 +130,16 @@ def test_workspace_layout_in_bounds(kw):
         assert furthest + esz <= total
 
 
-@pytest.mark.parametrize("K,p,prec", [(2, 16, pmg.PMG_F64), (4, 128, pmg.PMG_F64),
-                                      (8, 64, pmg.PMG_F32), (4, 256, pmg.PMG_F32)])
-def test_element_workspace_layout(K, p, prec):
+@pytest.mark.parametrize("dim,K,p,prec", [(2, 2, 16, pmg.PMG_F64), (2, 4, 128, pmg.PMG_F64),
+                                          (2, 8, 64, pmg.PMG_F32), (2, 4, 256, pmg.PMG_F32),
+                                          (3, 2, 16, pmg.PMG_F64), (3, 4, 64, pmg.PMG_F32)])
+def test_element_workspace_layout(dim, K, p, prec):
     """Several elements per axis: levels below degree 2K are absent; the
-    geometric factors and fluxes of a level hold K^2 (p_l/K + 1)^2 element
-    nodes per problem; the coarsest level holds its (2K-1)^2 square exact
+    geometric factors and fluxes of a level hold K^dim (p_l/K + 1)^dim element
+    nodes per problem; the coarsest level holds its (2K-1)^dim square exact
     inverse; every region in bounds, aligned, without overlap."""
     B = 3
-    desc = pmg.make_desc(dim=2, p_fine=p, batch=B, elements=K, smoother=pmg.PMG_SMOOTHER_FEM,
+    desc = pmg.make_desc(dim=dim, p_fine=p, batch=B, elements=K, smoother=pmg.PMG_SMOOTHER_FEM,
                          inner_prec=prec)
     l0 = pmg.pmg_first_level(desc)
     assert l0 == int(np.log2(2 * K)) - 1
@@ -158,16 +159,17 @@ def test_element_workspace_layout(K, p, prec):
         if not present:
             continue
         pl = 2 << l
-        ng = K * K * (pl // K + 1) ** 2
-        assert lev[f"G64[{l}]"] == 8 * B * 3 * ng
-        assert lev[f"TR[{l}]"] == tsz * B * 2 * ng
-        assert lev[f"X[{l}]"] == tsz * B * (pl + 1) ** 2
-    ni = (2 * K - 1) ** 2
+        ng = K ** dim * (pl // K + 1) ** dim
+        ncomp = 3 if dim == 2 else 6
+        assert lev[f"G64[{l}]"] == 8 * B * ncomp * ng
+        assert lev[f"TR[{l}]"] == tsz * B * dim * ng
+        assert lev[f"X[{l}]"] == tsz * B * (pl + 1) ** dim
+    ni = (2 * K - 1) ** dim
     cc = [n for n in lev if n.startswith("Cc")]
     assert cc == [f"Cc[{l0}]"] and lev[cc[0]] == 8 * B * ni * ni
 
 
-@pytest.mark.parametrize("kw", [dict(elements=3, p_fine=48), dict(elements=2, dim=3, p_fine=16),
+@pytest.mark.parametrize("kw", [dict(elements=3, p_fine=48), dict(elements=8, dim=3, p_fine=64),
                                 dict(elements=4, p_fine=8),
                                 dict(elements=16, p_fine=64), dict(elements=-1, p_fine=16)])
 def test_element_descriptions_rejected(kw):

@@ -34,9 +34,9 @@ def element_degrees(p_fine, K):
     return out[::-1]                       # coarsest first
 
 
-def gpu_elements(probs, K, p_fine, device="cuda", **kw):
-    """Solver for K x K elements; coordinates of the present levels only."""
-    desc = pmg.make_desc(dim=2, p_fine=p_fine, batch=len(probs), elements=K, **kw)
+def gpu_elements(probs, K, p_fine, device="cuda", dim=2, **kw):
+    """Solver for K^dim elements; coordinates of the present levels only."""
+    desc = pmg.make_desc(dim=dim, p_fine=p_fine, batch=len(probs), elements=K, **kw)
     nlev, l0 = pmg.pmg_num_levels(desc), pmg.pmg_first_level(desc)
     coords = [None] * nlev
     for i, pe in enumerate(element_degrees(p_fine, K)):
@@ -369,5 +369,101 @@ def test_elements_full_size():
         ex = rel_err(xg, xo)
         print(f"[elements full] K={K} p={p} b={b} its gpu {info['iterations'][b]} oracle {it} "
               f"oracle-operator relres {rr:.3e} err vs oracle {ex:.2e}")
+        assert info["status"][b] == 0 and rr <= 1.0001e-10 and st == 0
+        assert abs(int(info["iterations"][b]) - it) <= 1 and ex < 1e-7
+
+
+# ---------------------------------------------------------------- 3-D elements
+
+def oracle_elements3(prob, K, p_fine, gamma, alpha, restriction, smoother):
+    pes = element_degrees(p_fine, K)
+    coords = [prob.coords(inputs.composite_nodes(orc.gll(pe)[0], K)) for pe in pes]
+    h = orc.Hier(3, [K * pe for pe in pes], coords, gamma=gamma, m=1, alpha=alpha,
+                 smoother=smoother, restriction=restriction, elements=K)
+    X = coords[-1]
+    return h, prob.f(X), prob.g(X)
+
+
+CASES3 = [(2, 16, 1, pmg.PMG_RESTRICT_TRANSPOSE, FEM, 0.16),
+          (4, 32, 2, pmg.PMG_RESTRICT_INTERP, FEM, 0.16),
+          (2, 16, 1, pmg.PMG_RESTRICT_TRANSPOSE, GLL, 2.0 / 3.0),
+          (2, 16, 1, pmg.PMG_RESTRICT_TRANSPOSE, BAND2, 2.0 / 3.0)]
+SEEDS3 = [0, 1]
+
+
+@pytest.fixture(scope="module", params=CASES3,
+                ids=lambda c: f"3d-K{c[0]}-p{c[1]}-g{c[2]}-{'interp' if c[3] else 'PT'}-{SM_NAME[c[4]]}")
+def case3(request):
+    K, p, gamma, rst, sm, alpha = request.param
+    print(f"[gpu elements 3-D] K={K} p={p} gamma={gamma} restriction={rst} smoother={sm}",
+          flush=True)
+    probs = [inputs.config3(s) for s in SEEDS3]
+    s, f, g, l0 = gpu_elements(probs, K, p, gamma=gamma, alpha=alpha, smoother=sm,
+                               restriction=rst, restart=20, dim=3)
+    torch.cuda.synchronize()
+    ors = [oracle_elements3(pr, K, p, gamma, alpha, rst, sm) for pr in probs]
+    return dict(K=K, p=p, l0=l0, s=s, f=f, g=g, ors=ors, gamma=gamma, sm=sm)
+
+
+def test_3d_geometry_operator_transfers(case3):
+    s, K, l0 = case3["s"], case3["K"], case3["l0"]
+    B = len(SEEDS3)
+    info = s.info_host()
+    assert np.all(info["status"] == 0), info
+    pairs = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
+    for l in range(l0, s.nlev):
+        p, lo_ = 2 << l, l - l0
+        NE = (p // K + 1) ** 3
+        G = torch.empty((B, K ** 3, 6, NE), dtype=torch.float64, device="cuda")
+        pmg.pmg_geom(s.h, l, G)
+        x = np.stack([np.random.default_rng(60 + l + b).standard_normal((p + 1) ** 3)
+                      for b in range(B)])
+        m = interior_mask(3, p)
+        x = np.where(m[None, :], x, 0.0)
+        y = torch.empty((B, (p + 1) ** 3), dtype=torch.float64, device="cuda")
+        pmg.pmg_apply(s.h, l, pmg.PMG_F64, torch.from_numpy(x).cuda(), y)
+        torch.cuda.synchronize()
+        for b, (h, _, _) in enumerate(case3["ors"]):
+            Go = h.geom_elements(lo_)
+            for k, (a, c) in enumerate(pairs):
+                eg = rel_err(G.cpu().numpy()[b, :, k], Go[:, a, c])
+                tg = 1e-12 * max(1.0, np.abs(Go[:, a, a]).max() / max(np.abs(Go[:, a, c]).max(), 1e-300))
+                assert eg < tg, (l, b, a, c, eg)
+            ea = rel_err(y.cpu().numpy()[b], h.apply(x[b], lo_))
+            print(f"[elements 3-D] K={K} p={p} b={b} operator rel err {ea:.2e}")
+            assert ea < op_tol(p), (l, b, ea)
+        if l > l0:
+            pc = p // 2
+            rf = np.random.default_rng(l).standard_normal((B, (p + 1) ** 3))
+            rc = torch.empty((B, (pc + 1) ** 3), dtype=torch.float64, device="cuda")
+            pmg.pmg_restrict(s.h, l, pmg.PMG_F64, torch.from_numpy(rf).cuda(), rc)
+            torch.cuda.synchronize()
+            for b, (h, _, _) in enumerate(case3["ors"]):
+                assert rel_err(rc.cpu().numpy()[b], h.restrict(rf[b], lo_)) < 1e-12
+
+
+def test_3d_cycle_and_solve(case3):
+    s, p = case3["s"], case3["p"]
+    B = len(SEEDS3)
+    m = interior_mask(3, p)
+    r = np.where(m[None, :], np.random.default_rng(70).standard_normal((B, (p + 1) ** 3)), 0.0)
+    yc = torch.empty((B, (p + 1) ** 3), dtype=torch.float64, device="cuda")
+    pmg.pmg_gamma_cycle(s.h, pmg.PMG_F64, torch.from_numpy(r).cuda(), yc)
+    bt = torch.empty_like(case3["f"])
+    pmg.pmg_rhs(s.h, case3["f"], case3["g"], bt)
+    x = torch.empty_like(bt)
+    pmg.pmg_solve(s.h, bt, x, s.info)
+    torch.cuda.synchronize()
+    info = s.info_host()
+    for b, (h, f, g) in enumerate(case3["ors"]):
+        ec = rel_err(yc.cpu().numpy()[b], h.cycle(r[b]))
+        bo = h.rhs(f, g)
+        xg = x.cpu().numpy()[b]
+        rr = np.linalg.norm(bo - h.apply(xg)) / np.linalg.norm(bo)
+        xo, st, it, _ = h.fgmres(bo, rtol=1e-10, maxit=200, restart=20)
+        ex = rel_err(xg, xo)
+        print(f"[elements 3-D solve] K={case3['K']} p={p} b={b} cycle err {ec:.2e} its gpu "
+              f"{info['iterations'][b]} oracle {it} oracle-operator relres {rr:.3e} err {ex:.2e}")
+        assert ec < 1e-10
         assert info["status"][b] == 0 and rr <= 1.0001e-10 and st == 0
         assert abs(int(info["iterations"][b]) - it) <= 1 and ex < 1e-7

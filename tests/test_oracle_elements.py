@@ -188,3 +188,49 @@ def test_hp_multigrid_iterations_bounded_in_K(smoother, alpha):
         counts[K] = it
     print("iterations by K (pe = 8, gamma = 3, FEM lines):", counts)
     assert max(counts.values()) <= 1.5 * min(counts.values()) + 2
+
+
+def test_three_dimensional_elements():
+    """3-D: the undeformed cube's assembled operator is the Kronecker sum of
+    the assembled 1-D element stiffness and mass (scaled by 1 / 2K), A 1 = 0
+    on a deformed cube, and the element gamma-cycle preconditions FGMRES to
+    the dense solution."""
+    K, pe = 2, 4
+    cube = inputs.Problem(3, "deformed3d", {"beta": np.zeros(3), "amp": np.zeros(3),
+                                            "c": np.zeros((3, 3, 3))})
+    coords = [cube.coords(inputs.composite_nodes(orc.gll(pe)[0], K))]
+    h = orc.Hier(3, [K * pe], coords, smoother=orc.SMOOTHER_FEM, elements=K)
+    xi, rho = orc.gll(pe)
+    D = orc.deriv(pe, xi).reshape(pe + 1, pe + 1)
+    ke = D.T @ np.diag(rho) @ D
+    n1 = K * pe + 1
+    Kg, Mg = np.zeros((n1, n1)), np.zeros((n1, n1))
+    for e in range(K):
+        sl = slice(e * pe, e * pe + pe + 1)
+        Kg[sl, sl] += ke
+        Mg[sl, sl] += np.diag(rho)
+    A = (np.kron(np.kron(Mg, Mg), Kg) + np.kron(np.kron(Mg, Kg), Mg)
+         + np.kron(np.kron(Kg, Mg), Mg)) / (2 * K)
+    m = np.zeros((n1, n1, n1), dtype=bool)
+    m[1:-1, 1:-1, 1:-1] = True
+    m = m.reshape(-1)
+    err = np.abs(h.dense_interior() - A[np.ix_(m, m)]).max() / np.abs(A).max()
+    print(f"3-D K={K} pe={pe}: Kronecker sum difference {err:.2e}")
+    assert err < 1e-14
+    prob = inputs.config3(3)
+    pes = [2, 4, 8]
+    coords = [prob.coords(inputs.composite_nodes(orc.gll(q)[0], K)) for q in pes]
+    h = orc.Hier(3, [K * q for q in pes], coords, gamma=1, m=1, alpha=0.16,
+                 smoother=orc.SMOOTHER_FEM, restriction=orc.RESTRICT_TRANSPOSE, elements=K)
+    X = coords[-1]
+    assert np.abs(h.apply(np.ones(X.shape[1]), all_rows=True)).max() < 1e-12
+    b = h.rhs(prob.f(X), prob.g(X))
+    x, st, it, _ = h.fgmres(b, rtol=1e-10, maxit=100, restart=20)
+    n1 = K * pes[-1] + 1
+    mm = np.zeros((n1, n1, n1), dtype=bool)
+    mm[1:-1, 1:-1, 1:-1] = True
+    mm = mm.reshape(-1)
+    xd = np.linalg.solve(h.dense_interior(), b[mm])
+    print(f"3-D K={K} pe=8: {it} iterations")
+    assert st == 0 and it <= 25
+    assert np.abs(x[mm] - xd).max() <= 1e-8 * np.abs(xd).max()
