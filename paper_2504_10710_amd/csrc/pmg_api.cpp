@@ -842,7 +842,7 @@ int pmg_line_smooth(pmg_handle* h, int level, int dir, int prec, const void* d_r
         return rc;
     if (dir < 0 || dir >= h->d.dim) return fail(PMG_EINVAL, "dir %d out of range", dir);
     if (!d_r || !d_x) return fail(PMG_EINVAL, "NULL argument");
-    hipError_t e = launch_line_smooth(h->d.dim, 2 << level, f32, h->d.batch, hier_of(h, f32), dir,
+    hipError_t e = launch_line_smooth(h->d.dim, 2 << level, f32, h->K > 1, h->d.batch, hier_of(h, f32), dir,
                                       d_r, d_x, (hipStream_t)stream);
     return e == hipSuccess ? PMG_OK : hip_fail(e, "pmg_line_smooth");
 }
@@ -853,7 +853,7 @@ int pmg_gamma_cycle(pmg_handle* h, int prec, const void* d_r, void* d_y, pmg_str
     int rc;
     if ((rc = check_h(h)) || (rc = check_prec(h, prec, &f32))) return rc;
     if (!d_r || !d_y) return fail(PMG_EINVAL, "NULL argument");
-    hipError_t e = launch_cycle(h->d.dim, h->d.p_fine, f32, h->d.batch, hier_of(h, f32), d_r, d_y,
+    hipError_t e = launch_cycle(h->d.dim, h->d.p_fine, f32, h->K > 1, h->d.batch, hier_of(h, f32), d_r, d_y,
                                 (hipStream_t)stream);
     return e == hipSuccess ? PMG_OK : hip_fail(e, "pmg_gamma_cycle");
 }
@@ -871,6 +871,7 @@ int pmg_solve(pmg_handle* h, const double* d_b, double* d_x, pmg_info* d_info, p
     a.Hs = (double*)(h->ws + h->o_Hs);
     a.TR64 = (double*)(h->ws + h->o_TR64);
     a.EX64 = h->o_EX64 ? (double*)(h->ws + h->o_EX64) : nullptr;
+    a.elem = h->K > 1;
     a.info = d_info;
     a.nv = h->nv;
     a.hs = h->hs;
@@ -962,6 +963,7 @@ int pmg_solve_noalloc(pmg_handle* h, const double* d_b, double* d_x, pmg_info* d
     a.Hs = (double*)(sp + oHs);
     a.TR64 = (double*)(sp + oTR);
     a.EX64 = h->K > 1 ? (double*)(sp + oEX) : nullptr;
+    a.elem = h->K > 1;
     a.info = d_info;
     a.nv = h->nv;
     a.hs = h->hs;
@@ -1055,6 +1057,7 @@ static SolveArgs pool_solve_args(pmg_pool* P)
     a.Hs = (double*)(h->ws + h->o_Hs);
     a.TR64 = (double*)(h->ws + h->o_TR64);
     a.EX64 = h->o_EX64 ? (double*)(h->ws + h->o_EX64) : nullptr;
+    a.elem = h->K > 1;
     a.info = (pmg_info*)(h->ws + h->o_info);
     a.nv = h->nv;
     a.hs = h->hs;

@@ -5,21 +5,26 @@
 
 namespace pmg {
 
-template <class T, int P, int DIM>
+template <class T, int P, int DIM, bool E>
 __global__ void __launch_bounds__(NT, 4) k_cycle(const Hier<T>* __restrict__ Hp, const T* __restrict__ r, T* __restrict__ y)
 {
     const Hier<T>& H = *Hp;
     using S = Shape<P, DIM>;
     const long long b = blockIdx.x;
-    gamma_cycle<T, P, DIM>(H, (int)b, r + b * S::N, y + b * S::N);
+    gamma_cycle<T, P, DIM, collapse_p(DIM), E>(H, (int)b, r + b * S::N, y + b * S::N);
 }
 
-hipError_t launch_cycle(int dim, int p, bool f32, int B, const void* H, const void* r, void* y,
-                        hipStream_t s)
+hipError_t launch_cycle(int dim, int p, bool f32, bool elem, int B, const void* H, const void* r,
+                        void* y, hipStream_t s)
 {
-    PMG_TYPED(f32, PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_cycle<T_, P_, D_>), dim3(B),
-                                                              dim3(NT), 0, s, (const Hier<T_>*)H,
-                                                              (const T_*)r, (T_*)y)));
+    if (elem)
+        PMG_TYPED(f32, PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_cycle<T_, P_, D_, true>), dim3(B),
+                                                                  dim3(NT), 0, s, (const Hier<T_>*)H,
+                                                                  (const T_*)r, (T_*)y)));
+    else
+        PMG_TYPED(f32, PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_cycle<T_, P_, D_, false>), dim3(B),
+                                                                  dim3(NT), 0, s, (const Hier<T_>*)H,
+                                                                  (const T_*)r, (T_*)y)));
     return last();
 }
 
@@ -48,7 +53,7 @@ __global__ void __launch_bounds__(NT, 4) k_collapse(const Hier<T>* __restrict__ 
         const int qi = interior_node<PC, DIM>(i);
         for (int q = threadIdx.x; q < S::N; q += NT) rg[q] = q == qi ? T(1) : T(0);
         wg_barrier();
-        gamma_cycle<T, PC, DIM, PC / 2>(H, b, r, x);
+        gamma_cycle<T, PC, DIM, PC / 2>(H, b, r, x);   // one-element hierarchies only
         for (int j = threadIdx.x; j < ni; j += NT) C[(long long)i * ni + j] = (double)xg[interior_node<PC, DIM>(j)];
         wg_barrier();
     }

@@ -966,45 +966,47 @@ __device__ void apply2d_elements_mfma(const T* __restrict__ G_, const T* __restr
 // gradients g_b = D along axis b, fluxes f_a = sum_b G_ab g_b at every node,
 // then (A x)(n) = sum_a sum_k D[k][n_a] f_a(n with axis a <- k) on interior
 // rows.  RESID: out = r - A x.  out has zero boundary rows.
+// The operator of a level of K^dim elements (K > 1), out of line so that the
+// one-element operator's code and registers stay as they are: element degree
+// P / K >= 16 (2-D) on the matrix cores, else the vector units.
+template <class T, int P, int DIM, bool RESID>
+__device__ __attribute__((noinline)) void apply_elements_level(
+    int K, const T* __restrict__ G_, const T* __restrict__ D_, const T* __restrict__ DT_,
+    T* __restrict__ TR_, T* __restrict__ EX_, const T* __restrict__ x_, const T* __restrict__ r_,
+    T* __restrict__ out_)
+{
+    if constexpr (DIM == 2) {
+        if constexpr (P / 2 >= 16 && (P / 2) % 16 == 0) {
+            if (K == 2 && EX_) {
+                apply2d_elements_mfma<T, P, P / 2, RESID>(G_, D_, DT_, TR_, EX_, x_, r_, out_);
+                return;
+            }
+        }
+        if constexpr (P / 4 >= 16 && (P / 4) % 16 == 0) {
+            if (K == 4 && EX_) {
+                apply2d_elements_mfma<T, P, P / 4, RESID>(G_, D_, DT_, TR_, EX_, x_, r_, out_);
+                return;
+            }
+        }
+        if constexpr (P / 8 >= 16 && (P / 8) % 16 == 0) {
+            if (K == 8 && EX_) {
+                apply2d_elements_mfma<T, P, P / 8, RESID>(G_, D_, DT_, TR_, EX_, x_, r_, out_);
+                return;
+            }
+        }
+        apply2d_elements<T, P, RESID>(K, G_, D_, TR_, x_, r_, out_);
+    } else {
+        apply3d_elements<T, P, RESID>(K, G_, D_, TR_, x_, r_, out_);
+    }
+}
+
 template <class T, int P, int DIM, bool RESID>
 __device__ __attribute__((noinline)) void apply_level(const T* __restrict__ G_,
                                                       const T* __restrict__ D_,
                                                       const T* __restrict__ DT_, T* __restrict__ TR_,
                                                       const T* __restrict__ x_,
-                                                      const T* __restrict__ r_, T* __restrict__ out_,
-                                                      int K = 1, T* __restrict__ EX_ = nullptr)
+                                                      const T* __restrict__ r_, T* __restrict__ out_)
 {
-    if constexpr (DIM == 2 && P >= 4) {
-        if (K > 1) {
-            // element degree P / K >= 16 on the matrix cores, else the vector units
-            if constexpr (P / 2 >= 16 && (P / 2) % 16 == 0) {
-                if (K == 2 && EX_) {
-                    apply2d_elements_mfma<T, P, P / 2, RESID>(G_, D_, DT_, TR_, EX_, x_, r_, out_);
-                    return;
-                }
-            }
-            if constexpr (P / 4 >= 16 && (P / 4) % 16 == 0) {
-                if (K == 4 && EX_) {
-                    apply2d_elements_mfma<T, P, P / 4, RESID>(G_, D_, DT_, TR_, EX_, x_, r_, out_);
-                    return;
-                }
-            }
-            if constexpr (P / 8 >= 16 && (P / 8) % 16 == 0) {
-                if (K == 8 && EX_) {
-                    apply2d_elements_mfma<T, P, P / 8, RESID>(G_, D_, DT_, TR_, EX_, x_, r_, out_);
-                    return;
-                }
-            }
-            apply2d_elements<T, P, RESID>(K, G_, D_, TR_, x_, r_, out_);
-            return;
-        }
-    }
-    if constexpr (DIM == 3 && P >= 4) {
-        if (K > 1) {
-            apply3d_elements<T, P, RESID>(K, G_, D_, TR_, x_, r_, out_);
-            return;
-        }
-    }
     if constexpr (DIM == 2 && P >= MFMA_MIN_P) {
         apply2d_mfma<T, P, RESID>(G_, D_, DT_, TR_, x_, r_, out_);
         return;
@@ -1073,6 +1075,23 @@ __device__ __attribute__((noinline)) void apply_level(const T* __restrict__ G_,
         out[q] = RESID ? r[q] - y : y;
     }
     wg_barrier();
+}
+
+// A x of a level of one element (apply_level) or of K^dim elements
+// (apply_elements_level); the branch sits at the call site so that each
+// operator keeps its own code and registers.
+template <class T, int P, int DIM, bool RESID>
+__device__ __attribute__((always_inline)) inline void apply_any(
+    int K, T* EX, const T* __restrict__ G, const T* __restrict__ D, const T* __restrict__ DT,
+    T* __restrict__ TR, const T* __restrict__ x, const T* __restrict__ r, T* __restrict__ out)
+{
+    if constexpr (P >= 4) {
+        if (K > 1) {
+            apply_elements_level<T, P, DIM, RESID>(K, G, D, DT, TR, EX, x, r, out);
+            return;
+        }
+    }
+    apply_level<T, P, DIM, RESID>(G, D, DT, TR, x, r, out);
 }
 
 // ------------------------------------------------------------------ line solver
@@ -1680,7 +1699,9 @@ __device__ inline void level_lines(const LevelData<T>& L, int b, int dir, T* g, 
 }
 
 // x += alpha B_dir^{-1} (r - A x)   (Alg. 2 smoothing step)
-template <class T, int P, int DIM>
+// E: the hierarchy has several elements per axis (H.K > 1); the one-element
+// instances (E = false) carry no element code.
+template <class T, int P, int DIM, bool E = false>
 __device__ void smooth_step(const Hier<T>& H, int b, int dir, const T* r, T* x, bool x_is_zero)
 {
     using S = Shape<P, DIM>;
@@ -1697,9 +1718,14 @@ __device__ void smooth_step(const Hier<T>& H, int b, int dir, const T* r, T* x, 
         wg_copy(tmp, r, S::N);   // the thread-per-line form works in place
         wg_barrier();
     } else {
-        apply_level<T, P, DIM, true>(L.G + (long long)b * S::NC * L.ng, L.D, L.DT,
-                                     L.TR + (long long)b * DIM * L.ng, x, r, tmp, H.K,
-                                     L.EX ? L.EX + (long long)b * L.ng : nullptr);
+        if constexpr (E)
+            apply_elements_level<T, P, DIM, true>(H.K, L.G + (long long)b * S::NC * L.ng, L.D,
+                                                  L.DT, L.TR + (long long)b * DIM * L.ng,
+                                                  L.EX ? L.EX + (long long)b * L.ng : nullptr, x, r,
+                                                  tmp);
+        else
+            apply_level<T, P, DIM, true>(L.G + (long long)b * S::NC * S::N, L.D, L.DT,
+                                         L.TR + (long long)b * DIM * S::N, x, r, tmp);
     }
     level_lines<T, P, DIM, true>(L, b, dir, tmp, x, H.alpha);
 }
@@ -1748,13 +1774,13 @@ __device__ void collapsed_solve(const double* C_, const T* r_, T* x_)
 // m post-smoothing steps per axis in reverse axis order}; level 0 (p = 2,
 // one interior node) is solved exactly.  Levels of degree <= CMAX that the
 // hierarchy holds a dense matrix for are applied as that matrix.
-template <class T, int P, int DIM, int CMAX = collapse_p(DIM)>
+template <class T, int P, int DIM, int CMAX = collapse_p(DIM), bool E = false>
 __device__ __attribute__((noinline)) void gamma_cycle(const Hier<T>& H, int b, const T* r, T* x)
 {
     using S = Shape<P, DIM>;
     const LevelData<T>& L = lvl<T, P, DIM>(H);
     // (also the coarsest level of K x K elements, degree 2K: its exact inverse)
-    if constexpr (P <= CMAX && P >= 4) {
+    if constexpr (P <= CMAX && (P >= collapse_lo(DIM) || (E && P >= 4))) {
         if (H.Cc[S::LEV]) {
             constexpr int ni = ipow(P - 1, DIM);
             collapsed_solve<T, P, DIM>(H.Cc[S::LEV] + (long long)b * ni * ni, r, x);
@@ -1790,18 +1816,23 @@ __device__ __attribute__((noinline)) void gamma_cycle(const Hier<T>& H, int b, c
         bool zero = true;
         for (int dir = 0; dir < DIM; ++dir)
             for (int s = 0; s < H.m; ++s) {
-                smooth_step<T, P, DIM>(H, b, dir, r, x, zero);
+                smooth_step<T, P, DIM, E>(H, b, dir, r, x, zero);
                 zero = false;
             }
         for (int g = 0; g < H.gamma; ++g) {
-            apply_level<T, P, DIM, true>(L.G + (long long)b * S::NC * L.ng, L.D, L.DT,
-                                         L.TR + (long long)b * DIM * L.ng, x, r, tmp, H.K,
-                                         L.EX ? L.EX + (long long)b * L.ng : nullptr);
+            if constexpr (E)
+                apply_elements_level<T, P, DIM, true>(H.K, L.G + (long long)b * S::NC * L.ng, L.D,
+                                                      L.DT, L.TR + (long long)b * DIM * L.ng,
+                                                      L.EX ? L.EX + (long long)b * L.ng : nullptr,
+                                                      x, r, tmp);
+            else
+                apply_level<T, P, DIM, true>(L.G + (long long)b * S::NC * S::N, L.D, L.DT,
+                                             L.TR + (long long)b * DIM * S::N, x, r, tmp);
             restrict_level<T, P, DIM>(tmp, rc, L.JR, L.JT, w1, w2);
-            gamma_cycle<T, P / 2, DIM, CMAX>(H, b, rc, xc);
+            gamma_cycle<T, P / 2, DIM, CMAX, E>(H, b, rc, xc);
             prolong_level<T, P, DIM>(xc, x, L.J, L.JT, w1, w2);
             for (int dir = DIM - 1; dir >= 0; --dir)
-                for (int s = 0; s < H.m; ++s) smooth_step<T, P, DIM>(H, b, dir, r, x, false);
+                for (int s = 0; s < H.m; ++s) smooth_step<T, P, DIM, E>(H, b, dir, r, x, false);
         }
     }
 }

@@ -61,6 +61,7 @@ struct SolveArgs {
     double* Hs;         // [B][hs]
     double* TR64;       // [B][DIM][N]
     double* EX64;       // [B][ng] FP64 element-local operand (element hierarchies), or null
+    int elem;           // 1: the hierarchy has several elements per axis (element kernels)
     pmg_info* info;     // [B]
     long long nv, hs;
     int restart, max_iter, krylov;
@@ -84,9 +85,9 @@ hipError_t launch_prolong(int dim, int p, bool f32, int B, const void* H, const 
                           void* xf, hipStream_t s);
 hipError_t launch_line_solve(int dim, int p, bool f32, int B, const void* H, int dir,
                              const void* r, void* z, hipStream_t s);
-hipError_t launch_line_smooth(int dim, int p, bool f32, int B, const void* H, int dir,
+hipError_t launch_line_smooth(int dim, int p, bool f32, bool elem, int B, const void* H, int dir,
                               const void* r, void* x, hipStream_t s);
-hipError_t launch_cycle(int dim, int p, bool f32, int B, const void* H, const void* r,
+hipError_t launch_cycle(int dim, int p, bool f32, bool elem, int B, const void* H, const void* r,
                         void* y, hipStream_t s);
 // dense matrices of the collapsed coarse cycle of level pc (collapse_lo(dim)
 // or collapse_p(dim); the lower one first) for nb problems (all, or the

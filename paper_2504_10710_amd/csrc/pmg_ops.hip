@@ -15,9 +15,9 @@ __global__ void __launch_bounds__(NT) k_apply(const Hier<T>* __restrict__ Hp, co
     using S = Shape<P, DIM>;
     const long long b = blockIdx.x;
     const LevelData<T>& L = H.lev[S::LEV];
-    apply_level<T, P, DIM, false>(L.G + b * S::NC * L.ng, L.D, L.DT, L.TR + b * DIM * L.ng,
-                                  x + b * S::N, nullptr, y + b * S::N, H.K,
-                                  L.EX ? L.EX + b * L.ng : nullptr);
+    apply_any<T, P, DIM, false>(H.K, L.EX ? L.EX + b * L.ng : nullptr, L.G + b * S::NC * L.ng,
+                                L.D, L.DT, L.TR + b * DIM * L.ng, x + b * S::N, nullptr,
+                                y + b * S::N);
 }
 
 template <class T, int P, int DIM>
@@ -67,14 +67,14 @@ __global__ void __launch_bounds__(NT, 8) k_line_solve(const Hier<T>* __restrict_
     }
 }
 
-template <class T, int P, int DIM>
+template <class T, int P, int DIM, bool E>
 __global__ void __launch_bounds__(NT) k_line_smooth(const Hier<T>* __restrict__ Hp, int dir, const T* __restrict__ r,
                                                     T* __restrict__ x)
 {
     const Hier<T>& H = *Hp;
     using S = Shape<P, DIM>;
     const long long b = blockIdx.x;
-    smooth_step<T, P, DIM>(H, (int)b, dir, r + b * S::N, x + b * S::N, false);
+    smooth_step<T, P, DIM, E>(H, (int)b, dir, r + b * S::N, x + b * S::N, false);
 }
 
 hipError_t launch_apply(int dim, int p, bool f32, int B, const void* H, const void* x, void* y,
@@ -113,12 +113,19 @@ hipError_t launch_line_solve(int dim, int p, bool f32, int B, const void* H, int
     return last();
 }
 
-hipError_t launch_line_smooth(int dim, int p, bool f32, int B, const void* H, int dir,
+hipError_t launch_line_smooth(int dim, int p, bool f32, bool elem, int B, const void* H, int dir,
                               const void* r, void* x, hipStream_t s)
 {
-    PMG_TYPED(f32, PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_line_smooth<T_, P_, D_>), dim3(B),
-                                                              dim3(NT), 0, s, (const Hier<T_>*)H,
-                                                              dir, (const T_*)r, (T_*)x)));
+    if (elem)
+        PMG_TYPED(f32, PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_line_smooth<T_, P_, D_, true>),
+                                                                  dim3(B), dim3(NT), 0, s,
+                                                                  (const Hier<T_>*)H, dir,
+                                                                  (const T_*)r, (T_*)x)));
+    else
+        PMG_TYPED(f32, PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_line_smooth<T_, P_, D_, false>),
+                                                                  dim3(B), dim3(NT), 0, s,
+                                                                  (const Hier<T_>*)H, dir,
+                                                                  (const T_*)r, (T_*)x)));
     return last();
 }
 

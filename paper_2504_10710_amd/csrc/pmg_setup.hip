@@ -999,9 +999,8 @@ __global__ void __launch_bounds__(NT) k_rhs(const Hier<double>* __restrict__ Hp,
     for (int q = threadIdx.x; q < N; q += NT) v[q] = is_boundary<P, DIM>(q) ? g[b * N + q] : 0.0;
     wg_barrier();
     double* out = bo + b * N;
-    apply_level<double, P, DIM, false>(L.G64 + b * S::NC * L.ng, L.D64, L.DT64,
-                                       L.TR + b * DIM * L.ng, v, nullptr, out, H.K,
-                                       L.EX ? L.EX + b * L.ng : nullptr);
+    apply_any<double, P, DIM, false>(H.K, L.EX ? L.EX + b * L.ng : nullptr, L.G64 + b * S::NC * L.ng,
+                                     L.D64, L.DT64, L.TR + b * DIM * L.ng, v, nullptr, out);
     for (int q = threadIdx.x; q < N; q += NT)
         out[q] = is_boundary<P, DIM>(q) ? 0.0 : L.mass[b * N + q] * f[b * N + q] - out[q];
 }

@@ -29,12 +29,12 @@ __device__ inline void wg_scale_div(double* __restrict__ v_, double d, int n)
 }
 
 // z = M^{-1} v with the gamma-cycle in T (FP64 in/out)
-template <class T, int P, int DIM>
+template <class T, int P, int DIM, bool E>
 __device__ void precondition(const Hier<T>& H, int b, const double* v, double* z)
 {
     using S = Shape<P, DIM>;
     if constexpr (sizeof(T) == sizeof(double)) {
-        gamma_cycle<T, P, DIM>(H, b, (const T*)v, (T*)z);
+        gamma_cycle<T, P, DIM, collapse_p(DIM), E>(H, b, (const T*)v, (T*)z);
     } else {
         const LevelData<T>& L = H.lev[S::LEV];
         T* r = L.R + (long long)b * S::N;
@@ -45,7 +45,7 @@ __device__ void precondition(const Hier<T>& H, int b, const double* v, double* z
             for (int q = threadIdx.x; q < S::N; q += NT) rg[q] = (T)vg[q];
         }
         wg_barrier();
-        gamma_cycle<T, P, DIM>(H, b, r, x);
+        gamma_cycle<T, P, DIM, collapse_p(DIM), E>(H, b, r, x);
         {
             const auto zg = gmem(z);
             const auto xg = gmem((const T*)x);
@@ -55,21 +55,33 @@ __device__ void precondition(const Hier<T>& H, int b, const double* v, double* z
     }
 }
 
-template <class T, int P, int DIM>
+template <class T, int P, int DIM, bool E>
 __device__ void apply64(const Hier<T>& H, const SolveArgs& A, int b, const double* x,
                         const double* r, double* out)
 {
     using S = Shape<P, DIM>;
     const LevelData<T>& L = H.lev[S::LEV];
-    // the FP64 element-local operand of an element hierarchy's finest level
-    double* ex = A.EX64 ? A.EX64 + (long long)b * L.ng : nullptr;
-    if (r)
-        apply_level<double, P, DIM, true>(L.G64 + (long long)b * S::NC * L.ng, L.D64, L.DT64,
-                                          A.TR64 + (long long)b * DIM * L.ng, x, r, out, H.K, ex);
-    else
-        apply_level<double, P, DIM, false>(L.G64 + (long long)b * S::NC * L.ng, L.D64, L.DT64,
-                                           A.TR64 + (long long)b * DIM * L.ng, x, nullptr, out,
-                                           H.K, ex);
+    if constexpr (E) {
+        // the FP64 element-local operand of an element hierarchy's finest level
+        double* ex = A.EX64 ? A.EX64 + (long long)b * L.ng : nullptr;
+        if (r)
+            apply_elements_level<double, P, DIM, true>(H.K, L.G64 + (long long)b * S::NC * L.ng,
+                                                       L.D64, L.DT64,
+                                                       A.TR64 + (long long)b * DIM * L.ng, ex, x, r,
+                                                       out);
+        else
+            apply_elements_level<double, P, DIM, false>(H.K, L.G64 + (long long)b * S::NC * L.ng,
+                                                        L.D64, L.DT64,
+                                                        A.TR64 + (long long)b * DIM * L.ng, ex, x,
+                                                        nullptr, out);
+    } else {
+        if (r)
+            apply_level<double, P, DIM, true>(L.G64 + (long long)b * S::NC * S::N, L.D64, L.DT64,
+                                              A.TR64 + (long long)b * DIM * S::N, x, r, out);
+        else
+            apply_level<double, P, DIM, false>(L.G64 + (long long)b * S::NC * S::N, L.D64, L.DT64,
+                                               A.TR64 + (long long)b * DIM * S::N, x, nullptr, out);
+    }
 }
 
 // Modified Gram-Schmidt for column j of the Arnoldi process: for i = 0..j,
@@ -133,7 +145,7 @@ __device__ inline double mgs_column(double* w_, const double* V_, long long N, i
 // restarted every `restart` iterations; PCG; flexible CG.  Convergence is declared on the
 // true residual ||b - A x|| <= rtol ||b||.  At most A.budget iterations are
 // taken in this launch; the state is saved in A.st[b].
-template <class T, int P, int DIM>
+template <class T, int P, int DIM, bool E>
 __global__ void __launch_bounds__(NT, 4) k_solve(const Hier<T>* __restrict__ Hp, SolveArgs A)
 {
     const Hier<T>& H = *Hp;
@@ -193,11 +205,11 @@ __global__ void __launch_bounds__(NT, 4) k_solve(const Hier<T>* __restrict__ Hp,
             double* q = V + 3LL * N;
             wg_copy(r, bb, N);
             wg_barrier();
-            precondition<T, P, DIM>(H, b, r, z);
+            precondition<T, P, DIM, E>(H, b, r, z);
             wg_copy(pp, z, N);
             wg_barrier();
             if (flex) {
-                apply64<T, P, DIM>(H, A, b, pp, nullptr, q);
+                apply64<T, P, DIM, E>(H, A, b, pp, nullptr, q);
                 st.rz = wg_dot(pp, q, N, red);
             } else {
                 st.rz = wg_dot(r, z, N, red);
@@ -216,7 +228,7 @@ __global__ void __launch_bounds__(NT, 4) k_solve(const Hier<T>* __restrict__ Hp,
         const double tol = A.rtol * st.bn;
         for (;;) {
             if (st.phase == PH_RESTART) {
-                apply64<T, P, DIM>(H, A, b, x, bb, V);
+                apply64<T, P, DIM, E>(H, A, b, x, bb, V);
                 const double beta = sqrt(wg_dot(V, V, N, red));
                 relres = beta / st.bn;
                 if (!isfinite(beta)) { st.status = PMG_ENAN; goto done; }
@@ -237,8 +249,8 @@ __global__ void __launch_bounds__(NT, 4) k_solve(const Hier<T>* __restrict__ Hp,
             double* vj = V + (long long)j * N;
             double* zj = Z + (long long)j * N;
             double* w = V + (long long)(j + 1) * N;
-            precondition<T, P, DIM>(H, b, vj, zj);
-            apply64<T, P, DIM>(H, A, b, zj, nullptr, w);
+            precondition<T, P, DIM, E>(H, b, vj, zj);
+            apply64<T, P, DIM, E>(H, A, b, zj, nullptr, w);
             const double hn = mgs_column(w, V, N, j, Hm + j, kr, red);
             if (hn > 0.0) wg_scale_div(w, hn, N);
             if (threadIdx.x == 0) {
@@ -293,7 +305,7 @@ __global__ void __launch_bounds__(NT, 4) k_solve(const Hier<T>* __restrict__ Hp,
                 }
                 st.phase = PH_RESTART;
                 if (fail) {
-                    apply64<T, P, DIM>(H, A, b, x, bb, V);
+                    apply64<T, P, DIM, E>(H, A, b, x, bb, V);
                     relres = sqrt(wg_dot(V, V, N, red)) / st.bn;
                     st.status = isfinite(relres) ? (relres <= A.rtol ? PMG_OK : PMG_EBREAKDOWN) : PMG_ENAN;
                     goto done;
@@ -309,7 +321,7 @@ __global__ void __launch_bounds__(NT, 4) k_solve(const Hier<T>* __restrict__ Hp,
         double* t = V + 4LL * N;
         const double tol = A.rtol * st.bn;
         while (budget > 0) {
-            if (!flex) apply64<T, P, DIM>(H, A, b, pp, nullptr, q);
+            if (!flex) apply64<T, P, DIM, E>(H, A, b, pp, nullptr, q);
             const double pq = flex ? st.rz : wg_dot(pp, q, N, red);
             if (!(pq > 0.0)) { st.status = isfinite(pq) ? PMG_EBREAKDOWN : PMG_ENAN; goto done; }
             const double al = (flex ? wg_dot(pp, r, N, red) : st.rz) / pq;
@@ -328,7 +340,7 @@ __global__ void __launch_bounds__(NT, 4) k_solve(const Hier<T>* __restrict__ Hp,
             if (!isfinite(rn)) { st.status = PMG_ENAN; goto done; }
             relres = rn / st.bn;
             if (rn <= tol) {
-                apply64<T, P, DIM>(H, A, b, x, bb, t);
+                apply64<T, P, DIM, E>(H, A, b, x, bb, t);
                 const double tn = sqrt(wg_dot(t, t, N, red));
                 relres = tn / st.bn;
                 if (tn <= tol) { st.status = PMG_OK; goto done; }
@@ -336,19 +348,19 @@ __global__ void __launch_bounds__(NT, 4) k_solve(const Hier<T>* __restrict__ Hp,
                 wg_barrier();
             }
             if (st.it >= A.max_iter) {
-                apply64<T, P, DIM>(H, A, b, x, bb, t);
+                apply64<T, P, DIM, E>(H, A, b, x, bb, t);
                 relres = sqrt(wg_dot(t, t, N, red)) / st.bn;
                 st.status = PMG_ENOTCONV;
                 goto done;
             }
-            precondition<T, P, DIM>(H, b, r, z);
+            precondition<T, P, DIM, E>(H, b, r, z);
             if (flex) {
                 const double be = -wg_dot(z, q, N, red) / pq;
                 const auto pg = gmem(pp);
                 const auto zg = gmem((const double*)z);
                 for (int i = threadIdx.x; i < N; i += NT) pg[i] = zg[i] + be * pg[i];
                 wg_barrier();
-                apply64<T, P, DIM>(H, A, b, pp, nullptr, q);
+                apply64<T, P, DIM, E>(H, A, b, pp, nullptr, q);
                 st.rz = wg_dot(pp, q, N, red);
             } else {
                 const double rz2 = wg_dot(r, z, N, red);

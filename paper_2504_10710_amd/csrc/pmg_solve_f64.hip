@@ -6,9 +6,13 @@ namespace pmg {
 hipError_t launch_solve_f64(int dim, int p, bool f32, int B, const void* H, const SolveArgs& a,
                         hipStream_t s)
 {
-    PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_solve<double, P_, D_>), dim3(B),
-                                                              dim3(NT), 0, s, (const Hier<double>*)H,
-                                                              a));
+    // the element instances (several elements per axis) are separate kernels
+    if (a.elem)
+        PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_solve<double, P_, D_, true>), dim3(B), dim3(NT),
+                                                   0, s, (const Hier<double>*)H, a));
+    else
+        PMG_DISPATCH_P(dim, p, hipLaunchKernelGGL((k_solve<double, P_, D_, false>), dim3(B), dim3(NT),
+                                                   0, s, (const Hier<double>*)H, a));
     return last();
 }
 
@@ -16,7 +20,7 @@ int solve_blocks_per_cu_f64(int dim, int p)
 {
     int nb = 0;
     PMG_DISPATCH_P(dim, p, (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                               &nb, k_solve<double, P_, D_>, NT, 0));
+                               &nb, k_solve<double, P_, D_, false>, NT, 0));
     return nb;
 }
 
