@@ -655,10 +655,14 @@ def serve(args):
     def plain(prec):
         """The same requests solved the plain way: one one-shot batched
         pmg_solve per class over all of that class's requests (setup,
-        lifting, solve, lift), classes back to back."""
+        lifting, solve, lift), classes back to back.  prec None: each class
+        in the served class's own inner precision."""
         t0 = time.perf_counter()
         per_class = {}
-        for ci, (dim, p, _, _, gam, rst) in enumerate(SERVE_CLASSES):
+        prec_all = prec
+        for ci, (dim, p, _, cprec, gam, rst) in enumerate(SERVE_CLASSES):
+            prec = prec_all if prec_all is not None else (
+                pmg.PMG_F32 if cprec == "f32" else pmg.PMG_F64)
             idx = [i for i in range(n) if reqs[i] == ci]
             if not idx:
                 continue
@@ -695,13 +699,14 @@ def serve(args):
         return n / (time.perf_counter() - t0), per_class
 
     failed = {}
-    plain(pmg.PMG_F32)               # warm-up (module load, graph-free path)
+    plain(None)                      # warm-up (module load, graph-free path)
     failed.clear()
     plain64, plain64_cls = plain(pmg.PMG_F64)
     plain32, plain32_cls = plain(pmg.PMG_F32)
+    plainc, plainc_cls = plain(None)
     print(f"[bench] served mix, plain batched per class: FP64 cycle {plain64:.1f}, FP32 cycle "
-          f"{plain32:.1f} solves/s (seconds per class FP32: {plain32_cls})", file=sys.stderr,
-          flush=True)
+          f"{plain32:.1f}, served classes' precisions {plainc:.1f} solves/s (seconds per class "
+          f"FP32: {plain32_cls})", file=sys.stderr, flush=True)
     ws = torch.empty(pmg.pmg_server_workspace_bytes(sdesc), dtype=torch.uint8, device=dev)
     mk, lat_sat, steps_sat, worst_sat, its, last_sat, outs_sat = run(np.zeros(n))
     print(f"[bench] served saturated: last completion per class (s): {last_sat}",
@@ -728,6 +733,11 @@ def serve(args):
             "plain_fp64_batched_solves_per_s": round(plain64, 2),
             "plain_mixed_batched_solves_per_s": round(plain32, 2),
             "plain_mixed_seconds_per_class": plain32_cls,
+            # the same per-class settings as served (FP32 cycle except 3-D p = 64):
+            # what continuous batching adds over one batched solve per class
+            "plain_served_settings_batched_solves_per_s": round(plainc, 2),
+            "plain_served_settings_seconds_per_class": plainc_cls,
+            "speedup_vs_plain_served_settings": round(thr / plainc, 3),
             "saturated_last_done_s": last_sat,
             "speedup_vs_plain_fp64": round(thr / plain64, 3),
             "speedup_vs_plain_mixed": round(thr / plain32, 3),
@@ -739,7 +749,8 @@ def serve(args):
                            "p99": round(float(np.percentile(lat, 99)), 2)},
             "max_relres": worst, "iterations_median": int(np.median(its)),
             "plain_not_converged": {"fp64": failed.get(pmg.PMG_F64, 0),
-                                    "mixed": failed.get(pmg.PMG_F32, 0)},
+                                    "mixed": failed.get(pmg.PMG_F32, 0),
+                                    "served_settings": failed.get(None, 0)},
             "oracle_check": check,
             "budget_bytes": budget, "steps": int(steps), "iters_per_step": SERVE_ITERS_PER_STEP}
 
