@@ -434,7 +434,10 @@ __device__ void apply2d_mfma(const T* __restrict__ G_, const T* __restrict__ D_,
     const auto r = gmem(r_);
     const auto out = gmem(out_);
     static_assert(P % 16 == 0, "tiles cover rows 1..P");
-    constexpr int BLK = P >= 64 ? 2 : 1;           // tiles per block side
+    // tiles per block side: 2 x 2 blocks at p >= 128; at p = 64 single tiles
+    // keep all eight waves busy and the function under fewer registers to
+    // save and restore per call (measured faster inside the cycle)
+    constexpr int BLK = P >= 128 ? 2 : 1;
     constexpr int n1 = P + 1, N = n1 * n1, NB = P / (16 * BLK);
     using V4 = typename Mfma<T>::v4;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -467,18 +470,44 @@ __device__ void apply2d_mfma(const T* __restrict__ G_, const T* __restrict__ D_,
                 }
             }
     }
-    for (int e = threadIdx.x; e < 2 * P + 1; e += NT) {
-        const int j = e <= P ? 0 : e - P, i = e <= P ? e : 0;
-        T ur = 0, us = 0;
-#pragma unroll 8
-        for (int k = 0; k < n1; ++k) {   // loads of eight terms in flight
-            ur += x[j * n1 + k] * DT[k * n1 + i];
-            us += D[j * n1 + k] * x[k * n1 + i];
+    // Index 0 of the gradients on the vector units.  The second pass reads
+    // only F1 on row 0 (columns 1..P) and F0 on column 0 (rows 1..P), so
+    // those 2P fluxes are formed (the corner's are never read).  Each of
+    // their 4P dot products (ur and us of a node) is split over KS lanes
+    // that take every KS-th term, summed by a fixed butterfly, so that every
+    // thread of the workgroup carries a short chain of loads.
+    {
+        constexpr int NODES = 2 * P;
+        constexpr int KS = NT >= 16 * NODES ? 8 : NT >= 8 * NODES ? 4 : NT >= 4 * NODES ? 2 : 1;
+        constexpr int KT = (n1 + KS - 1) / KS;       // terms per lane
+        constexpr int TASKS = NODES * 2 * KS;        // node-major, then ur / us, then k-part
+        static_assert(64 % (2 * KS) == 0 && NT % (2 * KS) == 0, "a node's lanes share a wave");
+        for (int t = threadIdx.x; t < TASKS; t += NT) {
+            const int node = t / (2 * KS), a = (t / KS) & 1, part = t % KS;
+            const bool row = node < P;                // row 0, column node + 1
+            const int at = row ? 0 : (node - P + 1) * n1;   // first factor's row
+            const int bt = row ? node + 1 : 0;              // second factor's column
+            // ur = sum_k x[at + k] DT[k][bt], us = sum_k D[at + k] x[k][bt]
+            const auto A = a == 0 ? x : D;
+            const auto Bm = a == 0 ? DT : x;
+            T acc = 0;
+#pragma unroll 16
+            for (int u = 0; u < KT; ++u) {
+                const int k = part + u * KS;
+                if (KT * KS == n1 || k < n1) acc += A[at + k] * Bm[k * n1 + bt];
+            }
+#pragma unroll
+            for (int o = KS / 2; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+            const T other = __shfl_xor(acc, KS, 64);
+            if (a == 0 && part == 0) {
+                const T ur = acc, us = other;
+                const int q = at + bt;
+                if (row)
+                    TR[N + q] = G[2 * N + q] * ur + G[N + q] * us;   // F1 = g01 ur + g11 us
+                else
+                    TR[q] = G[q] * ur + G[2 * N + q] * us;           // F0 = g00 ur + g01 us
+            }
         }
-        const int q = j * n1 + i;
-        const T g00 = G[q], g11 = G[N + q], g01 = G[2 * N + q];
-        TR[q] = g00 * ur + g01 * us;
-        TR[N + q] = g01 * ur + g11 * us;
     }
     wg_barrier();
     for (int t = wave; t < NB * NB; t += NT / 64) {
@@ -1749,24 +1778,69 @@ __device__ inline int interior_node(int i)
     return DIM == 2 ? i0 + n1 * i1 : i0 + n1 * i1 + n1 * n1 * (i / (n * n) + 1);
 }
 
-// x = C r on the interior of level P (FP64 arithmetic whatever T), zero boundary
+// x = C r on the interior of level P (FP64 arithmetic whatever T), zero
+// boundary.  r's interior is staged in LDS (the line-strip buffer, free
+// between the phases of a cycle); each entry of C r is split over KS lanes
+// that take consecutive chunks of its terms (coalesced loads of C's rows),
+// and the chunks are added in a fixed order.  Out of line and small: the
+// function needs no callee-saved registers.
 template <class T, int P, int DIM>
-__device__ void collapsed_solve(const double* C_, const T* r_, T* x_)
+__device__ __attribute__((noinline)) void collapsed_solve(const double* C_, const T* r_, T* x_)
 {
     using S = Shape<P, DIM>;
     constexpr int ni = ipow(P - 1, DIM);
+    constexpr int KS = 2 * ni <= NT ? 2 : 1;          // lanes per entry
+    constexpr int KL = (ni + KS - 1) / KS;            // terms per lane
+    static_assert(3 * ni <= LINE_STRIP_WORDS, "r and the partial sums fit the strip buffer");
     const auto C = gmem(C_);
     const auto r = gmem(r_);
     const auto x = gmem(x_);
+    const auto rl = (__attribute__((address_space(3))) double*)line_strip_lds();
+    for (int i = threadIdx.x; i < ni; i += NT) rl[i] = (double)r[interior_node<P, DIM>(i)];
     for (int q = threadIdx.x; q < S::N; q += NT)
         if (is_boundary<P, DIM>(q)) x[q] = T(0);
-    for (int j = threadIdx.x; j < ni; j += NT) {
+    wg_barrier();
+    for (int t = threadIdx.x; t < KS * ni; t += NT) {
+        const int part = t / ni, j = t - part * ni;
+        const int i0 = part * KL, i1 = i0 + KL < ni ? i0 + KL : ni;
         double s = 0.0;
-#pragma unroll 7
-        for (int i = 0; i < ni; ++i) s += C[(long long)i * ni + j] * (double)r[interior_node<P, DIM>(i)];
-        x[interior_node<P, DIM>(j)] = T(s);
+#pragma unroll 8
+        for (int i = i0; i < i1; ++i) s += C[(long long)i * ni + j] * rl[i];
+        if (KS == 1)
+            x[interior_node<P, DIM>(j)] = T(s);
+        else if (part == 1)
+            rl[ni + j] = s;
+        else
+            rl[2 * ni + j] = s;
+    }
+    if constexpr (KS > 1) {
+        wg_barrier();
+        for (int j = threadIdx.x; j < ni; j += NT)
+            x[interior_node<P, DIM>(j)] = T(rl[2 * ni + j] + rl[ni + j]);
     }
     wg_barrier();
+}
+
+template <class T, int P, int DIM, int CMAX, bool E>
+__device__ __attribute__((noinline)) void gamma_cycle(const Hier<T>& H, int b, const T* r, T* x);
+
+// The coarse level's M^{-1} r of a coarse-grid correction: a level the
+// hierarchy holds a dense matrix for is applied here, in the caller, which
+// saves that level's out-of-line call and the registers it saves and
+// restores (27 visits per fine cycle at gamma = 3); others recurse.
+template <class T, int P, int DIM, int CMAX, bool E>
+__device__ __attribute__((always_inline)) inline void coarse_correction(const Hier<T>& H, int b,
+                                                                         const T* r, T* x)
+{
+    using S = Shape<P, DIM>;
+    if constexpr (P <= CMAX && (P >= collapse_lo(DIM) || (E && P >= 4))) {
+        if (H.Cc[S::LEV]) {
+            constexpr int ni = ipow(P - 1, DIM);
+            collapsed_solve<T, P, DIM>(H.Cc[S::LEV] + (long long)b * ni * ni, r, x);
+            return;
+        }
+    }
+    gamma_cycle<T, P, DIM, CMAX, E>(H, b, r, x);
 }
 
 // x = M_l^{-1} r (Alg. 2).  Readings: pre-smoothing m steps per axis in axis
@@ -1829,7 +1903,7 @@ __device__ __attribute__((noinline)) void gamma_cycle(const Hier<T>& H, int b, c
                 apply_level<T, P, DIM, true>(L.G + (long long)b * S::NC * S::N, L.D, L.DT,
                                              L.TR + (long long)b * DIM * S::N, x, r, tmp);
             restrict_level<T, P, DIM>(tmp, rc, L.JR, L.JT, w1, w2);
-            gamma_cycle<T, P / 2, DIM, CMAX, E>(H, b, rc, xc);
+            coarse_correction<T, P / 2, DIM, CMAX, E>(H, b, rc, xc);
             prolong_level<T, P, DIM>(xc, x, L.J, L.JT, w1, w2);
             for (int dir = DIM - 1; dir >= 0; --dir)
                 for (int s = 0; s < H.m; ++s) smooth_step<T, P, DIM, E>(H, b, dir, r, x, false);
