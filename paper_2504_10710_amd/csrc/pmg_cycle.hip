@@ -1,4 +1,6 @@
 // pmg_cycle.hip -- one gamma-cycle application per problem.
+// room in LDS for the 2-D operator at p = 64 (x and F0 in FP64)
+#define PMG_WORK_LDS_WORDS (2 * 65 * 65)
 #include <cmath>
 
 #include "pmg_dispatch.hpp"

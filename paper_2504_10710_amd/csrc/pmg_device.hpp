@@ -118,6 +118,29 @@ __device__ inline __attribute__((address_space(1))) T* gmem(__attribute__((addre
     return p;
 }
 
+// LDS pointers pass through unchanged (operands staged in LDS)
+template <class T>
+__device__ inline __attribute__((address_space(3))) T* gmem(__attribute__((address_space(3))) T* p)
+{
+    return p;
+}
+
+// One LDS work buffer per kernel, shared by the phases of a workgroup that
+// stage data on chip (strided line strips, the collapsed solve's right-hand
+// side, the operand and flux of the 2-D operator at p <= 64); every phase
+// ends with a barrier before the next one writes it.  Its size is set per
+// compilation unit: the one-launch solve and cycle kernels take room for the
+// p = 64 operator (two FP64 fields of 65^2 words, 68 KB, still two
+// workgroups per CU), the single-operation kernels the line strip only.
+#ifndef PMG_WORK_LDS_WORDS
+#define PMG_WORK_LDS_WORDS (127 * 17)
+#endif
+__device__ inline void* work_lds()
+{
+    __shared__ double buf[PMG_WORK_LDS_WORDS];
+    return buf;
+}
+
 template <class T>
 __device__ inline void wg_copy(T* __restrict__ dst_, const T* __restrict__ src_, int n)
 {
@@ -420,20 +443,28 @@ __device__ inline void mfma_blocks(PA0 a0_, PB0 b0_, PA1 a1_, PB1 b1_,
 // 16x16 tiles (both gradients of the block), combined into the fluxes at
 // once; row 0 and column 0 on the vector units.  Pass 2: F0 D + D^T F1 on
 // the same blocks, both products accumulating into one set of tiles; the
-// boundary rows and columns are zero.
-template <class T, int P, bool RESID>
-__device__ void apply2d_mfma(const T* __restrict__ G_, const T* __restrict__ D_,
-                             const T* __restrict__ DT_, T* __restrict__ TR_,
-                             const T* __restrict__ x_, const T* __restrict__ r_, T* __restrict__ out_)
+// boundary rows and columns are zero.  Where the work buffer holds them
+// (p <= 64), x and F0 (and F1 where three fields fit) live in LDS: x is
+// read once from memory and the flux round trip stays on chip; the
+// arithmetic is the same.
+// The two passes of apply2d_mfma on operands given by their own pointers
+// (LDS or global): xs the operand of the first pass, f0 / f1 the fluxes
+// (F1SEP false: F1 follows F0 at f0 + N, one base pointer, which is how the
+// global form is compiled best); x the operand in memory (boundary
+// gradients).
+template <class T, int P, bool RESID, bool F1SEP, class PX, class PF0, class PF1>
+__device__ inline void apply2d_mfma_passes(const T* __restrict__ G_, const T* __restrict__ D_,
+                                           const T* __restrict__ DT_, PX __restrict__ xs,
+                                           PF0 __restrict__ f0, PF1 __restrict__ f1,
+                                           const T* __restrict__ x_, const T* __restrict__ r_,
+                                           T* __restrict__ out_)
 {
     const auto G = gmem(G_);
     const auto D = gmem(D_);
     const auto DT = gmem(DT_);
-    const auto TR = gmem(TR_);
     const auto x = gmem(x_);
     const auto r = gmem(r_);
     const auto out = gmem(out_);
-    static_assert(P % 16 == 0, "tiles cover rows 1..P");
     // tiles per block side: 2 x 2 blocks at p >= 128; at p = 64 single tiles
     // keep all eight waves busy and the function under fewer registers to
     // save and restore per call (measured faster inside the cycle)
@@ -452,10 +483,10 @@ __device__ void apply2d_mfma(const T* __restrict__ G_, const T* __restrict__ D_,
                 ur[i][j] = V4{0, 0, 0, 0};
                 us[i][j] = V4{0, 0, 0, 0};
             }
-        mfma_blocks<T, n1, n1, n1, 1, n1, BLK, BLK, 2, 1, n1>(x + (r0 + lr) * n1 + kq,
+        mfma_blocks<T, n1, n1, n1, 1, n1, BLK, BLK, 2, 1, n1>(xs + (r0 + lr) * n1 + kq,
                                                               DT + kq * n1 + c0 + lr,
                                                               DT + kq * n1 + r0 + lr,
-                                                              x + kq * n1 + c0 + lr, ur, us);
+                                                              xs + kq * n1 + c0 + lr, ur, us);
 #pragma unroll
         for (int i = 0; i < BLK; ++i)
 #pragma unroll
@@ -465,8 +496,11 @@ __device__ void apply2d_mfma(const T* __restrict__ G_, const T* __restrict__ D_,
                 for (int v = 0; v < 4; ++v) {
                     const int q = (r0 + 16 * i + Mfma<T>::row(lane, v)) * n1 + col;
                     const T g00 = G[q], g11 = G[N + q], g01 = G[2 * N + q];
-                    TR[q] = g00 * ur[i][j][v] + g01 * us[i][j][v];
-                    TR[N + q] = g01 * ur[i][j][v] + g11 * us[i][j][v];
+                    f0[q] = g00 * ur[i][j][v] + g01 * us[i][j][v];
+                    if constexpr (F1SEP)
+                        f1[q] = g01 * ur[i][j][v] + g11 * us[i][j][v];
+                    else
+                        f0[N + q] = g01 * ur[i][j][v] + g11 * us[i][j][v];
                 }
             }
     }
@@ -502,10 +536,14 @@ __device__ void apply2d_mfma(const T* __restrict__ G_, const T* __restrict__ D_,
             if (a == 0 && part == 0) {
                 const T ur = acc, us = other;
                 const int q = at + bt;
-                if (row)
-                    TR[N + q] = G[2 * N + q] * ur + G[N + q] * us;   // F1 = g01 ur + g11 us
-                else
-                    TR[q] = G[q] * ur + G[2 * N + q] * us;           // F0 = g00 ur + g01 us
+                if (row) {   // F1 = g01 ur + g11 us
+                    if constexpr (F1SEP)
+                        f1[q] = G[2 * N + q] * ur + G[N + q] * us;
+                    else
+                        f0[N + q] = G[2 * N + q] * ur + G[N + q] * us;
+                } else {     // F0 = g00 ur + g01 us
+                    f0[q] = G[q] * ur + G[2 * N + q] * us;
+                }
             }
         }
     }
@@ -518,10 +556,16 @@ __device__ void apply2d_mfma(const T* __restrict__ G_, const T* __restrict__ D_,
 #pragma unroll
             for (int j = 0; j < BLK; ++j) y[i][j] = V4{0, 0, 0, 0};
         // sum_k F0[j][k] D[k][i] and sum_k D^T[j][k] F1[k][i]
-        mfma_blocks<T, n1, n1, n1, 1, n1, BLK, BLK, 2, 1, n1>(TR + (r0 + lr) * n1 + kq,
-                                                              D + kq * n1 + c0 + lr,
-                                                              D + kq * n1 + r0 + lr,
-                                                              TR + N + kq * n1 + c0 + lr, y, y);
+        if constexpr (F1SEP)
+            mfma_blocks<T, n1, n1, n1, 1, n1, BLK, BLK, 2, 1, n1>(f0 + (r0 + lr) * n1 + kq,
+                                                                  D + kq * n1 + c0 + lr,
+                                                                  D + kq * n1 + r0 + lr,
+                                                                  f1 + kq * n1 + c0 + lr, y, y);
+        else
+            mfma_blocks<T, n1, n1, n1, 1, n1, BLK, BLK, 2, 1, n1>(f0 + (r0 + lr) * n1 + kq,
+                                                                  D + kq * n1 + c0 + lr,
+                                                                  D + kq * n1 + r0 + lr,
+                                                                  f0 + N + kq * n1 + c0 + lr, y, y);
 #pragma unroll
         for (int i = 0; i < BLK; ++i)
 #pragma unroll
@@ -537,6 +581,32 @@ __device__ void apply2d_mfma(const T* __restrict__ G_, const T* __restrict__ D_,
     }
     for (int e = threadIdx.x; e < 2 * P + 1; e += NT) out[e <= P ? e : (e - P) * n1] = T(0);
     wg_barrier();
+}
+
+template <class T, int P, bool RESID>
+__device__ void apply2d_mfma(const T* __restrict__ G_, const T* __restrict__ D_,
+                             const T* __restrict__ DT_, T* __restrict__ TR_,
+                             const T* __restrict__ x_, const T* __restrict__ r_, T* __restrict__ out_)
+{
+    static_assert(P % 16 == 0, "tiles cover rows 1..P");
+    constexpr int N = (P + 1) * (P + 1);
+    constexpr int LDSW = PMG_WORK_LDS_WORDS * (int)(sizeof(double) / sizeof(T));   // in T words
+    constexpr bool XL = P <= 64 && 2 * N <= LDSW;    // x and F0 in LDS
+    constexpr bool F1L = XL && 3 * N <= LDSW;        // F1 as well
+    const auto TR = gmem(TR_);
+    if constexpr (XL) {
+        const auto wl = (__attribute__((address_space(3))) T*)work_lds();
+        const auto x = gmem(x_);
+        for (int q = threadIdx.x; q < N; q += NT) wl[q] = x[q];
+        wg_barrier();
+        if constexpr (F1L)
+            apply2d_mfma_passes<T, P, RESID, true>(G_, D_, DT_, wl, wl + N, wl + 2 * N, x_, r_,
+                                                   out_);
+        else
+            apply2d_mfma_passes<T, P, RESID, true>(G_, D_, DT_, wl, wl + N, TR + N, x_, r_, out_);
+    } else {
+        apply2d_mfma_passes<T, P, RESID, false>(G_, D_, DT_, gmem(x_), TR, TR, x_, r_, out_);
+    }
 }
 
 // 3-D A x on matrix cores, node q = i + n1 j + n1^2 k.  The four passes are
@@ -1397,15 +1467,9 @@ __device__ void line_cr_wave(const T* __restrict__ cr_, T* __restrict__ g_, T* _
     wg_barrier();
 }
 
-// LDS strip shared by the strided line solves of every level (one
-// allocation per kernel): up to 16 lines of 127 unknowns or 32 of 63, padded
-// rows.
+// LDS strip of the strided line solves: up to 16 lines of 127 unknowns or
+// 32 of 63, padded rows.
 constexpr int LINE_STRIP_WORDS = 127 * 17;
-__device__ inline void* line_strip_lds()
-{
-    __shared__ double buf[LINE_STRIP_WORDS];
-    return buf;
-}
 
 // Lines along the second axis (and the third in 3-D), strided in memory, in
 // strips of SW adjacent lines (consecutive first-axis positions at one value
@@ -1425,10 +1489,14 @@ __device__ void line_cr_wave_strided(const T* __restrict__ cr_, int dir, T* __re
     constexpr int n1 = S::n1, n = S::n, CRW = S::CRW;
     constexpr int W = (n + 1) / 2 > 0 ? (n + 1) / 2 : 1;
     constexpr int LPW = 64 / W;
-    constexpr int SW = n > 63 ? 16 : 32, LD = SW + 1;        // lines per strip, LDS row
+    // lines per strip: 64 long lines where the work buffer holds them (fewer
+    // barriers, 512-byte row segments), else 16; 32 short ones
+    constexpr int SW = n > 63 ? (n * 65 * (int)sizeof(T) <= 8 * PMG_WORK_LDS_WORDS ? 64 : 16) : 32;
+    constexpr int LD = SW + 1;                               // LDS row
     constexpr int NO = DIM == 2 ? 1 : n;                     // values of the outer coordinate
-    static_assert(n * LD * sizeof(T) <= sizeof(double) * LINE_STRIP_WORDS, "strip fits");
-    const auto strip = (__attribute__((address_space(3))) T*)line_strip_lds();
+    static_assert(n * LD * sizeof(T) <= sizeof(double) * PMG_WORK_LDS_WORDS, "strip fits");
+    static_assert(LINE_STRIP_WORDS <= PMG_WORK_LDS_WORDS, "the work buffer holds a strip");
+    const auto strip = (__attribute__((address_space(3))) T*)work_lds();
     const int RS = dir == 1 ? n1 : n1 * n1;                  // stride along the line
     const int OS = DIM == 2 ? 0 : (dir == 1 ? n1 * n1 : n1); // stride of the outer coordinate
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1779,8 +1847,7 @@ __device__ inline int interior_node(int i)
 }
 
 // x = C r on the interior of level P (FP64 arithmetic whatever T), zero
-// boundary.  r's interior is staged in LDS (the line-strip buffer, free
-// between the phases of a cycle); each entry of C r is split over KS lanes
+// boundary.  r's interior is staged in LDS (the work buffer); each entry of C r is split over KS lanes
 // that take consecutive chunks of its terms (coalesced loads of C's rows),
 // and the chunks are added in a fixed order.  Out of line and small: the
 // function needs no callee-saved registers.
@@ -1791,11 +1858,11 @@ __device__ __attribute__((noinline)) void collapsed_solve(const double* C_, cons
     constexpr int ni = ipow(P - 1, DIM);
     constexpr int KS = 2 * ni <= NT ? 2 : 1;          // lanes per entry
     constexpr int KL = (ni + KS - 1) / KS;            // terms per lane
-    static_assert(3 * ni <= LINE_STRIP_WORDS, "r and the partial sums fit the strip buffer");
+    static_assert(3 * ni <= PMG_WORK_LDS_WORDS, "r and the partial sums fit the work buffer");
     const auto C = gmem(C_);
     const auto r = gmem(r_);
     const auto x = gmem(x_);
-    const auto rl = (__attribute__((address_space(3))) double*)line_strip_lds();
+    const auto rl = (__attribute__((address_space(3))) double*)work_lds();
     for (int i = threadIdx.x; i < ni; i += NT) rl[i] = (double)r[interior_node<P, DIM>(i)];
     for (int q = threadIdx.x; q < S::N; q += NT)
         if (is_boundary<P, DIM>(q)) x[q] = T(0);

@@ -1,4 +1,6 @@
 // pmg_solve_f64.hip -- instances of the solve kernel, FP64 inner cycle.
+// room in LDS for the 2-D operator at p = 64 (x and F0 in FP64)
+#define PMG_WORK_LDS_WORDS (2 * 65 * 65)
 #include "pmg_solve.hpp"
 
 namespace pmg {
