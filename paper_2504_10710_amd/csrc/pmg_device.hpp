@@ -127,11 +127,12 @@ __device__ inline __attribute__((address_space(3))) T* gmem(__attribute__((addre
 
 // One LDS work buffer per kernel, shared by the phases of a workgroup that
 // stage data on chip (strided line strips, the collapsed solve's right-hand
-// side, the operand and flux of the 2-D operator at p <= 64); every phase
+// side, the operands and fluxes of the 2-D operator at p <= 64); every phase
 // ends with a barrier before the next one writes it.  Its size is set per
 // compilation unit: the one-launch solve and cycle kernels take room for the
-// p = 64 operator (two FP64 fields of 65^2 words, 68 KB, still two
-// workgroups per CU), the single-operation kernels the line strip only.
+// p = 32 operator's eight fields of 33^2 FP64 words (70 KB, which also holds
+// two p = 64 fields; still two workgroups per CU), the single-operation
+// kernels the line strip only.
 #ifndef PMG_WORK_LDS_WORDS
 #define PMG_WORK_LDS_WORDS (127 * 17)
 #endif
@@ -290,8 +291,8 @@ __device__ inline void mfma2(PA0 a0_, PB0 b0_, PA1 a1_, PB1 b1_,
 // a 16 x 32 block as two 16x16 tiles that share their A rows; rows and
 // columns past M, N are clamped in the loads and never stored.
 template <class T, int M, int N, int K, int LDA, int LDB, int MODE, bool ATR = false, int NS = 1,
-          int SB = 0, int SC = 0>
-__device__ void wg_gemm(const T* __restrict__ A, const T* __restrict__ B_, T* __restrict__ C_)
+          int SB = 0, int SC = 0, class PA, class PB, class PC>
+__device__ void wg_gemm(PA __restrict__ A, PB __restrict__ B_, PC __restrict__ C_)
 {
     const auto C = gmem(C_);
     constexpr int TM = (M + 15) / 16, TN2 = (N + 31) / 32;
@@ -303,11 +304,11 @@ __device__ void wg_gemm(const T* __restrict__ A, const T* __restrict__ B_, T* __
         const int r0 = (tt / TN2) * 16, c0 = (tt % TN2) * 32;
         const int ar = min(r0 + lr, M - 1);
         const int bc0 = min(c0 + lr, N - 1), bc1 = min(c0 + 16 + lr, N - 1);
-        const T* B = B_ + (long long)sl * SB;
+        const auto B = B_ + (long long)sl * SB;
         const auto Cs = C + (long long)sl * SC;
         V4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
         constexpr int SA = ATR ? LDA : 1;
-        const T* ap = ATR ? A + kq * LDA + ar : A + ar * LDA + kq;
+        const auto ap = ATR ? A + kq * LDA + ar : A + ar * LDA + kq;
         mfma2<T, K, SA, LDB, SA, LDB>(ap, B + kq * LDB + bc0, ap, B + kq * LDB + bc1, acc0, acc1);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -448,21 +449,19 @@ __device__ inline void mfma_blocks(PA0 a0_, PB0 b0_, PA1 a1_, PB1 b1_,
 // read once from memory and the flux round trip stays on chip; the
 // arithmetic is the same.
 // The two passes of apply2d_mfma on operands given by their own pointers
-// (LDS or global): xs the operand of the first pass, f0 / f1 the fluxes
-// (F1SEP false: F1 follows F0 at f0 + N, one base pointer, which is how the
-// global form is compiled best); x the operand in memory (boundary
-// gradients).
-template <class T, int P, bool RESID, bool F1SEP, class PX, class PF0, class PF1>
-__device__ inline void apply2d_mfma_passes(const T* __restrict__ G_, const T* __restrict__ D_,
-                                           const T* __restrict__ DT_, PX __restrict__ xs,
-                                           PF0 __restrict__ f0, PF1 __restrict__ f1,
-                                           const T* __restrict__ x_, const T* __restrict__ r_,
+// (LDS or global): G the geometric factors, D / DT the derivative matrix and
+// its transpose, xs the operand of the first pass, xb the operand of the
+// boundary gradients (in D's memory), f0 / f1 the fluxes (F1SEP false: F1
+// follows F0 at f0 + N, one base pointer, which is how the global form is
+// compiled best).
+template <class T, int P, bool RESID, bool F1SEP, class PG, class PD, class PX, class PB, class PF0,
+          class PF1>
+__device__ inline void apply2d_mfma_passes(PG __restrict__ G, PD __restrict__ D,
+                                           PD __restrict__ DT, PX __restrict__ xs,
+                                           PB __restrict__ xb, PF0 __restrict__ f0,
+                                           PF1 __restrict__ f1, const T* __restrict__ r_,
                                            T* __restrict__ out_)
 {
-    const auto G = gmem(G_);
-    const auto D = gmem(D_);
-    const auto DT = gmem(DT_);
-    const auto x = gmem(x_);
     const auto r = gmem(r_);
     const auto out = gmem(out_);
     // tiles per block side: 2 x 2 blocks at p >= 128; at p = 64 single tiles
@@ -522,8 +521,8 @@ __device__ inline void apply2d_mfma_passes(const T* __restrict__ G_, const T* __
             const int at = row ? 0 : (node - P + 1) * n1;   // first factor's row
             const int bt = row ? node + 1 : 0;              // second factor's column
             // ur = sum_k x[at + k] DT[k][bt], us = sum_k D[at + k] x[k][bt]
-            const auto A = a == 0 ? x : D;
-            const auto Bm = a == 0 ? DT : x;
+            const auto A = a == 0 ? xb : D;
+            const auto Bm = a == 0 ? DT : xb;
             T acc = 0;
 #pragma unroll 16
             for (int u = 0; u < KT; ++u) {
@@ -555,6 +554,14 @@ __device__ inline void apply2d_mfma_passes(const T* __restrict__ G_, const T* __
         for (int i = 0; i < BLK; ++i)
 #pragma unroll
             for (int j = 0; j < BLK; ++j) y[i][j] = V4{0, 0, 0, 0};
+        // single tiles: the residual's right-hand side is loaded before the
+        // products, its latency hidden behind them
+        constexpr bool PRE = RESID && BLK == 1;
+        T rv[4];
+        if constexpr (PRE) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) rv[v] = r[(r0 + Mfma<T>::row(lane, v)) * n1 + c0 + lr];
+        }
         // sum_k F0[j][k] D[k][i] and sum_k D^T[j][k] F1[k][i]
         if constexpr (F1SEP)
             mfma_blocks<T, n1, n1, n1, 1, n1, BLK, BLK, 2, 1, n1>(f0 + (r0 + lr) * n1 + kq,
@@ -575,7 +582,8 @@ __device__ inline void apply2d_mfma_passes(const T* __restrict__ G_, const T* __
                 for (int v = 0; v < 4; ++v) {
                     const int row = r0 + 16 * i + Mfma<T>::row(lane, v);
                     const int q = row * n1 + col;
-                    out[q] = (col == P || row == P) ? T(0) : (RESID ? r[q] - y[i][jj][v] : y[i][jj][v]);
+                    const T rq = RESID ? (PRE ? rv[v] : r[q]) : T(0);
+                    out[q] = (col == P || row == P) ? T(0) : (RESID ? rq - y[i][jj][v] : y[i][jj][v]);
                 }
             }
     }
@@ -591,21 +599,38 @@ __device__ void apply2d_mfma(const T* __restrict__ G_, const T* __restrict__ D_,
     static_assert(P % 16 == 0, "tiles cover rows 1..P");
     constexpr int N = (P + 1) * (P + 1);
     constexpr int LDSW = PMG_WORK_LDS_WORDS * (int)(sizeof(double) / sizeof(T));   // in T words
+    constexpr bool ALL = P <= 64 && 8 * N <= LDSW;   // x, F0, F1, G, D, D^T in LDS
     constexpr bool XL = P <= 64 && 2 * N <= LDSW;    // x and F0 in LDS
     constexpr bool F1L = XL && 3 * N <= LDSW;        // F1 as well
     const auto TR = gmem(TR_);
-    if constexpr (XL) {
-        const auto wl = (__attribute__((address_space(3))) T*)work_lds();
-        const auto x = gmem(x_);
+    const auto x = gmem(x_);
+    const auto G = gmem(G_);
+    const auto D = gmem(D_);
+    const auto DT = gmem(DT_);
+    const auto wl = (__attribute__((address_space(3))) T*)work_lds();
+    if constexpr (ALL) {
+        // every operand in one round trip; then only the residual's
+        // right-hand side and the result touch memory
+        for (int q = threadIdx.x; q < N; q += NT) {
+            wl[q] = x[q];
+            wl[3 * N + q] = G[q];
+            wl[4 * N + q] = G[N + q];
+            wl[5 * N + q] = G[2 * N + q];
+            wl[6 * N + q] = D[q];
+            wl[7 * N + q] = DT[q];
+        }
+        wg_barrier();
+        apply2d_mfma_passes<T, P, RESID, true>(wl + 3 * N, wl + 6 * N, wl + 7 * N, wl, wl, wl + N,
+                                               wl + 2 * N, r_, out_);
+    } else if constexpr (XL) {
         for (int q = threadIdx.x; q < N; q += NT) wl[q] = x[q];
         wg_barrier();
         if constexpr (F1L)
-            apply2d_mfma_passes<T, P, RESID, true>(G_, D_, DT_, wl, wl + N, wl + 2 * N, x_, r_,
-                                                   out_);
+            apply2d_mfma_passes<T, P, RESID, true>(G, D, DT, wl, x, wl + N, wl + 2 * N, r_, out_);
         else
-            apply2d_mfma_passes<T, P, RESID, true>(G_, D_, DT_, wl, wl + N, TR + N, x_, r_, out_);
+            apply2d_mfma_passes<T, P, RESID, true>(G, D, DT, wl, x, wl + N, TR + N, r_, out_);
     } else {
-        apply2d_mfma_passes<T, P, RESID, false>(G_, D_, DT_, gmem(x_), TR, TR, x_, r_, out_);
+        apply2d_mfma_passes<T, P, RESID, false>(G, D, DT, x, x, TR, TR, r_, out_);
     }
 }
 
@@ -1711,11 +1736,19 @@ __device__ __attribute__((noinline)) void restrict_level(const T* rf, T* rc, con
                                                          const T* JT, T* w1, T* w2)
 {
     constexpr int n1f = P + 1, n1c = P / 2 + 1;
+    constexpr int LDSW = PMG_WORK_LDS_WORDS * (int)(sizeof(double) / sizeof(T));
     if constexpr (DIM == 2 && P >= MFMA_MIN_P) {
-        // W1 = rf J (n1f x n1c); rc = J^T W1 with zero boundary
+        // W1 = rf J (n1f x n1c); rc = J^T W1 with zero boundary; W1 in the
+        // LDS work buffer where it fits (p <= 64)
         (void)w2;
-        wg_gemm<T, n1f, n1c, n1f, n1f, n1c, 0>(rf, J, w1);
-        wg_gemm<T, n1c, n1c, n1f, n1c, n1c, 2, true>(J, w1, rc);
+        if constexpr (P <= 64 && n1f * n1c <= LDSW) {
+            const auto wl = (__attribute__((address_space(3))) T*)work_lds();
+            wg_gemm<T, n1f, n1c, n1f, n1f, n1c, 0>(rf, J, wl);
+            wg_gemm<T, n1c, n1c, n1f, n1c, n1c, 2, true>(J, wl, rc);
+        } else {
+            wg_gemm<T, n1f, n1c, n1f, n1f, n1c, 0>(rf, J, w1);
+            wg_gemm<T, n1c, n1c, n1f, n1c, n1c, 2, true>(J, w1, rc);
+        }
         return;
     }
     if constexpr (DIM == 3 && P >= MFMA_MIN_P) {
@@ -1742,11 +1775,18 @@ template <class T, int P, int DIM>
 __device__ __attribute__((noinline)) void prolong_level(const T* ec, T* xf, const T* J, const T* JT, T* w1, T* w2)
 {
     constexpr int n1f = P + 1, n1c = P / 2 + 1;
+    constexpr int LDSW = PMG_WORK_LDS_WORDS * (int)(sizeof(double) / sizeof(T));
     if constexpr (DIM == 2 && P >= MFMA_MIN_P) {
-        // W1 = ec J^T (n1c x n1f); xf += J W1
+        // W1 = ec J^T (n1c x n1f); xf += J W1; W1 in LDS where it fits
         (void)w2;
-        wg_gemm<T, n1c, n1f, n1c, n1c, n1f, 0>(ec, JT, w1);
-        wg_gemm<T, n1f, n1f, n1c, n1f, n1f, 1, true>(JT, w1, xf);
+        if constexpr (P <= 64 && n1c * n1f <= LDSW) {
+            const auto wl = (__attribute__((address_space(3))) T*)work_lds();
+            wg_gemm<T, n1c, n1f, n1c, n1c, n1f, 0>(ec, JT, wl);
+            wg_gemm<T, n1f, n1f, n1c, n1f, n1f, 1, true>(JT, wl, xf);
+        } else {
+            wg_gemm<T, n1c, n1f, n1c, n1c, n1f, 0>(ec, JT, w1);
+            wg_gemm<T, n1f, n1f, n1c, n1f, n1f, 1, true>(JT, w1, xf);
+        }
         return;
     }
     if constexpr (DIM == 3 && P >= MFMA_MIN_P) {

@@ -1,6 +1,7 @@
 // pmg_solve_f64.hip -- instances of the solve kernel, FP64 inner cycle.
-// room in LDS for the 2-D operator at p = 64 (x and F0 in FP64)
-#define PMG_WORK_LDS_WORDS (2 * 65 * 65)
+// room in LDS for the 2-D operator at p = 64 (x and F0 in FP64) and at
+// p = 32 (every operand: x, F0, F1, G, D, D^T)
+#define PMG_WORK_LDS_WORDS (8 * 33 * 33)
 #include "pmg_solve.hpp"
 
 namespace pmg {
