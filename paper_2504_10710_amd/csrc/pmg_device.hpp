@@ -27,9 +27,12 @@ namespace pmg {
 
 constexpr int NT = 512;          // threads per workgroup (one problem each)
 constexpr int MAX_LEVELS = 9;
-// smallest 2-D degree whose operator and transfers run on the matrix cores
-// (16x16 tiles over rows and columns 1..p); below it the vector units
+// smallest degree whose operator and transfers run on the matrix cores
+// (16x16 tiles over rows and columns 1..p); below it the vector units.  The
+// 2-D operator and transfers start at p = 16, where their operands are
+// staged in LDS.
 constexpr int MFMA_MIN_P = 32;
+constexpr int MFMA_MIN_P2 = 16;
 
 __host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 __host__ __device__ constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
@@ -1131,7 +1134,7 @@ __device__ __attribute__((noinline)) void apply_level(const T* __restrict__ G_,
                                                       const T* __restrict__ x_,
                                                       const T* __restrict__ r_, T* __restrict__ out_)
 {
-    if constexpr (DIM == 2 && P >= MFMA_MIN_P) {
+    if constexpr (DIM == 2 && P >= MFMA_MIN_P2) {
         apply2d_mfma<T, P, RESID>(G_, D_, DT_, TR_, x_, r_, out_);
         return;
     }
@@ -1737,7 +1740,7 @@ __device__ __attribute__((noinline)) void restrict_level(const T* rf, T* rc, con
 {
     constexpr int n1f = P + 1, n1c = P / 2 + 1;
     constexpr int LDSW = PMG_WORK_LDS_WORDS * (int)(sizeof(double) / sizeof(T));
-    if constexpr (DIM == 2 && P >= MFMA_MIN_P) {
+    if constexpr (DIM == 2 && P >= MFMA_MIN_P2) {
         // W1 = rf J (n1f x n1c); rc = J^T W1 with zero boundary; W1 in the
         // LDS work buffer where it fits (p <= 64)
         (void)w2;
@@ -1776,7 +1779,7 @@ __device__ __attribute__((noinline)) void prolong_level(const T* ec, T* xf, cons
 {
     constexpr int n1f = P + 1, n1c = P / 2 + 1;
     constexpr int LDSW = PMG_WORK_LDS_WORDS * (int)(sizeof(double) / sizeof(T));
-    if constexpr (DIM == 2 && P >= MFMA_MIN_P) {
+    if constexpr (DIM == 2 && P >= MFMA_MIN_P2) {
         // W1 = ec J^T (n1c x n1f); xf += J W1; W1 in LDS where it fits
         (void)w2;
         if constexpr (P <= 64 && n1c * n1f <= LDSW) {
