@@ -1257,16 +1257,35 @@ __device__ inline void line_base(int dir, int line, int& base, int& st)
 template <int P>
 __host__ __device__ constexpr bool wave_lines() { return P >= 2 && P <= 128; }
 
+// The two tridiagonal rows lane u of a line's lane group holds (positions
+// 2u and 2u+1), loaded ahead of the solve so that the next line's loads can
+// be in flight while the current one is reduced.
+template <class T>
+struct CrRows {
+    T lF, aF, uF, cl, ca, cu;
+};
+template <class T, class PC>
+__device__ inline CrRows<T> cr_rows(PC c, int u, bool has1)
+{
+    CrRows<T> w;
+    w.lF = c[(2 * u) * 3 + 0];
+    w.aF = c[(2 * u) * 3 + 1];
+    w.uF = c[(2 * u) * 3 + 2];
+    w.cl = has1 ? c[(2 * u + 1) * 3 + 0] : T(0);
+    w.ca = has1 ? c[(2 * u + 1) * 3 + 1] : T(1);
+    w.cu = has1 ? c[(2 * u + 1) * 3 + 2] : T(0);
+    return w;
+}
+
 // Solve one line held by a lane group of W lanes (lane u: e0 = position 2u,
-// e1 = position 2u+1) with its tridiagonal rows c[s*3 + {0,1,2}] = (l, a, u).
-template <class T, int n, int W, class PC>
-__device__ inline void cr_wave_solve(PC c, int u, bool has1, T& e0, T& e1)
+// e1 = position 2u+1) with its tridiagonal rows c[s*3 + {0,1,2}] = (l, a, u),
+// given as the lane's two rows (cr_rows).
+template <class T, int n, int W>
+__device__ inline void cr_wave_solve_rows(const CrRows<T>& rw, int u, bool has1, T& e0, T& e1)
 {
     constexpr int NK = ilog2(n + 1);
-    const T lF = c[(2 * u) * 3 + 0], aF = c[(2 * u) * 3 + 1], uF = c[(2 * u) * 3 + 2];
-    T cl = has1 ? c[(2 * u + 1) * 3 + 0] : T(0);
-    T ca = has1 ? c[(2 * u + 1) * 3 + 1] : T(1);
-    T cu = has1 ? c[(2 * u + 1) * 3 + 2] : T(0);
+    const T lF = rw.lF, aF = rw.aF, uF = rw.uF;
+    T cl = rw.cl, ca = rw.ca, cu = rw.cu;
     // level 0 down: F solve, then C residual and C's coarse row
     const T iF = T(1) / aF;
     const T pl0 = lF * iF, pu0 = uF * iF;
@@ -1332,6 +1351,12 @@ __device__ inline void cr_wave_solve(PC c, int u, bool has1, T& e0, T& e1)
         if (has1) v -= pu0 * e1;
         e0 = v;
     }
+}
+
+template <class T, int n, int W, class PC>
+__device__ inline void cr_wave_solve(PC c, int u, bool has1, T& e0, T& e1)
+{
+    cr_wave_solve_rows<T, n, W>(cr_rows<T>(c, u, has1), u, has1, e0, e1);
 }
 
 // Block cyclic reduction of one line whose matrix has half-bandwidth 2, as a
@@ -1471,7 +1496,51 @@ __device__ void line_cr_wave(const T* __restrict__ cr_, T* __restrict__ g_, T* _
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int u = lane % W, sub = lane / W;
     const bool has1 = 2 * u + 1 < n;
-    for (int line0 = wave * LPW; line0 < NL; line0 += (NT / 64) * LPW) {
+    constexpr int STEP = (NT / 64) * LPW;
+    if constexpr (!BAND) {
+        // software-pipelined: a line's rows, right-hand side and (fused) x
+        // are loaded together, one line ahead of its reduction
+        const bool rdx = FUSED && !assign;
+        auto load = [&](int line0, CrRows<T>& rw, T& e0, T& e1, T& x0, T& x1) {
+            const int line = line0 + sub;
+            const int lc = line < NL ? line : NL - 1;
+            int base, st;
+            line_base<P, DIM>(0, lc, base, st);
+            rw = cr_rows<T>(cr + (long long)lc * 3 * CRW, u, has1);
+            e0 = g[base + 2 * u + 1];
+            e1 = has1 ? g[base + 2 * u + 2] : T(0);
+            x0 = rdx ? x[base + 2 * u + 1] : T(0);
+            x1 = rdx && has1 ? x[base + 2 * u + 2] : T(0);
+        };
+        CrRows<T> rn;
+        T e0n, e1n, x0n, x1n;
+        int line0 = wave * LPW;
+        if (line0 < NL) load(line0, rn, e0n, e1n, x0n, x1n);
+        for (; line0 < NL; line0 += STEP) {
+            const CrRows<T> rw = rn;
+            T e0 = e0n, e1 = e1n;
+            const T x0 = x0n, x1 = x1n;
+            if (line0 + STEP < NL) load(line0 + STEP, rn, e0n, e1n, x0n, x1n);
+            const int line = line0 + sub;
+            cr_wave_solve_rows<T, n, W>(rw, u, has1, e0, e1);
+            if (line < NL) {
+                int base, st;
+                line_base<P, DIM>(0, line, base, st);
+                const int q0 = base + 2 * u + 1;
+                if (FUSED) {
+                    x[q0] = x0 + alpha * e0;
+                    if (has1) x[q0 + 1] = x1 + alpha * e1;
+                } else {
+                    const auto z = x_ ? x : g;
+                    z[q0] = e0;
+                    if (has1) z[q0 + 1] = e1;
+                }
+            }
+        }
+        wg_barrier();
+        return;
+    }
+    for (int line0 = wave * LPW; line0 < NL; line0 += STEP) {
         const int line = line0 + sub;
         const bool act = line < NL;
         const int lc = act ? line : NL - 1;
@@ -1530,21 +1599,39 @@ __device__ void line_cr_wave_strided(const T* __restrict__ cr_, int dir, T* __re
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int u = lane % W, sub = lane / W;
     const bool has1 = 2 * u + 1 < n;
+    constexpr int STEP = (NT / 64) * LPW;
+    // the rows of the line a lane group solves (the same line index as the
+    // loop below), loaded one line ahead; the first ones while the strip's
+    // right-hand sides arrive
+    auto rows_of = [&](int s0, int l0, int o) {
+        const int sc = min(s0 + sub, SW - 1);
+        const int lc = min(l0 + sc, n - 1) + n * o;
+        return cr_rows<T>(cr + (long long)lc * 3 * CRW, u, has1);
+    };
     for (int o = 0; o < NO; ++o) {
         const int ob = DIM == 2 ? 0 : (o + 1) * OS;
         for (int l0 = 0; l0 < n; l0 += SW) {
+            CrRows<T> rn;
+            if constexpr (!BAND)
+                if (wave * LPW < SW) rn = rows_of(wave * LPW, l0, o);
             for (int e = threadIdx.x; e < n * SW; e += NT) {
                 const int r = e / SW, ci = e % SW, i = l0 + ci;
                 strip[r * LD + ci] = i < n ? g[ob + (r + 1) * RS + i + 1] : T(0);
             }
             wg_barrier();
-            for (int s0 = wave * LPW; s0 < SW; s0 += (NT / 64) * LPW) {
+            for (int s0 = wave * LPW; s0 < SW; s0 += STEP) {
                 const int sl = s0 + sub;                   // line within the strip
                 const int sc = min(sl, SW - 1);            // lane groups past the strip
                 const int lc = min(l0 + sc, n - 1) + n * o;   // compute on a copy, store nothing
                 T e0 = strip[(2 * u) * LD + sc];
                 T e1 = has1 ? strip[(2 * u + 1) * LD + sc] : T(0);
-                wave_line_solve<T, n, W, CRW, BAND>(cr, lc, u, has1, e0, e1);
+                if constexpr (BAND) {
+                    wave_line_solve<T, n, W, CRW, BAND>(cr, lc, u, has1, e0, e1);
+                } else {
+                    const CrRows<T> rw = rn;
+                    if (s0 + STEP < SW) rn = rows_of(s0 + STEP, l0, o);
+                    cr_wave_solve_rows<T, n, W>(rw, u, has1, e0, e1);
+                }
                 if (sl < SW) {
                     strip[(2 * u) * LD + sl] = e0;
                     if (has1) strip[(2 * u + 1) * LD + sl] = e1;
