@@ -1829,9 +1829,9 @@ __device__ __attribute__((noinline)) void restrict_level(const T* rf, T* rc, con
     constexpr int LDSW = PMG_WORK_LDS_WORDS * (int)(sizeof(double) / sizeof(T));
     if constexpr (DIM == 2 && P >= MFMA_MIN_P2) {
         // W1 = rf J (n1f x n1c); rc = J^T W1 with zero boundary; W1 in the
-        // LDS work buffer where it fits (p <= 64)
+        // LDS work buffer where it fits (p <= 128 in the solve kernels)
         (void)w2;
-        if constexpr (P <= 64 && n1f * n1c <= LDSW) {
+        if constexpr (n1f * n1c <= LDSW) {
             const auto wl = (__attribute__((address_space(3))) T*)work_lds();
             wg_gemm<T, n1f, n1c, n1f, n1f, n1c, 0>(rf, J, wl);
             wg_gemm<T, n1c, n1c, n1f, n1c, n1c, 2, true>(J, wl, rc);
@@ -1869,7 +1869,7 @@ __device__ __attribute__((noinline)) void prolong_level(const T* ec, T* xf, cons
     if constexpr (DIM == 2 && P >= MFMA_MIN_P2) {
         // W1 = ec J^T (n1c x n1f); xf += J W1; W1 in LDS where it fits
         (void)w2;
-        if constexpr (P <= 64 && n1c * n1f <= LDSW) {
+        if constexpr (n1c * n1f <= LDSW) {
             const auto wl = (__attribute__((address_space(3))) T*)work_lds();
             wg_gemm<T, n1c, n1f, n1c, n1c, n1f, 0>(ec, JT, wl);
             wg_gemm<T, n1f, n1f, n1c, n1f, n1f, 1, true>(JT, wl, xf);
@@ -2001,8 +2001,13 @@ __device__ __attribute__((noinline)) void collapsed_solve(const double* C_, cons
         const int part = t / ni, j = t - part * ni;
         const int i0 = part * KL, i1 = i0 + KL < ni ? i0 + KL : ni;
         double s = 0.0;
+        if constexpr (KL >= 64) {   // long rows: sixteen loads in flight
+#pragma unroll 16
+            for (int i = i0; i < i1; ++i) s += C[(long long)i * ni + j] * rl[i];
+        } else {
 #pragma unroll 8
-        for (int i = i0; i < i1; ++i) s += C[(long long)i * ni + j] * rl[i];
+            for (int i = i0; i < i1; ++i) s += C[(long long)i * ni + j] * rl[i];
+        }
         if (KS == 1)
             x[interior_node<P, DIM>(j)] = T(s);
         else if (part == 1)
