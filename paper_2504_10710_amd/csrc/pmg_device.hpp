@@ -475,8 +475,22 @@ __device__ inline void apply2d_mfma_passes(PG __restrict__ G, PD __restrict__ D,
     using V4 = typename Mfma<T>::v4;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lr = lane & 15, kq = lane >> 4;
+    // p = 128 (4 x 4 blocks, two rounds of eight): each round's two block
+    // rows of the row-major operand (64 full rows, x in pass 1, F0 in pass
+    // 2) are staged in the LDS work buffer where it holds them, so that the
+    // four waves sharing a row strip read it from LDS instead of L2 / memory
+    constexpr int LDSW = PMG_WORK_LDS_WORDS * (int)(sizeof(double) / sizeof(T));
+    constexpr bool STRIPS = BLK == 2 && NB == 4 && 64 * n1 <= LDSW;
+    static_assert(!STRIPS || NB * NB == 2 * (NT / 64), "two rounds of one block per wave");
+    const auto sl = (__attribute__((address_space(3))) T*)work_lds();
     for (int t = wave; t < NB * NB; t += NT / 64) {
         const int r0 = 1 + (t / NB) * 16 * BLK, c0 = 1 + (t % NB) * 16 * BLK;
+        const int row0 = 1 + (t / (2 * NB)) * 64;        // first staged row of this round
+        if constexpr (STRIPS) {
+            if (t >= NT / 64) wg_barrier();               // the first round's reads are done
+            for (int e = threadIdx.x; e < 64 * n1; e += NT) sl[e] = xs[row0 * n1 + e];
+            wg_barrier();
+        }
         V4 ur[BLK][BLK], us[BLK][BLK];
 #pragma unroll
         for (int i = 0; i < BLK; ++i)
@@ -485,10 +499,16 @@ __device__ inline void apply2d_mfma_passes(PG __restrict__ G, PD __restrict__ D,
                 ur[i][j] = V4{0, 0, 0, 0};
                 us[i][j] = V4{0, 0, 0, 0};
             }
-        mfma_blocks<T, n1, n1, n1, 1, n1, BLK, BLK, 2, 1, n1>(xs + (r0 + lr) * n1 + kq,
-                                                              DT + kq * n1 + c0 + lr,
-                                                              DT + kq * n1 + r0 + lr,
-                                                              xs + kq * n1 + c0 + lr, ur, us);
+        if constexpr (STRIPS)
+            mfma_blocks<T, n1, n1, n1, 1, n1, BLK, BLK, 2, 1, n1>(sl + (r0 - row0 + lr) * n1 + kq,
+                                                                  DT + kq * n1 + c0 + lr,
+                                                                  DT + kq * n1 + r0 + lr,
+                                                                  xs + kq * n1 + c0 + lr, ur, us);
+        else
+            mfma_blocks<T, n1, n1, n1, 1, n1, BLK, BLK, 2, 1, n1>(xs + (r0 + lr) * n1 + kq,
+                                                                  DT + kq * n1 + c0 + lr,
+                                                                  DT + kq * n1 + r0 + lr,
+                                                                  xs + kq * n1 + c0 + lr, ur, us);
 #pragma unroll
         for (int i = 0; i < BLK; ++i)
 #pragma unroll
@@ -552,6 +572,12 @@ __device__ inline void apply2d_mfma_passes(PG __restrict__ G, PD __restrict__ D,
     wg_barrier();
     for (int t = wave; t < NB * NB; t += NT / 64) {
         const int r0 = 1 + (t / NB) * 16 * BLK, c0 = 1 + (t % NB) * 16 * BLK;
+        const int row0 = 1 + (t / (2 * NB)) * 64;
+        if constexpr (STRIPS) {
+            if (t >= NT / 64) wg_barrier();
+            for (int e = threadIdx.x; e < 64 * n1; e += NT) sl[e] = f0[row0 * n1 + e];
+            wg_barrier();
+        }
         V4 y[BLK][BLK];
 #pragma unroll
         for (int i = 0; i < BLK; ++i)
@@ -566,7 +592,12 @@ __device__ inline void apply2d_mfma_passes(PG __restrict__ G, PD __restrict__ D,
             for (int v = 0; v < 4; ++v) rv[v] = r[(r0 + Mfma<T>::row(lane, v)) * n1 + c0 + lr];
         }
         // sum_k F0[j][k] D[k][i] and sum_k D^T[j][k] F1[k][i]
-        if constexpr (F1SEP)
+        if constexpr (STRIPS && !F1SEP)
+            mfma_blocks<T, n1, n1, n1, 1, n1, BLK, BLK, 2, 1, n1>(sl + (r0 - row0 + lr) * n1 + kq,
+                                                                  D + kq * n1 + c0 + lr,
+                                                                  D + kq * n1 + r0 + lr,
+                                                                  f0 + N + kq * n1 + c0 + lr, y, y);
+        else if constexpr (F1SEP)
             mfma_blocks<T, n1, n1, n1, 1, n1, BLK, BLK, 2, 1, n1>(f0 + (r0 + lr) * n1 + kq,
                                                                   D + kq * n1 + c0 + lr,
                                                                   D + kq * n1 + r0 + lr,
