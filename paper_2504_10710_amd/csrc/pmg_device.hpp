@@ -1158,26 +1158,14 @@ __device__ __attribute__((noinline)) void apply_elements_level(
     }
 }
 
-template <class T, int P, int DIM, bool RESID>
-__device__ __attribute__((noinline)) void apply_level(const T* __restrict__ G_,
-                                                      const T* __restrict__ D_,
-                                                      const T* __restrict__ DT_, T* __restrict__ TR_,
-                                                      const T* __restrict__ x_,
-                                                      const T* __restrict__ r_, T* __restrict__ out_)
+// The vector-unit operator (levels below the matrix-core tiles) on
+// operands given by their own pointers (LDS or global): G the geometric
+// factors, D / DT, x, TR the fluxes.
+template <class T, int P, int DIM, bool RESID, class PG, class PD, class PX, class PT>
+__device__ inline void apply_vector(PG __restrict__ G, PD __restrict__ D, PD __restrict__ DT,
+                                    PX __restrict__ x, PT __restrict__ TR,
+                                    const T* __restrict__ r_, T* __restrict__ out_)
 {
-    if constexpr (DIM == 2 && P >= MFMA_MIN_P2) {
-        apply2d_mfma<T, P, RESID>(G_, D_, DT_, TR_, x_, r_, out_);
-        return;
-    }
-    if constexpr (DIM == 3 && P >= MFMA_MIN_P) {
-        apply3d_mfma<T, P, RESID>(G_, D_, DT_, TR_, x_, r_, out_);
-        return;
-    }
-    const auto G = gmem(G_);
-    const auto D = gmem(D_);
-    const auto DT = gmem(DT_);
-    const auto TR = gmem(TR_);
-    const auto x = gmem(x_);
     const auto r = gmem(r_);
     const auto out = gmem(out_);
     using S = Shape<P, DIM>;
@@ -1233,6 +1221,48 @@ __device__ __attribute__((noinline)) void apply_level(const T* __restrict__ G_,
         out[q] = RESID ? r[q] - y : y;
     }
     wg_barrier();
+}
+
+template <class T, int P, int DIM, bool RESID>
+__device__ __attribute__((noinline)) void apply_level(const T* __restrict__ G_,
+                                                      const T* __restrict__ D_,
+                                                      const T* __restrict__ DT_, T* __restrict__ TR_,
+                                                      const T* __restrict__ x_,
+                                                      const T* __restrict__ r_, T* __restrict__ out_)
+{
+    if constexpr (DIM == 2 && P >= MFMA_MIN_P2) {
+        apply2d_mfma<T, P, RESID>(G_, D_, DT_, TR_, x_, r_, out_);
+        return;
+    }
+    if constexpr (DIM == 3 && P >= MFMA_MIN_P) {
+        apply3d_mfma<T, P, RESID>(G_, D_, DT_, TR_, x_, r_, out_);
+        return;
+    }
+    using S = Shape<P, DIM>;
+    constexpr int N = S::N, n1 = S::n1;
+    // every operand staged in the LDS work buffer where it fits (2-D and
+    // 3-D p <= 8 in the one-launch kernels): one memory round trip in
+    constexpr int LDSW = PMG_WORK_LDS_WORDS * (int)(sizeof(double) / sizeof(T));
+    constexpr int NG = S::NC * N, NTR = DIM * N, ND = n1 * n1;
+    if constexpr (N + NG + NTR + 2 * ND <= LDSW) {
+        const auto wl = (__attribute__((address_space(3))) T*)work_lds();
+        const auto G = gmem(G_);
+        const auto D = gmem(D_);
+        const auto DT = gmem(DT_);
+        const auto x = gmem(x_);
+        const auto lx = wl, lg = wl + N, ltr = wl + N + NG, ld = wl + N + NG + NTR, ldt = ld + ND;
+        for (int q = threadIdx.x; q < N; q += NT) lx[q] = x[q];
+        for (int q = threadIdx.x; q < NG; q += NT) lg[q] = G[q];
+        for (int q = threadIdx.x; q < ND; q += NT) {
+            ld[q] = D[q];
+            ldt[q] = DT[q];
+        }
+        wg_barrier();
+        apply_vector<T, P, DIM, RESID>(lg, ld, ldt, lx, ltr, r_, out_);
+    } else {
+        apply_vector<T, P, DIM, RESID>(gmem(G_), gmem(D_), gmem(DT_), gmem(x_), gmem(TR_), r_,
+                                       out_);
+    }
 }
 
 // A x of a level of one element (apply_level) or of K^dim elements
