@@ -864,15 +864,14 @@ __device__ void apply3d_mfma(const T* __restrict__ G_, const T* __restrict__ D_,
 // gradients and the fluxes into TR (per element: 2 NE).  Pass 2: per global
 // node, the sum over the elements holding it (one inside an element, two
 // on an edge, four at a corner, in element order) of D^T of their fluxes.
-template <class T, int P, bool RESID>
-__device__ void apply2d_elements(int K, const T* __restrict__ G_, const T* __restrict__ D_,
-                                 T* __restrict__ TR_, const T* __restrict__ x_,
-                                 const T* __restrict__ r_, T* __restrict__ out_)
+// The element operator's two passes on operands given by their own
+// pointers (LDS or global): G the element factors, D the element D, x the
+// composite operand, TR the element fluxes.
+template <class T, int P, bool RESID, class PG, class PD, class PX, class PT>
+__device__ inline void apply2d_elements_passes(int K, PG __restrict__ G, PD __restrict__ D,
+                                               PT __restrict__ TR, PX __restrict__ x,
+                                               const T* __restrict__ r_, T* __restrict__ out_)
 {
-    const auto G = gmem(G_);
-    const auto D = gmem(D_);
-    const auto TR = gmem(TR_);
-    const auto x = gmem(x_);
     const auto r = gmem(r_);
     const auto out = gmem(out_);
     constexpr int n1 = P + 1, N = n1 * n1;
@@ -882,6 +881,7 @@ __device__ void apply2d_elements(int K, const T* __restrict__ G_, const T* __res
         const int i = lq % ne1, j = lq / ne1;
         const int gx = (e % K) * pe, gy = (e / K) * pe;
         T g0 = 0, g1 = 0;
+#pragma unroll 4
         for (int k = 0; k < ne1; ++k) {
             g0 += D[i * ne1 + k] * x[(gx + k) + (gy + j) * n1];
             g1 += D[j * ne1 + k] * x[(gx + i) + (gy + k) * n1];
@@ -905,12 +905,40 @@ __device__ void apply2d_elements(int K, const T* __restrict__ G_, const T* __res
             for (int ex = ex0; ex <= ex1 && ex < K; ++ex) {
                 const int e = ex + K * ey, i = I - ex * pe, j = J - ey * pe;
                 const auto f = TR + (long long)2 * NE * e;
+#pragma unroll 4
                 for (int k = 0; k < ne1; ++k)
                     y += D[k * ne1 + i] * f[k + j * ne1] + D[k * ne1 + j] * f[NE + i + k * ne1];
             }
         out[q] = RESID ? r[q] - y : y;
     }
     wg_barrier();
+}
+
+template <class T, int P, bool RESID>
+__device__ void apply2d_elements(int K, const T* __restrict__ G_, const T* __restrict__ D_,
+                                 T* __restrict__ TR_, const T* __restrict__ x_,
+                                 const T* __restrict__ r_, T* __restrict__ out_)
+{
+    constexpr int n1 = P + 1, N = n1 * n1;
+    const int pe = P / K, ne1 = pe + 1, NE = ne1 * ne1, NG = 3 * K * K * NE, NTR = 2 * K * K * NE;
+    constexpr int LDSW = PMG_WORK_LDS_WORDS * (int)(sizeof(double) / sizeof(T));
+    // x, the element factors and fluxes and D staged in the LDS work buffer
+    // where they fit (one memory round trip in; 4 x 4 elements up to
+    // composite degree 32 in the one-launch kernels)
+    if (N + NG + NTR + NE <= LDSW) {
+        const auto wl = (__attribute__((address_space(3))) T*)work_lds();
+        const auto G = gmem(G_);
+        const auto D = gmem(D_);
+        const auto x = gmem(x_);
+        const auto lx = wl, lg = wl + N, ltr = wl + N + NG, ld = wl + N + NG + NTR;
+        for (int q = threadIdx.x; q < N; q += NT) lx[q] = x[q];
+        for (int q = threadIdx.x; q < NG; q += NT) lg[q] = G[q];
+        for (int q = threadIdx.x; q < NE; q += NT) ld[q] = D[q];
+        wg_barrier();
+        apply2d_elements_passes<T, P, RESID>(K, lg, ld, ltr, lx, r_, out_);
+    } else {
+        apply2d_elements_passes<T, P, RESID>(K, gmem(G_), gmem(D_), gmem(TR_), gmem(x_), r_, out_);
+    }
 }
 
 // The same in 3-D (K^3 elements of degree pe, per element G00, G11, G22,
@@ -1056,7 +1084,8 @@ __device__ void apply2d_elements_mfma(const T* __restrict__ G_, const T* __restr
         const int j = k2 <= PE ? 0 : k2 - PE, i = k2 <= PE ? k2 : 0;
         const auto xe = EX + (long long)NE * e;
         T ur = 0, us = 0;
-        for (int k = 0; k < ne1; ++k) {
+#pragma unroll 8
+        for (int k = 0; k < ne1; ++k) {   // loads of eight terms in flight
             ur += xe[j * ne1 + k] * DT[k * ne1 + i];
             us += D[j * ne1 + k] * xe[k * ne1 + i];
         }
@@ -1098,6 +1127,7 @@ __device__ void apply2d_elements_mfma(const T* __restrict__ G_, const T* __restr
         const int j = k2 <= PE ? 0 : k2 - PE, i = k2 <= PE ? k2 : 0;
         const auto Fe = TR + 2LL * NE * e;
         T y = 0;
+#pragma unroll 8
         for (int k = 0; k < ne1; ++k) y += Fe[j * ne1 + k] * D[k * ne1 + i] + D[k * ne1 + j] * Fe[NE + k * ne1 + i];
         EX[(long long)NE * e + j * ne1 + i] = y;
     }
