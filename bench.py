@@ -251,7 +251,7 @@ def run_batch(args, prec_name, dim=2, p=None, B=None, gamma=None, restriction=No
           file=sys.stderr, flush=True)
     # levels the library applies as dense matrices (named "Cc[l]" in the layout)
     coll = tuple(2 << int(name[3:-1]) for name, _, _ in pmg.pmg_workspace_layout(desc)
-                 if name.startswith("Cc[")) if K == 1 else ()
+                 if name.startswith("Cc["))
     flops = sum(flops_per_solve(dim, p, gamma, 1, int(k), args.krylov, restart, coll, K)
                 for k in its)
     xk = x[:keep].cpu().numpy() if keep else None

@@ -394,11 +394,12 @@ void plan(pmg_handle* h, std::vector<pmg_region>* rec = nullptr)
         const long long ni = dim == 2 ? (pl - 1) * (pl - 1) : (pl - 1) * (pl - 1) * (pl - 1);
         double visits = 1.0;
         for (int k = l; k < h->nlev - 1; ++k) visits *= d.gamma;
-        const bool coll = h->K > 1
-            // several elements: the coarsest level's exact inverse only
-            ? l == h->l0
-            : (pl == collapse_lo(dim) || pl == collapse_p(dim)) && d.p_fine > pl &&
-                  16.0 * visits >= (double)ni;
+        // several elements: the coarsest level holds its exact inverse, and
+        // in 2-D the levels above it are collapsed by the same rule as one
+        // element's
+        const bool rule = (pl == collapse_lo(dim) || pl == collapse_p(dim)) && d.p_fine > pl &&
+                          16.0 * visits >= (double)ni;
+        const bool coll = h->K > 1 ? (l == h->l0 || (dim == 2 && rule)) : rule;
         h->o_Cc[l] = coll ? L.take("Cc", l, sizeof(double) * (size_t)B * ni * ni) : 0;
     }
     h->o_hier64 = L.take("hier64", -1, sizeof(Hier<double>));
@@ -716,10 +717,11 @@ int pmg_setup(const pmg_desc* desc, const double* const* d_coords, void* d_ws, s
     setup_args(h, a);
     for (int l = h->l0; l < h->nlev; ++l) a.coords[l] = d_coords[l];
     hipError_t e = launch_setup(h->d.dim, h->d.p_fine, h->nlev, h->d.batch, a, d_info, s);
-    for (int l = 0; l < h->nlev && e == hipSuccess && h->K == 1; ++l)   // lower level first
+    // lower level first; above the coarsest level's exact inverse with elements
+    for (int l = h->K > 1 ? h->l0 + 1 : 0; l < h->nlev && e == hipSuccess; ++l)
         if (h->o_Cc[l])
-            e = launch_collapse(h->d.dim, 2 << l, h->f32, h->d.batch, hier_of(h, h->f32),
-                                (double*)(h->ws + h->o_Cc[l]), nullptr, s);
+            e = launch_collapse(h->d.dim, 2 << l, h->f32, h->K > 1, h->d.batch,
+                                hier_of(h, h->f32), (double*)(h->ws + h->o_Cc[l]), nullptr, s);
     if (e != hipSuccess) {
         delete h;
         return hip_fail(e, "setup kernels");
@@ -1165,9 +1167,9 @@ int pmg_pool_admit(pmg_pool* P, int n, const int* slots, const double* const* d_
     a.nslots = n;
     pmg_info* info = (pmg_info*)(h->ws + h->o_info);
     e = launch_setup(dim, h->d.p_fine, h->nlev, B, a, info, s);
-    for (int l = 0; l < h->nlev && e == hipSuccess && h->K == 1; ++l)   // lower level first
+    for (int l = h->K > 1 ? h->l0 + 1 : 0; l < h->nlev && e == hipSuccess; ++l)   // lower first
         if (h->o_Cc[l])
-            e = launch_collapse(dim, 2 << l, h->f32, n, hier_of(h, h->f32),
+            e = launch_collapse(dim, 2 << l, h->f32, h->K > 1, n, hier_of(h, h->f32),
                                 (double*)(h->ws + h->o_Cc[l]), dslots, s);
     if (e == hipSuccess)
         e = launch_rhs(dim, h->d.p_fine, B, hier64_dev(h), (const double*)(h->ws + h->o_in_f),

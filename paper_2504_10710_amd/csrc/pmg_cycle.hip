@@ -35,9 +35,10 @@ hipError_t launch_cycle(int dim, int p, bool f32, bool elem, int B, const void* 
 // below it) for each problem: column i = M^{-1} e_i for the i-th interior
 // node, the cycle applied to unit vectors in the level's own right-hand side
 // and iterate buffers, with the levels below PC applied by their matrices
-// where those are already built.  One workgroup per problem (or per listed
-// slot).
-template <class T, int PC, int DIM>
+// where those are already built (with several elements, E, the coarsest
+// level's exact inverse among them).  One workgroup per problem (or per
+// listed slot).
+template <class T, int PC, int DIM, bool E>
 __global__ void __launch_bounds__(NT, 4) k_collapse(const Hier<T>* __restrict__ Hp,
                                                     double* __restrict__ Cc,
                                                     const int* __restrict__ slots)
@@ -56,32 +57,40 @@ __global__ void __launch_bounds__(NT, 4) k_collapse(const Hier<T>* __restrict__ 
         const int qi = interior_node<PC, DIM>(i);
         for (int q = threadIdx.x; q < S::N; q += NT) rg[q] = q == qi ? T(1) : T(0);
         wg_barrier();
-        gamma_cycle<T, PC, DIM, PC / 2>(H, b, r, x);   // one-element hierarchies only
+        gamma_cycle<T, PC, DIM, PC / 2, E>(H, b, r, x);
         for (int j = threadIdx.x; j < ni; j += NT) C[(long long)i * ni + j] = (double)xg[interior_node<PC, DIM>(j)];
         wg_barrier();
     }
 }
 
-hipError_t launch_collapse(int dim, int pc, bool f32, int nb, const void* H, double* Cc,
-                           const int* slots, hipStream_t s)
+template <bool E>
+static hipError_t launch_collapse_e(int dim, int pc, bool f32, int nb, const void* H, double* Cc,
+                                    const int* slots, hipStream_t s)
 {
-    if (nb <= 0) return hipSuccess;
     if (dim == 2 && pc == collapse_lo(2)) {
-        PMG_TYPED(f32, hipLaunchKernelGGL((k_collapse<T_, collapse_lo(2), 2>), dim3(nb), dim3(NT), 0,
-                                          s, (const Hier<T_>*)H, Cc, slots));
+        PMG_TYPED(f32, hipLaunchKernelGGL((k_collapse<T_, collapse_lo(2), 2, E>), dim3(nb), dim3(NT),
+                                          0, s, (const Hier<T_>*)H, Cc, slots));
     } else if (dim == 2 && pc == collapse_p(2)) {
-        PMG_TYPED(f32, hipLaunchKernelGGL((k_collapse<T_, collapse_p(2), 2>), dim3(nb), dim3(NT), 0,
-                                          s, (const Hier<T_>*)H, Cc, slots));
+        PMG_TYPED(f32, hipLaunchKernelGGL((k_collapse<T_, collapse_p(2), 2, E>), dim3(nb), dim3(NT),
+                                          0, s, (const Hier<T_>*)H, Cc, slots));
     } else if (dim == 3 && pc == collapse_lo(3)) {
-        PMG_TYPED(f32, hipLaunchKernelGGL((k_collapse<T_, collapse_lo(3), 3>), dim3(nb), dim3(NT), 0,
-                                          s, (const Hier<T_>*)H, Cc, slots));
+        PMG_TYPED(f32, hipLaunchKernelGGL((k_collapse<T_, collapse_lo(3), 3, E>), dim3(nb), dim3(NT),
+                                          0, s, (const Hier<T_>*)H, Cc, slots));
     } else if (dim == 3 && pc == collapse_p(3)) {
-        PMG_TYPED(f32, hipLaunchKernelGGL((k_collapse<T_, collapse_p(3), 3>), dim3(nb), dim3(NT), 0,
-                                          s, (const Hier<T_>*)H, Cc, slots));
+        PMG_TYPED(f32, hipLaunchKernelGGL((k_collapse<T_, collapse_p(3), 3, E>), dim3(nb), dim3(NT),
+                                          0, s, (const Hier<T_>*)H, Cc, slots));
     } else {
         return hipErrorInvalidValue;
     }
     return last();
+}
+
+hipError_t launch_collapse(int dim, int pc, bool f32, bool elem, int nb, const void* H, double* Cc,
+                           const int* slots, hipStream_t s)
+{
+    if (nb <= 0) return hipSuccess;
+    return elem ? launch_collapse_e<true>(dim, pc, f32, nb, H, Cc, slots, s)
+                : launch_collapse_e<false>(dim, pc, f32, nb, H, Cc, slots, s);
 }
 
 }  // namespace pmg

@@ -91,8 +91,8 @@ hipError_t launch_cycle(int dim, int p, bool f32, bool elem, int B, const void* 
                         void* y, hipStream_t s);
 // dense matrices of the collapsed coarse cycle of level pc (collapse_lo(dim)
 // or collapse_p(dim); the lower one first) for nb problems (all, or the
-// listed slots)
-hipError_t launch_collapse(int dim, int pc, bool f32, int nb, const void* H, double* Cc,
+// listed slots); elem: the hierarchy has several elements per axis
+hipError_t launch_collapse(int dim, int pc, bool f32, bool elem, int nb, const void* H, double* Cc,
                            const int* slots, hipStream_t s);
 // grid = B workgroups (problem b = workgroup, or a.slots[workgroup])
 hipError_t launch_solve_f64(int dim, int p, bool f32, int B, const void* H, const SolveArgs& a,

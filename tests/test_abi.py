@@ -130,17 +130,21 @@ def test_workspace_layout_in_bounds(kw):
         assert furthest + esz <= total
 
 
-@pytest.mark.parametrize("dim,K,p,prec", [(2, 2, 16, pmg.PMG_F64), (2, 4, 128, pmg.PMG_F64),
-                                          (2, 8, 64, pmg.PMG_F32), (2, 4, 256, pmg.PMG_F32),
-                                          (3, 2, 16, pmg.PMG_F64), (3, 4, 64, pmg.PMG_F32)])
-def test_element_workspace_layout(dim, K, p, prec):
+@pytest.mark.parametrize("dim,K,p,prec,gamma", [(2, 2, 16, pmg.PMG_F64, 1), (2, 4, 128, pmg.PMG_F64, 1),
+                                                (2, 8, 64, pmg.PMG_F32, 1), (2, 4, 256, pmg.PMG_F32, 1),
+                                                (3, 2, 16, pmg.PMG_F64, 1), (3, 4, 64, pmg.PMG_F32, 1),
+                                                (2, 4, 128, pmg.PMG_F64, 3), (2, 2, 64, pmg.PMG_F64, 2),
+                                                (3, 2, 32, pmg.PMG_F64, 5)])
+def test_element_workspace_layout(dim, K, p, prec, gamma):
     """Several elements per axis: levels below degree 2K are absent; the
     geometric factors and fluxes of a level hold K^dim (p_l/K + 1)^dim element
     nodes per problem; the coarsest level holds its (2K-1)^dim square exact
-    inverse; every region in bounds, aligned, without overlap."""
+    inverse, and in 2-D the levels of degree 8 and 16 above it a collapsed
+    matrix where gamma^depth >= ni / 16 (none in 3-D); every region in
+    bounds, aligned, without overlap."""
     B = 3
     desc = pmg.make_desc(dim=dim, p_fine=p, batch=B, elements=K, smoother=pmg.PMG_SMOOTHER_FEM,
-                         inner_prec=prec)
+                         inner_prec=prec, gamma=gamma)
     l0 = pmg.pmg_first_level(desc)
     assert l0 == int(np.log2(2 * K)) - 1
     nlev = pmg.pmg_num_levels(desc)
@@ -166,7 +170,16 @@ def test_element_workspace_layout(dim, K, p, prec):
         assert lev[f"X[{l}]"] == tsz * B * (pl + 1) ** dim
     ni = (2 * K - 1) ** dim
     cc = [n for n in lev if n.startswith("Cc")]
-    assert cc == [f"Cc[{l0}]"] and lev[cc[0]] == 8 * B * ni * ni
+    want = [l0] + [l for l in range(l0 + 1, nlev)
+                   if dim == 2 and (2 << l) in (8, 16) and p > (2 << l)
+                   and 16 * gamma ** (nlev - 1 - l) >= ((2 << l) - 1) ** 2]
+    assert cc == [f"Cc[{l}]" for l in want], (cc, want)
+    assert lev[cc[0]] == 8 * B * ni * ni
+    for l in want[1:]:
+        nl = ((2 << l) - 1) ** 2
+        assert lev[f"Cc[{l}]"] == 8 * B * nl * nl
+    if (dim, K, p, gamma) == (2, 4, 128, 3):
+        assert want == [l0, l0 + 1]          # the exact inverse at 8 and the collapsed 16
 
 
 @pytest.mark.parametrize("kw", [dict(elements=3, p_fine=48), dict(elements=8, dim=3, p_fine=64),
