@@ -111,9 +111,13 @@ enum { PMG_RESTRICT_TRANSPOSE = 0, PMG_RESTRICT_INTERP = 1 };
  *              coarsest level has degree 2K (level index log2(2K) - 1; the
  *              levels below it are absent) and is solved exactly with the
  *              inverse of its (2K-1)^dim x (2K-1)^dim interior matrix, built at
- *              setup in FP64.  Line systems run along the composite grid
- *              lines across element interfaces (GLL rows: entries of the
- *              assembled operator; FEM rows: the composite node mesh). */
+ *              setup in FP64.  In 2-D the levels of composite degree 8 and
+ *              16 above it are collapsed into dense matrices by the same
+ *              rule as one element's (built at setup from the element
+ *              cycle; the cycle's result is the same up to rounding).  Line
+ *              systems run along the composite grid lines across element
+ *              interfaces (GLL rows: entries of the assembled operator; FEM
+ *              rows: the composite node mesh). */
 typedef struct {
     int dim;
     int p_fine;
