@@ -69,7 +69,12 @@ enum { PMG_RESTRICT_TRANSPOSE = 0, PMG_RESTRICT_INTERP = 1 };
  *   batch      B >= 1 problems
  *   gamma, m, alpha   gamma-cycle parameters of Alg. 2 (gamma >= 1 coarse
  *              corrections per visit, m smoothing steps per axis, relaxation
- *              alpha > 0)
+ *              alpha > 0).  The cycle is linear in its right-hand side, so
+ *              a coarse level of degree 8 or 16 (2-D; 4 or 8 in 3-D) entered
+ *              gamma^depth >= ni / 16 times per cycle (ni its interior
+ *              nodes) is applied as the dense FP64 matrix of its own cycle,
+ *              built at setup (workspace regions "Cc[l]"); the result is
+ *              the recursive cycle's up to rounding.
  *   smoother   PMG_SMOOTHER_GLL: tridiagonal part of A_p along each line
  *              (Def. line preconditioners with half-bandwidth 1);
  *              PMG_SMOOTHER_FEM: tridiagonal line systems of the bilinear
@@ -112,9 +117,9 @@ enum { PMG_RESTRICT_TRANSPOSE = 0, PMG_RESTRICT_INTERP = 1 };
  *              levels below it are absent) and is solved exactly with the
  *              inverse of its (2K-1)^dim x (2K-1)^dim interior matrix, built at
  *              setup in FP64.  In 2-D the levels of composite degree 8 and
- *              16 above it are collapsed into dense matrices by the same
- *              rule as one element's (built at setup from the element
- *              cycle; the cycle's result is the same up to rounding).  Line
+ *              16 above it are collapsed into dense matrices by the rule
+ *              given under gamma (built at setup from the element cycle).
+ *              Line
  *              systems run along the composite grid lines across element
  *              interfaces (GLL rows: entries of the assembled operator; FEM
  *              rows: the composite node mesh). */
