@@ -119,10 +119,9 @@ enum { PMG_RESTRICT_TRANSPOSE = 0, PMG_RESTRICT_INTERP = 1 };
  *              setup in FP64.  In 2-D the levels of composite degree 8 and
  *              16 above it are collapsed into dense matrices by the rule
  *              given under gamma (built at setup from the element cycle).
- *              Line
- *              systems run along the composite grid lines across element
- *              interfaces (GLL rows: entries of the assembled operator; FEM
- *              rows: the composite node mesh). */
+ *              Line systems run along the composite grid lines across
+ *              element interfaces (GLL rows: entries of the assembled
+ *              operator; FEM rows: the composite node mesh). */
 typedef struct {
     int dim;
     int p_fine;
