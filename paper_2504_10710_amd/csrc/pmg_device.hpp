@@ -499,6 +499,19 @@ __device__ inline void apply2d_mfma_passes(PG __restrict__ G, PD __restrict__ D,
                 ur[i][j] = V4{0, 0, 0, 0};
                 us[i][j] = V4{0, 0, 0, 0};
             }
+        // single tiles: the tile's geometric factors are loaded before the
+        // products, their latency hidden behind them
+        constexpr bool PREG = BLK == 1;
+        T gp[PREG ? 4 : 1][3];
+        if constexpr (PREG) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int q = (r0 + Mfma<T>::row(lane, v)) * n1 + c0 + lr;
+                gp[v][0] = G[q];
+                gp[v][1] = G[N + q];
+                gp[v][2] = G[2 * N + q];
+            }
+        }
         if constexpr (STRIPS)
             mfma_blocks<T, n1, n1, n1, 1, n1, BLK, BLK, 2, 1, n1>(sl + (r0 - row0 + lr) * n1 + kq,
                                                                   DT + kq * n1 + c0 + lr,
@@ -517,7 +530,8 @@ __device__ inline void apply2d_mfma_passes(PG __restrict__ G, PD __restrict__ D,
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int q = (r0 + 16 * i + Mfma<T>::row(lane, v)) * n1 + col;
-                    const T g00 = G[q], g11 = G[N + q], g01 = G[2 * N + q];
+                    const T g00 = PREG ? gp[v][0] : G[q], g11 = PREG ? gp[v][1] : G[N + q],
+                            g01 = PREG ? gp[v][2] : G[2 * N + q];
                     f0[q] = g00 * ur[i][j][v] + g01 * us[i][j][v];
                     if constexpr (F1SEP)
                         f1[q] = g01 * ur[i][j][v] + g11 * us[i][j][v];
